@@ -1,0 +1,164 @@
+"""Seeded synthetic inputs for the LSM dictionary (numpy only).
+
+This module produces operation streams and query sets; it holds none of the
+dictionary's arithmetic (no sorting, merging or query answering) and is the
+only code shared by the oracle side and the GPU side of the tests.
+
+Random numbers come from splitmix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014) used as a counter-based
+generator: draw i of stream (c, s) is mix64(seed + (i + 1) * GAMMA) with
+seed = (c << 32) | s, so any slice of a stream can be generated on its own.
+Streams: 1 keys, 2 values, 3 delete-key picks, 4 lookup picks, 5 count/range
+starts, 6 lookup miss keys, 7 Zipf draws, 8 batch sizes, 9 request mix.
+
+The paper's workloads are uniformly random 31-bit keys (sec. V-B, V-C); the
+recipes below follow that, and the Zipf recipe stands in for the skewed
+reinsertion workload that exercises stale and tombstoned elements.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+KEY_DOMAIN = 1 << 31
+
+
+def splitmix64(config: int, stream: int, start: int, count: int) -> np.ndarray:
+    """Draws start .. start+count-1 of stream (config, stream) as uint64."""
+    seed = np.uint64(((config & 0xFFFFFFFF) << 32) | (stream & 0xFFFFFFFF))
+    with np.errstate(over="ignore"):
+        i = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+        z = seed + i * GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform_keys(config: int, stream: int, start: int, n: int, bits: int = 31) -> np.ndarray:
+    return (splitmix64(config, stream, start, n) >> np.uint64(64 - bits)).astype(np.uint32)
+
+
+def values(config: int, stream: int, start: int, n: int) -> np.ndarray:
+    return (splitmix64(config, stream, start, n) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+
+
+def bounded(config: int, stream: int, start: int, n: int, bound: int) -> np.ndarray:
+    """Integers in [0, bound) (multiply-shift on the top 32 bits)."""
+    x = splitmix64(config, stream, start, n) >> np.uint64(32)
+    return ((x * np.uint64(bound)) >> np.uint64(32)).astype(np.int64)
+
+
+@dataclass
+class PlainWorkload:
+    """A build of R update batches of b slots followed by three query sets.
+
+    keys/vals: uint32 [R, b]; is_delete: bool [R] (a delete batch's values are
+    unused).  Queries: lookups [nq], count_lo/hi and range_lo/hi [nc].
+    """
+    name: str
+    b: int
+    keys: np.ndarray
+    vals: np.ndarray
+    is_delete: np.ndarray
+    lookups: np.ndarray
+    count_lo: np.ndarray
+    count_hi: np.ndarray
+    range_lo: np.ndarray
+    range_hi: np.ndarray
+    width: int
+    key_bits: int = 31
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def R(self) -> int:
+        return int(self.keys.shape[0])
+
+
+def _delete_batch_keys(config, keys, is_delete, b):
+    """Fill each delete batch with keys drawn, with replacement, from all keys
+    inserted by earlier insert batches."""
+    ins_rows: List[int] = []
+    draw = 0
+    for i in range(keys.shape[0]):
+        if not is_delete[i]:
+            ins_rows.append(i)
+            continue
+        pool = len(ins_rows) * b
+        assert pool > 0, "a delete batch needs earlier inserts"
+        idx = bounded(config, 3, draw, b, pool)
+        draw += b
+        rows = np.asarray(ins_rows, dtype=np.int64)[idx // b]
+        keys[i] = keys[rows, idx % b]
+
+
+def _queries(config, keys, is_delete, nq, ncount, expected_hits, domain):
+    ins = keys[~is_delete].reshape(-1)
+    pick = splitmix64(config, 4, 0, nq)
+    hit = (pick & np.uint64(1)).astype(bool)
+    idx = ((pick >> np.uint64(32)) * np.uint64(ins.size)) >> np.uint64(32)
+    miss = (splitmix64(config, 6, 0, nq) % np.uint64(domain)).astype(np.uint32)
+    lookups = np.where(hit, ins[idx.astype(np.int64)], miss).astype(np.uint32)
+    width = max(1, int(round(expected_hits * domain / max(1, ins.size))))
+    starts = bounded(config, 5, 0, 2 * ncount, domain - width + 1).astype(np.uint32)
+    c_lo, r_lo = starts[:ncount], starts[ncount:]
+    return lookups, c_lo, (c_lo + np.uint32(width - 1)), r_lo, (r_lo + np.uint32(width - 1)), width
+
+
+def tiny(config: int = 1) -> PlainWorkload:
+    """b = 1024: 16 insert batches, then 4 delete batches of keys drawn from
+    the inserted ones; 4096 lookups (half drawn from inserted keys), 1024
+    count and 1024 range queries whose width expects about 8 hits."""
+    b, R = 1024, 20
+    is_delete = np.array([False] * 16 + [True] * 4)
+    keys = uniform_keys(config, 1, 0, R * b).reshape(R, b)
+    vals = values(config, 2, 0, R * b).reshape(R, b)
+    _delete_batch_keys(config, keys, is_delete, b)
+    lk, clo, chi, rlo, rhi, w = _queries(config, keys, is_delete, 4096, 1024, 8, KEY_DOMAIN)
+    return PlainWorkload("tiny b=1024 R=20 (16 insert + 4 delete batches)", b, keys, vals,
+                         is_delete, lk, clo, chi, rlo, rhi, w)
+
+
+def paper_scale(config: int = 2, b: int = 1 << 16, R: int = 1024, nq: int = 1 << 22,
+                ncount: int = 1 << 20, expected_hits: int = 16) -> PlainWorkload:
+    """b = 2^16, R = 1024 batches (n = 2^26 slots), uniform 31-bit keys;
+    batch i deletes iff i mod 10 == 9 (keys drawn from earlier inserts).
+    Then 2^22 lookups (half drawn from inserted keys), 2^20 count and 2^20
+    range queries of a width that expects 16 hits."""
+    is_delete = (np.arange(R) % 10) == 9
+    keys = uniform_keys(config, 1, 0, R * b).reshape(R, b)
+    vals = values(config, 2, 0, R * b).reshape(R, b)
+    _delete_batch_keys(config, keys, is_delete, b)
+    lk, clo, chi, rlo, rhi, w = _queries(config, keys, is_delete, nq, ncount, expected_hits, KEY_DOMAIN)
+    return PlainWorkload("paper scale b=2^16 R=%d n=%d" % (R, R * b), b, keys, vals,
+                         is_delete, lk, clo, chi, rlo, rhi, w)
+
+
+def random_small(seed: int, b: int, R: int, domain: int, p_delete: float = 0.3,
+                 nq: int = 512, partial: bool = True):
+    """Small mixed stream for edge-case tests: list of (kind, keys, vals) with
+    batch sizes in [1, b] when partial, key domain [0, domain)."""
+    ops = []
+    off = 0
+    sizes = (bounded(seed, 8, 0, R, b) + 1) if partial else np.full(R, b)
+    kinds = bounded(seed, 9, 0, R, 1000)
+    n_ins = 0
+    for t in range(R):
+        n = int(sizes[t])
+        k = (splitmix64(seed, 1, off, n) % np.uint64(domain)).astype(np.uint32)
+        v = values(seed, 2, off, n)
+        off += n
+        if kinds[t] < p_delete * 1000 and n_ins > 0:
+            ops.append(("delete", k, None))
+        else:
+            ops.append(("insert", k, v))
+            n_ins += 1
+    q = (splitmix64(seed, 4, 0, nq) % np.uint64(domain + 2)).astype(np.uint32)
+    a = (splitmix64(seed, 5, 0, nq) % np.uint64(domain + 2)).astype(np.uint32)
+    c = (splitmix64(seed, 6, 0, nq) % np.uint64(domain + 2)).astype(np.uint32)
+    return ops, q, np.minimum(a, c), np.maximum(a, c)
