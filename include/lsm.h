@@ -1,0 +1,211 @@
+/*
+ * lsm.h -- C ABI of an MI355X (gfx950) batched LSM dictionary.
+ *
+ * The data structure and its operations are those of Ashkiani, Li,
+ * Farach-Colton, Amenta and Owens, "GPU LSM: A Dynamic Dictionary Data
+ * Structure for the GPU" (IPDPS 2018, arXiv 1707.05354):
+ *
+ *   - a dictionary of <key, value> pairs with INSERT, DELETE, LOOKUP, COUNT
+ *     and RANGE (sec. I-B), updated in batches of exactly b elements with the
+ *     batch semantics of sec. III-A;
+ *   - levels of b * 2^i elements, each a sorted array, occupied exactly where
+ *     the batch counter r has a set bit; an insertion sorts the batch and
+ *     merges it down the full levels like a binary-counter increment
+ *     (sec. III-B, Fig. 2(a), Fig. 3);
+ *   - deletion as insertion of tombstones (sec. III-C): each stored element
+ *     is a 32-bit key variable (original key << 1) | status, status 1 for a
+ *     regular element and 0 for a tombstone (sec. IV-A), plus a 32-bit value.
+ *
+ * Conventions for every call:
+ *   - Every array argument whose name starts with d_ is a DEVICE pointer
+ *     owned by the caller, on the device the handle was created on.  The
+ *     library keeps no caller pointer after the call returns.
+ *   - All device work is enqueued on the handle's HIP stream, in call order.
+ *     Inputs must stay valid, and outputs are complete, only once that
+ *     stream has passed the call (hipStreamSynchronize or an event).  Calls
+ *     that must read a result back (lsm_range, checked-mode updates)
+ *     synchronise the stream themselves.
+ *   - Original keys must be < 2^31 (one bit of the 32-bit key variable holds
+ *     the status, sec. IV-A), and < 2^k when the handle was created with
+ *     LSM_KEY_BITS(k).  Values are arbitrary 32-bit words.
+ *   - Every call returns a status.  On any error the dictionary is left
+ *     exactly as it was before the call (strong guarantee).
+ *   - A handle is not thread-safe; calls on different handles are
+ *     independent.
+ */
+#ifndef LSM_H_
+#define LSM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define LSM_API __attribute__((visibility("default")))
+#else
+#define LSM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lsm_s* lsm_t;
+
+typedef enum {
+  LSM_OK = 0,
+  LSM_EINVAL = 1,    /* null handle or pointer, b out of range, bad flags   */
+  LSM_EKEY = 2,      /* checked mode: a key is >= 2^key_bits                */
+  LSM_EBATCH = 3,    /* an update batch holds more than b elements          */
+  LSM_ENOMEM = 4,    /* a device or pinned-host allocation failed           */
+  LSM_ECAPACITY = 5, /* range output larger than cap, or the next level
+                        would exceed 2^31 elements                          */
+  LSM_EHIP = 6       /* a HIP runtime call or kernel launch failed          */
+} lsm_status_t;
+
+/* lsm_create flags. */
+#define LSM_CHECKED 0x1u /* validate update keys on the device (syncs)    */
+/* Promise that every original key is < 2^k (1 <= k <= 31; default 31).
+ * Fewer key bits mean fewer radix-sort passes over each batch. */
+#define LSM_KEY_BITS(k) ((((uint32_t)(k)) & 0x3Fu) << 8)
+
+/*
+ * lsm_create -- an empty dictionary with batch size b (sec. III-A rule 1:
+ * b is fixed and is also the size of level 0).
+ *   out    : receives the handle.
+ *   b      : batch size, 1 <= b <= 2^28.
+ *   flags  : LSM_CHECKED and/or LSM_KEY_BITS(k).
+ *   stream : hipStream_t to order all work on (NULL = the default stream);
+ *            the device current at this call becomes the handle's device.
+ * Allocates the batch scratch (about 40 * b bytes); levels are allocated
+ * when an insertion first reaches them.  LSM_EINVAL, LSM_ENOMEM, LSM_EHIP.
+ */
+LSM_API lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream);
+
+/* Re-target the handle to another stream of the same device. */
+LSM_API lsm_status_t lsm_set_stream(lsm_t h, void* stream);
+
+/*
+ * lsm_insert_batch -- INSERT(k, v) for n pairs as one batch (sec. III-B,
+ * Fig. 2(a)).  The batch is sorted, then merged down the full levels into
+ * the first empty level; the batch counter r grows by one.
+ *   d_keys, d_vals : n original keys and n values (device).
+ *   n              : 0 <= n <= b.  n == 0 is a no-op (r unchanged).  A batch
+ *                    with n < b is padded with copies of its last pair
+ *                    (sec. IV-A), so it still occupies b slots.
+ * Duplicate keys inside one batch: the last one in batch order wins.
+ * LSM_EBATCH if n > b; LSM_EKEY (checked mode); LSM_ENOMEM; LSM_ECAPACITY;
+ * LSM_EHIP.
+ */
+LSM_API lsm_status_t lsm_insert_batch(lsm_t h, const uint32_t* d_keys,
+                              const uint32_t* d_vals, uint32_t n);
+
+/*
+ * lsm_delete_batch -- DELETE(k) for n keys as one batch: the insertion of
+ * n tombstones (sec. III-C), which hide every older instance of their keys.
+ * Same size rules and errors as lsm_insert_batch.
+ */
+LSM_API lsm_status_t lsm_delete_batch(lsm_t h, const uint32_t* d_keys, uint32_t n);
+
+/*
+ * lsm_update_batch -- one mixed batch of insertions and deletions
+ * (sec. III-A rule 2).  d_is_delete[j] != 0 makes element j a deletion
+ * (its value is ignored).  A key inserted and deleted in the same batch
+ * ends up deleted (sec. III-A rule 5); otherwise the last insertion of a
+ * key in batch order wins.  Same size rules and errors as
+ * lsm_insert_batch.
+ */
+LSM_API lsm_status_t lsm_update_batch(lsm_t h, const uint32_t* d_keys,
+                              const uint32_t* d_vals,
+                              const uint8_t* d_is_delete, uint32_t n);
+
+/*
+ * lsm_lookup -- LOOKUP(k) for nq query keys (sec. III-D, IV-B): searches
+ * the occupied levels from the smallest (newest) up; a regular element
+ * with key k returns its value, a tombstone with key k ends the search
+ * with "not found".
+ *   d_keys  : nq query keys (device).
+ *   d_vals  : nq outputs; the value, or 0 when not found.
+ *   d_found : nq outputs; 1 when found, else 0.
+ * nq == 0 is a no-op.  Asynchronous.  LSM_EINVAL, LSM_EHIP.
+ */
+LSM_API lsm_status_t lsm_lookup(lsm_t h, const uint32_t* d_keys, uint32_t nq,
+                        uint32_t* d_vals, uint8_t* d_found);
+
+/*
+ * lsm_count -- COUNT(k1, k2) for nq queries (sec. III-E, IV-C): the number
+ * of live keys k with d_lo[q] <= k <= d_hi[q] (bounds inclusive; 0 when
+ * d_lo[q] > d_hi[q]).  Stale elements and tombstones are not counted.
+ *   d_counts : nq outputs (device).
+ * nq == 0 is a no-op.  Asynchronous.  LSM_EINVAL, LSM_ENOMEM, LSM_EHIP.
+ */
+LSM_API lsm_status_t lsm_count(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi,
+                       uint32_t nq, uint32_t* d_counts);
+
+/*
+ * lsm_range -- RANGE(k1, k2) for nq queries (sec. III-E, IV-D): every live
+ * pair with d_lo[q] <= k <= d_hi[q], per query in ascending key order,
+ * queries concatenated in query order.
+ *   d_offsets : nq + 1 outputs (device, uint64): the exclusive scan of the
+ *               per-query result sizes; d_offsets[nq] is the total.  Always
+ *               written.
+ *   d_keys, d_vals : outputs of cap elements each (device); written only
+ *               when total <= cap.  May be NULL when cap == 0.
+ *   cap       : capacity of d_keys / d_vals in elements.
+ *   h_total   : HOST pointer; receives the total.
+ * Two-phase use: call with cap = 0 to learn the total, allocate, call again.
+ * If total > cap the call writes d_offsets and *h_total, writes no keys or
+ * values and returns LSM_ECAPACITY.  Synchronises the stream (the total is
+ * read back).  LSM_EINVAL, LSM_ENOMEM, LSM_ECAPACITY, LSM_EHIP.
+ */
+LSM_API lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi,
+                       uint32_t nq, uint64_t* d_offsets, uint32_t* d_keys,
+                       uint32_t* d_vals, uint64_t cap, uint64_t* h_total);
+
+/* lsm_destroy -- synchronise the stream and free every allocation. */
+LSM_API lsm_status_t lsm_destroy(lsm_t h);
+
+/* ---------------------------------------------------------------------
+ * Introspection (tests and measurement; not part of the dictionary).
+ * ------------------------------------------------------------------- */
+
+/* Human-readable name of a status code (static string). */
+LSM_API const char* lsm_strerror(lsm_status_t s);
+
+/* Number of resident batches r (sec. III-B); 0 for a NULL handle. */
+LSM_API uint64_t lsm_num_batches(lsm_t h);
+
+/* The batch size b; 0 for a NULL handle. */
+LSM_API uint32_t lsm_batch_size(lsm_t h);
+
+/*
+ * Device pointers to level i's key variables and values and its length
+ * (b * 2^i when occupied, 0 when empty).  Valid until the next update
+ * call.  Synchronise the stream before reading them.
+ */
+LSM_API lsm_status_t lsm_level_view(lsm_t h, uint32_t i, const uint32_t** d_kv,
+                            const uint32_t** d_vals, uint64_t* len);
+
+/*
+ * Copy level i (occupied) into caller buffers d_kv_out / d_vals_out of
+ * b * 2^i elements each, enqueued on the handle's stream.  *len receives
+ * the length (0 and nothing copied when level i is empty).
+ */
+LSM_API lsm_status_t lsm_level_copy(lsm_t h, uint32_t i, uint32_t* d_kv_out,
+                                    uint32_t* d_vals_out, uint64_t* len);
+
+typedef struct {
+  uint64_t num_batches;        /* r                                        */
+  uint64_t resident_elems;     /* r * b                                    */
+  uint64_t merged_elems_last;  /* merge output elements, last update call  */
+  uint64_t merged_elems_total; /* merge output elements since creation     */
+  uint64_t sorted_elems_total; /* batch elements sorted since creation     */
+  uint64_t device_bytes;       /* device memory held by the handle         */
+} lsm_stats_t;
+
+LSM_API lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSM_H_ */

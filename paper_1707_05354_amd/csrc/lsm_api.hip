@@ -1,0 +1,457 @@
+// Host side of the C ABI declared in include/lsm.h: the handle, the level
+// table and the order of kernel launches for each operation.
+//
+// State kept on the host: the batch counter r (sec. III-B: level i is full
+// exactly when bit i of r is set) and one device allocation per level,
+// made the first time an insertion reaches that level and kept until the
+// handle is destroyed (an emptied level's contents are simply ignored).
+//
+// Strong guarantee: an update only reads the full levels 0 .. j-1 and
+// writes scratch buffers and the empty level j = ffz(r); r is incremented
+// only after every launch has been accepted, so a failure leaves the
+// dictionary as it was.
+#include <new>
+#include <string.h>
+
+#include "lsm.h"
+#include "lsm_internal.h"
+
+using namespace lsm;
+
+struct lsm_s {
+  uint32_t b = 0;
+  uint32_t flags = 0;
+  uint32_t key_bits = 31;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  uint64_t r = 0;
+
+  uint32_t* lvl_kv[kMaxLevels] = {};
+  uint32_t* lvl_val[kMaxLevels] = {};
+
+  uint32_t* tmp_kv[2] = {};  // radix ping-pong, b elements each
+  uint32_t* tmp_val[2] = {};
+  uint32_t* buf_kv = nullptr;  // the sorted batch when it has to be merged
+  uint32_t* buf_val = nullptr;
+  uint32_t* meta = nullptr;  // sort histograms, look-back words, counters
+
+  uint32_t* mrg_kv[2] = {};  // cascade ping-pong
+  uint32_t* mrg_val[2] = {};
+  uint64_t mrg_cap = 0;
+
+  uint32_t* q_counts = nullptr;  // range pass 1 output
+  uint64_t* q_status = nullptr;  // range scan look-back words
+  uint64_t q_cap = 0;
+
+  uint64_t* h_pinned = nullptr;  // read-backs (range total, key check)
+
+  uint64_t merged_last = 0, merged_total = 0, sorted_total = 0;
+  uint64_t device_bytes = 0;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+lsm_status_t dev_alloc(lsm_t h, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 4;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return LSM_ENOMEM;
+  }
+  h->device_bytes += bytes;
+  return LSM_OK;
+}
+
+void dev_free(lsm_t h, void* p, size_t bytes) {
+  if (p != nullptr) {
+    (void)hipFree(p);
+    h->device_bytes -= bytes;
+  }
+}
+
+inline uint64_t level_len(const lsm_t h, int i) { return static_cast<uint64_t>(h->b) << i; }
+
+// Number of radix passes over the key-variable bits [lo_bit, key_bits + 1).
+inline int sort_passes(uint32_t key_bits, int lo_bit) {
+  return static_cast<int>((key_bits + 1 - lo_bit + kRadixBits - 1) / kRadixBits);
+}
+
+LevelSet occupied_levels(const lsm_t h) {
+  LevelSet s;
+  memset(&s, 0, sizeof(s));
+  for (int i = 0; i < kMaxLevels; ++i) {
+    if ((h->r >> i) & 1u) {
+      s.kv[s.count] = h->lvl_kv[i];
+      s.val[s.count] = h->lvl_val[i];
+      s.len[s.count] = static_cast<uint32_t>(level_len(h, i));
+      ++s.count;
+    }
+  }
+  return s;
+}
+
+lsm_status_t ensure_level(lsm_t h, int j) {
+  if (h->lvl_kv[j] != nullptr) return LSM_OK;
+  const size_t bytes = level_len(h, j) * sizeof(uint32_t);
+  void *k = nullptr, *v = nullptr;
+  lsm_status_t s = dev_alloc(h, &k, bytes);
+  if (s != LSM_OK) return s;
+  s = dev_alloc(h, &v, bytes);
+  if (s != LSM_OK) {
+    dev_free(h, k, bytes);
+    return s;
+  }
+  h->lvl_kv[j] = static_cast<uint32_t*>(k);
+  h->lvl_val[j] = static_cast<uint32_t*>(v);
+  return LSM_OK;
+}
+
+lsm_status_t ensure_merge_scratch(lsm_t h, uint64_t elems) {
+  if (h->mrg_cap >= elems) return LSM_OK;
+  void* p[4] = {};
+  const size_t bytes = elems * sizeof(uint32_t);
+  for (int i = 0; i < 4; ++i) {
+    if (dev_alloc(h, &p[i], bytes) != LSM_OK) {
+      for (int k = 0; k < i; ++k) dev_free(h, p[k], bytes);
+      return LSM_ENOMEM;
+    }
+  }
+  const size_t old = h->mrg_cap * sizeof(uint32_t);
+  for (int i = 0; i < 2; ++i) {
+    dev_free(h, h->mrg_kv[i], old);
+    dev_free(h, h->mrg_val[i], old);
+  }
+  h->mrg_kv[0] = static_cast<uint32_t*>(p[0]);
+  h->mrg_kv[1] = static_cast<uint32_t*>(p[1]);
+  h->mrg_val[0] = static_cast<uint32_t*>(p[2]);
+  h->mrg_val[1] = static_cast<uint32_t*>(p[3]);
+  h->mrg_cap = elems;
+  return LSM_OK;
+}
+
+lsm_status_t ensure_query_scratch(lsm_t h, uint32_t nq) {
+  if (h->q_cap >= nq) return LSM_OK;
+  uint64_t cap = h->q_cap ? h->q_cap : 4096;
+  while (cap < nq) cap *= 2;
+  void *c = nullptr, *s = nullptr;
+  if (dev_alloc(h, &c, cap * sizeof(uint32_t)) != LSM_OK) return LSM_ENOMEM;
+  const size_t sw = scan_status_words(static_cast<uint32_t>(cap < 0xFFFFFFFFull ? cap : 0xFFFFFFFFull));
+  if (dev_alloc(h, &s, sw * sizeof(uint64_t)) != LSM_OK) {
+    dev_free(h, c, cap * sizeof(uint32_t));
+    return LSM_ENOMEM;
+  }
+  if (h->q_cap) {
+    dev_free(h, h->q_counts, h->q_cap * sizeof(uint32_t));
+    dev_free(h, h->q_status, scan_status_words(static_cast<uint32_t>(h->q_cap)) * sizeof(uint64_t));
+  }
+  h->q_counts = static_cast<uint32_t*>(c);
+  h->q_status = static_cast<uint64_t*>(s);
+  h->q_cap = cap;
+  return LSM_OK;
+}
+
+void release_all(lsm_t h) {
+  const size_t bb = static_cast<size_t>(h->b) * sizeof(uint32_t);
+  for (int i = 0; i < kMaxLevels; ++i) {
+    dev_free(h, h->lvl_kv[i], level_len(h, i) * sizeof(uint32_t));
+    dev_free(h, h->lvl_val[i], level_len(h, i) * sizeof(uint32_t));
+  }
+  for (int i = 0; i < 2; ++i) {
+    dev_free(h, h->tmp_kv[i], bb);
+    dev_free(h, h->tmp_val[i], bb);
+    dev_free(h, h->mrg_kv[i], h->mrg_cap * sizeof(uint32_t));
+    dev_free(h, h->mrg_val[i], h->mrg_cap * sizeof(uint32_t));
+  }
+  dev_free(h, h->buf_kv, bb);
+  dev_free(h, h->buf_val, bb);
+  dev_free(h, h->meta, sort_meta_words(h->b, kMaxPasses) * sizeof(uint32_t));
+  if (h->q_cap) {
+    dev_free(h, h->q_counts, h->q_cap * sizeof(uint32_t));
+    dev_free(h, h->q_status, scan_status_words(static_cast<uint32_t>(h->q_cap)) * sizeof(uint64_t));
+  }
+  if (h->h_pinned) (void)hipHostFree(h->h_pinned);
+}
+
+// One update batch (sec. III-B insertion; deletions and mixed batches are
+// insertions whose elements carry status 0 where they delete).
+lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
+                          const uint8_t* is_delete, uint32_t n, BatchMode mode) {
+  if (h == nullptr) return LSM_EINVAL;
+  if (n == 0) return LSM_OK;
+  if (n > h->b) return LSM_EBATCH;
+  if (keys == nullptr || (mode != kDelete && vals == nullptr) ||
+      (mode == kMixed && is_delete == nullptr))
+    return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+
+  // First empty level j = ffz(r); the merges fill it with b * 2^j elements.
+  const int j = __builtin_ctzll(~h->r);
+  if (j >= kMaxLevels || level_len(h, j) > (1ull << 31)) return LSM_ECAPACITY;
+  lsm_status_t s = ensure_level(h, j);
+  if (s != LSM_OK) return s;
+  if (j >= 2) {
+    s = ensure_merge_scratch(h, level_len(h, j - 1));
+    if (s != LSM_OK) return s;
+  }
+
+  const bool checked = (h->flags & LSM_CHECKED) != 0;
+  const int lo_bit = (mode == kMixed) ? 0 : 1;
+  const int passes = sort_passes(h->key_bits, lo_bit);
+  SortMeta meta = sort_meta_carve(h->meta, h->b, passes);
+  BatchSrc src{keys, vals, is_delete, n, h->b, static_cast<int>(mode)};
+  if (checked && hipMemsetAsync(meta.err, 0, sizeof(uint32_t), h->stream) != hipSuccess)
+    return LSM_EHIP;
+
+  uint32_t* sorted_kv = (j == 0) ? h->lvl_kv[0] : h->buf_kv;
+  uint32_t* sorted_val = (j == 0) ? h->lvl_val[0] : h->buf_val;
+  if (launch_sort(src, lo_bit, passes, h->key_bits, checked ? 1 : 0, meta, h->tmp_kv, h->tmp_val,
+                  sorted_kv, sorted_val, h->stream) != hipSuccess)
+    return LSM_EHIP;
+
+  if (checked) {
+    if (hipMemcpyAsync(h->h_pinned, meta.err, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                       h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return LSM_EHIP;
+    if (*reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u) return LSM_EKEY;
+  }
+
+  // while level i is full: buffer <- merge(buffer, level i)  (Fig. 2(a)).
+  // The last merge writes straight into level j.
+  const uint32_t* cur_kv = sorted_kv;
+  const uint32_t* cur_val = sorted_val;
+  uint64_t merged = 0;
+  for (int i = 0; i < j; ++i) {
+    uint32_t* o_kv = (i == j - 1) ? h->lvl_kv[j] : h->mrg_kv[i & 1];
+    uint32_t* o_val = (i == j - 1) ? h->lvl_val[j] : h->mrg_val[i & 1];
+    const uint32_t len = static_cast<uint32_t>(level_len(h, i));
+    if (launch_merge(cur_kv, cur_val, len, h->lvl_kv[i], h->lvl_val[i], len, o_kv, o_val,
+                     h->stream) != hipSuccess)
+      return LSM_EHIP;
+    merged += 2ull * len;
+    cur_kv = o_kv;
+    cur_val = o_val;
+  }
+  h->r += 1;
+  h->merged_last = merged;
+  h->merged_total += merged;
+  h->sorted_total += h->b;
+  return LSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
+  if (out == nullptr) return LSM_EINVAL;
+  *out = nullptr;
+  if (b == 0 || b > (1u << 28)) return LSM_EINVAL;
+  if (flags & ~(LSM_CHECKED | LSM_KEY_BITS(0x3F))) return LSM_EINVAL;
+  uint32_t kb = (flags >> 8) & 0x3Fu;
+  if (kb == 0) kb = 31;
+  if (kb > 31) return LSM_EINVAL;
+
+  lsm_t h = new (std::nothrow) lsm_s();
+  if (h == nullptr) return LSM_ENOMEM;
+  h->b = b;
+  h->flags = flags;
+  h->key_bits = kb;
+  h->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return LSM_EHIP;
+  }
+  const size_t bb = static_cast<size_t>(b) * sizeof(uint32_t);
+  void* p = nullptr;
+  lsm_status_t s = LSM_OK;
+  for (int i = 0; i < 2 && s == LSM_OK; ++i) {
+    if ((s = dev_alloc(h, &p, bb)) == LSM_OK) h->tmp_kv[i] = static_cast<uint32_t*>(p);
+    if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->tmp_val[i] = static_cast<uint32_t*>(p);
+  }
+  if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->buf_kv = static_cast<uint32_t*>(p);
+  if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->buf_val = static_cast<uint32_t*>(p);
+  if (s == LSM_OK &&
+      (s = dev_alloc(h, &p, sort_meta_words(b, kMaxPasses) * sizeof(uint32_t))) == LSM_OK)
+    h->meta = static_cast<uint32_t*>(p);
+  if (s == LSM_OK) {
+    void* hp = nullptr;
+    if (hipHostMalloc(&hp, 64, hipHostMallocDefault) != hipSuccess) s = LSM_ENOMEM;
+    else h->h_pinned = static_cast<uint64_t*>(hp);
+  }
+  if (s != LSM_OK) {
+    release_all(h);
+    delete h;
+    return s;
+  }
+  *out = h;
+  return LSM_OK;
+}
+
+lsm_status_t lsm_set_stream(lsm_t h, void* stream) {
+  if (h == nullptr) return LSM_EINVAL;
+  h->stream = static_cast<hipStream_t>(stream);
+  return LSM_OK;
+}
+
+lsm_status_t lsm_insert_batch(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals, uint32_t n) {
+  return update_batch(h, d_keys, d_vals, nullptr, n, kInsert);
+}
+
+lsm_status_t lsm_delete_batch(lsm_t h, const uint32_t* d_keys, uint32_t n) {
+  return update_batch(h, d_keys, nullptr, nullptr, n, kDelete);
+}
+
+lsm_status_t lsm_update_batch(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals,
+                              const uint8_t* d_is_delete, uint32_t n) {
+  return update_batch(h, d_keys, d_vals, d_is_delete, n, kMixed);
+}
+
+lsm_status_t lsm_lookup(lsm_t h, const uint32_t* d_keys, uint32_t nq, uint32_t* d_vals,
+                        uint8_t* d_found) {
+  if (h == nullptr) return LSM_EINVAL;
+  if (nq == 0) return LSM_OK;
+  if (d_keys == nullptr || d_vals == nullptr || d_found == nullptr) return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  const LevelSet lv = occupied_levels(h);
+  return launch_lookup(lv, d_keys, nq, d_vals, d_found, h->stream) == hipSuccess ? LSM_OK : LSM_EHIP;
+}
+
+lsm_status_t lsm_count(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint32_t nq,
+                       uint32_t* d_counts) {
+  if (h == nullptr) return LSM_EINVAL;
+  if (nq == 0) return LSM_OK;
+  if (d_lo == nullptr || d_hi == nullptr || d_counts == nullptr) return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  const LevelSet lv = occupied_levels(h);
+  return launch_count(lv, d_lo, d_hi, nq, d_counts, nullptr, 0, h->stream) == hipSuccess ? LSM_OK
+                                                                                          : LSM_EHIP;
+}
+
+lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint32_t nq,
+                       uint64_t* d_offsets, uint32_t* d_keys, uint32_t* d_vals, uint64_t cap,
+                       uint64_t* h_total) {
+  if (h == nullptr || h_total == nullptr || d_offsets == nullptr) return LSM_EINVAL;
+  if (nq > 0 && (d_lo == nullptr || d_hi == nullptr)) return LSM_EINVAL;
+  if (cap > 0 && (d_keys == nullptr || d_vals == nullptr)) return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  if (nq == 0) {
+    *h_total = 0;
+    return hipMemsetAsync(d_offsets, 0, sizeof(uint64_t), h->stream) == hipSuccess ? LSM_OK
+                                                                                  : LSM_EHIP;
+  }
+  lsm_status_t s = ensure_query_scratch(h, nq);
+  if (s != LSM_OK) return s;
+  const LevelSet lv = occupied_levels(h);
+  // Stage 1: per-query live counts (also clears the scan's look-back words).
+  if (launch_count(lv, d_lo, d_hi, nq, h->q_counts, h->q_status, scan_status_words(nq),
+                   h->stream) != hipSuccess)
+    return LSM_EHIP;
+  // Stage 2: exclusive scan into the caller's offsets.
+  if (launch_scan(h->q_counts, nq, d_offsets, h->q_status, h->stream) != hipSuccess) return LSM_EHIP;
+  if (hipMemcpyAsync(h->h_pinned, d_offsets + nq, sizeof(uint64_t), hipMemcpyDeviceToHost,
+                     h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return LSM_EHIP;
+  const uint64_t total = *reinterpret_cast<volatile uint64_t*>(h->h_pinned);
+  *h_total = total;
+  if (total > cap) return LSM_ECAPACITY;
+  if (total == 0) return LSM_OK;
+  // Stage 3: each query writes its live pairs in key order at its offset.
+  return launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, d_keys, d_vals, h->stream) == hipSuccess
+             ? LSM_OK
+             : LSM_EHIP;
+}
+
+lsm_status_t lsm_destroy(lsm_t h) {
+  if (h == nullptr) return LSM_EINVAL;
+  lsm_status_t s = LSM_OK;
+  {
+    DeviceGuard g(h->device);
+    if (!g.ok || hipStreamSynchronize(h->stream) != hipSuccess) s = LSM_EHIP;
+    release_all(h);
+  }
+  delete h;
+  return s;
+}
+
+const char* lsm_strerror(lsm_status_t s) {
+  switch (s) {
+    case LSM_OK: return "ok";
+    case LSM_EINVAL: return "invalid argument";
+    case LSM_EKEY: return "key out of range";
+    case LSM_EBATCH: return "batch larger than b";
+    case LSM_ENOMEM: return "out of memory";
+    case LSM_ECAPACITY: return "capacity exceeded";
+    case LSM_EHIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+uint64_t lsm_num_batches(lsm_t h) { return h ? h->r : 0; }
+uint32_t lsm_batch_size(lsm_t h) { return h ? h->b : 0; }
+
+lsm_status_t lsm_level_view(lsm_t h, uint32_t i, const uint32_t** d_kv, const uint32_t** d_vals,
+                            uint64_t* len) {
+  if (h == nullptr || d_kv == nullptr || d_vals == nullptr || len == nullptr) return LSM_EINVAL;
+  if (i >= static_cast<uint32_t>(kMaxLevels) || !((h->r >> i) & 1u)) {
+    *d_kv = nullptr;
+    *d_vals = nullptr;
+    *len = 0;
+    return LSM_OK;
+  }
+  *d_kv = h->lvl_kv[i];
+  *d_vals = h->lvl_val[i];
+  *len = level_len(h, static_cast<int>(i));
+  return LSM_OK;
+}
+
+lsm_status_t lsm_level_copy(lsm_t h, uint32_t i, uint32_t* d_kv_out, uint32_t* d_vals_out,
+                            uint64_t* len) {
+  if (h == nullptr || len == nullptr) return LSM_EINVAL;
+  if (i >= static_cast<uint32_t>(kMaxLevels) || !((h->r >> i) & 1u)) {
+    *len = 0;
+    return LSM_OK;
+  }
+  if (d_kv_out == nullptr || d_vals_out == nullptr) return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  const uint64_t n = level_len(h, static_cast<int>(i));
+  *len = n;
+  if (hipMemcpyAsync(d_kv_out, h->lvl_kv[i], n * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                     h->stream) != hipSuccess ||
+      hipMemcpyAsync(d_vals_out, h->lvl_val[i], n * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                     h->stream) != hipSuccess)
+    return LSM_EHIP;
+  return LSM_OK;
+}
+
+lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out) {
+  if (h == nullptr || out == nullptr) return LSM_EINVAL;
+  out->num_batches = h->r;
+  out->resident_elems = h->r * h->b;
+  out->merged_elems_last = h->merged_last;
+  out->merged_elems_total = h->merged_total;
+  out->sorted_elems_total = h->sorted_total;
+  out->device_bytes = h->device_bytes;
+  return LSM_OK;
+}
+
+}  // extern "C"

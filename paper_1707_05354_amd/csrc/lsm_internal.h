@@ -1,0 +1,104 @@
+// Internal interface between the C-ABI host code (lsm_api.hip) and the
+// gfx950 kernels (lsm_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lsm {
+
+constexpr int kMaxLevels = 32;
+
+// Work-group shape shared by every kernel: four wave64 waves.
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+// Radix sort: 8-bit digits, tiles of kThreads * kSortItems elements.
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kThreads * kSortItems;
+constexpr int kMaxPasses = 4;
+// Histogram kernel tile (one partial histogram per tile).
+constexpr int kHistTile = 8192;
+
+// Merge: tiles of kThreads * kMergeItems output elements.
+constexpr int kMergeItems = 8;
+constexpr int kMergeTile = kThreads * kMergeItems;
+
+// Scan (range offsets): tiles of kThreads * kScanItems counts.
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kThreads * kScanItems;
+
+// Query kernels: one thread per query.
+constexpr int kQueryThreads = 256;
+
+// The occupied levels, newest (smallest) first, passed by value.
+struct LevelSet {
+  const uint32_t* kv[kMaxLevels];
+  const uint32_t* val[kMaxLevels];
+  uint32_t len[kMaxLevels];
+  int count;
+};
+
+// How the batch's status bit is formed while the batch is read.
+enum BatchMode : int { kInsert = 0, kDelete = 1, kMixed = 2 };
+
+// Source of one batch as the caller handed it over.
+struct BatchSrc {
+  const uint32_t* keys;
+  const uint32_t* vals;       // null for deletions
+  const uint8_t* is_delete;   // mixed batches only
+  uint32_t n;                 // 1 <= n <= b
+  uint32_t b;
+  int mode;                   // BatchMode
+};
+
+// Sort scratch layout (uint32 words) for a batch of b elements and P passes.
+struct SortMeta {
+  uint32_t* hist_parts;   // [num_hist_tiles][P][256]
+  uint32_t* status;       // [P][num_sort_tiles][256] look-back words
+  uint32_t* tile_ctr;     // [P] dynamic tile counters
+  uint32_t* err;          // [1] key-range violation flag (checked mode)
+  uint32_t num_hist_tiles;
+  uint32_t num_sort_tiles;
+};
+
+size_t sort_meta_words(uint32_t b, int passes);
+SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int passes);
+
+// Sorts one batch into (out_kv, out_val): key variables ascending over bits
+// [lo_bit, lo_bit + 8 * passes), equal key variables with the later batch
+// position first.  tmp_* are two ping-pong buffers of b elements each.
+hipError_t launch_sort(const BatchSrc& src, int lo_bit, int passes, uint32_t key_limit_bits,
+                       int checked, const SortMeta& meta, uint32_t* tmp_kv[2],
+                       uint32_t* tmp_val[2], uint32_t* out_kv, uint32_t* out_val,
+                       hipStream_t stream);
+
+// Stable merge of a newer run (first on equal original keys) with an older
+// run into out (na + nb elements).
+hipError_t launch_merge(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na,
+                        const uint32_t* b_kv, const uint32_t* b_val, uint32_t nb,
+                        uint32_t* out_kv, uint32_t* out_val, hipStream_t stream);
+
+hipError_t launch_lookup(const LevelSet& lv, const uint32_t* q, uint32_t nq, uint32_t* out_val,
+                         uint8_t* out_found, hipStream_t stream);
+
+// Count pass: per query number of live keys in [lo, hi].  When scan_status
+// is non-null the kernel also clears the scan's look-back words
+// (scan_words of them, tile counter included) for the following scan.
+hipError_t launch_count(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi, uint32_t nq,
+                        uint32_t* counts, uint64_t* scan_status, size_t scan_words,
+                        hipStream_t stream);
+
+// Exclusive scan of nq uint32 counts into nq + 1 uint64 offsets.
+size_t scan_status_words(uint32_t nq);
+hipError_t launch_scan(const uint32_t* counts, uint32_t nq, uint64_t* offsets,
+                       uint64_t* scan_status, hipStream_t stream);
+
+// Range emission pass: writes each query's live pairs at offsets[q].
+hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi,
+                             uint32_t nq, const uint64_t* offsets, uint32_t* out_keys,
+                             uint32_t* out_vals, hipStream_t stream);
+
+}  // namespace lsm

@@ -1,0 +1,671 @@
+// gfx950 kernels of the batched LSM dictionary.
+//
+// Every kernel runs in work-groups of four wave64 waves.  Nothing here is a
+// dense contraction, so there is no MFMA: the batch sort and the level
+// merges are HBM/L2 streams, the searches are random-access.
+//
+//   k_sort_hist / k_sort_pass : stable LSD radix sort of one batch (the
+//       "sort the batch" step of sec. III-B / Fig. 2(a)).  The batch is read
+//       back to front, so among equal key variables the later batch
+//       position comes first (the last duplicate wins), and padded with
+//       copies of its last element (sec. IV-A).
+//   k_merge : merge of a newer run with an older run on the original key,
+//       the newer element first on equal keys (sec. IV-A), merge-path
+//       partitioned with a 64-ary wave search.
+//   k_lookup : per-query lower bound over the occupied levels, newest first,
+//       stopping at the first hit (sec. III-D, IV-B).
+//   k_count / k_range_emit : per-query bounds in every occupied level and a
+//       merge of the per-level candidate runs in level order, keeping the
+//       first element of each key run when it is a regular element
+//       (sec. III-E, IV-C, IV-D).
+//   k_scan : single-pass exclusive scan with decoupled look-back for the
+//       range output offsets (stage 2 of sec. IV-C).
+#include "lsm_internal.h"
+
+namespace lsm {
+namespace {
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+// Number of set bits of m below this lane.
+__device__ __forceinline__ uint32_t count_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, uint32_t lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= static_cast<uint32_t>(o)) x += y;
+  }
+  return x;
+}
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x, uint32_t lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint64_t y = __shfl_up(x, o, 64);
+    if (lane >= static_cast<uint32_t>(o)) x += y;
+  }
+  return x;
+}
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Exclusive scan over the work-group, one value per thread.  tmp holds
+// kWaves words; the call contains two barriers.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* tmp) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = wave_incl_scan(x, lane);
+  if (lane == 63) tmp[wave] = inc;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (uint32_t w = 0; w < wave; ++w) pre += tmp[w];
+  __syncthreads();
+  return pre + inc - x;
+}
+
+// Device-scope relaxed atomics for the look-back words: each word carries
+// its own payload, so no other memory needs ordering with it.
+__device__ __forceinline__ uint32_t ld_dev(const uint32_t* p) {
+  return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_dev64(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------ searches
+// First index i in [0, n) with (kv[i] >> 1) >= k, or n.  Branch-free.
+__device__ __forceinline__ uint32_t lower_bound_key(const uint32_t* kv, uint32_t n, uint32_t k) {
+  if (n == 0) return 0;
+  uint32_t base = 0, len = n;
+  while (len > 1) {
+    const uint32_t half = len >> 1;
+    base = ((kv[base + half] >> 1) < k) ? base + half : base;
+    len -= half;
+  }
+  return base + ((kv[base] >> 1) < k ? 1u : 0u);
+}
+// First index i in [0, n) with (kv[i] >> 1) > k, or n.
+__device__ __forceinline__ uint32_t upper_bound_key(const uint32_t* kv, uint32_t n, uint32_t k) {
+  if (n == 0) return 0;
+  uint32_t base = 0, len = n;
+  while (len > 1) {
+    const uint32_t half = len >> 1;
+    base = ((kv[base + half] >> 1) <= k) ? base + half : base;
+    len -= half;
+  }
+  return base + ((kv[base] >> 1) <= k ? 1u : 0u);
+}
+
+// ------------------------------------------------------------ radix sort
+constexpr uint32_t kFlagAgg = 1u << 30;  // tile aggregate published
+constexpr uint32_t kFlagInc = 2u << 30;  // inclusive prefix published
+constexpr uint32_t kCountMask = (1u << 30) - 1;
+
+// Element e of the batch as the sort sees it: read back to front and padded
+// with copies of the caller's last element, so e = 0 .. b-n-1 are padding
+// and e = b-n .. b-1 are the caller's elements n-1 .. 0.
+__device__ __forceinline__ void batch_elem(const BatchSrc& s, uint32_t e, uint32_t& kv,
+                                           uint32_t& val, uint32_t& key) {
+  uint32_t src = s.b - 1 - e;
+  if (src > s.n - 1) src = s.n - 1;
+  key = s.keys[src];
+  uint32_t st;
+  if (s.mode == kInsert) st = 1u;
+  else if (s.mode == kDelete) st = 0u;
+  else st = s.is_delete[src] ? 0u : 1u;
+  kv = (key << 1) | st;
+  val = st ? s.vals[src] : 0u;  // tombstones carry value 0
+}
+
+// Per-tile digit histograms of every pass in one read of the batch.  Also
+// clears the look-back words and tile counters of the passes that follow.
+__global__ __launch_bounds__(kThreads) void k_sort_hist(BatchSrc src, int lo_bit, int passes,
+                                                        uint32_t key_limit_bits, int checked,
+                                                        SortMeta meta) {
+  __shared__ uint32_t s_h[kMaxPasses * kRadix];
+  const uint32_t tid = threadIdx.x;
+  const size_t nstatus = static_cast<size_t>(passes) * meta.num_sort_tiles * kRadix;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * kThreads + tid; i < nstatus;
+       i += static_cast<size_t>(gridDim.x) * kThreads)
+    meta.status[i] = 0u;
+  if (blockIdx.x == 0 && tid < static_cast<uint32_t>(passes)) meta.tile_ctr[tid] = 0u;
+  for (uint32_t i = tid; i < static_cast<uint32_t>(passes * kRadix); i += kThreads) s_h[i] = 0u;
+  __syncthreads();
+
+  bool bad = false;
+  for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * kThreads + tid; e < src.b;
+       e += static_cast<uint64_t>(gridDim.x) * kThreads) {
+    uint32_t kv, val, key;
+    batch_elem(src, static_cast<uint32_t>(e), kv, val, key);
+    if (checked) bad |= (key_limit_bits >= 32 ? false : (key >> key_limit_bits) != 0u);
+    for (int p = 0; p < passes; ++p)
+      atomicAdd(&s_h[p * kRadix + ((kv >> (lo_bit + kRadixBits * p)) & (kRadix - 1))], 1u);
+  }
+  __syncthreads();
+  uint32_t* out = meta.hist_parts + static_cast<size_t>(blockIdx.x) * passes * kRadix;
+  for (uint32_t i = tid; i < static_cast<uint32_t>(passes * kRadix); i += kThreads) out[i] = s_h[i];
+  if (checked && bad) atomicOr(meta.err, 1u);
+}
+
+// One stable counting pass on the digit at bit `shift`.  Tiles take dynamic
+// ids in start order; each publishes its digit counts and looks back over
+// its predecessors for their prefix (every predecessor has started, so
+// every wait ends).  in_kv == nullptr means "read the caller's batch".
+__global__ __launch_bounds__(kThreads) void k_sort_pass(BatchSrc src, const uint32_t* in_kv,
+                                                        const uint32_t* in_val, uint32_t* out_kv,
+                                                        uint32_t* out_val, int pass, int passes,
+                                                        int shift, SortMeta meta) {
+  __shared__ uint32_t s_kv[kSortTile];
+  __shared__ uint32_t s_val[kSortTile];
+  __shared__ uint32_t s_wcnt[kWaves][kRadix];
+  __shared__ uint32_t s_local[kRadix];
+  __shared__ uint32_t s_gbase[kRadix];
+  __shared__ uint32_t s_tmp[kWaves];
+  __shared__ uint32_t s_tile;
+
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t b = src.b;
+  if (tid == 0) s_tile = atomicAdd(&meta.tile_ctr[pass], 1u);
+  for (uint32_t i = tid; i < kWaves * kRadix; i += kThreads) (&s_wcnt[0][0])[i] = 0u;
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const uint32_t tbase = tile * kSortTile;
+
+  // Wave w owns tile positions [w*64*I, (w+1)*64*I); item i of lane l sits
+  // at w*64*I + i*64 + l, so (item, lane) order is batch order.
+  uint32_t kv[kSortItems], val[kSortItems], off[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const uint32_t e = tbase + wave * 64 * kSortItems + i * 64 + lane;
+    kv[i] = 0u;
+    val[i] = 0u;
+    if (e < b) {
+      if (in_kv == nullptr) {
+        uint32_t key;
+        batch_elem(src, e, kv[i], val[i], key);
+      } else {
+        kv[i] = in_kv[e];
+        val[i] = in_val[e];
+      }
+    }
+  }
+  // Stable rank inside the wave: lanes holding the same digit find each
+  // other with eight ballots; the lowest such lane bumps the wave counter.
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const uint32_t e = tbase + wave * 64 * kSortItems + i * 64 + lane;
+    const bool valid = e < b;
+    const uint32_t d = (kv[i] >> shift) & (kRadix - 1);
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < kRadixBits; ++bit) {
+      const bool set = (d >> bit) & 1u;
+      const uint64_t m = ballot(set);
+      peers &= set ? m : ~m;
+    }
+    const uint32_t r = count_below(peers);
+    uint32_t prev = 0;
+    if (valid) prev = s_wcnt[wave][d];
+    if (valid && r == 0) s_wcnt[wave][d] = prev + static_cast<uint32_t>(__popcll(peers));
+    off[i] = prev + r;
+  }
+  __syncthreads();
+
+  // Thread tid owns digit d = tid (kThreads == kRadix).
+  const uint32_t d = tid;
+  uint32_t tile_count = 0;
+  for (uint32_t w = 0; w < kWaves; ++w) {
+    const uint32_t c = s_wcnt[w][d];
+    s_wcnt[w][d] = tile_count;
+    tile_count += c;
+  }
+  uint32_t* st = meta.status + static_cast<size_t>(pass) * meta.num_sort_tiles * kRadix;
+  if (tile == 0) st_dev(&st[d], kFlagInc | tile_count);
+  else st_dev(&st[static_cast<size_t>(tile) * kRadix + d], kFlagAgg | tile_count);
+
+  const uint32_t local_start = block_excl_scan(tile_count, s_tmp);
+  s_local[d] = local_start;
+
+  uint32_t gtotal = 0;
+  for (uint32_t part = 0; part < meta.num_hist_tiles; ++part)
+    gtotal += meta.hist_parts[(static_cast<size_t>(part) * passes + pass) * kRadix + d];
+  const uint32_t gstart = block_excl_scan(gtotal, s_tmp);
+
+  // Look back in chunks of eight predecessors (loads issued together).
+  uint32_t excl = 0;
+  if (tile > 0) {
+    int64_t j = static_cast<int64_t>(tile) - 1;
+    for (;;) {
+      const int nchunk = j + 1 < 8 ? static_cast<int>(j + 1) : 8;
+      uint32_t w[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        w[k] = (k < nchunk) ? ld_dev(&st[static_cast<size_t>(j - k) * kRadix + d]) : 0u;
+      int used = 0;
+      bool done = false;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (k >= nchunk || done) break;
+        const uint32_t f = w[k] & ~kCountMask;
+        if (f == 0u) break;
+        excl += w[k] & kCountMask;
+        ++used;
+        if (f == kFlagInc) done = true;
+      }
+      if (done) break;
+      j -= used;
+      if (used == 0) __builtin_amdgcn_s_sleep(1);
+    }
+    st_dev(&st[static_cast<size_t>(tile) * kRadix + d], kFlagInc | (excl + tile_count));
+  }
+  s_gbase[d] = gstart + excl;
+  __syncthreads();
+
+  // Scatter into the tile's digit-sorted order in LDS, then write out with
+  // consecutive threads on consecutive output addresses.
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const uint32_t e = tbase + wave * 64 * kSortItems + i * 64 + lane;
+    if (e < b) {
+      const uint32_t dd = (kv[i] >> shift) & (kRadix - 1);
+      const uint32_t pos = s_local[dd] + s_wcnt[wave][dd] + off[i];
+      s_kv[pos] = kv[i];
+      s_val[pos] = val[i];
+    }
+  }
+  __syncthreads();
+  const uint32_t tile_n = (b - tbase) < static_cast<uint32_t>(kSortTile) ? (b - tbase) : kSortTile;
+  for (uint32_t x = tid; x < tile_n; x += kThreads) {
+    const uint32_t k = s_kv[x];
+    const uint32_t dd = (k >> shift) & (kRadix - 1);
+    const uint32_t o = s_gbase[dd] + (x - s_local[dd]);
+    out_kv[o] = k;
+    out_val[o] = s_val[x];
+  }
+}
+
+// ------------------------------------------------------------ merge
+// Number of elements of a (the newer run) among the first `diag` outputs of
+// the merge, a first on equal original keys.  The whole wave searches: each
+// round tests 64 evenly spaced candidates of the open interval and keeps the
+// gap where the predicate flips, so a run of 2^26 takes five rounds.
+__device__ uint32_t wave_merge_path(const uint32_t* a, uint32_t na, const uint32_t* bb,
+                                    uint32_t nb, uint64_t diag) {
+  const uint32_t lane = lane_id();
+  uint64_t lo = diag > nb ? diag - nb : 0;
+  uint64_t hi = diag < na ? diag : na;
+  while (hi > lo) {
+    const uint64_t len = hi - lo;
+    if (len <= 64) {
+      bool p = false;
+      if (lane < len) {
+        const uint64_t i = lo + lane;
+        p = (a[i] >> 1) <= (bb[diag - 1 - i] >> 1);
+      }
+      return static_cast<uint32_t>(lo + __popcll(ballot(p)));
+    }
+    const uint64_t pos = lo + ((lane + 1) * len) / 65;
+    const bool p = (a[pos] >> 1) <= (bb[diag - 1 - pos] >> 1);
+    const uint32_t c = static_cast<uint32_t>(__popcll(ballot(p)));
+    if (c == 0) {
+      hi = lo + len / 65;
+    } else if (c == 64) {
+      lo = lo + (64 * len) / 65 + 1;
+    } else {
+      const uint64_t plo = lo + (c * len) / 65;
+      const uint64_t phi = lo + ((c + 1) * len) / 65;
+      lo = plo + 1;
+      hi = phi;
+    }
+  }
+  return static_cast<uint32_t>(lo);
+}
+
+__global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const uint32_t* a_val,
+                                                    uint32_t na, const uint32_t* b_kv,
+                                                    const uint32_t* b_val, uint32_t nb,
+                                                    uint32_t* out_kv, uint32_t* out_val) {
+  __shared__ uint32_t s_kv[kMergeTile];
+  __shared__ uint32_t s_val[kMergeTile];
+  __shared__ uint32_t s_split[2];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t total = static_cast<uint64_t>(na) + nb;
+  const uint64_t d0 = static_cast<uint64_t>(blockIdx.x) * kMergeTile;
+  const uint64_t d1 = (d0 + kMergeTile < total) ? d0 + kMergeTile : total;
+  if (wave == 0) {
+    const uint32_t s = wave_merge_path(a_kv, na, b_kv, nb, d0);
+    if (lane == 0) s_split[0] = s;
+  } else if (wave == 1) {
+    const uint32_t s = wave_merge_path(a_kv, na, b_kv, nb, d1);
+    if (lane == 0) s_split[1] = s;
+  }
+  __syncthreads();
+  const uint32_t a0 = s_split[0], a1 = s_split[1];
+  const uint32_t b0 = static_cast<uint32_t>(d0 - a0), b1 = static_cast<uint32_t>(d1 - a1);
+  const uint32_t la = a1 - a0, lb = b1 - b0, n = la + lb;
+  for (uint32_t x = tid; x < la; x += kThreads) {
+    s_kv[x] = a_kv[a0 + x];
+    s_val[x] = a_val[a0 + x];
+  }
+  for (uint32_t x = tid; x < lb; x += kThreads) {
+    s_kv[la + x] = b_kv[b0 + x];
+    s_val[la + x] = b_val[b0 + x];
+  }
+  __syncthreads();
+
+  // This thread's outputs: tile positions [dt, dt + kMergeItems).
+  const uint32_t dt = (tid * kMergeItems < n) ? tid * kMergeItems : n;
+  uint32_t lo = dt > lb ? dt - lb : 0, hi = dt < la ? dt : la;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if ((s_kv[mid] >> 1) <= (s_kv[la + dt - 1 - mid] >> 1)) lo = mid + 1;
+    else hi = mid;
+  }
+  uint32_t ia = lo, ib = dt - lo;
+  uint32_t rk[kMergeItems], rv[kMergeItems];
+#pragma unroll
+  for (int k = 0; k < kMergeItems; ++k) {
+    rk[k] = 0u;
+    rv[k] = 0u;
+    if (dt + k < n) {
+      bool take_a;
+      if (ia < la && ib < lb) take_a = (s_kv[ia] >> 1) <= (s_kv[la + ib] >> 1);
+      else take_a = ia < la;
+      const uint32_t s = take_a ? ia : la + ib;
+      rk[k] = s_kv[s];
+      rv[k] = s_val[s];
+      ia += take_a ? 1u : 0u;
+      ib += take_a ? 0u : 1u;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kMergeItems; ++k) {
+    if (dt + k < n) {
+      s_kv[dt + k] = rk[k];
+      s_val[dt + k] = rv[k];
+    }
+  }
+  __syncthreads();
+  for (uint32_t x = tid; x < n; x += kThreads) {
+    out_kv[d0 + x] = s_kv[x];
+    out_val[d0 + x] = s_val[x];
+  }
+}
+
+// ------------------------------------------------------------ queries
+__global__ __launch_bounds__(kQueryThreads) void k_lookup(LevelSet lv, const uint32_t* q,
+                                                          uint32_t nq, uint32_t* out_val,
+                                                          uint8_t* out_found) {
+  const uint32_t i = blockIdx.x * kQueryThreads + threadIdx.x;
+  if (i >= nq) return;
+  const uint32_t k = q[i];
+  uint32_t v = 0u;
+  uint8_t f = 0;
+  for (int l = 0; l < lv.count; ++l) {
+    const uint32_t* kv = lv.kv[l];
+    const uint32_t n = lv.len[l];
+    const uint32_t p = lower_bound_key(kv, n, k);
+    if (p < n) {
+      const uint32_t x = kv[p];
+      if ((x >> 1) == k) {
+        if (x & 1u) {
+          v = lv.val[l][p];
+          f = 1;
+        }
+        break;  // the newest instance decides, tombstone or not
+      }
+    }
+  }
+  out_val[i] = v;
+  out_found[i] = f;
+}
+
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;  // above every original key (< 2^31)
+
+// Walk the candidate runs [lower_bound(k1), upper_bound(k2)) of all occupied
+// levels in key order.  For each distinct key the element met first is the
+// newest instance (smaller levels are newer, and inside a level a key's run
+// starts with its newest element); it counts when it is a regular element.
+template <bool kEmit>
+__device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, uint32_t k2,
+                                               uint32_t* out_keys, uint32_t* out_vals) {
+  if (k1 > k2) return 0u;
+  uint32_t cur[kMaxLevels], end[kMaxLevels], ck[kMaxLevels];
+  const int L = lv.count;
+  for (int l = 0; l < L; ++l) {
+    const uint32_t* kv = lv.kv[l];
+    const uint32_t n = lv.len[l];
+    cur[l] = lower_bound_key(kv, n, k1);
+    end[l] = upper_bound_key(kv, n, k2);
+    ck[l] = cur[l] < end[l] ? (kv[cur[l]] >> 1) : kNoKey;
+  }
+  uint32_t count = 0;
+  for (;;) {
+    uint32_t mk = kNoKey;
+    int mi = -1;
+    for (int l = 0; l < L; ++l) {
+      if (ck[l] < mk) {
+        mk = ck[l];
+        mi = l;
+      }
+    }
+    if (mi < 0) break;
+    const uint32_t x = lv.kv[mi][cur[mi]];
+    if (x & 1u) {
+      if (kEmit) {
+        out_keys[count] = mk;
+        out_vals[count] = lv.val[mi][cur[mi]];
+      }
+      ++count;
+    }
+    for (int l = mi; l < L; ++l) {
+      while (ck[l] == mk) {
+        ++cur[l];
+        ck[l] = cur[l] < end[l] ? (lv.kv[l][cur[l]] >> 1) : kNoKey;
+      }
+    }
+  }
+  return count;
+}
+
+__global__ __launch_bounds__(kQueryThreads) void k_count(LevelSet lv, const uint32_t* lo,
+                                                         const uint32_t* hi, uint32_t nq,
+                                                         uint32_t* counts, uint64_t* scan_status,
+                                                         uint64_t scan_words) {
+  const uint64_t gi = static_cast<uint64_t>(blockIdx.x) * kQueryThreads + threadIdx.x;
+  if (scan_status != nullptr) {
+    for (uint64_t w = gi; w < scan_words; w += static_cast<uint64_t>(gridDim.x) * kQueryThreads)
+      scan_status[w] = 0ull;
+  }
+  if (gi >= nq) return;
+  counts[gi] = range_walk<false>(lv, lo[gi], hi[gi], nullptr, nullptr);
+}
+
+__global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const uint32_t* lo,
+                                                              const uint32_t* hi, uint32_t nq,
+                                                              const uint64_t* offsets,
+                                                              uint32_t* out_keys,
+                                                              uint32_t* out_vals) {
+  const uint32_t i = blockIdx.x * kQueryThreads + threadIdx.x;
+  if (i >= nq) return;
+  const uint64_t o = offsets[i];
+  range_walk<true>(lv, lo[i], hi[i], out_keys + o, out_vals + o);
+}
+
+// ------------------------------------------------------------ scan
+constexpr uint64_t kFlagAgg64 = 1ull << 62;
+constexpr uint64_t kFlagInc64 = 2ull << 62;
+constexpr uint64_t kSumMask64 = (1ull << 62) - 1;
+
+// status[0] is the dynamic tile counter, status[1 + t] tile t's look-back
+// word; all cleared beforehand by k_count.
+__global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* counts, uint32_t nq,
+                                                   uint64_t* offsets, uint64_t* status) {
+  __shared__ uint64_t s_w[kWaves];
+  __shared__ uint32_t s_tile;
+  __shared__ uint64_t s_prefix;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_tile = static_cast<uint32_t>(atomicAdd(reinterpret_cast<unsigned long long*>(status), 1ull));
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const uint64_t base = static_cast<uint64_t>(tile) * kScanTile + static_cast<uint64_t>(tid) * kScanItems;
+  uint32_t v[kScanItems];
+  uint64_t tsum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < nq) ? counts[base + k] : 0u;
+    tsum += v[k];
+  }
+  const uint64_t winc = wave_incl_scan64(tsum, lane);
+  if (lane == 63) s_w[wave] = winc;
+  __syncthreads();
+  uint64_t wpre = 0, tile_total = 0;
+  for (uint32_t w = 0; w < kWaves; ++w) {
+    if (w < wave) wpre += s_w[w];
+    tile_total += s_w[w];
+  }
+  const uint64_t texcl = wpre + winc - tsum;
+
+  if (wave == 0) {
+    uint64_t excl = 0;
+    if (tile == 0) {
+      if (lane == 0) st_dev64(&status[1], kFlagInc64 | tile_total);
+    } else {
+      if (lane == 0) st_dev64(&status[1 + tile], kFlagAgg64 | tile_total);
+      int64_t j = static_cast<int64_t>(tile) - 1;
+      for (;;) {
+        const int64_t idx = j - static_cast<int64_t>(lane);
+        const uint64_t w = idx >= 0 ? ld_dev64(&status[1 + idx]) : kFlagInc64;
+        const uint64_t f = w & ~kSumMask64;
+        const uint64_t nr = ballot(f == 0), inc = ballot(f == kFlagInc64);
+        const uint32_t first_nr = nr ? static_cast<uint32_t>(__builtin_ctzll(nr)) : 64u;
+        const uint32_t first_inc = inc ? static_cast<uint32_t>(__builtin_ctzll(inc)) : 64u;
+        if (first_inc < first_nr) {
+          excl += wave_sum64(lane <= first_inc ? (w & kSumMask64) : 0ull);
+          break;
+        }
+        excl += wave_sum64(lane < first_nr ? (w & kSumMask64) : 0ull);
+        j -= first_nr;
+        if (first_nr == 0) __builtin_amdgcn_s_sleep(1);
+      }
+      if (lane == 0) st_dev64(&status[1 + tile], kFlagInc64 | (excl + tile_total));
+    }
+    if (lane == 0) s_prefix = excl;
+  }
+  __syncthreads();
+  uint64_t run = s_prefix + texcl;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < nq) offsets[base + k] = run;
+    run += v[k];
+  }
+  const uint64_t tiles = (static_cast<uint64_t>(nq) + kScanTile - 1) / kScanTile;
+  if (tile == tiles - 1 && tid == kThreads - 1) offsets[nq] = s_prefix + tile_total;
+}
+
+inline unsigned grid_for(uint64_t n, uint64_t per) { return static_cast<unsigned>((n + per - 1) / per); }
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+size_t sort_meta_words(uint32_t b, int passes) {
+  const uint32_t nh = grid_for(b, kHistTile) < 128u ? grid_for(b, kHistTile) : 128u;
+  const uint32_t ns = grid_for(b, kSortTile);
+  return static_cast<size_t>(nh) * passes * kRadix + static_cast<size_t>(passes) * ns * kRadix +
+         kMaxPasses + 1;
+}
+
+SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int passes) {
+  SortMeta m;
+  m.num_hist_tiles = grid_for(b, kHistTile) < 128u ? grid_for(b, kHistTile) : 128u;
+  m.num_sort_tiles = grid_for(b, kSortTile);
+  m.hist_parts = base;
+  m.status = m.hist_parts + static_cast<size_t>(m.num_hist_tiles) * passes * kRadix;
+  m.tile_ctr = m.status + static_cast<size_t>(passes) * m.num_sort_tiles * kRadix;
+  m.err = m.tile_ctr + kMaxPasses;
+  return m;
+}
+
+hipError_t launch_sort(const BatchSrc& src, int lo_bit, int passes, uint32_t key_limit_bits,
+                       int checked, const SortMeta& meta, uint32_t* tmp_kv[2],
+                       uint32_t* tmp_val[2], uint32_t* out_kv, uint32_t* out_val,
+                       hipStream_t stream) {
+  k_sort_hist<<<meta.num_hist_tiles, kThreads, 0, stream>>>(src, lo_bit, passes, key_limit_bits,
+                                                            checked, meta);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint32_t* in_kv = nullptr;
+  const uint32_t* in_val = nullptr;
+  for (int p = 0; p < passes; ++p) {
+    uint32_t* o_kv = (p == passes - 1) ? out_kv : tmp_kv[p & 1];
+    uint32_t* o_val = (p == passes - 1) ? out_val : tmp_val[p & 1];
+    k_sort_pass<<<meta.num_sort_tiles, kThreads, 0, stream>>>(src, in_kv, in_val, o_kv, o_val, p,
+                                                              passes, lo_bit + kRadixBits * p, meta);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    in_kv = o_kv;
+    in_val = o_val;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_merge(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na,
+                        const uint32_t* b_kv, const uint32_t* b_val, uint32_t nb,
+                        uint32_t* out_kv, uint32_t* out_val, hipStream_t stream) {
+  const uint64_t total = static_cast<uint64_t>(na) + nb;
+  if (total == 0) return hipSuccess;
+  k_merge<<<grid_for(total, kMergeTile), kThreads, 0, stream>>>(a_kv, a_val, na, b_kv, b_val, nb,
+                                                               out_kv, out_val);
+  return hipGetLastError();
+}
+
+hipError_t launch_lookup(const LevelSet& lv, const uint32_t* q, uint32_t nq, uint32_t* out_val,
+                         uint8_t* out_found, hipStream_t stream) {
+  if (nq == 0) return hipSuccess;
+  k_lookup<<<grid_for(nq, kQueryThreads), kQueryThreads, 0, stream>>>(lv, q, nq, out_val, out_found);
+  return hipGetLastError();
+}
+
+hipError_t launch_count(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi, uint32_t nq,
+                        uint32_t* counts, uint64_t* scan_status, size_t scan_words,
+                        hipStream_t stream) {
+  if (nq == 0) return hipSuccess;
+  k_count<<<grid_for(nq, kQueryThreads), kQueryThreads, 0, stream>>>(lv, lo, hi, nq, counts,
+                                                                     scan_status, scan_words);
+  return hipGetLastError();
+}
+
+size_t scan_status_words(uint32_t nq) { return 1 + grid_for(nq, kScanTile); }
+
+hipError_t launch_scan(const uint32_t* counts, uint32_t nq, uint64_t* offsets,
+                       uint64_t* scan_status, hipStream_t stream) {
+  if (nq == 0) return hipSuccess;
+  k_scan<<<grid_for(nq, kScanTile), kThreads, 0, stream>>>(counts, nq, offsets, scan_status);
+  return hipGetLastError();
+}
+
+hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi,
+                             uint32_t nq, const uint64_t* offsets, uint32_t* out_keys,
+                             uint32_t* out_vals, hipStream_t stream) {
+  if (nq == 0) return hipSuccess;
+  k_range_emit<<<grid_for(nq, kQueryThreads), kQueryThreads, 0, stream>>>(lv, lo, hi, nq, offsets,
+                                                                          out_keys, out_vals);
+  return hipGetLastError();
+}
+
+}  // namespace lsm

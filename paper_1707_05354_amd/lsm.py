@@ -1,0 +1,253 @@
+"""Thin ctypes binding of the C ABI in include/lsm.h.
+
+Argument marshalling only: every step of every operation runs in the HIP
+kernels of liblsm_hip.so.  Tensors are torch tensors on the handle's GPU
+(int32 or uint32 storage; keys and values are reinterpreted as uint32 and
+never interpreted by torch).  If the library is missing this module raises;
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Tuple
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblsm_hip.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "lsm.h")
+
+LSM_OK, LSM_EINVAL, LSM_EKEY, LSM_EBATCH, LSM_ENOMEM, LSM_ECAPACITY, LSM_EHIP = range(7)
+LSM_CHECKED = 0x1
+
+
+def LSM_KEY_BITS(k: int) -> int:
+    return (int(k) & 0x3F) << 8
+
+
+class LSMError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = int(status)
+        super().__init__("%s failed: %s (%d)" % (where, _strerror(status), status))
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "num_batches", "resident_elems", "merged_elems_last", "merged_elems_total",
+        "sorted_elems_total", "device_bytes")]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+
+_SIGNATURES = {
+    "lsm_create": (ctypes.c_int, [ctypes.POINTER(_vp), _u32, _u32, _vp]),
+    "lsm_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "lsm_insert_batch": (ctypes.c_int, [_vp, _vp, _vp, _u32]),
+    "lsm_delete_batch": (ctypes.c_int, [_vp, _vp, _u32]),
+    "lsm_update_batch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32]),
+    "lsm_lookup": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
+    "lsm_count": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp]),
+    "lsm_range": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _u64, ctypes.POINTER(_u64)]),
+    "lsm_destroy": (ctypes.c_int, [_vp]),
+    "lsm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "lsm_num_batches": (_u64, [_vp]),
+    "lsm_batch_size": (_u32, [_vp]),
+    "lsm_level_view": (ctypes.c_int, [_vp, _u32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                      ctypes.POINTER(_u64)]),
+    "lsm_level_copy": (ctypes.c_int, [_vp, _u32, _vp, _vp, ctypes.POINTER(_u64)]),
+    "lsm_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Stats)]),
+}
+
+
+def header_symbols(path: str = HEADER):
+    """Names of every function the public header declares."""
+    text = open(path).read()
+    return re.findall(r"^LSM_API\s+[\w\s\*]+?\b(lsm_\w+)\s*\(", text, flags=re.M)
+
+
+def load_library(path: str = LIB_PATH):
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError("HIP library %s is not built (python -m paper_1707_05354_amd.build)"
+                               % path)
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _strerror(status: int) -> str:
+    try:
+        return load_library().lsm_strerror(int(status)).decode()
+    except Exception:  # library missing: still report the number
+        return "status"
+
+
+def _dev(t: torch.Tensor, name: str, dtypes=(torch.int32, torch.uint32)) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype not in dtypes:
+        raise TypeError("%s must have dtype in %s, got %s" % (name, dtypes, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t.data_ptr()
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != LSM_OK:
+        raise LSMError(rc, where)
+
+
+class LSM:
+    """A batched LSM dictionary resident on one GPU (see include/lsm.h)."""
+
+    def __init__(self, b: int, checked: bool = False, key_bits: int = 31,
+                 stream: Optional[torch.cuda.Stream] = None):
+        self._lib = load_library()
+        self.b = int(b)
+        self.device = torch.cuda.current_device()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        flags = (LSM_CHECKED if checked else 0) | LSM_KEY_BITS(key_bits)
+        h = _vp()
+        _check(self._lib.lsm_create(ctypes.byref(h), self.b, flags, _vp(self.stream.cuda_stream)),
+               "lsm_create")
+        self._h = h
+        self._last_total = 0
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self) -> None:
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            _check(self._lib.lsm_destroy(h), "lsm_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- updates ------------------------------------------------------------
+    def insert(self, keys: torch.Tensor, vals: torch.Tensor) -> None:
+        if keys.numel() != vals.numel():
+            raise ValueError("keys and vals differ in length")
+        _check(self._lib.lsm_insert_batch(self._h, _dev(keys, "keys"), _dev(vals, "vals"),
+                                          keys.numel()), "lsm_insert_batch")
+
+    def delete(self, keys: torch.Tensor) -> None:
+        _check(self._lib.lsm_delete_batch(self._h, _dev(keys, "keys"), keys.numel()),
+               "lsm_delete_batch")
+
+    def update(self, keys: torch.Tensor, vals: torch.Tensor, is_delete: torch.Tensor) -> None:
+        if not (keys.numel() == vals.numel() == is_delete.numel()):
+            raise ValueError("keys, vals and is_delete differ in length")
+        _check(self._lib.lsm_update_batch(
+            self._h, _dev(keys, "keys"), _dev(vals, "vals"),
+            _dev(is_delete, "is_delete", (torch.uint8, torch.bool)), keys.numel()),
+            "lsm_update_batch")
+
+    # -- queries ------------------------------------------------------------
+    def lookup(self, q: torch.Tensor, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):
+        nq = q.numel()
+        if out is None:
+            vals = torch.empty(nq, dtype=torch.int32, device=q.device)
+            found = torch.empty(nq, dtype=torch.uint8, device=q.device)
+        else:
+            vals, found = out
+        _check(self._lib.lsm_lookup(self._h, _dev(q, "q"), nq, _dev(vals, "vals"),
+                                    _dev(found, "found", (torch.uint8, torch.bool))), "lsm_lookup")
+        return vals, found
+
+    def count(self, lo: torch.Tensor, hi: torch.Tensor, out: Optional[torch.Tensor] = None):
+        nq = lo.numel()
+        if hi.numel() != nq:
+            raise ValueError("lo and hi differ in length")
+        counts = out if out is not None else torch.empty(nq, dtype=torch.int32, device=lo.device)
+        _check(self._lib.lsm_count(self._h, _dev(lo, "lo"), _dev(hi, "hi"), nq,
+                                   _dev(counts, "counts")), "lsm_count")
+        return counts
+
+    def range_raw(self, lo, hi, offsets, keys, vals, cap: int) -> int:
+        """One lsm_range call; returns the total (raises on any error)."""
+        total = _u64(0)
+        kp = _dev(keys, "keys") if keys is not None else None
+        vp = _dev(vals, "vals") if vals is not None else None
+        rc = self._lib.lsm_range(self._h, _dev(lo, "lo"), _dev(hi, "hi"), lo.numel(),
+                                 _dev(offsets, "offsets", (torch.int64, torch.uint64)), kp, vp,
+                                 int(cap), ctypes.byref(total))
+        _check(rc, "lsm_range")
+        return int(total.value)
+
+    def range(self, lo: torch.Tensor, hi: torch.Tensor, cap: Optional[int] = None):
+        """Returns (offsets[nq+1] int64, keys int32, vals int32); two-phase
+        when the first output guess is too small."""
+        nq = lo.numel()
+        if hi.numel() != nq:
+            raise ValueError("lo and hi differ in length")
+        offsets = torch.empty(nq + 1, dtype=torch.int64, device=lo.device)
+        guess = int(cap) if cap is not None else max(1024, 2 * self._last_total)
+        keys = torch.empty(max(guess, 1), dtype=torch.int32, device=lo.device)
+        vals = torch.empty(max(guess, 1), dtype=torch.int32, device=lo.device)
+        total = _u64(0)
+        rc = self._lib.lsm_range(self._h, _dev(lo, "lo"), _dev(hi, "hi"), nq,
+                                 _dev(offsets, "offsets", (torch.int64,)), keys.data_ptr(),
+                                 vals.data_ptr(), guess, ctypes.byref(total))
+        if rc == LSM_ECAPACITY and cap is None:
+            need = int(total.value)
+            keys = torch.empty(need, dtype=torch.int32, device=lo.device)
+            vals = torch.empty(need, dtype=torch.int32, device=lo.device)
+            rc = self._lib.lsm_range(self._h, _dev(lo, "lo"), _dev(hi, "hi"), nq,
+                                     _dev(offsets, "offsets", (torch.int64,)), keys.data_ptr(),
+                                     vals.data_ptr(), need, ctypes.byref(total))
+        _check(rc, "lsm_range")
+        n = int(total.value)
+        self._last_total = n
+        return offsets, keys[:n], vals[:n]
+
+    # -- introspection ------------------------------------------------------
+    @property
+    def num_batches(self) -> int:
+        return int(self._lib.lsm_num_batches(self._h))
+
+    def stats(self) -> Stats:
+        s = Stats()
+        _check(self._lib.lsm_get_stats(self._h, ctypes.byref(s)), "lsm_get_stats")
+        return s
+
+    def occupied(self):
+        r, out, i = self.num_batches, [], 0
+        while (r >> i) != 0:
+            if (r >> i) & 1:
+                out.append(i)
+            i += 1
+        return out
+
+    def level(self, i: int):
+        """Copies of level i's key variables and values (int32 tensors),
+        enqueued on the handle's stream."""
+        kp, vp, n = _vp(), _vp(), _u64()
+        _check(self._lib.lsm_level_view(self._h, int(i), ctypes.byref(kp), ctypes.byref(vp),
+                                        ctypes.byref(n)), "lsm_level_view")
+        n = int(n.value)
+        dev = torch.device("cuda", self.device)
+        kv = torch.empty(n, dtype=torch.int32, device=dev)
+        val = torch.empty(n, dtype=torch.int32, device=dev)
+        if n:
+            got = _u64()
+            _check(self._lib.lsm_level_copy(self._h, int(i), kv.data_ptr(), val.data_ptr(),
+                                            ctypes.byref(got)), "lsm_level_copy")
+        return kv, val

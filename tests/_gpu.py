@@ -1,0 +1,91 @@
+"""Helpers shared by the GPU tests: host/device conversion and building the
+GPU dictionary and both oracles from one operation stream."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+from paper_1707_05354_amd.lsm import LSM
+
+
+def dev(a) -> torch.Tensor:
+    a = np.ascontiguousarray(np.asarray(a).astype(np.uint32))
+    return torch.from_numpy(a.view(np.int32)).cuda()
+
+
+def dev_u8(a) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.uint8))).cuda()
+
+
+def host(t: torch.Tensor) -> np.ndarray:
+    a = t.detach().cpu().numpy()
+    if a.dtype == np.int32:
+        return a.view(np.uint32)
+    if a.dtype == np.int64:
+        return a.view(np.uint64)
+    return a
+
+
+def note(msg: str) -> None:
+    """Name the case before a GPU step (visible even if the step dies)."""
+    sys.stdout.write("[case] %s\n" % msg)
+    sys.stdout.flush()
+
+
+class Trio:
+    """The GPU dictionary next to the map oracle and the cascade oracle."""
+
+    def __init__(self, b: int, key_bits: int = 31, checked: bool = False):
+        self.g = LSM(b, checked=checked, key_bits=key_bits)
+        self.m = oracle.MapOracle()
+        self.c = oracle.CascadeOracle(b)
+        self.b = b
+
+    def insert(self, keys, vals):
+        self.g.insert(dev(keys), dev(vals))
+        self.m.insert(keys, vals)
+        self.c.insert(keys, vals)
+
+    def delete(self, keys):
+        self.g.delete(dev(keys))
+        self.m.delete(keys)
+        self.c.delete(keys)
+
+    def mixed(self, keys, vals, is_delete):
+        self.g.update(dev(keys), dev(vals), dev_u8(is_delete))
+        self.m.mixed(keys, vals, is_delete)
+        self.c.insert(keys, vals, (1 - np.asarray(is_delete, np.uint8)).astype(np.uint8))
+
+    def check_levels(self):
+        torch.cuda.synchronize()
+        assert self.g.num_batches == self.c.r
+        assert self.g.occupied() == self.c.occupied()
+        for i in self.c.occupied():
+            kv, v = self.g.level(i)
+            okv, ov = self.c.level(i)
+            gk, gv = host(kv), host(v)
+            if not np.array_equal(gk, okv):
+                bad = np.nonzero(gk != okv)[0]
+                raise AssertionError("level %d key variables differ at %d positions, first %d: "
+                                     "gpu %d oracle %d" % (i, bad.size, bad[0], gk[bad[0]], okv[bad[0]]))
+            assert np.array_equal(gv, ov), "level %d values differ" % i
+        st = self.g.stats()
+        assert st.merged_elems_last == self.c.merged_last
+
+    def check_queries(self, q, lo, hi):
+        q, lo, hi = (np.asarray(x, np.uint32) for x in (q, lo, hi))
+        gv, gf = self.g.lookup(dev(q))
+        gc = self.g.count(dev(lo), dev(hi))
+        go, gk, gval = self.g.range(dev(lo), dev(hi))
+        torch.cuda.synchronize()
+        ov, of = self.m.lookup(q)
+        assert np.array_equal(host(gf), of), "lookup found flags differ"
+        assert np.array_equal(host(gv), ov), "lookup values differ"
+        assert np.array_equal(host(gc), self.m.count(lo, hi)), "counts differ"
+        oo, ok, oval = self.m.range(lo, hi)
+        assert np.array_equal(host(go), oo), "range offsets differ"
+        assert np.array_equal(host(gk), ok), "range keys differ"
+        assert np.array_equal(host(gval), oval), "range values differ"

@@ -1,0 +1,237 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer results, so the bar is bit-exactness: every occupied level (key
+variables and values, stale elements and tombstones included) must equal
+the cascade oracle byte for byte, r and the merge count must match, and
+every lookup / count / range answer must equal the map oracle's.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1707_05354_amd import workload as W
+from paper_1707_05354_amd.lsm import LSM, LSMError, LSM_EBATCH, LSM_ECAPACITY, LSM_EKEY
+from _gpu import Trio, dev, dev_u8, host, note
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tiny_workload_b1024():
+    """b = 1024, 16 insert + 4 delete batches, 4096 lookups, 1024 count and
+    1024 range queries (about 8 hits each)."""
+    w = W.tiny()
+    note("tiny b=1024")
+    t = Trio(w.b)
+    for i in range(w.R):
+        if w.is_delete[i]:
+            t.delete(w.keys[i])
+        else:
+            t.insert(w.keys[i], w.vals[i])
+        t.check_levels()
+    assert t.g.occupied() == [2, 4]
+    t.check_queries(w.lookups, w.count_lo, w.count_hi)
+    t.check_queries(w.lookups[:10], w.range_lo, w.range_hi)
+    assert 4 <= float(host(t.g.count(dev(w.count_lo), dev(w.count_hi))).mean()) <= 12
+
+
+CASES = [
+    # (b, key domain, batches, seed)
+    (1, 8, 40, 1),
+    (2, 16, 33, 2),
+    (3, 1 << 31, 20, 3),
+    (7, 50, 37, 4),
+    (64, 200, 31, 5),
+    (2047, 3000, 9, 6),
+    (2048, 1 << 31, 9, 7),
+    (2049, 5000, 9, 8),
+    (6161, 1 << 20, 7, 9),
+]
+
+
+@pytest.mark.parametrize("b,domain,R,seed", CASES)
+def test_random_streams(b, domain, R, seed):
+    """Partial batches (padding), duplicates inside and across batches,
+    deletes of present and absent keys, b across sort/merge tile edges."""
+    ops, q, lo, hi = W.random_small(seed, b, R, domain, p_delete=0.3, nq=700)
+    note("random stream b=%d domain=%d R=%d seed=%d" % (b, domain, R, seed))
+    t = Trio(b)
+    for j, (kind, k, v) in enumerate(ops):
+        if kind == "insert":
+            t.insert(k, v)
+        else:
+            t.delete(k)
+        t.check_levels()
+        if j % 5 == 4:
+            t.check_queries(q, lo, hi)
+    t.check_queries(q, lo, hi)
+
+
+@pytest.mark.parametrize("b", [1, 5, 300, 4096])
+def test_mixed_batches(b):
+    """Insertions and deletions in one batch; a key inserted and deleted in
+    the same batch is deleted (sec. III-A rule 5)."""
+    rng = np.random.default_rng(b)
+    note("mixed b=%d" % b)
+    t = Trio(b)
+    for _ in range(13):
+        n = int(rng.integers(1, b + 1))
+        k = rng.integers(0, max(4, b // 2), n).astype(np.uint32)
+        v = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        d = (rng.random(n) < 0.35).astype(np.uint8)
+        t.mixed(k, v, d)
+        t.check_levels()
+    dom = max(4, b // 2) + 2
+    q = np.arange(dom, dtype=np.uint32)
+    t.check_queries(q, q[: dom // 2], q[dom // 2:dom // 2 * 2])
+
+
+def test_many_levels_b1():
+    """b = 1 and 4095 batches: twelve occupied levels at once."""
+    rng = np.random.default_rng(12)
+    note("b=1 R=4095")
+    t = Trio(1)
+    keys = rng.integers(0, 3000, 4095).astype(np.uint32)
+    vals = rng.integers(0, 2**32, 4095, dtype=np.uint64).astype(np.uint32)
+    dels = rng.random(4095) < 0.2
+    for i in range(4095):
+        if dels[i]:
+            t.delete(keys[i:i + 1])
+        else:
+            t.insert(keys[i:i + 1], vals[i:i + 1])
+    assert len(t.g.occupied()) == 12
+    t.check_levels()
+    q = np.arange(3002, dtype=np.uint32)
+    lo = rng.integers(0, 3002, 2000).astype(np.uint32)
+    hi = np.minimum(lo + rng.integers(0, 300, 2000), 3001).astype(np.uint32)
+    t.check_queries(q, lo, hi)
+
+
+def test_large_batches_many_tiles():
+    """b = 2^19 + 3: 257 sort tiles with a ragged tail, then merges of
+    2^19 + 3 runs spanning hundreds of merge tiles; heavy duplication."""
+    b = (1 << 19) + 3
+    rng = np.random.default_rng(19)
+    note("b=2^19+3")
+    t = Trio(b)
+    for r in range(3):
+        k = rng.integers(0, 1 << 18, b).astype(np.uint32)
+        v = rng.integers(0, 2**32, b, dtype=np.uint64).astype(np.uint32)
+        t.insert(k, v)
+        t.check_levels()
+    t.delete(rng.integers(0, 1 << 18, b // 3).astype(np.uint32))
+    t.check_levels()
+    q = rng.integers(0, (1 << 18) + 5, 20000).astype(np.uint32)
+    lo = rng.integers(0, 1 << 18, 5000).astype(np.uint32)
+    t.check_queries(q, lo, lo + 40)
+
+
+def test_all_equal_keys_and_extremes():
+    """Every key equal (one long run through every merge tile), then keys 0
+    and 2^31-1 with values 0 and 2^32-1, and bounds up to 2^32-1."""
+    b = 5000
+    note("all-equal keys b=5000")
+    t = Trio(b)
+    for r in range(4):
+        t.insert(np.full(b, 77, np.uint32), np.arange(r * b, (r + 1) * b, dtype=np.uint32))
+        t.check_levels()
+    t.insert(np.array([0, 2**31 - 1, 77], np.uint32), np.array([0, 2**32 - 1, 5], np.uint32))
+    t.check_levels()
+    t.delete(np.array([77], np.uint32))
+    t.check_levels()
+    q = np.array([0, 1, 76, 77, 78, 2**31 - 2, 2**31 - 1, 2**31, 2**32 - 1], np.uint32)
+    lo = np.array([0, 0, 77, 78, 2**31 - 1, 5, 0], np.uint32)
+    hi = np.array([2**32 - 1, 2**31 - 1, 77, 2**31 - 1, 2**31 - 1, 4, 0], np.uint32)
+    t.check_queries(q, lo, hi)
+
+
+def test_empty_dictionary_and_empty_queries():
+    note("empty dictionary")
+    g = LSM(256)
+    q = dev(np.array([0, 5, 2**31 - 1], np.uint32))
+    v, f = g.lookup(q)
+    assert host(f).tolist() == [0, 0, 0] and host(v).tolist() == [0, 0, 0]
+    assert host(g.count(q, q)).tolist() == [0, 0, 0]
+    off, k, val = g.range(q, q)
+    assert host(off).tolist() == [0, 0, 0, 0] and k.numel() == 0
+    e = dev(np.zeros(0, np.uint32))
+    v, f = g.lookup(e)
+    assert v.numel() == 0
+    assert g.count(e, e).numel() == 0
+    off, k, val = g.range(e, e)
+    assert host(off).tolist() == [0]
+    g.insert(e, e)  # n == 0: no-op
+    assert g.num_batches == 0
+    g.close()
+
+
+def test_batch_size_errors_leave_state_unchanged():
+    note("batch size errors")
+    t = Trio(8)
+    t.insert(np.arange(8, dtype=np.uint32), np.arange(8, dtype=np.uint32))
+    with pytest.raises(LSMError) as ei:
+        t.g.insert(dev(np.arange(9, dtype=np.uint32)), dev(np.arange(9, dtype=np.uint32)))
+    assert ei.value.status == LSM_EBATCH
+    with pytest.raises(LSMError):
+        t.g.delete(dev(np.arange(9, dtype=np.uint32)))
+    t.check_levels()
+
+
+@pytest.mark.parametrize("key_bits", [31, 24])
+def test_checked_mode_rejects_out_of_range_keys(key_bits):
+    note("checked mode key_bits=%d" % key_bits)
+    t = Trio(16, key_bits=key_bits, checked=True)
+    rng = np.random.default_rng(key_bits)
+    for _ in range(3):
+        t.insert(rng.integers(0, 1 << key_bits, 16).astype(np.uint32),
+                 rng.integers(0, 2**32, 16, dtype=np.uint64).astype(np.uint32))
+    before = t.g.num_batches
+    bad = rng.integers(0, 1 << key_bits, 16).astype(np.uint32)
+    bad[7] = 1 << key_bits
+    with pytest.raises(LSMError) as ei:
+        t.g.insert(dev(bad), dev(bad))
+    assert ei.value.status == LSM_EKEY
+    with pytest.raises(LSMError):
+        t.g.delete(dev(bad))
+    assert t.g.num_batches == before
+    t.check_levels()
+    t.insert(bad[:7], bad[:7])
+    t.check_levels()
+
+
+def test_key_bits_24_fewer_passes():
+    """Keys < 2^24 sorted with three digit passes give the same layout."""
+    rng = np.random.default_rng(24)
+    note("key_bits=24 b=8192")
+    t = Trio(8192, key_bits=24)
+    for r in range(6):
+        k = rng.integers(0, 1 << 24, 8192).astype(np.uint32)
+        if r % 3 == 2:
+            t.delete(k[:4000])
+        else:
+            t.insert(k, rng.integers(0, 2**32, 8192, dtype=np.uint64).astype(np.uint32))
+        t.check_levels()
+    q = rng.integers(0, 1 << 24, 4000).astype(np.uint32)
+    t.check_queries(q, q, q + 5000)
+
+
+def test_range_two_phase_capacity():
+    note("range capacity")
+    t = Trio(1024)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        t.insert(rng.integers(0, 10000, 1024).astype(np.uint32),
+                 rng.integers(0, 2**32, 1024, dtype=np.uint64).astype(np.uint32))
+    lo = dev(np.array([0, 100, 5000], np.uint32))
+    hi = dev(np.array([50, 3000, 9999], np.uint32))
+    off = torch.empty(4, dtype=torch.int64, device="cuda")
+    with pytest.raises(LSMError) as ei:
+        t.g.range_raw(lo, hi, off, None, None, 0)
+    assert ei.value.status == LSM_ECAPACITY
+    want_off, want_k, want_v = t.m.range(np.array([0, 100, 5000]), np.array([50, 3000, 9999]))
+    torch.cuda.synchronize()
+    assert np.array_equal(host(off), want_off)
+    k = torch.empty(int(want_off[-1]), dtype=torch.int32, device="cuda")
+    v = torch.empty(int(want_off[-1]), dtype=torch.int32, device="cuda")
+    assert t.g.range_raw(lo, hi, off, k, v, int(want_off[-1])) == int(want_off[-1])
+    torch.cuda.synchronize()
+    assert np.array_equal(host(k), want_k) and np.array_equal(host(v), want_v)
