@@ -161,6 +161,12 @@ LSM_API lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_
                        uint32_t nq, uint64_t* d_offsets, uint32_t* d_keys,
                        uint32_t* d_vals, uint64_t cap, uint64_t* h_total);
 
+/*
+ * lsm_clear -- empty the dictionary (r = 0) and keep every allocation, so a
+ * rebuild reuses the level memory.  Work already enqueued is unaffected.
+ */
+LSM_API lsm_status_t lsm_clear(lsm_t h);
+
 /* lsm_destroy -- synchronise the stream and free every allocation. */
 LSM_API lsm_status_t lsm_destroy(lsm_t h);
 
@@ -203,6 +209,39 @@ typedef struct {
 } lsm_stats_t;
 
 LSM_API lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out);
+
+/*
+ * Device-time profile, gathered while profiling is on (lsm_profile_enable):
+ * every kernel is launched between a start and a stop HIP event on the
+ * handle's stream (hipExtLaunchKernelGGL), so kernel_ms sums the kernels'
+ * own execution times.  lsm_profile_read synchronises the stream, resolves
+ * the events and returns the sums since the last reset.
+ *
+ * Kernel index k: 0 batch-sort histogram, 1 batch-sort digit pass, 2 level
+ * merge, 3 lookup, 4 count, 5 range offset scan, 6 range emission.
+ * kernel_bytes[k] is the algorithmic traffic of those launches: 4 B per
+ * batch element for the histogram, 16 B per element for a digit pass (key
+ * and value read and written), 16 B per merge output element, 12 B per
+ * scanned count; 0 for the search kernels, which are latency-bound.
+ */
+#define LSM_PROF_KERNELS 7
+typedef struct {
+  uint64_t update_calls;                   /* update calls (n > 0)          */
+  uint64_t query_calls[3];                 /* lookup, count, range calls    */
+  uint64_t query_items[3];                 /* queries answered by each      */
+  uint64_t launches[LSM_PROF_KERNELS];     /* launches per kernel           */
+  uint64_t elems[LSM_PROF_KERNELS];        /* elements / queries processed  */
+  double kernel_ms[LSM_PROF_KERNELS];      /* summed kernel time            */
+  double kernel_bytes[LSM_PROF_KERNELS];   /* algorithmic bytes             */
+  double update_ms;      /* per update call: first kernel start to last end  */
+  double update_p50_ms;
+  double update_p99_ms;
+  double update_max_ms;
+  double query_ms[3];    /* lookup, count, range: first start to last end    */
+} lsm_profile_t;
+
+LSM_API lsm_status_t lsm_profile_enable(lsm_t h, int on);
+LSM_API lsm_status_t lsm_profile_read(lsm_t h, lsm_profile_t* out, int reset);
 
 #ifdef __cplusplus
 }

@@ -10,8 +10,10 @@
 // writes scratch buffers and the empty level j = ffz(r); r is incremented
 // only after every launch has been accepted, so a failure leaves the
 // dictionary as it was.
+#include <algorithm>
 #include <new>
 #include <string.h>
+#include <vector>
 
 #include "lsm.h"
 #include "lsm_internal.h"
@@ -34,6 +36,7 @@ struct lsm_s {
   uint32_t* buf_kv = nullptr;  // the sorted batch when it has to be merged
   uint32_t* buf_val = nullptr;
   uint32_t* meta = nullptr;  // sort histograms, look-back words, counters
+  int hist_parity = 0;       // which global histogram buffer the next sort uses
 
   uint32_t* mrg_kv[2] = {};  // cascade ping-pong
   uint32_t* mrg_val[2] = {};
@@ -47,6 +50,19 @@ struct lsm_s {
 
   uint64_t merged_last = 0, merged_total = 0, sorted_total = 0;
   uint64_t device_bytes = 0;
+
+  // Profiling: events recorded on the stream between kernels, resolved on
+  // lsm_profile_read.  A span is a pair of indices into `marks`.
+  struct Span {
+    int kind;  // KernelKind for a kernel; 10 update call; 11..13 lookup/count/range call
+    uint32_t a, b;
+    uint64_t items;
+  };
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool, marks;
+  std::vector<Span> spans;
+  std::vector<double> update_times;
+  lsm_profile_t acc = {};
 };
 
 namespace {
@@ -177,12 +193,63 @@ void release_all(lsm_t h) {
   }
   dev_free(h, h->buf_kv, bb);
   dev_free(h, h->buf_val, bb);
-  dev_free(h, h->meta, sort_meta_words(h->b, kMaxPasses) * sizeof(uint32_t));
+  dev_free(h, h->meta, sort_meta_words(h->b) * sizeof(uint32_t));
   if (h->q_cap) {
     dev_free(h, h->q_counts, h->q_cap * sizeof(uint32_t));
     dev_free(h, h->q_status, scan_status_words(static_cast<uint32_t>(h->q_cap)) * sizeof(uint64_t));
   }
   if (h->h_pinned) (void)hipHostFree(h->h_pinned);
+}
+
+// Two pooled events for one kernel launch (start, stop), remembered as a
+// span of the given kind; returns nullptr when profiling is off.
+struct Timed {
+  KTimer t;
+  int64_t a = -1, b = -1;
+};
+
+hipEvent_t pooled_event(lsm_t h) {
+  hipEvent_t e = nullptr;
+  if (!h->ev_pool.empty()) {
+    e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+
+const KTimer* timer(lsm_t h, Timed& slot, int kind, uint64_t items) {
+  if (!h->prof) return nullptr;
+  hipEvent_t a = pooled_event(h), b = pooled_event(h);
+  if (a == nullptr || b == nullptr) {
+    if (a) h->ev_pool.push_back(a);
+    if (b) h->ev_pool.push_back(b);
+    return nullptr;
+  }
+  h->marks.push_back(a);
+  slot.a = static_cast<int64_t>(h->marks.size() - 1);
+  h->marks.push_back(b);
+  slot.b = static_cast<int64_t>(h->marks.size() - 1);
+  slot.t.start = a;
+  slot.t.stop = b;
+  h->spans.push_back({kind, static_cast<uint32_t>(slot.a), static_cast<uint32_t>(slot.b), items});
+  return &slot.t;
+}
+
+// A call-level span from the start event of one launch to the stop event
+// of another.
+void call_span(lsm_t h, int kind, const Timed& first, const Timed& last, uint64_t items) {
+  if (first.a >= 0 && last.b >= 0)
+    h->spans.push_back({kind, static_cast<uint32_t>(first.a), static_cast<uint32_t>(last.b), items});
+}
+
+void release_events(lsm_t h) {
+  for (hipEvent_t e : h->marks) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  h->marks.clear();
+  h->ev_pool.clear();
+  h->spans.clear();
 }
 
 // One update batch (sec. III-B insertion; deletions and mixed batches are
@@ -211,16 +278,27 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
   const bool checked = (h->flags & LSM_CHECKED) != 0;
   const int lo_bit = (mode == kMixed) ? 0 : 1;
   const int passes = sort_passes(h->key_bits, lo_bit);
-  SortMeta meta = sort_meta_carve(h->meta, h->b, passes);
+  SortMeta meta = sort_meta_carve(h->meta, h->b, h->hist_parity);
   BatchSrc src{keys, vals, is_delete, n, h->b, static_cast<int>(mode)};
   if (checked && hipMemsetAsync(meta.err, 0, sizeof(uint32_t), h->stream) != hipSuccess)
     return LSM_EHIP;
 
   uint32_t* sorted_kv = (j == 0) ? h->lvl_kv[0] : h->buf_kv;
   uint32_t* sorted_val = (j == 0) ? h->lvl_val[0] : h->buf_val;
-  if (launch_sort(src, lo_bit, passes, h->key_bits, checked ? 1 : 0, meta, h->tmp_kv, h->tmp_val,
-                  sorted_kv, sorted_val, h->stream) != hipSuccess)
-    return LSM_EHIP;
+  Timed st[1 + kMaxPasses];
+  KTimer sort_t[1 + kMaxPasses];
+  bool timed = h->prof;
+  for (int p = 0; p <= passes && timed; ++p) {
+    const KTimer* t = timer(h, st[p], p == 0 ? kKSortHist : kKSortPass, h->b);
+    if (t == nullptr) timed = false;
+    else sort_t[p] = *t;
+  }
+  const hipError_t se = launch_sort(src, lo_bit, passes, h->key_bits, checked ? 1 : 0, meta,
+                                    h->tmp_kv, h->tmp_val, sorted_kv, sorted_val, h->stream,
+                                    timed ? sort_t : nullptr);
+  h->hist_parity ^= 1;  // the histogram kernel cleared the other buffer for the next sort
+  if (se != hipSuccess) return LSM_EHIP;
+  Timed last = st[passes];
 
   if (checked) {
     if (hipMemcpyAsync(h->h_pinned, meta.err, sizeof(uint32_t), hipMemcpyDeviceToHost,
@@ -229,6 +307,7 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
       return LSM_EHIP;
     if (*reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u) return LSM_EKEY;
   }
+
 
   // while level i is full: buffer <- merge(buffer, level i)  (Fig. 2(a)).
   // The last merge writes straight into level j.
@@ -239,13 +318,17 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
     uint32_t* o_kv = (i == j - 1) ? h->lvl_kv[j] : h->mrg_kv[i & 1];
     uint32_t* o_val = (i == j - 1) ? h->lvl_val[j] : h->mrg_val[i & 1];
     const uint32_t len = static_cast<uint32_t>(level_len(h, i));
+    Timed mt;
+    const KTimer* t = timer(h, mt, kKMerge, 2ull * len);
     if (launch_merge(cur_kv, cur_val, len, h->lvl_kv[i], h->lvl_val[i], len, o_kv, o_val,
-                     h->stream) != hipSuccess)
+                     h->stream, t) != hipSuccess)
       return LSM_EHIP;
+    if (t != nullptr) last = mt;
     merged += 2ull * len;
     cur_kv = o_kv;
     cur_val = o_val;
   }
+  if (timed) call_span(h, 10, st[0], last, h->b);
   h->r += 1;
   h->merged_last = merged;
   h->merged_total += merged;
@@ -285,9 +368,12 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
   }
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->buf_kv = static_cast<uint32_t*>(p);
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->buf_val = static_cast<uint32_t*>(p);
-  if (s == LSM_OK &&
-      (s = dev_alloc(h, &p, sort_meta_words(b, kMaxPasses) * sizeof(uint32_t))) == LSM_OK)
+  if (s == LSM_OK && (s = dev_alloc(h, &p, sort_meta_words(b) * sizeof(uint32_t))) == LSM_OK) {
     h->meta = static_cast<uint32_t*>(p);
+    // Both global histogram buffers start zeroed (each sort then clears
+    // the buffer of the next one).
+    if (hipMemset(h->meta, 0, sort_meta_words(b) * sizeof(uint32_t)) != hipSuccess) s = LSM_EHIP;
+  }
   if (s == LSM_OK) {
     void* hp = nullptr;
     if (hipHostMalloc(&hp, 64, hipHostMallocDefault) != hipSuccess) s = LSM_ENOMEM;
@@ -329,7 +415,11 @@ lsm_status_t lsm_lookup(lsm_t h, const uint32_t* d_keys, uint32_t nq, uint32_t* 
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
   const LevelSet lv = occupied_levels(h);
-  return launch_lookup(lv, d_keys, nq, d_vals, d_found, h->stream) == hipSuccess ? LSM_OK : LSM_EHIP;
+  Timed tl;
+  const KTimer* t = timer(h, tl, kKLookup, nq);
+  if (launch_lookup(lv, d_keys, nq, d_vals, d_found, h->stream, t) != hipSuccess) return LSM_EHIP;
+  if (t != nullptr) call_span(h, 11, tl, tl, nq);
+  return LSM_OK;
 }
 
 lsm_status_t lsm_count(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint32_t nq,
@@ -340,8 +430,12 @@ lsm_status_t lsm_count(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
   const LevelSet lv = occupied_levels(h);
-  return launch_count(lv, d_lo, d_hi, nq, d_counts, nullptr, 0, h->stream) == hipSuccess ? LSM_OK
-                                                                                          : LSM_EHIP;
+  Timed tc;
+  const KTimer* t = timer(h, tc, kKCount, nq);
+  if (launch_count(lv, d_lo, d_hi, nq, d_counts, nullptr, 0, h->stream, t) != hipSuccess)
+    return LSM_EHIP;
+  if (t != nullptr) call_span(h, 12, tc, tc, nq);
+  return LSM_OK;
 }
 
 lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint32_t nq,
@@ -360,12 +454,15 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   lsm_status_t s = ensure_query_scratch(h, nq);
   if (s != LSM_OK) return s;
   const LevelSet lv = occupied_levels(h);
+  Timed t1, t2, t3;
   // Stage 1: per-query live counts (also clears the scan's look-back words).
   if (launch_count(lv, d_lo, d_hi, nq, h->q_counts, h->q_status, scan_status_words(nq),
-                   h->stream) != hipSuccess)
+                   h->stream, timer(h, t1, kKCount, nq)) != hipSuccess)
     return LSM_EHIP;
   // Stage 2: exclusive scan into the caller's offsets.
-  if (launch_scan(h->q_counts, nq, d_offsets, h->q_status, h->stream) != hipSuccess) return LSM_EHIP;
+  if (launch_scan(h->q_counts, nq, d_offsets, h->q_status, h->stream,
+                  timer(h, t2, kKScan, nq)) != hipSuccess)
+    return LSM_EHIP;
   if (hipMemcpyAsync(h->h_pinned, d_offsets + nq, sizeof(uint64_t), hipMemcpyDeviceToHost,
                      h->stream) != hipSuccess ||
       hipStreamSynchronize(h->stream) != hipSuccess)
@@ -373,11 +470,74 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   const uint64_t total = *reinterpret_cast<volatile uint64_t*>(h->h_pinned);
   *h_total = total;
   if (total > cap) return LSM_ECAPACITY;
-  if (total == 0) return LSM_OK;
   // Stage 3: each query writes its live pairs in key order at its offset.
-  return launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, d_keys, d_vals, h->stream) == hipSuccess
-             ? LSM_OK
-             : LSM_EHIP;
+  if (total > 0) {
+    if (launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, d_keys, d_vals, h->stream,
+                          timer(h, t3, kKRangeEmit, nq)) != hipSuccess)
+      return LSM_EHIP;
+    call_span(h, 13, t1, t3, nq);
+  } else {
+    call_span(h, 13, t1, t2, nq);
+  }
+  return LSM_OK;
+}
+
+lsm_status_t lsm_clear(lsm_t h) {
+  if (h == nullptr) return LSM_EINVAL;
+  h->r = 0;
+  h->merged_last = 0;
+  return LSM_OK;
+}
+
+lsm_status_t lsm_profile_enable(lsm_t h, int on) {
+  if (h == nullptr) return LSM_EINVAL;
+  h->prof = on != 0;
+  return LSM_OK;
+}
+
+lsm_status_t lsm_profile_read(lsm_t h, lsm_profile_t* out, int reset) {
+  if (h == nullptr || out == nullptr) return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok || hipStreamSynchronize(h->stream) != hipSuccess) return LSM_EHIP;
+  lsm_profile_t& p = h->acc;
+  // Algorithmic bytes per processed element, by kernel kind.
+  static const double kBytesPerItem[kNumKernelKinds] = {4.0, 16.0, 16.0, 0.0, 0.0, 12.0, 0.0};
+  for (const auto& sp : h->spans) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->marks[sp.a], h->marks[sp.b]) != hipSuccess) continue;
+    if (sp.kind < kNumKernelKinds) {
+      p.launches[sp.kind] += 1;
+      p.elems[sp.kind] += sp.items;
+      p.kernel_ms[sp.kind] += ms;
+      p.kernel_bytes[sp.kind] += kBytesPerItem[sp.kind] * static_cast<double>(sp.items);
+    } else if (sp.kind == 10) {
+      p.update_ms += ms;
+      p.update_calls += 1;
+      h->update_times.push_back(ms);
+    } else {
+      const int q = sp.kind - 11;
+      p.query_ms[q] += ms;
+      p.query_calls[q] += 1;
+      p.query_items[q] += sp.items;
+    }
+  }
+  for (hipEvent_t e : h->marks) h->ev_pool.push_back(e);
+  h->marks.clear();
+  h->spans.clear();
+  if (!h->update_times.empty()) {
+    std::vector<double> t = h->update_times;
+    std::sort(t.begin(), t.end());
+    auto q = [&](double f) { return t[static_cast<size_t>(f * (t.size() - 1) + 0.5)]; };
+    p.update_p50_ms = q(0.50);
+    p.update_p99_ms = q(0.99);
+    p.update_max_ms = t.back();
+  }
+  *out = p;
+  if (reset) {
+    h->acc = lsm_profile_t{};
+    h->update_times.clear();
+  }
+  return LSM_OK;
 }
 
 lsm_status_t lsm_destroy(lsm_t h) {
@@ -386,6 +546,7 @@ lsm_status_t lsm_destroy(lsm_t h) {
   {
     DeviceGuard g(h->device);
     if (!g.ok || hipStreamSynchronize(h->stream) != hipSuccess) s = LSM_EHIP;
+    release_events(h);
     release_all(h);
   }
   delete h;

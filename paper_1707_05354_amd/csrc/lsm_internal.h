@@ -19,8 +19,11 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kThreads * kSortItems;
 constexpr int kMaxPasses = 4;
-// Histogram kernel tile (one partial histogram per tile).
-constexpr int kHistTile = 8192;
+// Histogram kernel: tiles of kThreads * kHistItems elements, at most
+// kMaxHistBlocks work-groups (grid-stride beyond that).
+constexpr int kHistItems = 8;
+constexpr int kHistTile = kThreads * kHistItems;
+constexpr int kMaxHistBlocks = 512;
 
 // Merge: tiles of kThreads * kMergeItems output elements.
 constexpr int kMergeItems = 8;
@@ -54,51 +57,69 @@ struct BatchSrc {
   int mode;                   // BatchMode
 };
 
-// Sort scratch layout (uint32 words) for a batch of b elements and P passes.
+// Sort scratch layout (uint32 words) for a batch of b elements.  The global
+// digit histogram is double-buffered: a sort accumulates into hist[parity]
+// and clears hist[parity ^ 1] for the next sort (both start zeroed).
 struct SortMeta {
-  uint32_t* hist_parts;   // [num_hist_tiles][P][256]
-  uint32_t* status;       // [P][num_sort_tiles][256] look-back words
-  uint32_t* tile_ctr;     // [P] dynamic tile counters
+  uint32_t* hist;         // [2][kMaxPasses][256]
+  uint32_t* status;       // [kMaxPasses][num_sort_tiles][256] look-back words
+  uint32_t* tile_ctr;     // [kMaxPasses] dynamic tile counters
   uint32_t* err;          // [1] key-range violation flag (checked mode)
-  uint32_t num_hist_tiles;
+  uint32_t num_hist_blocks;
   uint32_t num_sort_tiles;
+  int parity;
 };
 
-size_t sort_meta_words(uint32_t b, int passes);
-SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int passes);
+// Optional per-launch timing: when start is non-null the kernel is launched
+// with hipExtLaunchKernelGGL so the two events bracket the kernel itself.
+struct KTimer {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+
+// Kernel kinds of the profile (indices of lsm_profile_t's per-kernel arrays).
+enum KernelKind : int {
+  kKSortHist = 0, kKSortPass = 1, kKMerge = 2, kKLookup = 3, kKCount = 4, kKScan = 5,
+  kKRangeEmit = 6, kNumKernelKinds = 7
+};
+
+size_t sort_meta_words(uint32_t b);
+SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity);
 
 // Sorts one batch into (out_kv, out_val): key variables ascending over bits
 // [lo_bit, lo_bit + 8 * passes), equal key variables with the later batch
 // position first.  tmp_* are two ping-pong buffers of b elements each.
+// timers (optional) holds 1 + passes entries: histogram, then each pass.
 hipError_t launch_sort(const BatchSrc& src, int lo_bit, int passes, uint32_t key_limit_bits,
                        int checked, const SortMeta& meta, uint32_t* tmp_kv[2],
                        uint32_t* tmp_val[2], uint32_t* out_kv, uint32_t* out_val,
-                       hipStream_t stream);
+                       hipStream_t stream, const KTimer* timers);
 
 // Stable merge of a newer run (first on equal original keys) with an older
 // run into out (na + nb elements).
 hipError_t launch_merge(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na,
                         const uint32_t* b_kv, const uint32_t* b_val, uint32_t nb,
-                        uint32_t* out_kv, uint32_t* out_val, hipStream_t stream);
+                        uint32_t* out_kv, uint32_t* out_val, hipStream_t stream,
+                        const KTimer* t);
 
 hipError_t launch_lookup(const LevelSet& lv, const uint32_t* q, uint32_t nq, uint32_t* out_val,
-                         uint8_t* out_found, hipStream_t stream);
+                         uint8_t* out_found, hipStream_t stream, const KTimer* t);
 
 // Count pass: per query number of live keys in [lo, hi].  When scan_status
 // is non-null the kernel also clears the scan's look-back words
 // (scan_words of them, tile counter included) for the following scan.
 hipError_t launch_count(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi, uint32_t nq,
                         uint32_t* counts, uint64_t* scan_status, size_t scan_words,
-                        hipStream_t stream);
+                        hipStream_t stream, const KTimer* t);
 
 // Exclusive scan of nq uint32 counts into nq + 1 uint64 offsets.
 size_t scan_status_words(uint32_t nq);
 hipError_t launch_scan(const uint32_t* counts, uint32_t nq, uint64_t* offsets,
-                       uint64_t* scan_status, hipStream_t stream);
+                       uint64_t* scan_status, hipStream_t stream, const KTimer* t);
 
 // Range emission pass: writes each query's live pairs at offsets[q].
 hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi,
                              uint32_t nq, const uint64_t* offsets, uint32_t* out_keys,
-                             uint32_t* out_vals, hipStream_t stream);
+                             uint32_t* out_vals, hipStream_t stream, const KTimer* t);
 
 }  // namespace lsm

@@ -20,6 +20,8 @@
 //       (sec. III-E, IV-C, IV-D).
 //   k_scan : single-pass exclusive scan with decoupled look-back for the
 //       range output offsets (stage 2 of sec. IV-C).
+#include <hip/hip_ext.h>
+
 #include "lsm_internal.h"
 
 namespace lsm {
@@ -131,33 +133,49 @@ __device__ __forceinline__ void batch_elem(const BatchSrc& s, uint32_t e, uint32
   val = st ? s.vals[src] : 0u;  // tombstones carry value 0
 }
 
-// Per-tile digit histograms of every pass in one read of the batch.  Also
-// clears the look-back words and tile counters of the passes that follow.
+// Digit histograms of every pass in one read of the batch, accumulated into
+// hist[parity].  Also clears hist[parity ^ 1] (for the next sort) and the
+// look-back words and tile counters of the passes that follow.
 __global__ __launch_bounds__(kThreads) void k_sort_hist(BatchSrc src, int lo_bit, int passes,
                                                         uint32_t key_limit_bits, int checked,
                                                         SortMeta meta) {
   __shared__ uint32_t s_h[kMaxPasses * kRadix];
   const uint32_t tid = threadIdx.x;
+  const size_t gthreads = static_cast<size_t>(gridDim.x) * kThreads;
+  const size_t gid = static_cast<size_t>(blockIdx.x) * kThreads + tid;
   const size_t nstatus = static_cast<size_t>(passes) * meta.num_sort_tiles * kRadix;
-  for (size_t i = static_cast<size_t>(blockIdx.x) * kThreads + tid; i < nstatus;
-       i += static_cast<size_t>(gridDim.x) * kThreads)
-    meta.status[i] = 0u;
-  if (blockIdx.x == 0 && tid < static_cast<uint32_t>(passes)) meta.tile_ctr[tid] = 0u;
-  for (uint32_t i = tid; i < static_cast<uint32_t>(passes * kRadix); i += kThreads) s_h[i] = 0u;
+  for (size_t i = gid; i < nstatus; i += gthreads) meta.status[i] = 0u;
+  uint32_t* other = meta.hist + static_cast<size_t>(meta.parity ^ 1) * kMaxPasses * kRadix;
+  for (size_t i = gid; i < static_cast<size_t>(kMaxPasses) * kRadix; i += gthreads) other[i] = 0u;
+  if (gid < static_cast<size_t>(kMaxPasses)) meta.tile_ctr[gid] = 0u;
+  for (uint32_t i = tid; i < static_cast<uint32_t>(kMaxPasses * kRadix); i += kThreads) s_h[i] = 0u;
   __syncthreads();
 
   bool bad = false;
-  for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * kThreads + tid; e < src.b;
-       e += static_cast<uint64_t>(gridDim.x) * kThreads) {
-    uint32_t kv, val, key;
-    batch_elem(src, static_cast<uint32_t>(e), kv, val, key);
-    if (checked) bad |= (key_limit_bits >= 32 ? false : (key >> key_limit_bits) != 0u);
-    for (int p = 0; p < passes; ++p)
-      atomicAdd(&s_h[p * kRadix + ((kv >> (lo_bit + kRadixBits * p)) & (kRadix - 1))], 1u);
+  for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * kHistTile; base < src.b;
+       base += static_cast<uint64_t>(gridDim.x) * kHistTile) {
+    uint32_t kv[kHistItems], key[kHistItems];
+#pragma unroll
+    for (int i = 0; i < kHistItems; ++i) {  // all loads first, then count
+      const uint64_t e = base + static_cast<uint64_t>(i) * kThreads + tid;
+      uint32_t val;
+      kv[i] = 0u;
+      key[i] = 0u;
+      if (e < src.b) batch_elem(src, static_cast<uint32_t>(e), kv[i], val, key[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kHistItems; ++i) {
+      const uint64_t e = base + static_cast<uint64_t>(i) * kThreads + tid;
+      if (e >= src.b) continue;
+      if (checked) bad |= (key[i] >> key_limit_bits) != 0u;
+      for (int p = 0; p < passes; ++p)
+        atomicAdd(&s_h[p * kRadix + ((kv[i] >> (lo_bit + kRadixBits * p)) & (kRadix - 1))], 1u);
+    }
   }
   __syncthreads();
-  uint32_t* out = meta.hist_parts + static_cast<size_t>(blockIdx.x) * passes * kRadix;
-  for (uint32_t i = tid; i < static_cast<uint32_t>(passes * kRadix); i += kThreads) out[i] = s_h[i];
+  uint32_t* mine = meta.hist + static_cast<size_t>(meta.parity) * kMaxPasses * kRadix;
+  for (uint32_t i = tid; i < static_cast<uint32_t>(passes * kRadix); i += kThreads)
+    if (s_h[i] != 0u) atomicAdd(&mine[i], s_h[i]);
   if (checked && bad) atomicOr(meta.err, 1u);
 }
 
@@ -240,25 +258,25 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(BatchSrc src, const uint
   const uint32_t local_start = block_excl_scan(tile_count, s_tmp);
   s_local[d] = local_start;
 
-  uint32_t gtotal = 0;
-  for (uint32_t part = 0; part < meta.num_hist_tiles; ++part)
-    gtotal += meta.hist_parts[(static_cast<size_t>(part) * passes + pass) * kRadix + d];
+  const uint32_t gtotal =
+      meta.hist[(static_cast<size_t>(meta.parity) * kMaxPasses + pass) * kRadix + d];
   const uint32_t gstart = block_excl_scan(gtotal, s_tmp);
 
-  // Look back in chunks of eight predecessors (loads issued together).
+  // Look back in chunks of kChunk predecessors (loads issued together).
+  constexpr int kChunk = 16;
   uint32_t excl = 0;
   if (tile > 0) {
     int64_t j = static_cast<int64_t>(tile) - 1;
     for (;;) {
-      const int nchunk = j + 1 < 8 ? static_cast<int>(j + 1) : 8;
-      uint32_t w[8];
+      const int nchunk = j + 1 < kChunk ? static_cast<int>(j + 1) : kChunk;
+      uint32_t w[kChunk];
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
+      for (int k = 0; k < kChunk; ++k)
         w[k] = (k < nchunk) ? ld_dev(&st[static_cast<size_t>(j - k) * kRadix + d]) : 0u;
       int used = 0;
       bool done = false;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < kChunk; ++k) {
         if (k >= nchunk || done) break;
         const uint32_t f = w[k] & ~kCountMask;
         if (f == 0u) break;
@@ -580,43 +598,54 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* counts, uint3
 
 inline unsigned grid_for(uint64_t n, uint64_t per) { return static_cast<unsigned>((n + per - 1) / per); }
 
+template <typename Kernel, typename... Args>
+hipError_t launch(Kernel k, unsigned grid, unsigned block, hipStream_t s, const KTimer* t,
+                  Args... args) {
+  if (t != nullptr && t->start != nullptr)
+    hipExtLaunchKernelGGL(k, dim3(grid), dim3(block), 0, s, t->start, t->stop, 0, args...);
+  else
+    k<<<grid, block, 0, s>>>(args...);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers
-size_t sort_meta_words(uint32_t b, int passes) {
-  const uint32_t nh = grid_for(b, kHistTile) < 128u ? grid_for(b, kHistTile) : 128u;
-  const uint32_t ns = grid_for(b, kSortTile);
-  return static_cast<size_t>(nh) * passes * kRadix + static_cast<size_t>(passes) * ns * kRadix +
+size_t sort_meta_words(uint32_t b) {
+  const size_t ns = grid_for(b, kSortTile);
+  return static_cast<size_t>(2) * kMaxPasses * kRadix + static_cast<size_t>(kMaxPasses) * ns * kRadix +
          kMaxPasses + 1;
 }
 
-SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int passes) {
+SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
   SortMeta m;
-  m.num_hist_tiles = grid_for(b, kHistTile) < 128u ? grid_for(b, kHistTile) : 128u;
+  const uint32_t nh = grid_for(b, kHistTile);
+  m.num_hist_blocks = nh < static_cast<uint32_t>(kMaxHistBlocks) ? nh : kMaxHistBlocks;
   m.num_sort_tiles = grid_for(b, kSortTile);
-  m.hist_parts = base;
-  m.status = m.hist_parts + static_cast<size_t>(m.num_hist_tiles) * passes * kRadix;
-  m.tile_ctr = m.status + static_cast<size_t>(passes) * m.num_sort_tiles * kRadix;
+  m.hist = base;
+  m.status = m.hist + static_cast<size_t>(2) * kMaxPasses * kRadix;
+  m.tile_ctr = m.status + static_cast<size_t>(kMaxPasses) * m.num_sort_tiles * kRadix;
   m.err = m.tile_ctr + kMaxPasses;
+  m.parity = parity;
   return m;
 }
 
 hipError_t launch_sort(const BatchSrc& src, int lo_bit, int passes, uint32_t key_limit_bits,
                        int checked, const SortMeta& meta, uint32_t* tmp_kv[2],
                        uint32_t* tmp_val[2], uint32_t* out_kv, uint32_t* out_val,
-                       hipStream_t stream) {
-  k_sort_hist<<<meta.num_hist_tiles, kThreads, 0, stream>>>(src, lo_bit, passes, key_limit_bits,
-                                                            checked, meta);
-  hipError_t e = hipGetLastError();
+                       hipStream_t stream, const KTimer* timers) {
+  hipError_t e = launch(k_sort_hist, meta.num_hist_blocks, kThreads, stream,
+                        timers ? &timers[0] : nullptr, src, lo_bit, passes, key_limit_bits,
+                        checked, meta);
   if (e != hipSuccess) return e;
   const uint32_t* in_kv = nullptr;
   const uint32_t* in_val = nullptr;
   for (int p = 0; p < passes; ++p) {
     uint32_t* o_kv = (p == passes - 1) ? out_kv : tmp_kv[p & 1];
     uint32_t* o_val = (p == passes - 1) ? out_val : tmp_val[p & 1];
-    k_sort_pass<<<meta.num_sort_tiles, kThreads, 0, stream>>>(src, in_kv, in_val, o_kv, o_val, p,
-                                                              passes, lo_bit + kRadixBits * p, meta);
-    e = hipGetLastError();
+    e = launch(k_sort_pass, meta.num_sort_tiles, kThreads, stream,
+               timers ? &timers[1 + p] : nullptr, src, in_kv, in_val, o_kv, o_val, p, passes,
+               lo_bit + kRadixBits * p, meta);
     if (e != hipSuccess) return e;
     in_kv = o_kv;
     in_val = o_val;
@@ -626,46 +655,44 @@ hipError_t launch_sort(const BatchSrc& src, int lo_bit, int passes, uint32_t key
 
 hipError_t launch_merge(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na,
                         const uint32_t* b_kv, const uint32_t* b_val, uint32_t nb,
-                        uint32_t* out_kv, uint32_t* out_val, hipStream_t stream) {
+                        uint32_t* out_kv, uint32_t* out_val, hipStream_t stream,
+                        const KTimer* t) {
   const uint64_t total = static_cast<uint64_t>(na) + nb;
   if (total == 0) return hipSuccess;
-  k_merge<<<grid_for(total, kMergeTile), kThreads, 0, stream>>>(a_kv, a_val, na, b_kv, b_val, nb,
-                                                               out_kv, out_val);
-  return hipGetLastError();
+  return launch(k_merge, grid_for(total, kMergeTile), kThreads, stream, t, a_kv, a_val, na, b_kv,
+                b_val, nb, out_kv, out_val);
 }
 
 hipError_t launch_lookup(const LevelSet& lv, const uint32_t* q, uint32_t nq, uint32_t* out_val,
-                         uint8_t* out_found, hipStream_t stream) {
+                         uint8_t* out_found, hipStream_t stream, const KTimer* t) {
   if (nq == 0) return hipSuccess;
-  k_lookup<<<grid_for(nq, kQueryThreads), kQueryThreads, 0, stream>>>(lv, q, nq, out_val, out_found);
-  return hipGetLastError();
+  return launch(k_lookup, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, q, nq,
+                out_val, out_found);
 }
 
 hipError_t launch_count(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi, uint32_t nq,
                         uint32_t* counts, uint64_t* scan_status, size_t scan_words,
-                        hipStream_t stream) {
+                        hipStream_t stream, const KTimer* t) {
   if (nq == 0) return hipSuccess;
-  k_count<<<grid_for(nq, kQueryThreads), kQueryThreads, 0, stream>>>(lv, lo, hi, nq, counts,
-                                                                     scan_status, scan_words);
-  return hipGetLastError();
+  return launch(k_count, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi, nq,
+                counts, scan_status, static_cast<uint64_t>(scan_words));
 }
 
 size_t scan_status_words(uint32_t nq) { return 1 + grid_for(nq, kScanTile); }
 
 hipError_t launch_scan(const uint32_t* counts, uint32_t nq, uint64_t* offsets,
-                       uint64_t* scan_status, hipStream_t stream) {
+                       uint64_t* scan_status, hipStream_t stream, const KTimer* t) {
   if (nq == 0) return hipSuccess;
-  k_scan<<<grid_for(nq, kScanTile), kThreads, 0, stream>>>(counts, nq, offsets, scan_status);
-  return hipGetLastError();
+  return launch(k_scan, grid_for(nq, kScanTile), kThreads, stream, t, counts, nq, offsets,
+                scan_status);
 }
 
 hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi,
                              uint32_t nq, const uint64_t* offsets, uint32_t* out_keys,
-                             uint32_t* out_vals, hipStream_t stream) {
+                             uint32_t* out_vals, hipStream_t stream, const KTimer* t) {
   if (nq == 0) return hipSuccess;
-  k_range_emit<<<grid_for(nq, kQueryThreads), kQueryThreads, 0, stream>>>(lv, lo, hi, nq, offsets,
-                                                                          out_keys, out_vals);
-  return hipGetLastError();
+  return launch(k_range_emit, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi,
+                nq, offsets, out_keys, out_vals);
 }
 
 }  // namespace lsm

@@ -39,6 +39,19 @@ class Stats(ctypes.Structure):
         "sorted_elems_total", "device_bytes")]
 
 
+KERNEL_NAMES = ("k_sort_hist", "k_sort_pass", "k_merge", "k_lookup", "k_count", "k_scan",
+                "k_range_emit")
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("update_calls", ctypes.c_uint64), ("query_calls", ctypes.c_uint64 * 3),
+                ("query_items", ctypes.c_uint64 * 3), ("launches", ctypes.c_uint64 * 7),
+                ("elems", ctypes.c_uint64 * 7), ("kernel_ms", ctypes.c_double * 7),
+                ("kernel_bytes", ctypes.c_double * 7), ("update_ms", ctypes.c_double),
+                ("update_p50_ms", ctypes.c_double), ("update_p99_ms", ctypes.c_double),
+                ("update_max_ms", ctypes.c_double), ("query_ms", ctypes.c_double * 3)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _u32 = ctypes.c_uint32
@@ -54,6 +67,9 @@ _SIGNATURES = {
     "lsm_count": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp]),
     "lsm_range": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _u64, ctypes.POINTER(_u64)]),
     "lsm_destroy": (ctypes.c_int, [_vp]),
+    "lsm_clear": (ctypes.c_int, [_vp]),
+    "lsm_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lsm_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(Profile), ctypes.c_int]),
     "lsm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "lsm_num_batches": (_u64, [_vp]),
     "lsm_batch_size": (_u32, [_vp]),
@@ -140,6 +156,19 @@ class LSM:
 
     def __exit__(self, *exc):
         self.close()
+
+    def clear(self) -> None:
+        """Empty the dictionary, keeping its device memory."""
+        _check(self._lib.lsm_clear(self._h), "lsm_clear")
+
+    def profile(self, on: bool = True) -> None:
+        _check(self._lib.lsm_profile_enable(self._h, 1 if on else 0), "lsm_profile_enable")
+
+    def profile_read(self, reset: bool = True) -> Profile:
+        p = Profile()
+        _check(self._lib.lsm_profile_read(self._h, ctypes.byref(p), 1 if reset else 0),
+               "lsm_profile_read")
+        return p
 
     # -- updates ------------------------------------------------------------
     def insert(self, keys: torch.Tensor, vals: torch.Tensor) -> None:
