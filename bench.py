@@ -189,6 +189,7 @@ def main() -> int:
     step(ev)
     prof = g.profile_read(reset=True)
     g.profile(False)
+    g.sync()
     log("profiled step: %.1f ms" % ev[0].elapsed_time(ev[4]))
 
     K = args.steps

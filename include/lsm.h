@@ -167,6 +167,15 @@ LSM_API lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_
  */
 LSM_API lsm_status_t lsm_clear(lsm_t h);
 
+/*
+ * lsm_sync -- synchronise the handle's stream and report device-side
+ * faults: every wait inside the kernels is bounded, and a wait that ran out
+ * (which a correct run never does) is recorded on the device; lsm_sync then
+ * returns LSM_EHIP once and clears the record.  LSM_EHIP also for a failed
+ * synchronisation.
+ */
+LSM_API lsm_status_t lsm_sync(lsm_t h);
+
 /* lsm_destroy -- synchronise the stream and free every allocation. */
 LSM_API lsm_status_t lsm_destroy(lsm_t h);
 
@@ -219,10 +228,11 @@ LSM_API lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out);
  *
  * Kernel index k: 0 batch-sort histogram, 1 batch-sort digit pass, 2 level
  * merge, 3 lookup, 4 count, 5 range offset scan, 6 range emission.
- * kernel_bytes[k] is the algorithmic traffic of those launches: 4 B per
- * batch element for the histogram, 16 B per element for a digit pass (key
- * and value read and written), 16 B per merge output element, 12 B per
- * scanned count; 0 for the search kernels, which are latency-bound.
+ * kernel_bytes[k] is the algorithmic traffic of those launches: 8 B per
+ * batch element for the histogram (key and value read), 16 B per element
+ * for a digit pass (key and value read and written), 16 B per merge output
+ * element, 12 B per scanned count; 0 for the search kernels, which are
+ * latency-bound.
  */
 #define LSM_PROF_KERNELS 7
 typedef struct {

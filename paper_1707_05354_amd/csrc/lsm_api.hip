@@ -35,8 +35,9 @@ struct lsm_s {
   uint32_t* tmp_val[2] = {};
   uint32_t* buf_kv = nullptr;  // the sorted batch when it has to be merged
   uint32_t* buf_val = nullptr;
-  uint32_t* meta = nullptr;  // sort histograms, look-back words, counters
+  uint32_t* meta = nullptr;  // sort histograms, look-back words, barrier, error words
   int hist_parity = 0;       // which global histogram buffer the next sort uses
+  uint32_t* fault = nullptr; // sticky device fault word (inside meta)
 
   uint32_t* mrg_kv[2] = {};  // cascade ping-pong
   uint32_t* mrg_val[2] = {};
@@ -57,6 +58,7 @@ struct lsm_s {
     int kind;  // KernelKind for a kernel; 10 update call; 11..13 lookup/count/range call
     uint32_t a, b;
     uint64_t items;
+    double bytes;  // algorithmic bytes of a kernel launch
   };
   bool prof = false;
   std::vector<hipEvent_t> ev_pool, marks;
@@ -219,7 +221,7 @@ hipEvent_t pooled_event(lsm_t h) {
   return e;
 }
 
-const KTimer* timer(lsm_t h, Timed& slot, int kind, uint64_t items) {
+const KTimer* timer(lsm_t h, Timed& slot, int kind, uint64_t items, double bytes) {
   if (!h->prof) return nullptr;
   hipEvent_t a = pooled_event(h), b = pooled_event(h);
   if (a == nullptr || b == nullptr) {
@@ -233,7 +235,8 @@ const KTimer* timer(lsm_t h, Timed& slot, int kind, uint64_t items) {
   slot.b = static_cast<int64_t>(h->marks.size() - 1);
   slot.t.start = a;
   slot.t.stop = b;
-  h->spans.push_back({kind, static_cast<uint32_t>(slot.a), static_cast<uint32_t>(slot.b), items});
+  h->spans.push_back(
+      {kind, static_cast<uint32_t>(slot.a), static_cast<uint32_t>(slot.b), items, bytes});
   return &slot.t;
 }
 
@@ -241,7 +244,8 @@ const KTimer* timer(lsm_t h, Timed& slot, int kind, uint64_t items) {
 // of another.
 void call_span(lsm_t h, int kind, const Timed& first, const Timed& last, uint64_t items) {
   if (first.a >= 0 && last.b >= 0)
-    h->spans.push_back({kind, static_cast<uint32_t>(first.a), static_cast<uint32_t>(last.b), items});
+    h->spans.push_back(
+        {kind, static_cast<uint32_t>(first.a), static_cast<uint32_t>(last.b), items, 0.0});
 }
 
 void release_events(lsm_t h) {
@@ -277,49 +281,55 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
 
   const bool checked = (h->flags & LSM_CHECKED) != 0;
   const int lo_bit = (mode == kMixed) ? 0 : 1;
-  const int passes = sort_passes(h->key_bits, lo_bit);
-  SortMeta meta = sort_meta_carve(h->meta, h->b, h->hist_parity);
-  BatchSrc src{keys, vals, is_delete, n, h->b, static_cast<int>(mode)};
-  if (checked && hipMemsetAsync(meta.err, 0, sizeof(uint32_t), h->stream) != hipSuccess)
+  SortArgs sa;
+  sa.src = BatchSrc{keys, vals, is_delete, n, h->b, static_cast<int>(mode)};
+  sa.lo_bit = lo_bit;
+  sa.passes = sort_passes(h->key_bits, lo_bit);
+  sa.key_limit_bits = h->key_bits;
+  sa.checked = checked ? 1 : 0;
+  sa.meta = sort_meta_carve(h->meta, h->b, h->hist_parity);
+  sa.tmp_kv[0] = h->tmp_kv[0];
+  sa.tmp_kv[1] = h->tmp_kv[1];
+  sa.tmp_val[0] = h->tmp_val[0];
+  sa.tmp_val[1] = h->tmp_val[1];
+  sa.out_kv = (j == 0) ? h->lvl_kv[0] : h->buf_kv;
+  sa.out_val = (j == 0) ? h->lvl_val[0] : h->buf_val;
+  if (checked && hipMemsetAsync(sa.meta.err, 0, sizeof(uint32_t), h->stream) != hipSuccess)
     return LSM_EHIP;
 
-  uint32_t* sorted_kv = (j == 0) ? h->lvl_kv[0] : h->buf_kv;
-  uint32_t* sorted_val = (j == 0) ? h->lvl_val[0] : h->buf_val;
   Timed st[1 + kMaxPasses];
   KTimer sort_t[1 + kMaxPasses];
   bool timed = h->prof;
-  for (int p = 0; p <= passes && timed; ++p) {
-    const KTimer* t = timer(h, st[p], p == 0 ? kKSortHist : kKSortPass, h->b);
+  for (int p = 0; p <= sa.passes && timed; ++p) {
+    const KTimer* t = (p == 0) ? timer(h, st[p], kKSortHist, h->b, 8.0 * h->b)
+                               : timer(h, st[p], kKSortPass, h->b, 16.0 * h->b);
     if (t == nullptr) timed = false;
     else sort_t[p] = *t;
   }
-  const hipError_t se = launch_sort(src, lo_bit, passes, h->key_bits, checked ? 1 : 0, meta,
-                                    h->tmp_kv, h->tmp_val, sorted_kv, sorted_val, h->stream,
-                                    timed ? sort_t : nullptr);
+  const hipError_t se = launch_sort(sa, h->stream, timed ? sort_t : nullptr);
   h->hist_parity ^= 1;  // the histogram kernel cleared the other buffer for the next sort
   if (se != hipSuccess) return LSM_EHIP;
-  Timed last = st[passes];
+  Timed last = st[sa.passes];
 
   if (checked) {
-    if (hipMemcpyAsync(h->h_pinned, meta.err, sizeof(uint32_t), hipMemcpyDeviceToHost,
+    if (hipMemcpyAsync(h->h_pinned, sa.meta.err, sizeof(uint32_t), hipMemcpyDeviceToHost,
                        h->stream) != hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess)
       return LSM_EHIP;
     if (*reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u) return LSM_EKEY;
   }
 
-
   // while level i is full: buffer <- merge(buffer, level i)  (Fig. 2(a)).
   // The last merge writes straight into level j.
-  const uint32_t* cur_kv = sorted_kv;
-  const uint32_t* cur_val = sorted_val;
+  const uint32_t* cur_kv = sa.out_kv;
+  const uint32_t* cur_val = sa.out_val;
   uint64_t merged = 0;
   for (int i = 0; i < j; ++i) {
     uint32_t* o_kv = (i == j - 1) ? h->lvl_kv[j] : h->mrg_kv[i & 1];
     uint32_t* o_val = (i == j - 1) ? h->lvl_val[j] : h->mrg_val[i & 1];
     const uint32_t len = static_cast<uint32_t>(level_len(h, i));
     Timed mt;
-    const KTimer* t = timer(h, mt, kKMerge, 2ull * len);
+    const KTimer* t = timer(h, mt, kKMerge, 2ull * len, 16.0 * 2.0 * len);
     if (launch_merge(cur_kv, cur_val, len, h->lvl_kv[i], h->lvl_val[i], len, o_kv, o_val,
                      h->stream, t) != hipSuccess)
       return LSM_EHIP;
@@ -370,6 +380,7 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->buf_val = static_cast<uint32_t*>(p);
   if (s == LSM_OK && (s = dev_alloc(h, &p, sort_meta_words(b) * sizeof(uint32_t))) == LSM_OK) {
     h->meta = static_cast<uint32_t*>(p);
+    h->fault = sort_meta_carve(h->meta, b, 0).err + 1;
     // Both global histogram buffers start zeroed (each sort then clears
     // the buffer of the next one).
     if (hipMemset(h->meta, 0, sort_meta_words(b) * sizeof(uint32_t)) != hipSuccess) s = LSM_EHIP;
@@ -416,7 +427,7 @@ lsm_status_t lsm_lookup(lsm_t h, const uint32_t* d_keys, uint32_t nq, uint32_t* 
   if (!g.ok) return LSM_EHIP;
   const LevelSet lv = occupied_levels(h);
   Timed tl;
-  const KTimer* t = timer(h, tl, kKLookup, nq);
+  const KTimer* t = timer(h, tl, kKLookup, nq, 0.0);
   if (launch_lookup(lv, d_keys, nq, d_vals, d_found, h->stream, t) != hipSuccess) return LSM_EHIP;
   if (t != nullptr) call_span(h, 11, tl, tl, nq);
   return LSM_OK;
@@ -431,7 +442,7 @@ lsm_status_t lsm_count(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   if (!g.ok) return LSM_EHIP;
   const LevelSet lv = occupied_levels(h);
   Timed tc;
-  const KTimer* t = timer(h, tc, kKCount, nq);
+  const KTimer* t = timer(h, tc, kKCount, nq, 0.0);
   if (launch_count(lv, d_lo, d_hi, nq, d_counts, nullptr, 0, h->stream, t) != hipSuccess)
     return LSM_EHIP;
   if (t != nullptr) call_span(h, 12, tc, tc, nq);
@@ -457,11 +468,11 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   Timed t1, t2, t3;
   // Stage 1: per-query live counts (also clears the scan's look-back words).
   if (launch_count(lv, d_lo, d_hi, nq, h->q_counts, h->q_status, scan_status_words(nq),
-                   h->stream, timer(h, t1, kKCount, nq)) != hipSuccess)
+                   h->stream, timer(h, t1, kKCount, nq, 0.0)) != hipSuccess)
     return LSM_EHIP;
   // Stage 2: exclusive scan into the caller's offsets.
-  if (launch_scan(h->q_counts, nq, d_offsets, h->q_status, h->stream,
-                  timer(h, t2, kKScan, nq)) != hipSuccess)
+  if (launch_scan(h->q_counts, nq, d_offsets, h->q_status, h->fault, h->stream,
+                  timer(h, t2, kKScan, nq, 12.0 * nq)) != hipSuccess)
     return LSM_EHIP;
   if (hipMemcpyAsync(h->h_pinned, d_offsets + nq, sizeof(uint64_t), hipMemcpyDeviceToHost,
                      h->stream) != hipSuccess ||
@@ -473,11 +484,27 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   // Stage 3: each query writes its live pairs in key order at its offset.
   if (total > 0) {
     if (launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, d_keys, d_vals, h->stream,
-                          timer(h, t3, kKRangeEmit, nq)) != hipSuccess)
+                          timer(h, t3, kKRangeEmit, nq, 0.0)) != hipSuccess)
       return LSM_EHIP;
     call_span(h, 13, t1, t3, nq);
   } else {
     call_span(h, 13, t1, t2, nq);
+  }
+  return LSM_OK;
+}
+
+lsm_status_t lsm_sync(lsm_t h) {
+  if (h == nullptr) return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  if (hipMemcpyAsync(h->h_pinned, h->fault, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return LSM_EHIP;
+  if (*reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u) {
+    (void)hipMemsetAsync(h->fault, 0, sizeof(uint32_t), h->stream);
+    (void)hipStreamSynchronize(h->stream);
+    return LSM_EHIP;
   }
   return LSM_OK;
 }
@@ -500,8 +527,6 @@ lsm_status_t lsm_profile_read(lsm_t h, lsm_profile_t* out, int reset) {
   DeviceGuard g(h->device);
   if (!g.ok || hipStreamSynchronize(h->stream) != hipSuccess) return LSM_EHIP;
   lsm_profile_t& p = h->acc;
-  // Algorithmic bytes per processed element, by kernel kind.
-  static const double kBytesPerItem[kNumKernelKinds] = {4.0, 16.0, 16.0, 0.0, 0.0, 12.0, 0.0};
   for (const auto& sp : h->spans) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, h->marks[sp.a], h->marks[sp.b]) != hipSuccess) continue;
@@ -509,7 +534,7 @@ lsm_status_t lsm_profile_read(lsm_t h, lsm_profile_t* out, int reset) {
       p.launches[sp.kind] += 1;
       p.elems[sp.kind] += sp.items;
       p.kernel_ms[sp.kind] += ms;
-      p.kernel_bytes[sp.kind] += kBytesPerItem[sp.kind] * static_cast<double>(sp.items);
+      p.kernel_bytes[sp.kind] += sp.bytes;
     } else if (sp.kind == 10) {
       p.update_ms += ms;
       p.update_calls += 1;

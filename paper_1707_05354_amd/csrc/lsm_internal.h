@@ -19,15 +19,14 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kThreads * kSortItems;
 constexpr int kMaxPasses = 4;
-// Histogram kernel: tiles of kThreads * kHistItems elements, at most
-// kMaxHistBlocks work-groups (grid-stride beyond that).
-constexpr int kHistItems = 8;
-constexpr int kHistTile = kThreads * kHistItems;
+// The histogram kernel uses at most this many work-groups (tile-strided).
 constexpr int kMaxHistBlocks = 512;
 
 // Merge: tiles of kThreads * kMergeItems output elements.
 constexpr int kMergeItems = 8;
 constexpr int kMergeTile = kThreads * kMergeItems;
+// At most this many merge work-groups; each takes a contiguous run of tiles.
+constexpr int kMaxMergeBlocks = 1024;
 
 // Scan (range offsets): tiles of kThreads * kScanItems counts.
 constexpr int kScanItems = 8;
@@ -63,11 +62,24 @@ struct BatchSrc {
 struct SortMeta {
   uint32_t* hist;         // [2][kMaxPasses][256]
   uint32_t* status;       // [kMaxPasses][num_sort_tiles][256] look-back words
-  uint32_t* tile_ctr;     // [kMaxPasses] dynamic tile counters
-  uint32_t* err;          // [1] key-range violation flag (checked mode)
-  uint32_t num_hist_blocks;
+  uint32_t* tile_ctr;     // [kMaxPasses] dynamic tile ids of each pass
+  uint32_t* err;          // [0] key-range violation (checked mode),
+                          // [1] sticky device fault (a bounded wait expired)
   uint32_t num_sort_tiles;
   int parity;
+};
+
+struct SortArgs {
+  BatchSrc src;
+  int lo_bit;               // lowest key-variable bit sorted
+  int passes;               // 8-bit digit passes
+  uint32_t key_limit_bits;  // checked mode: keys must be < 2^key_limit_bits
+  int checked;
+  SortMeta meta;
+  uint32_t* tmp_kv[2];      // radix ping-pong, b elements each
+  uint32_t* tmp_val[2];
+  uint32_t* out_kv;         // sorted batch
+  uint32_t* out_val;
 };
 
 // Optional per-launch timing: when start is non-null the kernel is launched
@@ -88,12 +100,9 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity);
 
 // Sorts one batch into (out_kv, out_val): key variables ascending over bits
 // [lo_bit, lo_bit + 8 * passes), equal key variables with the later batch
-// position first.  tmp_* are two ping-pong buffers of b elements each.
-// timers (optional) holds 1 + passes entries: histogram, then each pass.
-hipError_t launch_sort(const BatchSrc& src, int lo_bit, int passes, uint32_t key_limit_bits,
-                       int checked, const SortMeta& meta, uint32_t* tmp_kv[2],
-                       uint32_t* tmp_val[2], uint32_t* out_kv, uint32_t* out_val,
-                       hipStream_t stream, const KTimer* timers);
+// position first.  timers (optional) holds 1 + passes entries: the
+// histogram kernel, then each digit pass.
+hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers);
 
 // Stable merge of a newer run (first on equal original keys) with an older
 // run into out (na + nb elements).
@@ -115,7 +124,8 @@ hipError_t launch_count(const LevelSet& lv, const uint32_t* lo, const uint32_t* 
 // Exclusive scan of nq uint32 counts into nq + 1 uint64 offsets.
 size_t scan_status_words(uint32_t nq);
 hipError_t launch_scan(const uint32_t* counts, uint32_t nq, uint64_t* offsets,
-                       uint64_t* scan_status, hipStream_t stream, const KTimer* t);
+                       uint64_t* scan_status, uint32_t* fault, hipStream_t stream,
+                       const KTimer* t);
 
 // Range emission pass: writes each query's live pairs at offsets[q].
 hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi,

@@ -5,10 +5,11 @@
 // merges are HBM/L2 streams, the searches are random-access.
 //
 //   k_sort_hist / k_sort_pass : stable LSD radix sort of one batch (the
-//       "sort the batch" step of sec. III-B / Fig. 2(a)).  The batch is read
-//       back to front, so among equal key variables the later batch
-//       position comes first (the last duplicate wins), and padded with
-//       copies of its last element (sec. IV-A).
+//       "sort the batch" step of sec. III-B / Fig. 2(a)): one histogram
+//       kernel, then one counting pass per 8-bit digit with decoupled
+//       look-back.  The batch is read back to front, so among equal key
+//       variables the later batch position comes first (the last duplicate
+//       wins), and padded with copies of its last element (sec. IV-A).
 //   k_merge : merge of a newer run with an older run on the original key,
 //       the newer element first on equal keys (sec. IV-A), merge-path
 //       partitioned with a 64-ary wave search.
@@ -117,6 +118,15 @@ constexpr uint32_t kFlagAgg = 1u << 30;  // tile aggregate published
 constexpr uint32_t kFlagInc = 2u << 30;  // inclusive prefix published
 constexpr uint32_t kCountMask = (1u << 30) - 1;
 
+// Every device-side wait is bounded: after kSpinLimit polls the waiter
+// records kFaultTimeout in the fault word and stops waiting; writes whose
+// position could then be wrong are skipped, so a broken protocol can give
+// wrong results (reported by lsm_sync) but never hangs or writes out of
+// bounds.  A correct run never reaches the limit: every tile a look-back
+// waits for has already started.
+constexpr uint32_t kSpinLimit = 1u << 24;
+constexpr uint32_t kFaultTimeout = 2u;
+
 // Element e of the batch as the sort sees it: read back to front and padded
 // with copies of the caller's last element, so e = 0 .. b-n-1 are padding
 // and e = b-n .. b-1 are the caller's elements n-1 .. 0.
@@ -133,100 +143,42 @@ __device__ __forceinline__ void batch_elem(const BatchSrc& s, uint32_t e, uint32
   val = st ? s.vals[src] : 0u;  // tombstones carry value 0
 }
 
-// Digit histograms of every pass in one read of the batch, accumulated into
-// hist[parity].  Also clears hist[parity ^ 1] (for the next sort) and the
-// look-back words and tile counters of the passes that follow.
-__global__ __launch_bounds__(kThreads) void k_sort_hist(BatchSrc src, int lo_bit, int passes,
-                                                        uint32_t key_limit_bits, int checked,
-                                                        SortMeta meta) {
-  __shared__ uint32_t s_h[kMaxPasses * kRadix];
-  const uint32_t tid = threadIdx.x;
-  const size_t gthreads = static_cast<size_t>(gridDim.x) * kThreads;
-  const size_t gid = static_cast<size_t>(blockIdx.x) * kThreads + tid;
-  const size_t nstatus = static_cast<size_t>(passes) * meta.num_sort_tiles * kRadix;
-  for (size_t i = gid; i < nstatus; i += gthreads) meta.status[i] = 0u;
-  uint32_t* other = meta.hist + static_cast<size_t>(meta.parity ^ 1) * kMaxPasses * kRadix;
-  for (size_t i = gid; i < static_cast<size_t>(kMaxPasses) * kRadix; i += gthreads) other[i] = 0u;
-  if (gid < static_cast<size_t>(kMaxPasses)) meta.tile_ctr[gid] = 0u;
-  for (uint32_t i = tid; i < static_cast<uint32_t>(kMaxPasses * kRadix); i += kThreads) s_h[i] = 0u;
-  __syncthreads();
+struct SortLds {
+  uint32_t kv[kSortTile];
+  uint32_t val[kSortTile];
+  uint32_t wcnt[kWaves][kRadix];
+  uint32_t local[kRadix];
+  uint32_t gbase[kRadix];
+  uint32_t gstart[kRadix];
+  uint32_t hist[kMaxPasses * kRadix];
+  uint32_t tmp[kWaves];
+  uint32_t abort;
+};
 
-  bool bad = false;
-  for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * kHistTile; base < src.b;
-       base += static_cast<uint64_t>(gridDim.x) * kHistTile) {
-    uint32_t kv[kHistItems], key[kHistItems];
-#pragma unroll
-    for (int i = 0; i < kHistItems; ++i) {  // all loads first, then count
-      const uint64_t e = base + static_cast<uint64_t>(i) * kThreads + tid;
-      uint32_t val;
-      kv[i] = 0u;
-      key[i] = 0u;
-      if (e < src.b) batch_elem(src, static_cast<uint32_t>(e), kv[i], val, key[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < kHistItems; ++i) {
-      const uint64_t e = base + static_cast<uint64_t>(i) * kThreads + tid;
-      if (e >= src.b) continue;
-      if (checked) bad |= (key[i] >> key_limit_bits) != 0u;
-      for (int p = 0; p < passes; ++p)
-        atomicAdd(&s_h[p * kRadix + ((kv[i] >> (lo_bit + kRadixBits * p)) & (kRadix - 1))], 1u);
-    }
-  }
-  __syncthreads();
-  uint32_t* mine = meta.hist + static_cast<size_t>(meta.parity) * kMaxPasses * kRadix;
-  for (uint32_t i = tid; i < static_cast<uint32_t>(passes * kRadix); i += kThreads)
-    if (s_h[i] != 0u) atomicAdd(&mine[i], s_h[i]);
-  if (checked && bad) atomicOr(meta.err, 1u);
+// Item i of lane l of wave w holds tile position w*64*I + i*64 + l, so
+// (item, lane) order is batch order.
+__device__ __forceinline__ uint32_t tile_pos(uint32_t wave, int i, uint32_t lane) {
+  return wave * 64 * kSortItems + static_cast<uint32_t>(i) * 64 + lane;
 }
 
-// One stable counting pass on the digit at bit `shift`.  Tiles take dynamic
-// ids in start order; each publishes its digit counts and looks back over
-// its predecessors for their prefix (every predecessor has started, so
-// every wait ends).  in_kv == nullptr means "read the caller's batch".
-__global__ __launch_bounds__(kThreads) void k_sort_pass(BatchSrc src, const uint32_t* in_kv,
-                                                        const uint32_t* in_val, uint32_t* out_kv,
-                                                        uint32_t* out_val, int pass, int passes,
-                                                        int shift, SortMeta meta) {
-  __shared__ uint32_t s_kv[kSortTile];
-  __shared__ uint32_t s_val[kSortTile];
-  __shared__ uint32_t s_wcnt[kWaves][kRadix];
-  __shared__ uint32_t s_local[kRadix];
-  __shared__ uint32_t s_gbase[kRadix];
-  __shared__ uint32_t s_tmp[kWaves];
-  __shared__ uint32_t s_tile;
-
+// One stable counting pass over one tile held in registers: wave64 match-any
+// ranking, publication of the tile's digit counts, decoupled look-back over
+// the tiles before it, and a scatter through LDS so consecutive threads
+// write consecutive output addresses.
+__device__ void sort_tile_pass(const uint32_t (&kv)[kSortItems], const uint32_t (&val)[kSortItems],
+                               uint32_t tile, uint32_t b, int shift, uint32_t* st,
+                               uint32_t* out_kv, uint32_t* out_val, bool coherent_out,
+                               uint32_t* fault, SortLds& L) {
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t b = src.b;
-  if (tid == 0) s_tile = atomicAdd(&meta.tile_ctr[pass], 1u);
-  for (uint32_t i = tid; i < kWaves * kRadix; i += kThreads) (&s_wcnt[0][0])[i] = 0u;
-  __syncthreads();
-  const uint32_t tile = s_tile;
   const uint32_t tbase = tile * kSortTile;
+  for (uint32_t i = tid; i < kWaves * kRadix; i += kThreads) (&L.wcnt[0][0])[i] = 0u;
+  if (tid == 0) L.abort = 0u;
+  __syncthreads();
 
-  // Wave w owns tile positions [w*64*I, (w+1)*64*I); item i of lane l sits
-  // at w*64*I + i*64 + l, so (item, lane) order is batch order.
-  uint32_t kv[kSortItems], val[kSortItems], off[kSortItems];
+  uint32_t off[kSortItems];
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
-    const uint32_t e = tbase + wave * 64 * kSortItems + i * 64 + lane;
-    kv[i] = 0u;
-    val[i] = 0u;
-    if (e < b) {
-      if (in_kv == nullptr) {
-        uint32_t key;
-        batch_elem(src, e, kv[i], val[i], key);
-      } else {
-        kv[i] = in_kv[e];
-        val[i] = in_val[e];
-      }
-    }
-  }
-  // Stable rank inside the wave: lanes holding the same digit find each
-  // other with eight ballots; the lowest such lane bumps the wave counter.
-#pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    const uint32_t e = tbase + wave * 64 * kSortItems + i * 64 + lane;
-    const bool valid = e < b;
+    const bool valid = tbase + tile_pos(wave, i, lane) < b;
     const uint32_t d = (kv[i] >> shift) & (kRadix - 1);
     uint64_t peers = ballot(valid);
 #pragma unroll
@@ -237,8 +189,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(BatchSrc src, const uint
     }
     const uint32_t r = count_below(peers);
     uint32_t prev = 0;
-    if (valid) prev = s_wcnt[wave][d];
-    if (valid && r == 0) s_wcnt[wave][d] = prev + static_cast<uint32_t>(__popcll(peers));
+    if (valid) prev = L.wcnt[wave][d];
+    if (valid && r == 0) L.wcnt[wave][d] = prev + static_cast<uint32_t>(__popcll(peers));
     off[i] = prev + r;
   }
   __syncthreads();
@@ -247,26 +199,20 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(BatchSrc src, const uint
   const uint32_t d = tid;
   uint32_t tile_count = 0;
   for (uint32_t w = 0; w < kWaves; ++w) {
-    const uint32_t c = s_wcnt[w][d];
-    s_wcnt[w][d] = tile_count;
+    const uint32_t c = L.wcnt[w][d];
+    L.wcnt[w][d] = tile_count;
     tile_count += c;
   }
-  uint32_t* st = meta.status + static_cast<size_t>(pass) * meta.num_sort_tiles * kRadix;
   if (tile == 0) st_dev(&st[d], kFlagInc | tile_count);
   else st_dev(&st[static_cast<size_t>(tile) * kRadix + d], kFlagAgg | tile_count);
-
-  const uint32_t local_start = block_excl_scan(tile_count, s_tmp);
-  s_local[d] = local_start;
-
-  const uint32_t gtotal =
-      meta.hist[(static_cast<size_t>(meta.parity) * kMaxPasses + pass) * kRadix + d];
-  const uint32_t gstart = block_excl_scan(gtotal, s_tmp);
+  L.local[d] = block_excl_scan(tile_count, L.tmp);
 
   // Look back in chunks of kChunk predecessors (loads issued together).
   constexpr int kChunk = 16;
   uint32_t excl = 0;
   if (tile > 0) {
     int64_t j = static_cast<int64_t>(tile) - 1;
+    uint32_t spins = 0;
     for (;;) {
       const int nchunk = j + 1 < kChunk ? static_cast<int>(j + 1) : kChunk;
       uint32_t w[kChunk];
@@ -286,34 +232,140 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(BatchSrc src, const uint
       }
       if (done) break;
       j -= used;
-      if (used == 0) __builtin_amdgcn_s_sleep(1);
+      if (used == 0) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins == kSpinLimit) {
+          atomicOr(fault, kFaultTimeout);
+          L.abort = 1u;
+          break;
+        }
+      }
     }
     st_dev(&st[static_cast<size_t>(tile) * kRadix + d], kFlagInc | (excl + tile_count));
   }
-  s_gbase[d] = gstart + excl;
+  L.gbase[d] = L.gstart[d] + excl;
   __syncthreads();
 
-  // Scatter into the tile's digit-sorted order in LDS, then write out with
-  // consecutive threads on consecutive output addresses.
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
-    const uint32_t e = tbase + wave * 64 * kSortItems + i * 64 + lane;
-    if (e < b) {
+    if (tbase + tile_pos(wave, i, lane) < b) {
       const uint32_t dd = (kv[i] >> shift) & (kRadix - 1);
-      const uint32_t pos = s_local[dd] + s_wcnt[wave][dd] + off[i];
-      s_kv[pos] = kv[i];
-      s_val[pos] = val[i];
+      const uint32_t pos = L.local[dd] + L.wcnt[wave][dd] + off[i];
+      L.kv[pos] = kv[i];
+      L.val[pos] = val[i];
     }
   }
   __syncthreads();
   const uint32_t tile_n = (b - tbase) < static_cast<uint32_t>(kSortTile) ? (b - tbase) : kSortTile;
-  for (uint32_t x = tid; x < tile_n; x += kThreads) {
-    const uint32_t k = s_kv[x];
-    const uint32_t dd = (k >> shift) & (kRadix - 1);
-    const uint32_t o = s_gbase[dd] + (x - s_local[dd]);
-    out_kv[o] = k;
-    out_val[o] = s_val[x];
+  if (L.abort == 0u) {
+    for (uint32_t x = tid; x < tile_n; x += kThreads) {
+      const uint32_t k = L.kv[x];
+      const uint32_t dd = (k >> shift) & (kRadix - 1);
+      const uint32_t o = L.gbase[dd] + (x - L.local[dd]);
+      if (o < b) {
+        if (coherent_out) {  // read by other work-groups after a grid barrier
+          st_dev(&out_kv[o], k);
+          st_dev(&out_val[o], L.val[x]);
+        } else {
+          out_kv[o] = k;
+          out_val[o] = L.val[x];
+        }
+      }
+    }
   }
+  __syncthreads();
+}
+
+// Digit histograms of every pass in one read of the batch, accumulated into
+// hist[parity] (LDS first, then one global atomic per non-zero bucket).
+// Also clears hist[parity ^ 1] for the next sort, and this sort's look-back
+// words and tile counters.
+__global__ __launch_bounds__(kThreads) void k_sort_hist(SortArgs a) {
+  __shared__ uint32_t s_h[kMaxPasses * kRadix];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const SortMeta& m = a.meta;
+  const uint32_t b = a.src.b;
+  const size_t gthreads = static_cast<size_t>(gridDim.x) * kThreads;
+  const size_t gid = static_cast<size_t>(blockIdx.x) * kThreads + tid;
+  const size_t nstatus = static_cast<size_t>(a.passes) * m.num_sort_tiles * kRadix;
+  for (size_t i = gid; i < nstatus; i += gthreads) m.status[i] = 0u;
+  uint32_t* other = m.hist + static_cast<size_t>(m.parity ^ 1) * kMaxPasses * kRadix;
+  for (size_t i = gid; i < static_cast<size_t>(kMaxPasses) * kRadix; i += gthreads) other[i] = 0u;
+  if (gid < static_cast<size_t>(kMaxPasses)) m.tile_ctr[gid] = 0u;
+  for (uint32_t i = tid; i < static_cast<uint32_t>(kMaxPasses * kRadix); i += kThreads) s_h[i] = 0u;
+  __syncthreads();
+
+  bool bad = false;
+  for (uint32_t t = blockIdx.x; t < m.num_sort_tiles; t += gridDim.x) {
+    const uint32_t tb = t * kSortTile;
+    uint32_t kv[kSortItems], key[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {  // all loads first, then count
+      const uint32_t e = tb + tile_pos(wave, i, lane);
+      uint32_t val;
+      kv[i] = 0u;
+      key[i] = 0u;
+      if (e < b) batch_elem(a.src, e, kv[i], val, key[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+      if (tb + tile_pos(wave, i, lane) >= b) continue;
+      if (a.checked) bad |= (key[i] >> a.key_limit_bits) != 0u;
+      for (int p = 0; p < a.passes; ++p)
+        atomicAdd(&s_h[p * kRadix + ((kv[i] >> (a.lo_bit + kRadixBits * p)) & (kRadix - 1))], 1u);
+    }
+  }
+  __syncthreads();
+  uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
+  for (uint32_t i = tid; i < static_cast<uint32_t>(a.passes * kRadix); i += kThreads)
+    if (s_h[i] != 0u) atomicAdd(&mine[i], s_h[i]);
+  if (a.checked && bad) atomicOr(&m.err[0], 1u);
+}
+
+// One stable counting pass of the batch sort on digit `pass`.  Tiles take
+// dynamic ids in start order (so every predecessor a tile waits for has
+// started); the tile a work-group most likely receives is loaded while the
+// id is in flight.
+__global__ __launch_bounds__(kThreads) void k_sort_pass(SortArgs a, int pass) {
+  __shared__ SortLds L;
+  __shared__ uint32_t s_tile;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const SortMeta& m = a.meta;
+  const uint32_t b = a.src.b;
+  if (tid == 0) s_tile = atomicAdd(&m.tile_ctr[pass], 1u);
+  const uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
+  const uint32_t gtotal = mine[static_cast<size_t>(pass) * kRadix + tid];
+  const uint32_t* in_kv = (pass == 0) ? nullptr : a.tmp_kv[(pass - 1) & 1];
+  const uint32_t* in_val = (pass == 0) ? nullptr : a.tmp_val[(pass - 1) & 1];
+  uint32_t* o_kv = (pass == a.passes - 1) ? a.out_kv : a.tmp_kv[pass & 1];
+  uint32_t* o_val = (pass == a.passes - 1) ? a.out_val : a.tmp_val[pass & 1];
+
+  uint32_t kv[kSortItems], val[kSortItems];
+  auto load_tile = [&](uint32_t t) {
+    const uint32_t tb = t * kSortTile;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+      const uint32_t e = tb + tile_pos(wave, i, lane);
+      kv[i] = 0u;
+      val[i] = 0u;
+      if (e < b) {
+        if (in_kv == nullptr) {
+          uint32_t key;
+          batch_elem(a.src, e, kv[i], val[i], key);
+        } else {
+          kv[i] = in_kv[e];
+          val[i] = in_val[e];
+        }
+      }
+    }
+  };
+  load_tile(blockIdx.x);
+  L.gstart[tid] = block_excl_scan(gtotal, L.tmp);  // contains the barrier publishing s_tile
+  const uint32_t tile = s_tile;
+  if (tile != blockIdx.x) load_tile(tile);
+  uint32_t* st = m.status + static_cast<size_t>(pass) * m.num_sort_tiles * kRadix;
+  sort_tile_pass(kv, val, tile, b, a.lo_bit + kRadixBits * pass, st, o_kv, o_val, false,
+                 &m.err[1], L);
 }
 
 // ------------------------------------------------------------ merge
@@ -353,75 +405,97 @@ __device__ uint32_t wave_merge_path(const uint32_t* a, uint32_t na, const uint32
   return static_cast<uint32_t>(lo);
 }
 
+// Merge-path position of diagonal dt inside two LDS windows A = s[0, wa)
+// and B = s[off, off + wb): the number of A elements among the first dt
+// outputs, A first on equal original keys.
+__device__ __forceinline__ uint32_t lds_merge_path(const uint32_t* s, uint32_t wa, uint32_t off,
+                                                   uint32_t wb, uint32_t dt) {
+  uint32_t lo = dt > wb ? dt - wb : 0, hi = dt < wa ? dt : wa;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if ((s[mid] >> 1) <= (s[off + dt - 1 - mid] >> 1)) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Each work-group merges a contiguous run of `tiles_per_wg` output tiles of
+// kMergeTile elements.  Only the first tile's split is searched in global
+// memory (64-ary wave search); every later split is found inside LDS
+// windows holding the next kMergeTile elements of each input, which are the
+// elements the tile is about to consume anyway.
 __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const uint32_t* a_val,
                                                     uint32_t na, const uint32_t* b_kv,
                                                     const uint32_t* b_val, uint32_t nb,
-                                                    uint32_t* out_kv, uint32_t* out_val) {
-  __shared__ uint32_t s_kv[kMergeTile];
-  __shared__ uint32_t s_val[kMergeTile];
-  __shared__ uint32_t s_split[2];
+                                                    uint32_t* out_kv, uint32_t* out_val,
+                                                    uint32_t tiles_per_wg) {
+  __shared__ uint32_t s_kv[2 * kMergeTile];
+  __shared__ uint32_t s_val[2 * kMergeTile];
+  __shared__ uint32_t s_split;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t total = static_cast<uint64_t>(na) + nb;
-  const uint64_t d0 = static_cast<uint64_t>(blockIdx.x) * kMergeTile;
-  const uint64_t d1 = (d0 + kMergeTile < total) ? d0 + kMergeTile : total;
+  const uint64_t tiles = (total + kMergeTile - 1) / kMergeTile;
+  uint64_t t = static_cast<uint64_t>(blockIdx.x) * tiles_per_wg;
+  const uint64_t t_end = (t + tiles_per_wg < tiles) ? t + tiles_per_wg : tiles;
+  if (t >= t_end) return;
   if (wave == 0) {
-    const uint32_t s = wave_merge_path(a_kv, na, b_kv, nb, d0);
-    if (lane == 0) s_split[0] = s;
-  } else if (wave == 1) {
-    const uint32_t s = wave_merge_path(a_kv, na, b_kv, nb, d1);
-    if (lane == 0) s_split[1] = s;
+    const uint32_t sp = wave_merge_path(a_kv, na, b_kv, nb, t * kMergeTile);
+    if (lane == 0) s_split = sp;
   }
   __syncthreads();
-  const uint32_t a0 = s_split[0], a1 = s_split[1];
-  const uint32_t b0 = static_cast<uint32_t>(d0 - a0), b1 = static_cast<uint32_t>(d1 - a1);
-  const uint32_t la = a1 - a0, lb = b1 - b0, n = la + lb;
-  for (uint32_t x = tid; x < la; x += kThreads) {
-    s_kv[x] = a_kv[a0 + x];
-    s_val[x] = a_val[a0 + x];
-  }
-  for (uint32_t x = tid; x < lb; x += kThreads) {
-    s_kv[la + x] = b_kv[b0 + x];
-    s_val[la + x] = b_val[b0 + x];
-  }
-  __syncthreads();
-
-  // This thread's outputs: tile positions [dt, dt + kMergeItems).
-  const uint32_t dt = (tid * kMergeItems < n) ? tid * kMergeItems : n;
-  uint32_t lo = dt > lb ? dt - lb : 0, hi = dt < la ? dt : la;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if ((s_kv[mid] >> 1) <= (s_kv[la + dt - 1 - mid] >> 1)) lo = mid + 1;
-    else hi = mid;
-  }
-  uint32_t ia = lo, ib = dt - lo;
-  uint32_t rk[kMergeItems], rv[kMergeItems];
-#pragma unroll
-  for (int k = 0; k < kMergeItems; ++k) {
-    rk[k] = 0u;
-    rv[k] = 0u;
-    if (dt + k < n) {
-      bool take_a;
-      if (ia < la && ib < lb) take_a = (s_kv[ia] >> 1) <= (s_kv[la + ib] >> 1);
-      else take_a = ia < la;
-      const uint32_t s = take_a ? ia : la + ib;
-      rk[k] = s_kv[s];
-      rv[k] = s_val[s];
-      ia += take_a ? 1u : 0u;
-      ib += take_a ? 0u : 1u;
+  uint32_t a0 = s_split;
+  uint32_t b0 = static_cast<uint32_t>(t * kMergeTile - a0);
+  for (; t < t_end; ++t) {
+    const uint64_t d = t * kMergeTile;
+    const uint32_t n = static_cast<uint32_t>((total - d) < kMergeTile ? (total - d) : kMergeTile);
+    const uint32_t wa = (na - a0) < n ? (na - a0) : n;
+    const uint32_t wb = (nb - b0) < n ? (nb - b0) : n;
+    for (uint32_t x = tid; x < wa; x += kThreads) {
+      s_kv[x] = a_kv[a0 + x];
+      s_val[x] = a_val[a0 + x];
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kMergeItems; ++k) {
-    if (dt + k < n) {
-      s_kv[dt + k] = rk[k];
-      s_val[dt + k] = rv[k];
+    for (uint32_t x = tid; x < wb; x += kThreads) {
+      s_kv[kMergeTile + x] = b_kv[b0 + x];
+      s_val[kMergeTile + x] = b_val[b0 + x];
     }
-  }
-  __syncthreads();
-  for (uint32_t x = tid; x < n; x += kThreads) {
-    out_kv[d0 + x] = s_kv[x];
-    out_val[d0 + x] = s_val[x];
+    __syncthreads();
+    const uint32_t dt = (tid * kMergeItems < n) ? tid * kMergeItems : n;
+    uint32_t ia = lds_merge_path(s_kv, wa, kMergeTile, wb, dt);
+    uint32_t ib = dt - ia;
+    uint32_t rk[kMergeItems], rv[kMergeItems];
+#pragma unroll
+    for (int k = 0; k < kMergeItems; ++k) {
+      rk[k] = 0u;
+      rv[k] = 0u;
+      if (dt + k < n) {
+        bool take_a;
+        if (ia < wa && ib < wb) take_a = (s_kv[ia] >> 1) <= (s_kv[kMergeTile + ib] >> 1);
+        else take_a = ia < wa;
+        const uint32_t src = take_a ? ia : kMergeTile + ib;
+        rk[k] = s_kv[src];
+        rv[k] = s_val[src];
+        ia += take_a ? 1u : 0u;
+        ib += take_a ? 0u : 1u;
+      }
+    }
+    if (tid == kThreads - 1) s_split = lds_merge_path(s_kv, wa, kMergeTile, wb, n);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kMergeItems; ++k) {
+      if (dt + k < n) {
+        s_kv[dt + k] = rk[k];
+        s_val[dt + k] = rv[k];
+      }
+    }
+    __syncthreads();
+    for (uint32_t x = tid; x < n; x += kThreads) {
+      out_kv[d + x] = s_kv[x];
+      out_val[d + x] = s_val[x];
+    }
+    const uint32_t la = s_split;
+    a0 += la;
+    b0 += n - la;
+    __syncthreads();
   }
 }
 
@@ -461,7 +535,8 @@ constexpr uint32_t kNoKey = 0xFFFFFFFFu;  // above every original key (< 2^31)
 // starts with its newest element); it counts when it is a regular element.
 template <bool kEmit>
 __device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, uint32_t k2,
-                                               uint32_t* out_keys, uint32_t* out_vals) {
+                                               uint32_t* out_keys, uint32_t* out_vals,
+                                               uint64_t limit) {
   if (k1 > k2) return 0u;
   uint32_t cur[kMaxLevels], end[kMaxLevels], ck[kMaxLevels];
   const int L = lv.count;
@@ -485,7 +560,7 @@ __device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, 
     if (mi < 0) break;
     const uint32_t x = lv.kv[mi][cur[mi]];
     if (x & 1u) {
-      if (kEmit) {
+      if (kEmit && count < limit) {
         out_keys[count] = mk;
         out_vals[count] = lv.val[mi][cur[mi]];
       }
@@ -511,7 +586,7 @@ __global__ __launch_bounds__(kQueryThreads) void k_count(LevelSet lv, const uint
       scan_status[w] = 0ull;
   }
   if (gi >= nq) return;
-  counts[gi] = range_walk<false>(lv, lo[gi], hi[gi], nullptr, nullptr);
+  counts[gi] = range_walk<false>(lv, lo[gi], hi[gi], nullptr, nullptr, 0);
 }
 
 __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const uint32_t* lo,
@@ -522,7 +597,12 @@ __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const
   const uint32_t i = blockIdx.x * kQueryThreads + threadIdx.x;
   if (i >= nq) return;
   const uint64_t o = offsets[i];
-  range_walk<true>(lv, lo[i], hi[i], out_keys + o, out_vals + o);
+  // The walk writes exactly offsets[i+1] - offsets[i] pairs (the same walk
+  // produced the count); the limits only guard against offsets corrupted by
+  // a timed-out scan.
+  const uint64_t e = offsets[i + 1];
+  if (e < o || e > offsets[nq]) return;
+  range_walk<true>(lv, lo[i], hi[i], out_keys + o, out_vals + o, e - o);
 }
 
 // ------------------------------------------------------------ scan
@@ -533,7 +613,8 @@ constexpr uint64_t kSumMask64 = (1ull << 62) - 1;
 // status[0] is the dynamic tile counter, status[1 + t] tile t's look-back
 // word; all cleared beforehand by k_count.
 __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* counts, uint32_t nq,
-                                                   uint64_t* offsets, uint64_t* status) {
+                                                   uint64_t* offsets, uint64_t* status,
+                                                   uint32_t* fault) {
   __shared__ uint64_t s_w[kWaves];
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_prefix;
@@ -566,6 +647,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* counts, uint3
     } else {
       if (lane == 0) st_dev64(&status[1 + tile], kFlagAgg64 | tile_total);
       int64_t j = static_cast<int64_t>(tile) - 1;
+      uint32_t spins = 0;
       for (;;) {
         const int64_t idx = j - static_cast<int64_t>(lane);
         const uint64_t w = idx >= 0 ? ld_dev64(&status[1 + idx]) : kFlagInc64;
@@ -579,7 +661,13 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* counts, uint3
         }
         excl += wave_sum64(lane < first_nr ? (w & kSumMask64) : 0ull);
         j -= first_nr;
-        if (first_nr == 0) __builtin_amdgcn_s_sleep(1);
+        if (first_nr == 0) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins == kSpinLimit) {
+            if (lane == 0) atomicOr(fault, kFaultTimeout);
+            break;
+          }
+        }
       }
       if (lane == 0) st_dev64(&status[1 + tile], kFlagInc64 | (excl + tile_total));
     }
@@ -614,13 +702,11 @@ hipError_t launch(Kernel k, unsigned grid, unsigned block, hipStream_t s, const 
 size_t sort_meta_words(uint32_t b) {
   const size_t ns = grid_for(b, kSortTile);
   return static_cast<size_t>(2) * kMaxPasses * kRadix + static_cast<size_t>(kMaxPasses) * ns * kRadix +
-         kMaxPasses + 1;
+         kMaxPasses + 2;
 }
 
 SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
   SortMeta m;
-  const uint32_t nh = grid_for(b, kHistTile);
-  m.num_hist_blocks = nh < static_cast<uint32_t>(kMaxHistBlocks) ? nh : kMaxHistBlocks;
   m.num_sort_tiles = grid_for(b, kSortTile);
   m.hist = base;
   m.status = m.hist + static_cast<size_t>(2) * kMaxPasses * kRadix;
@@ -630,25 +716,14 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
   return m;
 }
 
-hipError_t launch_sort(const BatchSrc& src, int lo_bit, int passes, uint32_t key_limit_bits,
-                       int checked, const SortMeta& meta, uint32_t* tmp_kv[2],
-                       uint32_t* tmp_val[2], uint32_t* out_kv, uint32_t* out_val,
-                       hipStream_t stream, const KTimer* timers) {
-  hipError_t e = launch(k_sort_hist, meta.num_hist_blocks, kThreads, stream,
-                        timers ? &timers[0] : nullptr, src, lo_bit, passes, key_limit_bits,
-                        checked, meta);
+hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers) {
+  const uint32_t tiles = a.meta.num_sort_tiles;
+  const uint32_t hist_grid = tiles < static_cast<uint32_t>(kMaxHistBlocks) ? tiles : kMaxHistBlocks;
+  hipError_t e = launch(k_sort_hist, hist_grid, kThreads, stream, timers ? &timers[0] : nullptr, a);
   if (e != hipSuccess) return e;
-  const uint32_t* in_kv = nullptr;
-  const uint32_t* in_val = nullptr;
-  for (int p = 0; p < passes; ++p) {
-    uint32_t* o_kv = (p == passes - 1) ? out_kv : tmp_kv[p & 1];
-    uint32_t* o_val = (p == passes - 1) ? out_val : tmp_val[p & 1];
-    e = launch(k_sort_pass, meta.num_sort_tiles, kThreads, stream,
-               timers ? &timers[1 + p] : nullptr, src, in_kv, in_val, o_kv, o_val, p, passes,
-               lo_bit + kRadixBits * p, meta);
+  for (int p = 0; p < a.passes; ++p) {
+    e = launch(k_sort_pass, tiles, kThreads, stream, timers ? &timers[1 + p] : nullptr, a, p);
     if (e != hipSuccess) return e;
-    in_kv = o_kv;
-    in_val = o_val;
   }
   return hipSuccess;
 }
@@ -659,8 +734,10 @@ hipError_t launch_merge(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na
                         const KTimer* t) {
   const uint64_t total = static_cast<uint64_t>(na) + nb;
   if (total == 0) return hipSuccess;
-  return launch(k_merge, grid_for(total, kMergeTile), kThreads, stream, t, a_kv, a_val, na, b_kv,
-                b_val, nb, out_kv, out_val);
+  const uint64_t tiles = (total + kMergeTile - 1) / kMergeTile;
+  const uint32_t per = static_cast<uint32_t>((tiles + kMaxMergeBlocks - 1) / kMaxMergeBlocks);
+  return launch(k_merge, grid_for(tiles, per), kThreads, stream, t, a_kv, a_val, na, b_kv, b_val,
+                nb, out_kv, out_val, per);
 }
 
 hipError_t launch_lookup(const LevelSet& lv, const uint32_t* q, uint32_t nq, uint32_t* out_val,
@@ -681,10 +758,11 @@ hipError_t launch_count(const LevelSet& lv, const uint32_t* lo, const uint32_t* 
 size_t scan_status_words(uint32_t nq) { return 1 + grid_for(nq, kScanTile); }
 
 hipError_t launch_scan(const uint32_t* counts, uint32_t nq, uint64_t* offsets,
-                       uint64_t* scan_status, hipStream_t stream, const KTimer* t) {
+                       uint64_t* scan_status, uint32_t* fault, hipStream_t stream,
+                       const KTimer* t) {
   if (nq == 0) return hipSuccess;
   return launch(k_scan, grid_for(nq, kScanTile), kThreads, stream, t, counts, nq, offsets,
-                scan_status);
+                scan_status, fault);
 }
 
 hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi,

@@ -41,13 +41,14 @@ class Stats(ctypes.Structure):
 
 KERNEL_NAMES = ("k_sort_hist", "k_sort_pass", "k_merge", "k_lookup", "k_count", "k_scan",
                 "k_range_emit")
+_NK = len(KERNEL_NAMES)
 
 
 class Profile(ctypes.Structure):
     _fields_ = [("update_calls", ctypes.c_uint64), ("query_calls", ctypes.c_uint64 * 3),
-                ("query_items", ctypes.c_uint64 * 3), ("launches", ctypes.c_uint64 * 7),
-                ("elems", ctypes.c_uint64 * 7), ("kernel_ms", ctypes.c_double * 7),
-                ("kernel_bytes", ctypes.c_double * 7), ("update_ms", ctypes.c_double),
+                ("query_items", ctypes.c_uint64 * 3), ("launches", ctypes.c_uint64 * _NK),
+                ("elems", ctypes.c_uint64 * _NK), ("kernel_ms", ctypes.c_double * _NK),
+                ("kernel_bytes", ctypes.c_double * _NK), ("update_ms", ctypes.c_double),
                 ("update_p50_ms", ctypes.c_double), ("update_p99_ms", ctypes.c_double),
                 ("update_max_ms", ctypes.c_double), ("query_ms", ctypes.c_double * 3)]
 
@@ -68,6 +69,7 @@ _SIGNATURES = {
     "lsm_range": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _u64, ctypes.POINTER(_u64)]),
     "lsm_destroy": (ctypes.c_int, [_vp]),
     "lsm_clear": (ctypes.c_int, [_vp]),
+    "lsm_sync": (ctypes.c_int, [_vp]),
     "lsm_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lsm_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(Profile), ctypes.c_int]),
     "lsm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -156,6 +158,10 @@ class LSM:
 
     def __exit__(self, *exc):
         self.close()
+
+    def sync(self) -> None:
+        """Wait for the handle's stream; raises if a device-side wait ran out."""
+        _check(self._lib.lsm_sync(self._h), "lsm_sync")
 
     def clear(self) -> None:
         """Empty the dictionary, keeping its device memory."""

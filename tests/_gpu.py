@@ -60,6 +60,7 @@ class Trio:
         self.c.insert(keys, vals, (1 - np.asarray(is_delete, np.uint8)).astype(np.uint8))
 
     def check_levels(self):
+        self.g.sync()
         torch.cuda.synchronize()
         assert self.g.num_batches == self.c.r
         assert self.g.occupied() == self.c.occupied()

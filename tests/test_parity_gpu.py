@@ -235,3 +235,20 @@ def test_range_two_phase_capacity():
     assert t.g.range_raw(lo, hi, off, k, v, int(want_off[-1])) == int(want_off[-1])
     torch.cuda.synchronize()
     assert np.array_equal(host(k), want_k) and np.array_equal(host(v), want_v)
+
+
+def test_merges_with_several_tiles_per_workgroup():
+    """b = 2^20 + 5: merges of 2^21 + 10 and 2^22 + 20 outputs need more
+    tiles than work-groups, so each work-group walks a run of tiles (ragged
+    last run), and one key is hot enough to span many tiles."""
+    b = (1 << 20) + 5
+    rng = np.random.default_rng(20)
+    note("b=2^20+5 multi-tile merges")
+    t = Trio(b)
+    for r in range(4):
+        k = rng.integers(0, 1 << 30, b).astype(np.uint32)
+        k[rng.random(b) < 0.05] = 12345
+        t.insert(k, rng.integers(0, 2**32, b, dtype=np.uint64).astype(np.uint32))
+        t.check_levels()
+    q = np.concatenate([np.array([12345], np.uint32), rng.integers(0, 1 << 30, 5000).astype(np.uint32)])
+    t.check_queries(q, q[:2000], q[:2000] + 200000)
