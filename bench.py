@@ -69,6 +69,53 @@ def cpu_baseline(w, budget_s: float = 15.0):
     }
 
 
+def zipf_sweep(torch, L, W, reps: int = 2):
+    """Batch-size sweep at n = 2^25 slots: b in {2^13, 2^15, 2^17, 2^19}, Zipf(1.1)
+    keys over [0, 2^24) (24-bit sort), 20% delete batches, then 2^22 Zipf
+    lookups.  Best of `reps` builds per point."""
+    res = []
+    for lb in (13, 15, 17, 19):
+        b = 1 << lb
+        t0 = time.perf_counter()
+        w = W.zipf_sweep(b)
+        log("sweep b=2^%d: workload ready in %.1f s" % (lb, time.perf_counter() - t0))
+        kd = torch.from_numpy(w.keys.view(np.int32)).cuda()
+        vd = torch.from_numpy(w.vals.view(np.int32)).cuda()
+        qd = torch.from_numpy(w.lookups.view(np.int32)).cuda()
+        lv = torch.empty(qd.numel(), dtype=torch.int32, device="cuda")
+        lf = torch.empty(qd.numel(), dtype=torch.uint8, device="cuda")
+        g = L.LSM(b, key_bits=24)
+        lib, h = g._lib, g._h
+        rows_k = [kd[i].data_ptr() for i in range(w.R)]
+        rows_v = [vd[i].data_ptr() for i in range(w.R)]
+        best_u, best_l = None, None
+        for _ in range(reps):
+            g.clear()
+            torch.cuda.synchronize()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record()
+            for i in range(w.R):
+                rc = (lib.lsm_delete_batch(h, rows_k[i], b) if w.is_delete[i]
+                      else lib.lsm_insert_batch(h, rows_k[i], rows_v[i], b))
+                if rc:
+                    raise L.LSMError(rc, "sweep update")
+            e[1].record()
+            g.lookup(qd, out=(lv, lf))
+            e[2].record()
+            torch.cuda.synchronize()
+            u, l = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+            best_u = u if best_u is None else min(best_u, u)
+            best_l = l if best_l is None else min(best_l, l)
+        g.sync()
+        res.append({"b": b, "batches": w.R, "levels": g.occupied(),
+                    "M_updates_per_s": round(w.R * b / (best_u * 1e-3) / 1e6, 2),
+                    "M_lookups_per_s": round(qd.numel() / (best_l * 1e-3) / 1e6, 2),
+                    "lookup_hit_rate": round(float(lf.float().mean().item()), 4)})
+        log("sweep b=2^%d: %s" % (lb, res[-1]))
+        g.close()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +123,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batches", type=int, default=1024, help="update batches per step")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the Zipf batch-size sweep (b = 2^13..2^19 at n = 2^25)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 4 times (PMC byte calibration)")
     args = ap.parse_args()
@@ -268,10 +317,12 @@ def main() -> int:
         "context": "paper (K40c): 98.0 M updates/s mean at b=2^16 over r=1..2048 (n=2^27); "
                    "lookups 54.9 M/s (all present) at b=2^16, n=2^24",
     }
+    g.close()
+    if not args.no_sweep:
+        out["sweep"] = zipf_sweep(torch, L, W)
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w)
-    g.close()
     print(json.dumps(out), flush=True)
     return 0
 

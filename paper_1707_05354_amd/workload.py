@@ -162,3 +162,70 @@ def random_small(seed: int, b: int, R: int, domain: int, p_delete: float = 0.3,
     a = (splitmix64(seed, 5, 0, nq) % np.uint64(domain + 2)).astype(np.uint32)
     c = (splitmix64(seed, 6, 0, nq) % np.uint64(domain + 2)).astype(np.uint32)
     return ops, q, np.minimum(a, c), np.maximum(a, c)
+
+
+# ---------------------------------------------------------------- Zipf sweep
+ZIPF_S = 1.1
+ZIPF_BITS = 24
+
+
+def zipf_ranks(config: int, stream: int, start: int, n: int, s: float = ZIPF_S,
+               bits: int = ZIPF_BITS, _cache={}) -> np.ndarray:
+    """Ranks 1..2^bits drawn from the bounded Zipf law P(k) ~ k^-s by
+    inverting its cumulative distribution (numpy float64 cumulative sum,
+    deterministic for a given numpy)."""
+    key = (s, bits)
+    if key not in _cache:
+        w = np.arange(1, (1 << bits) + 1, dtype=np.float64) ** (-s)
+        cdf = np.cumsum(w)
+        cdf /= cdf[-1]
+        _cache.clear()
+        _cache[key] = cdf
+    cdf = _cache[key]
+    u = (splitmix64(config, stream, start, n) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    r = np.searchsorted(cdf, u, side="right") + 1
+    return np.minimum(r, 1 << bits).astype(np.int64)
+
+
+def zipf_keys(config: int, stream: int, start: int, n: int, bits: int = ZIPF_BITS) -> np.ndarray:
+    """Zipf ranks mapped to keys in [0, 2^bits) by a seeded bijection
+    (multiply by an odd constant, then XOR a seeded mask), so hot keys are
+    spread over the key space."""
+    mask_bits = (1 << bits) - 1
+    r = zipf_ranks(config, stream, start, n, bits=bits) - 1
+    odd = 0x9E3779B1 & mask_bits | 1
+    xmask = int(splitmix64(config, 15, 0, 1)[0]) & mask_bits
+    return (((r * odd) & mask_bits) ^ xmask).astype(np.uint32)
+
+
+_ZIPF_STREAM = {}
+
+
+def _zipf_stream(config: int, n_total: int, nq: int):
+    """Keys, values and lookups shared by every sweep point (cached)."""
+    k = (config, n_total, nq)
+    if k not in _ZIPF_STREAM:
+        _ZIPF_STREAM.clear()
+        _ZIPF_STREAM[k] = (zipf_keys(config, 1, 0, n_total), values(config, 2, 0, n_total),
+                           zipf_keys(config, 4, 0, nq))
+    return _ZIPF_STREAM[k]
+
+
+def zipf_sweep(b: int, config: int = 3, n_total: int = 1 << 25, nq: int = 1 << 22) -> PlainWorkload:
+    """Batch-size sweep point: n_total slots in batches of b, keys Zipf(1.1)
+    over [0, 2^24) from one shared stream (every sweep point sees the same key
+    sequence, cut into batches of its own b), batch i deletes iff
+    i mod 5 == 4 (its keys drawn from the same law), then nq Zipf lookups and
+    2^16 count / range queries of width 2^8 over the 2^24 key space."""
+    R = n_total // b
+    keys, vals, lookups = _zipf_stream(config, n_total, nq)
+    keys = keys[:R * b].reshape(R, b)
+    vals = vals[:R * b].reshape(R, b)
+    is_delete = (np.arange(R) % 5) == 4
+    nc = 1 << 16
+    width = 1 << 8
+    starts = bounded(config, 5, 0, 2 * nc, (1 << ZIPF_BITS) - width + 1).astype(np.uint32)
+    c_lo, r_lo = starts[:nc], starts[nc:]
+    return PlainWorkload("zipf sweep b=%d R=%d n=%d" % (b, R, R * b), b, keys, vals, is_delete,
+                         lookups, c_lo, c_lo + np.uint32(width - 1), r_lo,
+                         r_lo + np.uint32(width - 1), width, key_bits=ZIPF_BITS)
