@@ -65,6 +65,7 @@ def _load():
             "oc_create": (vp, [ctypes.c_uint32]),
             "oc_destroy": (None, [vp]),
             "oc_insert": (ctypes.c_int, [vp, _u32p, _u32p, _u8p, ctypes.c_uint32]),
+            "oc_insert_ordered": (ctypes.c_int, [vp, _u32p, _u32p, _u8p, ctypes.c_uint32]),
             "oc_num_batches": (ctypes.c_uint64, [vp]),
             "oc_merged_last": (ctypes.c_uint64, [vp]),
             "oc_merged_total": (ctypes.c_uint64, [vp]),
@@ -182,6 +183,15 @@ class CascadeOracle:
     def delete(self, keys) -> None:
         k = _u32(keys)
         self.insert(k, None, np.zeros(k.size, np.uint8))
+
+    def insert_ordered(self, keys, vals, status) -> None:
+        """A coalesced batch of 1..b elements: user batches packed in arrival
+        order; the newest operation on a key wins whatever its type."""
+        k, v = _u32(keys), _u32(vals)
+        s = np.ascontiguousarray(status, dtype=np.uint8)
+        rc = self._lib.oc_insert_ordered(self._h, _p32(k), _p32(v), s.ctypes.data_as(_u8p), k.size)
+        if rc != 0:
+            raise ValueError("batch size must be in [1, b]")
 
     @property
     def r(self) -> int:

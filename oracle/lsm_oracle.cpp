@@ -33,7 +33,12 @@
 //     prose overrides);
 //   - count and range bounds are inclusive; k1 > k2 gives 0 / empty;
 //   - a mixed batch applies its inserts in batch order and then its deletes
-//     (sec. III-A rule 5: inserted and deleted in one batch means deleted).
+//     (sec. III-A rule 5: inserted and deleted in one batch means deleted);
+//   - a coalesced batch (several single-type user batches packed in arrival
+//     order into one batch of b) must instead behave like its user batches
+//     applied one after another: it is sorted on the original key alone, the
+//     later position first, so the newest operation on a key wins whatever
+//     its type (oc_insert_ordered).
 //
 // Build: g++ -O2 -std=c++17 -shared -fPIC lsm_oracle.cpp -o liblsm_oracle.so
 #include <algorithm>
@@ -179,8 +184,8 @@ void oc_destroy(void* h) { delete static_cast<CascadeOracle*>(h); }
 // INSERT(tombed(batch)), sec. III-C); status == nullptr means all regular.
 // vals == nullptr means all values are 0.  Returns 0, or -1 if n == 0 or
 // n > b (nothing is changed then).
-int oc_insert(void* h, const uint32_t* keys, const uint32_t* vals,
-              const uint8_t* status, uint32_t n) {
+static int insert_impl(void* h, const uint32_t* keys, const uint32_t* vals,
+                       const uint8_t* status, uint32_t n, bool status_in_sort) {
   auto* c = static_cast<CascadeOracle*>(h);
   const uint32_t b = c->b;
   if (n == 0 || n > b) return -1;
@@ -203,8 +208,10 @@ int oc_insert(void* h, const uint32_t* keys, const uint32_t* vals,
   // buffer <- sort(input): radix order on the whole key variable, status bit
   // included (tombstone before regular element of the same key); equal key
   // variables ordered so the later batch position comes first.
-  std::sort(batch.begin(), batch.end(), [](const Tagged& x, const Tagged& y) {
-    if (x.e.kv != y.e.kv) return x.e.kv < y.e.kv;
+  std::sort(batch.begin(), batch.end(), [status_in_sort](const Tagged& x, const Tagged& y) {
+    const uint32_t kx = status_in_sort ? x.e.kv : (x.e.kv >> 1);
+    const uint32_t ky = status_in_sort ? y.e.kv : (y.e.kv >> 1);
+    if (kx != ky) return kx < ky;
     return x.pos > y.pos;
   });
   std::vector<Elem> buffer(b);
@@ -230,6 +237,18 @@ int oc_insert(void* h, const uint32_t* keys, const uint32_t* vals,
   c->r += 1;
   c->merged_elems_total += c->merged_elems_last;
   return 0;
+}
+
+int oc_insert(void* h, const uint32_t* keys, const uint32_t* vals, const uint8_t* status,
+              uint32_t n) {
+  return insert_impl(h, keys, vals, status, n, true);
+}
+
+// A coalesced batch (see the readings above): identical to oc_insert except
+// that the batch sort ignores the status bit.
+int oc_insert_ordered(void* h, const uint32_t* keys, const uint32_t* vals, const uint8_t* status,
+                      uint32_t n) {
+  return insert_impl(h, keys, vals, status, n, false);
 }
 
 uint64_t oc_num_batches(void* h) { return static_cast<CascadeOracle*>(h)->r; }

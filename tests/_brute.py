@@ -62,9 +62,11 @@ class LogBrute:
         return out
 
 
-def closed_form_levels(batches, b):
+def closed_form_levels(batches, b, status_in_sort=True):
     """batches: list of (keys, vals_or_None, status_list) as inserted, each of
-    1..b elements.  Returns {level: [(kv, val), ...]} for occupied levels."""
+    1..b elements.  Returns {level: [(kv, val), ...]} for occupied levels.
+    status_in_sort=False is the coalesced-batch order: inside a batch the
+    later position comes first whatever the status."""
     padded = []
     for keys, vals, status in batches:
         n = len(keys)
@@ -84,9 +86,9 @@ def closed_form_levels(batches, b):
             elems = []
             for t in range(base, base + (1 << i)):
                 for (k, s, v, p) in padded[t]:
-                    elems.append((k, -t, s, -p, v))
+                    elems.append((k, -t, s if status_in_sort else 0, -p, s, v))
             elems.sort()
-            levels[i] = [((k << 1) | s, v) for (k, _t, s, _p, v) in elems]
+            levels[i] = [((k << 1) | s, v) for (k, _t, _s, _p, s, v) in elems]
         i += 1
     return levels
 

@@ -29,6 +29,9 @@ MUTATIONS = [
      "  for (uint64_t j = 0; j < n; ++j) m.emplace(keys[j], vals[j]);\n}"),
     ("mixed_deletes_first", "    if (!is_delete[j]) m[keys[j]] = vals[j];\n  for (uint64_t j = 0; j < n; ++j)\n    if (is_delete[j]) m.erase(keys[j]);",
      "    if (is_delete[j]) m.erase(keys[j]);\n  for (uint64_t j = 0; j < n; ++j)\n    if (!is_delete[j]) m[keys[j]] = vals[j];"),
+    ("ordered_batch_sorts_on_status",
+     "    const uint32_t kx = status_in_sort ? x.e.kv : (x.e.kv >> 1);",
+     "    const uint32_t kx = x.e.kv;"),
     ("lookup_miss_value", "      vals[i] = 0;\n      found[i] = 0;", "      vals[i] = 1;\n      found[i] = 0;"),
 ]
 

@@ -274,3 +274,61 @@ def test_partial_batch_padding_is_invisible():
     assert lookup_over_levels(levels, 2) == (2, 1)
     assert tuple(a.tolist()[0] for a in m.lookup([4])) == (3, 1)
     assert casc.level(0)[0].size == 8
+
+
+def _pack(user_batches, b):
+    """Coalesce single-type user batches, in arrival order, into batches of
+    b: returns list of (keys, vals, status) with the last one partial."""
+    k = np.concatenate([u[0] for u in user_batches]).astype(np.uint32)
+    v = np.concatenate([u[1] for u in user_batches]).astype(np.uint32)
+    s = np.concatenate([np.full(u[0].size, 0 if u[2] else 1, np.uint8) for u in user_batches])
+    return [(k[o:o + b], v[o:o + b], s[o:o + b]) for o in range(0, k.size, b)]
+
+
+@pytest.mark.parametrize("b", [1, 3, 8])
+def test_coalesced_batches_match_sequential_user_batches(b):
+    """Packing user batches into LSM batches keeps their meaning: the
+    ordered-batch layout read as sec. III-D prescribes answers like the user
+    batches applied one after another, and equals its closed form."""
+    domain = 12
+    for seed in range(60):
+        rng = np.random.default_rng(40000 + 100 * b + seed)
+        m = oracle.MapOracle()
+        users = []
+        for _ in range(int(rng.integers(1, 15))):
+            n = int(rng.integers(1, 2 * b + 2))
+            k = rng.integers(0, domain, n).astype(np.uint32)
+            v = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+            dele = bool(rng.random() < 0.35)
+            users.append((k, v, dele))
+            if dele:
+                m.delete(k)
+            else:
+                m.insert(k, v)
+        casc = oracle.CascadeOracle(b)
+        hist = []
+        for (k, v, s) in _pack(users, b):
+            casc.insert_ordered(k, v, s)
+            hist.append((k, v, list(s)))
+        levels = _layout(casc)
+        want = closed_form_levels(hist, b, status_in_sort=False)
+        assert sorted(levels) == sorted(want)
+        for i in want:
+            assert list(zip(*levels[i])) == want[i]
+        vals, found = m.lookup(np.arange(domain, dtype=np.uint32))
+        for key in range(domain):
+            assert lookup_over_levels(levels, key) == (int(vals[key]), int(found[key])), (b, seed, key)
+        for k1 in range(domain):
+            k2 = min(domain - 1, k1 + 3)
+            assert count_over_levels(levels, k1, k2) == int(m.count([k1], [k2])[0])
+
+
+def test_coalesced_insert_after_delete_in_one_batch():
+    """The case that separates the two batch orders: a delete then a later
+    insert of the same key inside one packed batch leaves the key present."""
+    casc = oracle.CascadeOracle(4)
+    casc.insert_ordered([5, 5, 2, 7], [0, 99, 1, 2], [0, 1, 1, 1])
+    assert lookup_over_levels(_layout(casc), 5) == (99, 1)
+    casc2 = oracle.CascadeOracle(4)
+    casc2.insert([5, 5, 2, 7], [0, 99, 1, 2], [0, 1, 1, 1])
+    assert lookup_over_levels(_layout(casc2), 5) == (0, 0)
