@@ -118,6 +118,59 @@ LSM_API lsm_status_t lsm_update_batch(lsm_t h, const uint32_t* d_keys,
                               const uint32_t* d_vals,
                               const uint8_t* d_is_delete, uint32_t n);
 
+/* ---------------------------------------------------------------------
+ * Batching form: a coalescer in front of the batch insertion.
+ * ------------------------------------------------------------------- */
+
+/*
+ * lsm_submit -- one user batch of n >= 0 insertions (is_delete == 0) or
+ * deletions (is_delete != 0) of any size.  User batches are packed, in
+ * arrival order, into LSM batches of exactly b elements (a user batch may
+ * be split across two); every time b elements are staged they are inserted
+ * as one batch.  A packed batch means the same as its user batches applied
+ * one after another: the newest operation on a key wins whatever its type
+ * (unlike lsm_update_batch, where sec. III-A rule 5 makes a key inserted
+ * and deleted in one batch deleted).  This implements the partial-batch
+ * remark of sec. IV-A (padding costs b'/b of the insertion rate) by packing
+ * instead of padding, and the multi-batch ordering of sec. V-B.
+ *   d_keys, d_vals : n keys and values (device; d_vals unused for deletes).
+ * Staged elements are copied on the stream; the caller's buffers may be
+ * reused once the stream has passed the call.  Queries (lsm_lookup,
+ * lsm_count, lsm_range) flush the staged elements first.
+ * LSM_EKEY (checked mode, nothing staged), LSM_ENOMEM, LSM_ECAPACITY,
+ * LSM_EHIP.
+ */
+LSM_API lsm_status_t lsm_submit(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals,
+                                uint32_t n, int is_delete);
+
+/* lsm_flush -- insert the staged elements as one (padded) batch, if any. */
+LSM_API lsm_status_t lsm_flush(lsm_t h);
+
+/* Number of elements staged and not yet inserted. */
+LSM_API uint32_t lsm_pending(lsm_t h);
+
+/*
+ * lsm_set_graphs -- when on, every full staged batch is inserted by
+ * replaying a hipGraph captured (on a private stream, at first use) for its
+ * first empty level and histogram buffer; graphs are recaptured whenever a
+ * buffer they name is reallocated or a merge variant changes.  Not
+ * available with LSM_CHECKED (LSM_EINVAL).
+ */
+LSM_API lsm_status_t lsm_set_graphs(lsm_t h, int on);
+
+/*
+ * Merge-kernel autotuner.  Variant v in [0, 6) merges with 4, 8 or 16
+ * elements per thread (v % 3) and at most 1024 or 4096 work-groups (v / 3).
+ * lsm_autotune times every variant on merges of two interleaved runs of
+ * b * 2^i elements for i = 0 .. max_level (reps launches each, requires
+ * b * 2^max_level <= 2^27) and keeps the fastest per level; it synchronises
+ * the stream.  lsm_get_tuning returns the chosen variant of merge input
+ * level i and, when us != NULL, the 6 measured microseconds per launch.
+ */
+LSM_API lsm_status_t lsm_autotune(lsm_t h, uint32_t max_level, uint32_t reps);
+LSM_API lsm_status_t lsm_get_tuning(lsm_t h, uint32_t level, uint32_t* variant, float* us);
+LSM_API lsm_status_t lsm_set_tuning(lsm_t h, uint32_t level, uint32_t variant);
+
 /*
  * lsm_lookup -- LOOKUP(k) for nq query keys (sec. III-D, IV-B): searches
  * the occupied levels from the smallest (newest) up; a regular element

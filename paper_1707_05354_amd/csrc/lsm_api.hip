@@ -49,6 +49,23 @@ struct lsm_s {
 
   uint64_t* h_pinned = nullptr;  // read-backs (range total, key check)
 
+  // Coalescer (batching form): user batches staged as key variables in
+  // arrival order until b are collected.
+  uint32_t* stage_kv = nullptr;
+  uint32_t* stage_val = nullptr;
+  uint32_t stage_fill = 0;
+
+  // Captured insertion graphs for full staged batches, by first empty level
+  // and histogram parity; recaptured whenever a buffer they name changes.
+  bool graphs = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph[kMaxLevels][2] = {};
+  hipGraphExec_t graph_exec[kMaxLevels][2] = {};
+
+  // Merge variant per merge input level (autotuned or set).
+  int merge_variant[kMaxLevels];
+  float tune_us[kMaxLevels][kMergeVariants] = {};
+
   uint64_t merged_last = 0, merged_total = 0, sorted_total = 0;
   uint64_t device_bytes = 0;
 
@@ -68,6 +85,8 @@ struct lsm_s {
 };
 
 namespace {
+
+void drop_graphs(lsm_t h);
 
 struct DeviceGuard {
   int prev = -1;
@@ -147,6 +166,7 @@ lsm_status_t ensure_merge_scratch(lsm_t h, uint64_t elems) {
       return LSM_ENOMEM;
     }
   }
+  drop_graphs(h);  // captured graphs name the old buffers
   const size_t old = h->mrg_cap * sizeof(uint32_t);
   for (int i = 0; i < 2; ++i) {
     dev_free(h, h->mrg_kv[i], old);
@@ -181,7 +201,21 @@ lsm_status_t ensure_query_scratch(lsm_t h, uint32_t nq) {
   return LSM_OK;
 }
 
+void drop_graphs(lsm_t h) {
+  for (int j = 0; j < kMaxLevels; ++j)
+    for (int p = 0; p < 2; ++p) {
+      if (h->graph_exec[j][p]) (void)hipGraphExecDestroy(h->graph_exec[j][p]);
+      if (h->graph[j][p]) (void)hipGraphDestroy(h->graph[j][p]);
+      h->graph_exec[j][p] = nullptr;
+      h->graph[j][p] = nullptr;
+    }
+}
+
 void release_all(lsm_t h) {
+  drop_graphs(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  dev_free(h, h->stage_kv, static_cast<size_t>(h->b) * sizeof(uint32_t));
+  dev_free(h, h->stage_val, static_cast<size_t>(h->b) * sizeof(uint32_t));
   const size_t bb = static_cast<size_t>(h->b) * sizeof(uint32_t);
   for (int i = 0; i < kMaxLevels; ++i) {
     dev_free(h, h->lvl_kv[i], level_len(h, i) * sizeof(uint32_t));
@@ -256,21 +290,9 @@ void release_events(lsm_t h) {
   h->spans.clear();
 }
 
-// One update batch (sec. III-B insertion; deletions and mixed batches are
-// insertions whose elements carry status 0 where they delete).
-lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
-                          const uint8_t* is_delete, uint32_t n, BatchMode mode) {
-  if (h == nullptr) return LSM_EINVAL;
-  if (n == 0) return LSM_OK;
-  if (n > h->b) return LSM_EBATCH;
-  if (keys == nullptr || (mode != kDelete && vals == nullptr) ||
-      (mode == kMixed && is_delete == nullptr))
-    return LSM_EINVAL;
-  DeviceGuard g(h->device);
-  if (!g.ok) return LSM_EHIP;
-
-  // First empty level j = ffz(r); the merges fill it with b * 2^j elements.
-  const int j = __builtin_ctzll(~h->r);
+// Allocations an insertion into level j = ffz(r) needs: level j itself and,
+// for j >= 2, the cascade ping-pong buffers.
+lsm_status_t prepare_insert(lsm_t h, int j) {
   if (j >= kMaxLevels || level_len(h, j) > (1ull << 31)) return LSM_ECAPACITY;
   lsm_status_t s = ensure_level(h, j);
   if (s != LSM_OK) return s;
@@ -278,15 +300,16 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
     s = ensure_merge_scratch(h, level_len(h, j - 1));
     if (s != LSM_OK) return s;
   }
+  return LSM_OK;
+}
 
-  const bool checked = (h->flags & LSM_CHECKED) != 0;
-  const int lo_bit = (mode == kMixed) ? 0 : 1;
+SortArgs sort_args(lsm_t h, const BatchSrc& src, int j) {
   SortArgs sa;
-  sa.src = BatchSrc{keys, vals, is_delete, n, h->b, static_cast<int>(mode)};
-  sa.lo_bit = lo_bit;
-  sa.passes = sort_passes(h->key_bits, lo_bit);
+  sa.src = src;
+  sa.lo_bit = (src.mode == kMixed) ? 0 : 1;
+  sa.passes = sort_passes(h->key_bits, sa.lo_bit);
   sa.key_limit_bits = h->key_bits;
-  sa.checked = checked ? 1 : 0;
+  sa.checked = 0;
   sa.meta = sort_meta_carve(h->meta, h->b, h->hist_parity);
   sa.tmp_kv[0] = h->tmp_kv[0];
   sa.tmp_kv[1] = h->tmp_kv[1];
@@ -294,6 +317,62 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
   sa.tmp_val[1] = h->tmp_val[1];
   sa.out_kv = (j == 0) ? h->lvl_kv[0] : h->buf_kv;
   sa.out_val = (j == 0) ? h->lvl_val[0] : h->buf_val;
+  return sa;
+}
+
+// The cascade of Fig. 2(a): while level i is full, buffer <- merge(buffer,
+// level i); the last merge writes straight into level j.  Enqueued on s.
+hipError_t enqueue_cascade(lsm_t h, const SortArgs& sa, int j, hipStream_t s, Timed* last,
+                           uint64_t* merged_out) {
+  const uint32_t* cur_kv = sa.out_kv;
+  const uint32_t* cur_val = sa.out_val;
+  uint64_t merged = 0;
+  for (int i = 0; i < j; ++i) {
+    uint32_t* o_kv = (i == j - 1) ? h->lvl_kv[j] : h->mrg_kv[i & 1];
+    uint32_t* o_val = (i == j - 1) ? h->lvl_val[j] : h->mrg_val[i & 1];
+    const uint32_t len = static_cast<uint32_t>(level_len(h, i));
+    Timed mt;
+    const KTimer* t = (last != nullptr) ? timer(h, mt, kKMerge, 2ull * len, 16.0 * 2.0 * len) : nullptr;
+    const hipError_t e = launch_merge(cur_kv, cur_val, len, h->lvl_kv[i], h->lvl_val[i], len,
+                                      o_kv, o_val, h->merge_variant[i], s, t);
+    if (e != hipSuccess) return e;
+    if (t != nullptr) *last = mt;
+    merged += 2ull * len;
+    cur_kv = o_kv;
+    cur_val = o_val;
+  }
+  if (merged_out) *merged_out = merged;
+  return hipSuccess;
+}
+
+void commit_insert(lsm_t h, uint64_t merged) {
+  h->r += 1;
+  h->merged_last = merged;
+  h->merged_total += merged;
+  h->sorted_total += h->b;
+}
+
+// One update batch (sec. III-B insertion; deletions and mixed batches are
+// insertions whose elements carry status 0 where they delete).
+lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
+                          const uint8_t* is_delete, uint32_t n, BatchMode mode) {
+  if (h == nullptr) return LSM_EINVAL;
+  if (n == 0) return LSM_OK;
+  if (n > h->b) return LSM_EBATCH;
+  if (keys == nullptr || (mode != kDelete && mode != kEncoded && vals == nullptr) ||
+      (mode == kMixed && is_delete == nullptr))
+    return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+
+  // First empty level j = ffz(r); the merges fill it with b * 2^j elements.
+  const int j = __builtin_ctzll(~h->r);
+  lsm_status_t s = prepare_insert(h, j);
+  if (s != LSM_OK) return s;
+
+  const bool checked = (h->flags & LSM_CHECKED) != 0 && mode != kEncoded;
+  SortArgs sa = sort_args(h, BatchSrc{keys, vals, is_delete, n, h->b, static_cast<int>(mode)}, j);
+  sa.checked = checked ? 1 : 0;
   if (checked && hipMemsetAsync(sa.meta.err, 0, sizeof(uint32_t), h->stream) != hipSuccess)
     return LSM_EHIP;
 
@@ -319,31 +398,72 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
     if (*reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u) return LSM_EKEY;
   }
 
-  // while level i is full: buffer <- merge(buffer, level i)  (Fig. 2(a)).
-  // The last merge writes straight into level j.
-  const uint32_t* cur_kv = sa.out_kv;
-  const uint32_t* cur_val = sa.out_val;
   uint64_t merged = 0;
-  for (int i = 0; i < j; ++i) {
-    uint32_t* o_kv = (i == j - 1) ? h->lvl_kv[j] : h->mrg_kv[i & 1];
-    uint32_t* o_val = (i == j - 1) ? h->lvl_val[j] : h->mrg_val[i & 1];
-    const uint32_t len = static_cast<uint32_t>(level_len(h, i));
-    Timed mt;
-    const KTimer* t = timer(h, mt, kKMerge, 2ull * len, 16.0 * 2.0 * len);
-    if (launch_merge(cur_kv, cur_val, len, h->lvl_kv[i], h->lvl_val[i], len, o_kv, o_val,
-                     h->stream, t) != hipSuccess)
-      return LSM_EHIP;
-    if (t != nullptr) last = mt;
-    merged += 2ull * len;
-    cur_kv = o_kv;
-    cur_val = o_val;
-  }
+  if (enqueue_cascade(h, sa, j, h->stream, timed ? &last : nullptr, &merged) != hipSuccess)
+    return LSM_EHIP;
   if (timed) call_span(h, 10, st[0], last, h->b);
-  h->r += 1;
-  h->merged_last = merged;
-  h->merged_total += merged;
-  h->sorted_total += h->b;
+  commit_insert(h, merged);
   return LSM_OK;
+}
+
+// Inserts the staged batch (n elements, padded when n < b).  A full staged
+// batch replays the graph captured for (ffz(r), parity) when graphs are on.
+lsm_status_t insert_staged(lsm_t h, uint32_t n) {
+  if (!h->graphs || n != h->b) {
+    const lsm_status_t s = update_batch(h, h->stage_kv, h->stage_val, nullptr, n, kEncoded);
+    if (s == LSM_OK) h->stage_fill = 0;
+    return s;
+  }
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  const int j = __builtin_ctzll(~h->r);
+  lsm_status_t s = prepare_insert(h, j);
+  if (s != LSM_OK) return s;
+  const int par = h->hist_parity;
+  if (h->graph_exec[j][par] == nullptr) {
+    if (h->cap_stream == nullptr &&
+        hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+      return LSM_EHIP;
+    const SortArgs sa =
+        sort_args(h, BatchSrc{h->stage_kv, h->stage_val, nullptr, h->b, h->b, kEncoded}, j);
+    if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return LSM_EHIP;
+    hipError_t e = launch_sort(sa, h->cap_stream, nullptr);
+    if (e == hipSuccess) e = enqueue_cascade(h, sa, j, h->cap_stream, nullptr, nullptr);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
+    if (e != hipSuccess || ec != hipSuccess || graph == nullptr) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return LSM_EHIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return LSM_EHIP;
+    }
+    h->graph[j][par] = graph;
+    h->graph_exec[j][par] = exec;
+  }
+  Timed tg;
+  const KTimer* t = timer(h, tg, kKSortHist, 0, 0.0);  // whole-graph span, reported as an update
+  if (t != nullptr) {
+    h->spans.pop_back();  // keep only the update-call span below
+    (void)hipEventRecord(t->start, h->stream);
+  }
+  if (hipGraphLaunch(h->graph_exec[j][par], h->stream) != hipSuccess) return LSM_EHIP;
+  if (t != nullptr) {
+    (void)hipEventRecord(t->stop, h->stream);
+    call_span(h, 10, tg, tg, h->b);
+  }
+  h->hist_parity ^= 1;
+  commit_insert(h, (j == 0) ? 0 : (2ull << j) * h->b - 2ull * h->b);
+  h->stage_fill = 0;
+  return LSM_OK;
+}
+
+lsm_status_t flush_staged(lsm_t h) {
+  if (h->stage_fill == 0) return LSM_OK;
+  return insert_staged(h, h->stage_fill);
 }
 
 }  // namespace
@@ -376,6 +496,9 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
     if ((s = dev_alloc(h, &p, bb)) == LSM_OK) h->tmp_kv[i] = static_cast<uint32_t*>(p);
     if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->tmp_val[i] = static_cast<uint32_t*>(p);
   }
+  for (int i = 0; i < kMaxLevels; ++i) h->merge_variant[i] = kDefaultMergeVariant;
+  if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->stage_kv = static_cast<uint32_t*>(p);
+  if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->stage_val = static_cast<uint32_t*>(p);
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->buf_kv = static_cast<uint32_t*>(p);
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->buf_val = static_cast<uint32_t*>(p);
   if (s == LSM_OK && (s = dev_alloc(h, &p, sort_meta_words(b) * sizeof(uint32_t))) == LSM_OK) {
@@ -425,6 +548,8 @@ lsm_status_t lsm_lookup(lsm_t h, const uint32_t* d_keys, uint32_t nq, uint32_t* 
   if (d_keys == nullptr || d_vals == nullptr || d_found == nullptr) return LSM_EINVAL;
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
+  lsm_status_t fs = flush_staged(h);
+  if (fs != LSM_OK) return fs;
   const LevelSet lv = occupied_levels(h);
   Timed tl;
   const KTimer* t = timer(h, tl, kKLookup, nq, 0.0);
@@ -440,6 +565,8 @@ lsm_status_t lsm_count(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   if (d_lo == nullptr || d_hi == nullptr || d_counts == nullptr) return LSM_EINVAL;
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
+  lsm_status_t fs = flush_staged(h);
+  if (fs != LSM_OK) return fs;
   const LevelSet lv = occupied_levels(h);
   Timed tc;
   const KTimer* t = timer(h, tc, kKCount, nq, 0.0);
@@ -462,7 +589,9 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
     return hipMemsetAsync(d_offsets, 0, sizeof(uint64_t), h->stream) == hipSuccess ? LSM_OK
                                                                                   : LSM_EHIP;
   }
-  lsm_status_t s = ensure_query_scratch(h, nq);
+  lsm_status_t s = flush_staged(h);
+  if (s != LSM_OK) return s;
+  s = ensure_query_scratch(h, nq);
   if (s != LSM_OK) return s;
   const LevelSet lv = occupied_levels(h);
   Timed t1, t2, t3;
@@ -493,6 +622,138 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   return LSM_OK;
 }
 
+lsm_status_t lsm_submit(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals, uint32_t n,
+                        int is_delete) {
+  if (h == nullptr) return LSM_EINVAL;
+  if (n == 0) return LSM_OK;
+  if (d_keys == nullptr || (!is_delete && d_vals == nullptr)) return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  if (h->flags & LSM_CHECKED) {
+    // Validate the whole user batch before staging any of it.
+    const SortMeta m = sort_meta_carve(h->meta, h->b, 0);
+    if (hipMemsetAsync(m.err, 0, sizeof(uint32_t), h->stream) != hipSuccess ||
+        launch_check_keys(d_keys, n, h->key_bits, m.err, h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->h_pinned, m.err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return LSM_EHIP;
+    if (*reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u) return LSM_EKEY;
+  }
+  // Pack in arrival order; every b staged elements form one LSM batch.
+  uint32_t done = 0;
+  while (done < n) {
+    const uint32_t take = (n - done) < (h->b - h->stage_fill) ? (n - done) : (h->b - h->stage_fill);
+    if (launch_stage(d_keys + done, is_delete ? nullptr : d_vals + done, take, is_delete,
+                     h->stage_kv, h->stage_val, h->stage_fill, h->stream) != hipSuccess)
+      return LSM_EHIP;
+    h->stage_fill += take;
+    done += take;
+    if (h->stage_fill == h->b) {
+      const lsm_status_t s = insert_staged(h, h->b);
+      if (s != LSM_OK) return s;
+    }
+  }
+  return LSM_OK;
+}
+
+lsm_status_t lsm_flush(lsm_t h) {
+  if (h == nullptr) return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  return flush_staged(h);
+}
+
+uint32_t lsm_pending(lsm_t h) { return h ? h->stage_fill : 0; }
+
+lsm_status_t lsm_set_graphs(lsm_t h, int on) {
+  if (h == nullptr) return LSM_EINVAL;
+  if (on && (h->flags & LSM_CHECKED)) return LSM_EINVAL;
+  h->graphs = on != 0;
+  return LSM_OK;
+}
+
+lsm_status_t lsm_set_tuning(lsm_t h, uint32_t level, uint32_t variant) {
+  if (h == nullptr || level >= static_cast<uint32_t>(kMaxLevels) ||
+      variant >= static_cast<uint32_t>(kMergeVariants))
+    return LSM_EINVAL;
+  if (h->merge_variant[level] != static_cast<int>(variant)) {
+    h->merge_variant[level] = static_cast<int>(variant);
+    drop_graphs(h);
+  }
+  return LSM_OK;
+}
+
+lsm_status_t lsm_get_tuning(lsm_t h, uint32_t level, uint32_t* variant, float* us) {
+  if (h == nullptr || variant == nullptr || level >= static_cast<uint32_t>(kMaxLevels))
+    return LSM_EINVAL;
+  *variant = static_cast<uint32_t>(h->merge_variant[level]);
+  if (us != nullptr)
+    for (int v = 0; v < kMergeVariants; ++v) us[v] = h->tune_us[level][v];
+  return LSM_OK;
+}
+
+lsm_status_t lsm_autotune(lsm_t h, uint32_t max_level, uint32_t reps) {
+  if (h == nullptr || reps == 0) return LSM_EINVAL;
+  if (max_level >= static_cast<uint32_t>(kMaxLevels) || level_len(h, max_level) > (1ull << 27))
+    return LSM_ECAPACITY;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  const uint64_t len_max = level_len(h, max_level);
+  void* buf[6] = {};
+  const size_t sz[6] = {len_max * 4, len_max * 4, len_max * 4, len_max * 4, len_max * 8, len_max * 8};
+  lsm_status_t s = LSM_OK;
+  for (int i = 0; i < 6 && s == LSM_OK; ++i) s = dev_alloc(h, &buf[i], sz[i]);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (s == LSM_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    s = LSM_EHIP;
+  auto* ak = static_cast<uint32_t*>(buf[0]);
+  auto* av = static_cast<uint32_t*>(buf[1]);
+  auto* bk = static_cast<uint32_t*>(buf[2]);
+  auto* bv = static_cast<uint32_t*>(buf[3]);
+  auto* ok = static_cast<uint32_t*>(buf[4]);
+  auto* ov = static_cast<uint32_t*>(buf[5]);
+  // Merges of the sizes the cascade performs: two runs of b * 2^i each.
+  for (uint32_t i = 0; i <= max_level && s == LSM_OK; ++i) {
+    const uint32_t len = static_cast<uint32_t>(level_len(h, static_cast<int>(i)));
+    if (launch_fill_runs(ak, av, bk, bv, len, h->stream) != hipSuccess) {
+      s = LSM_EHIP;
+      break;
+    }
+    int best = kDefaultMergeVariant;
+    float best_us = 0.f;
+    for (int v = 0; v < kMergeVariants && s == LSM_OK; ++v) {
+      if (launch_merge(ak, av, len, bk, bv, len, ok, ov, v, h->stream, nullptr) != hipSuccess ||
+          hipEventRecord(e0, h->stream) != hipSuccess) {
+        s = LSM_EHIP;
+        break;
+      }
+      for (uint32_t k = 0; k < reps; ++k)
+        if (launch_merge(ak, av, len, bk, bv, len, ok, ov, v, h->stream, nullptr) != hipSuccess)
+          s = LSM_EHIP;
+      float ms = 0.f;
+      if (s != LSM_OK || hipEventRecord(e1, h->stream) != hipSuccess ||
+          hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        s = LSM_EHIP;
+        break;
+      }
+      const float us = 1000.f * ms / static_cast<float>(reps);
+      h->tune_us[i][v] = us;
+      if (v == 0 || us < best_us) {
+        best_us = us;
+        best = v;
+      }
+    }
+    if (s == LSM_OK) h->merge_variant[i] = best;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(h->stream);
+  for (int i = 0; i < 6; ++i) dev_free(h, buf[i], sz[i]);
+  drop_graphs(h);
+  return s;
+}
+
 lsm_status_t lsm_sync(lsm_t h) {
   if (h == nullptr) return LSM_EINVAL;
   DeviceGuard g(h->device);
@@ -512,6 +773,7 @@ lsm_status_t lsm_sync(lsm_t h) {
 lsm_status_t lsm_clear(lsm_t h) {
   if (h == nullptr) return LSM_EINVAL;
   h->r = 0;
+  h->stage_fill = 0;
   h->merged_last = 0;
   return LSM_OK;
 }

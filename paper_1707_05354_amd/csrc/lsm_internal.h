@@ -22,11 +22,14 @@ constexpr int kMaxPasses = 4;
 // The histogram kernel uses at most this many work-groups (tile-strided).
 constexpr int kMaxHistBlocks = 512;
 
-// Merge: tiles of kThreads * kMergeItems output elements.
-constexpr int kMergeItems = 8;
-constexpr int kMergeTile = kThreads * kMergeItems;
-// At most this many merge work-groups; each takes a contiguous run of tiles.
-constexpr int kMaxMergeBlocks = 1024;
+// Merge variants (autotuned per level): items per thread x work-group cap.
+// Variant v uses kMergeItemsOf[v % 3] items per thread (tiles of 256 x that)
+// and at most kMergeBlocksOf[v / 3] work-groups, each taking a contiguous
+// run of tiles.
+constexpr int kMergeVariants = 6;
+constexpr int kMergeItemsOf[3] = {4, 8, 16};
+constexpr int kMergeBlocksOf[2] = {1024, 4096};
+constexpr int kDefaultMergeVariant = 1;  // 8 items, 1024 work-groups
 
 // Scan (range offsets): tiles of kThreads * kScanItems counts.
 constexpr int kScanItems = 8;
@@ -43,8 +46,9 @@ struct LevelSet {
   int count;
 };
 
-// How the batch's status bit is formed while the batch is read.
-enum BatchMode : int { kInsert = 0, kDelete = 1, kMixed = 2 };
+// How the batch's status bit is formed while the batch is read.  kEncoded
+// batches (the coalescer's staging buffer) already hold key variables.
+enum BatchMode : int { kInsert = 0, kDelete = 1, kMixed = 2, kEncoded = 3 };
 
 // Source of one batch as the caller handed it over.
 struct BatchSrc {
@@ -105,11 +109,25 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity);
 hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers);
 
 // Stable merge of a newer run (first on equal original keys) with an older
-// run into out (na + nb elements).
+// run into out (na + nb elements), with merge variant `variant`.
 hipError_t launch_merge(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na,
                         const uint32_t* b_kv, const uint32_t* b_val, uint32_t nb,
-                        uint32_t* out_kv, uint32_t* out_val, hipStream_t stream,
+                        uint32_t* out_kv, uint32_t* out_val, int variant, hipStream_t stream,
                         const KTimer* t);
+
+// Coalescer: encodes n keys of one user batch as key variables (status 0
+// for a deletion, value 0) into staging[at .. at + n).
+hipError_t launch_stage(const uint32_t* keys, const uint32_t* vals, uint32_t n, int is_delete,
+                        uint32_t* stage_kv, uint32_t* stage_val, uint32_t at,
+                        hipStream_t stream);
+
+// Sets err |= 1 when any of n keys is >= 2^limit_bits.
+hipError_t launch_check_keys(const uint32_t* keys, uint32_t n, uint32_t limit_bits,
+                             uint32_t* err, hipStream_t stream);
+
+// Fills two interleaved sorted runs (keys 2i and 2i + 1) for the autotuner.
+hipError_t launch_fill_runs(uint32_t* a_kv, uint32_t* a_val, uint32_t* b_kv, uint32_t* b_val,
+                            uint32_t n, hipStream_t stream);
 
 hipError_t launch_lookup(const LevelSet& lv, const uint32_t* q, uint32_t nq, uint32_t* out_val,
                          uint8_t* out_found, hipStream_t stream, const KTimer* t);

@@ -134,6 +134,12 @@ __device__ __forceinline__ void batch_elem(const BatchSrc& s, uint32_t e, uint32
                                            uint32_t& val, uint32_t& key) {
   uint32_t src = s.b - 1 - e;
   if (src > s.n - 1) src = s.n - 1;
+  if (s.mode == kEncoded) {
+    kv = s.keys[src];
+    val = s.vals[src];
+    key = kv >> 1;
+    return;
+  }
   key = s.keys[src];
   uint32_t st;
   if (s.mode == kInsert) st = 1u;
@@ -420,15 +426,17 @@ __device__ __forceinline__ uint32_t lds_merge_path(const uint32_t* s, uint32_t w
 }
 
 // Each work-group merges a contiguous run of `tiles_per_wg` output tiles of
-// kMergeTile elements.  Only the first tile's split is searched in global
+// kMergeTile = 256 * kMergeItems elements.  Only the first tile's split is searched in global
 // memory (64-ary wave search); every later split is found inside LDS
 // windows holding the next kMergeTile elements of each input, which are the
 // elements the tile is about to consume anyway.
+template <int kMergeItems>
 __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const uint32_t* a_val,
                                                     uint32_t na, const uint32_t* b_kv,
                                                     const uint32_t* b_val, uint32_t nb,
                                                     uint32_t* out_kv, uint32_t* out_val,
                                                     uint32_t tiles_per_wg) {
+  constexpr uint32_t kMergeTile = kThreads * kMergeItems;
   __shared__ uint32_t s_kv[2 * kMergeTile];
   __shared__ uint32_t s_val[2 * kMergeTile];
   __shared__ uint32_t s_split;
@@ -497,6 +505,34 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
     b0 += n - la;
     __syncthreads();
   }
+}
+
+// ------------------------------------------------------------ coalescer
+__global__ __launch_bounds__(kThreads) void k_stage(const uint32_t* keys, const uint32_t* vals,
+                                                    uint32_t n, int is_delete, uint32_t* stage_kv,
+                                                    uint32_t* stage_val, uint32_t at) {
+  const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t st = is_delete ? 0u : 1u;
+  stage_kv[at + i] = (keys[i] << 1) | st;
+  stage_val[at + i] = st ? vals[i] : 0u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_check_keys(const uint32_t* keys, uint32_t n,
+                                                         uint32_t limit_bits, uint32_t* err) {
+  const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < n && (keys[i] >> limit_bits) != 0u) atomicOr(err, 1u);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_runs(uint32_t* a_kv, uint32_t* a_val,
+                                                        uint32_t* b_kv, uint32_t* b_val,
+                                                        uint32_t n) {
+  const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  a_kv[i] = ((2u * i) << 1) | 1u;
+  a_val[i] = i;
+  b_kv[i] = ((2u * i + 1u) << 1) | 1u;
+  b_val[i] = i;
 }
 
 // ------------------------------------------------------------ queries
@@ -728,16 +764,60 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* time
   return hipSuccess;
 }
 
+template <int kItems>
+hipError_t launch_merge_items(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na,
+                              const uint32_t* b_kv, const uint32_t* b_val, uint32_t nb,
+                              uint32_t* out_kv, uint32_t* out_val, uint32_t max_blocks,
+                              hipStream_t stream, const KTimer* t) {
+  const uint64_t total = static_cast<uint64_t>(na) + nb;
+  const uint64_t tile = static_cast<uint64_t>(kThreads) * kItems;
+  const uint64_t tiles = (total + tile - 1) / tile;
+  const uint32_t per = static_cast<uint32_t>((tiles + max_blocks - 1) / max_blocks);
+  return launch(k_merge<kItems>, grid_for(tiles, per), kThreads, stream, t, a_kv, a_val, na, b_kv,
+                b_val, nb, out_kv, out_val, per);
+}
+
 hipError_t launch_merge(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na,
                         const uint32_t* b_kv, const uint32_t* b_val, uint32_t nb,
-                        uint32_t* out_kv, uint32_t* out_val, hipStream_t stream,
+                        uint32_t* out_kv, uint32_t* out_val, int variant, hipStream_t stream,
                         const KTimer* t) {
   const uint64_t total = static_cast<uint64_t>(na) + nb;
   if (total == 0) return hipSuccess;
-  const uint64_t tiles = (total + kMergeTile - 1) / kMergeTile;
-  const uint32_t per = static_cast<uint32_t>((tiles + kMaxMergeBlocks - 1) / kMaxMergeBlocks);
-  return launch(k_merge, grid_for(tiles, per), kThreads, stream, t, a_kv, a_val, na, b_kv, b_val,
-                nb, out_kv, out_val, per);
+  if (variant < 0 || variant >= kMergeVariants) variant = kDefaultMergeVariant;
+  const uint32_t blocks = static_cast<uint32_t>(kMergeBlocksOf[variant / 3]);
+  switch (kMergeItemsOf[variant % 3]) {
+    case 4:
+      return launch_merge_items<4>(a_kv, a_val, na, b_kv, b_val, nb, out_kv, out_val, blocks,
+                                   stream, t);
+    case 16:
+      return launch_merge_items<16>(a_kv, a_val, na, b_kv, b_val, nb, out_kv, out_val, blocks,
+                                    stream, t);
+    default:
+      return launch_merge_items<8>(a_kv, a_val, na, b_kv, b_val, nb, out_kv, out_val, blocks,
+                                   stream, t);
+  }
+}
+
+hipError_t launch_stage(const uint32_t* keys, const uint32_t* vals, uint32_t n, int is_delete,
+                        uint32_t* stage_kv, uint32_t* stage_val, uint32_t at,
+                        hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  return launch(k_stage, grid_for(n, kThreads), kThreads, stream, nullptr, keys, vals, n, is_delete,
+                stage_kv, stage_val, at);
+}
+
+hipError_t launch_check_keys(const uint32_t* keys, uint32_t n, uint32_t limit_bits,
+                             uint32_t* err, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  return launch(k_check_keys, grid_for(n, kThreads), kThreads, stream, nullptr, keys, n,
+                limit_bits, err);
+}
+
+hipError_t launch_fill_runs(uint32_t* a_kv, uint32_t* a_val, uint32_t* b_kv, uint32_t* b_val,
+                            uint32_t n, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  return launch(k_fill_runs, grid_for(n, kThreads), kThreads, stream, nullptr, a_kv, a_val, b_kv,
+                b_val, n);
 }
 
 hipError_t launch_lookup(const LevelSet& lv, const uint32_t* q, uint32_t nq, uint32_t* out_val,

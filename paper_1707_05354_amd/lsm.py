@@ -79,6 +79,13 @@ _SIGNATURES = {
                                       ctypes.POINTER(_u64)]),
     "lsm_level_copy": (ctypes.c_int, [_vp, _u32, _vp, _vp, ctypes.POINTER(_u64)]),
     "lsm_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Stats)]),
+    "lsm_submit": (ctypes.c_int, [_vp, _vp, _vp, _u32, ctypes.c_int]),
+    "lsm_flush": (ctypes.c_int, [_vp]),
+    "lsm_pending": (_u32, [_vp]),
+    "lsm_set_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lsm_autotune": (ctypes.c_int, [_vp, _u32, _u32]),
+    "lsm_get_tuning": (ctypes.c_int, [_vp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float)]),
+    "lsm_set_tuning": (ctypes.c_int, [_vp, _u32, _u32]),
 }
 
 
@@ -194,6 +201,40 @@ class LSM:
             self._h, _dev(keys, "keys"), _dev(vals, "vals"),
             _dev(is_delete, "is_delete", (torch.uint8, torch.bool)), keys.numel()),
             "lsm_update_batch")
+
+    # -- batching form --------------------------------------------------------
+    def submit(self, keys: torch.Tensor, vals: Optional[torch.Tensor] = None,
+               delete: bool = False) -> None:
+        """One user batch of any size, packed into LSM batches of b."""
+        n = keys.numel()
+        if not delete and (vals is None or vals.numel() != n):
+            raise ValueError("an insert batch needs one value per key")
+        vp = _dev(vals, "vals") if (vals is not None and not delete) else None
+        _check(self._lib.lsm_submit(self._h, _dev(keys, "keys"), vp, n, 1 if delete else 0),
+               "lsm_submit")
+
+    def flush(self) -> None:
+        _check(self._lib.lsm_flush(self._h), "lsm_flush")
+
+    @property
+    def pending(self) -> int:
+        return int(self._lib.lsm_pending(self._h))
+
+    def use_graphs(self, on: bool = True) -> None:
+        _check(self._lib.lsm_set_graphs(self._h, 1 if on else 0), "lsm_set_graphs")
+
+    def autotune(self, max_level: int, reps: int = 5) -> None:
+        _check(self._lib.lsm_autotune(self._h, int(max_level), int(reps)), "lsm_autotune")
+
+    def tuning(self, level: int):
+        """(chosen merge variant, [us per launch of each of the 6 variants])."""
+        v = _u32()
+        us = (ctypes.c_float * 6)()
+        _check(self._lib.lsm_get_tuning(self._h, int(level), ctypes.byref(v), us), "lsm_get_tuning")
+        return int(v.value), [float(x) for x in us]
+
+    def set_tuning(self, level: int, variant: int) -> None:
+        _check(self._lib.lsm_set_tuning(self._h, int(level), int(variant)), "lsm_set_tuning")
 
     # -- queries ------------------------------------------------------------
     def lookup(self, q: torch.Tensor, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):

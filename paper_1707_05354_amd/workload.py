@@ -229,3 +229,41 @@ def zipf_sweep(b: int, config: int = 3, n_total: int = 1 << 25, nq: int = 1 << 2
     return PlainWorkload("zipf sweep b=%d R=%d n=%d" % (b, R, R * b), b, keys, vals, is_delete,
                          lookups, c_lo, c_lo + np.uint32(width - 1), r_lo,
                          r_lo + np.uint32(width - 1), width, key_bits=ZIPF_BITS)
+
+
+# ---------------------------------------------------------------- batching
+def batching_stream(config: int = 4, n_batches: int = 4096, median: int = 4096,
+                    sigma: float = 1.0, lo: int = 256, hi: int = 65536, b: int = 1 << 16):
+    """User batches for the batching form: sizes round(exp(N(ln median,
+    sigma))) clipped to [lo, min(hi, b)], uniform 31-bit keys; batch i
+    deletes iff i mod 10 == 9, with keys drawn from earlier inserted keys.
+    Returns a list of (keys, vals, is_delete).  Normal deviates come from
+    the Box-Muller transform of two splitmix64 uniforms."""
+    u1 = (splitmix64(config, 8, 0, n_batches) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    u2 = (splitmix64(config, 9, 0, n_batches) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    z = np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)
+    sizes = np.clip(np.round(np.exp(np.log(median) + sigma * z)), lo, min(hi, b)).astype(np.int64)
+    total = int(sizes.sum())
+    keys = uniform_keys(config, 1, 0, total)
+    vals = values(config, 2, 0, total)
+    out = []
+    off = 0
+    ins_start, ins_cum = [], [0]  # inserted ranges, cumulative lengths
+    draw = 0
+    for i in range(n_batches):
+        n = int(sizes[i])
+        k = keys[off:off + n].copy()
+        v = vals[off:off + n]
+        dele = (i % 10) == 9
+        if dele:
+            idx = bounded(config, 3, draw, n, ins_cum[-1])
+            draw += n
+            cum = np.asarray(ins_cum, dtype=np.int64)
+            which = np.searchsorted(cum, idx, side="right") - 1
+            k = keys[np.asarray(ins_start, dtype=np.int64)[which] + (idx - cum[which])]
+        else:
+            ins_start.append(off)
+            ins_cum.append(ins_cum[-1] + n)
+        out.append((k, v, dele))
+        off += n
+    return out
