@@ -116,6 +116,79 @@ def zipf_sweep(torch, L, W, reps: int = 2):
     return res
 
 
+def batching_form(torch, L, W, reps: int = 2):
+    """4096 user batches, log-normal sizes (median 4096, sigma 1, clipped to
+    [256, 65536]), uniform keys, every tenth a delete batch: the plain path
+    (one padded LSM batch of b = 2^16 per user batch) against the batching
+    form (coalescer packing into ~426 LSM batches, captured hipGraphs,
+    autotuned merges).  Best of `reps` runs of each; user ops per second."""
+    b = 1 << 16
+    t0 = time.perf_counter()
+    ub = W.batching_stream(b=b)
+    sizes = [u[0].size for u in ub]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    allk = np.concatenate([u[0] for u in ub])
+    allv = np.concatenate([u[1] for u in ub])
+    kd = torch.from_numpy(allk.view(np.int32)).cuda()
+    vd = torch.from_numpy(allv.view(np.int32)).cuda()
+    kp, vp = kd.data_ptr(), vd.data_ptr()
+    dels = [u[2] for u in ub]
+    n_ops = int(offs[-1])
+    log("batching: %d user batches, %d ops, ready in %.1f s" % (len(ub), n_ops, time.perf_counter() - t0))
+
+    def run(g, batched):
+        lib, h = g._lib, g._h
+        best = None
+        for _ in range(reps):
+            g.clear()
+            torch.cuda.synchronize()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record()
+            for i, n in enumerate(sizes):
+                o = int(offs[i]) * 4
+                if batched:
+                    rc = lib.lsm_submit(h, kp + o, None if dels[i] else vp + o, n, 1 if dels[i] else 0)
+                elif dels[i]:
+                    rc = lib.lsm_delete_batch(h, kp + o, n)
+                else:
+                    rc = lib.lsm_insert_batch(h, kp + o, vp + o, n)
+                if rc:
+                    raise L.LSMError(rc, "batching run")
+            if batched:
+                g.flush()
+            e[1].record()
+            torch.cuda.synchronize()
+            ms = e[0].elapsed_time(e[1])
+            best = ms if best is None else min(best, ms)
+        g.sync()
+        return best, g.num_batches
+
+    gp = L.LSM(b)
+    plain_ms, plain_r = run(gp, False)
+    gp.close()
+    gb = L.LSM(b)
+    t0 = time.perf_counter()
+    gb.autotune(max_level=8, reps=3)
+    tune_s = time.perf_counter() - t0
+    tuning = [gb.tuning(i)[0] for i in range(9)]
+    gb.use_graphs(True)
+    run(gb, True)  # first run captures the graphs
+    batch_ms, batch_r = run(gb, True)
+    gb.close()
+    res = {
+        "user_batches": len(ub), "user_ops": n_ops,
+        "plain": {"lsm_batches": plain_r, "ms": round(plain_ms, 3),
+                  "M_user_ops_per_s": round(n_ops / (plain_ms * 1e-3) / 1e6, 2)},
+        "batched": {"lsm_batches": batch_r, "ms": round(batch_ms, 3),
+                    "M_user_ops_per_s": round(n_ops / (batch_ms * 1e-3) / 1e6, 2),
+                    "graphs": True, "merge_variant_by_level": tuning,
+                    "autotune_s": round(tune_s, 2)},
+        "speedup": round(plain_ms / batch_ms, 2),
+    }
+    log("batching: %s" % res)
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +198,8 @@ def main() -> int:
     ap.add_argument("--batches", type=int, default=1024, help="update batches per step")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the Zipf batch-size sweep (b = 2^13..2^19 at n = 2^25)")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the batching-form comparison (4096 log-normal user batches)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 4 times (PMC byte calibration)")
     args = ap.parse_args()
@@ -320,6 +395,8 @@ def main() -> int:
     g.close()
     if not args.no_sweep:
         out["sweep"] = zipf_sweep(torch, L, W)
+    if not args.no_batching:
+        out["batching"] = batching_form(torch, L, W)
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w)

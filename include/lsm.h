@@ -143,6 +143,15 @@ LSM_API lsm_status_t lsm_update_batch(lsm_t h, const uint32_t* d_keys,
 LSM_API lsm_status_t lsm_submit(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals,
                                 uint32_t n, int is_delete);
 
+/*
+ * lsm_submit_encoded -- stage n operations already encoded as key
+ * variables (original key << 1 | status; status 0 deletes), in arrival
+ * order, with their values (ignored for deletions).  One call can carry
+ * many user requests of both types; the packing rules of lsm_submit apply.
+ */
+LSM_API lsm_status_t lsm_submit_encoded(lsm_t h, const uint32_t* d_kv, const uint32_t* d_vals,
+                                        uint32_t n);
+
 /* lsm_flush -- insert the staged elements as one (padded) batch, if any. */
 LSM_API lsm_status_t lsm_flush(lsm_t h);
 
@@ -228,6 +237,19 @@ LSM_API lsm_status_t lsm_clear(lsm_t h);
  * synchronisation.
  */
 LSM_API lsm_status_t lsm_sync(lsm_t h);
+
+/*
+ * lsm_range_async -- lsm_range without any host synchronisation: always
+ * enqueues count, scan and emission.  d_offsets[nq + 1] receives the
+ * exclusive scan of the result sizes as in lsm_range; query q writes its
+ * pairs only when d_offsets[q + 1] <= cap (all of them, or none), so the
+ * caller finds the queries that did not fit by comparing the offsets with
+ * cap once the stream has passed the call.  LSM_EINVAL, LSM_ENOMEM,
+ * LSM_EHIP.
+ */
+LSM_API lsm_status_t lsm_range_async(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi,
+                                     uint32_t nq, uint64_t* d_offsets, uint32_t* d_keys,
+                                     uint32_t* d_vals, uint64_t cap);
 
 /* lsm_destroy -- synchronise the stream and free every allocation. */
 LSM_API lsm_status_t lsm_destroy(lsm_t h);

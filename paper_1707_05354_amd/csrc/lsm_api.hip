@@ -612,7 +612,7 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   if (total > cap) return LSM_ECAPACITY;
   // Stage 3: each query writes its live pairs in key order at its offset.
   if (total > 0) {
-    if (launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, d_keys, d_vals, h->stream,
+    if (launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, d_keys, d_vals, cap, h->stream,
                           timer(h, t3, kKRangeEmit, nq, 0.0)) != hipSuccess)
       return LSM_EHIP;
     call_span(h, 13, t1, t3, nq);
@@ -633,7 +633,7 @@ lsm_status_t lsm_submit(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals,
     // Validate the whole user batch before staging any of it.
     const SortMeta m = sort_meta_carve(h->meta, h->b, 0);
     if (hipMemsetAsync(m.err, 0, sizeof(uint32_t), h->stream) != hipSuccess ||
-        launch_check_keys(d_keys, n, h->key_bits, m.err, h->stream) != hipSuccess ||
+        launch_check_keys(d_keys, n, h->key_bits, 0, m.err, h->stream) != hipSuccess ||
         hipMemcpyAsync(h->h_pinned, m.err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream) !=
             hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess)
@@ -654,6 +654,66 @@ lsm_status_t lsm_submit(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals,
       if (s != LSM_OK) return s;
     }
   }
+  return LSM_OK;
+}
+
+lsm_status_t lsm_submit_encoded(lsm_t h, const uint32_t* d_kv, const uint32_t* d_vals,
+                                uint32_t n) {
+  if (h == nullptr) return LSM_EINVAL;
+  if (n == 0) return LSM_OK;
+  if (d_kv == nullptr || d_vals == nullptr) return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  if (h->flags & LSM_CHECKED) {
+    const SortMeta m = sort_meta_carve(h->meta, h->b, 0);
+    if (hipMemsetAsync(m.err, 0, sizeof(uint32_t), h->stream) != hipSuccess ||
+        launch_check_keys(d_kv, n, h->key_bits, 1, m.err, h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->h_pinned, m.err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return LSM_EHIP;
+    if (*reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u) return LSM_EKEY;
+  }
+  uint32_t done = 0;
+  while (done < n) {
+    const uint32_t take = (n - done) < (h->b - h->stage_fill) ? (n - done) : (h->b - h->stage_fill);
+    if (launch_stage_encoded(d_kv + done, d_vals + done, take, h->stage_kv, h->stage_val,
+                             h->stage_fill, h->stream) != hipSuccess)
+      return LSM_EHIP;
+    h->stage_fill += take;
+    done += take;
+    if (h->stage_fill == h->b) {
+      const lsm_status_t s = insert_staged(h, h->b);
+      if (s != LSM_OK) return s;
+    }
+  }
+  return LSM_OK;
+}
+
+lsm_status_t lsm_range_async(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint32_t nq,
+                             uint64_t* d_offsets, uint32_t* d_keys, uint32_t* d_vals,
+                             uint64_t cap) {
+  if (h == nullptr || d_offsets == nullptr) return LSM_EINVAL;
+  if (nq > 0 && (d_lo == nullptr || d_hi == nullptr)) return LSM_EINVAL;
+  if (cap > 0 && (d_keys == nullptr || d_vals == nullptr)) return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  if (nq == 0)
+    return hipMemsetAsync(d_offsets, 0, sizeof(uint64_t), h->stream) == hipSuccess ? LSM_OK
+                                                                                  : LSM_EHIP;
+  lsm_status_t s = flush_staged(h);
+  if (s != LSM_OK) return s;
+  s = ensure_query_scratch(h, nq);
+  if (s != LSM_OK) return s;
+  const LevelSet lv = occupied_levels(h);
+  Timed t1, t2, t3;
+  if (launch_count(lv, d_lo, d_hi, nq, h->q_counts, h->q_status, scan_status_words(nq),
+                   h->stream, timer(h, t1, kKCount, nq, 0.0)) != hipSuccess ||
+      launch_scan(h->q_counts, nq, d_offsets, h->q_status, h->fault, h->stream,
+                  timer(h, t2, kKScan, nq, 12.0 * nq)) != hipSuccess ||
+      launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, d_keys, d_vals, cap, h->stream,
+                        timer(h, t3, kKRangeEmit, nq, 0.0)) != hipSuccess)
+    return LSM_EHIP;
   return LSM_OK;
 }
 

@@ -121,8 +121,15 @@ hipError_t launch_stage(const uint32_t* keys, const uint32_t* vals, uint32_t n, 
                         uint32_t* stage_kv, uint32_t* stage_val, uint32_t at,
                         hipStream_t stream);
 
-// Sets err |= 1 when any of n keys is >= 2^limit_bits.
-hipError_t launch_check_keys(const uint32_t* keys, uint32_t n, uint32_t limit_bits,
+// Coalescer: copies n pre-encoded key variables (and values; 0 for
+// tombstones) into staging[at .. at + n).
+hipError_t launch_stage_encoded(const uint32_t* kv, const uint32_t* vals, uint32_t n,
+                                uint32_t* stage_kv, uint32_t* stage_val, uint32_t at,
+                                hipStream_t stream);
+
+// Sets err |= 1 when any of n keys (key variables when encoded) is
+// >= 2^limit_bits.
+hipError_t launch_check_keys(const uint32_t* keys, uint32_t n, uint32_t limit_bits, int encoded,
                              uint32_t* err, hipStream_t stream);
 
 // Fills two interleaved sorted runs (keys 2i and 2i + 1) for the autotuner.
@@ -145,9 +152,11 @@ hipError_t launch_scan(const uint32_t* counts, uint32_t nq, uint64_t* offsets,
                        uint64_t* scan_status, uint32_t* fault, hipStream_t stream,
                        const KTimer* t);
 
-// Range emission pass: writes each query's live pairs at offsets[q].
+// Range emission pass: writes each query's live pairs at offsets[q], for
+// the queries whose pairs end at or before cap.
 hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi,
                              uint32_t nq, const uint64_t* offsets, uint32_t* out_keys,
-                             uint32_t* out_vals, hipStream_t stream, const KTimer* t);
+                             uint32_t* out_vals, uint64_t cap, hipStream_t stream,
+                             const KTimer* t);
 
 }  // namespace lsm

@@ -518,10 +518,23 @@ __global__ __launch_bounds__(kThreads) void k_stage(const uint32_t* keys, const 
   stage_val[at + i] = st ? vals[i] : 0u;
 }
 
-__global__ __launch_bounds__(kThreads) void k_check_keys(const uint32_t* keys, uint32_t n,
-                                                         uint32_t limit_bits, uint32_t* err) {
+__global__ __launch_bounds__(kThreads) void k_stage_encoded(const uint32_t* kv, const uint32_t* vals,
+                                                            uint32_t n, uint32_t* stage_kv,
+                                                            uint32_t* stage_val, uint32_t at) {
   const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
-  if (i < n && (keys[i] >> limit_bits) != 0u) atomicOr(err, 1u);
+  if (i >= n) return;
+  const uint32_t x = kv[i];
+  stage_kv[at + i] = x;
+  stage_val[at + i] = (x & 1u) ? vals[i] : 0u;  // tombstones carry value 0
+}
+
+__global__ __launch_bounds__(kThreads) void k_check_keys(const uint32_t* keys, uint32_t n,
+                                                         uint32_t limit_bits, int encoded,
+                                                         uint32_t* err) {
+  const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = encoded ? (keys[i] >> 1) : keys[i];
+  if ((k >> limit_bits) != 0u) atomicOr(err, 1u);
 }
 
 __global__ __launch_bounds__(kThreads) void k_fill_runs(uint32_t* a_kv, uint32_t* a_val,
@@ -629,15 +642,16 @@ __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const
                                                               const uint32_t* hi, uint32_t nq,
                                                               const uint64_t* offsets,
                                                               uint32_t* out_keys,
-                                                              uint32_t* out_vals) {
+                                                              uint32_t* out_vals, uint64_t cap) {
   const uint32_t i = blockIdx.x * kQueryThreads + threadIdx.x;
   if (i >= nq) return;
   const uint64_t o = offsets[i];
   // The walk writes exactly offsets[i+1] - offsets[i] pairs (the same walk
-  // produced the count); the limits only guard against offsets corrupted by
-  // a timed-out scan.
+  // produced the count).  A query whose pairs would end beyond cap writes
+  // nothing (the caller sees offsets[i+1] > cap); the other limits only
+  // guard against offsets corrupted by a timed-out scan.
   const uint64_t e = offsets[i + 1];
-  if (e < o || e > offsets[nq]) return;
+  if (e < o || e > offsets[nq] || e > cap) return;
   range_walk<true>(lv, lo[i], hi[i], out_keys + o, out_vals + o, e - o);
 }
 
@@ -806,11 +820,19 @@ hipError_t launch_stage(const uint32_t* keys, const uint32_t* vals, uint32_t n, 
                 stage_kv, stage_val, at);
 }
 
-hipError_t launch_check_keys(const uint32_t* keys, uint32_t n, uint32_t limit_bits,
+hipError_t launch_stage_encoded(const uint32_t* kv, const uint32_t* vals, uint32_t n,
+                                uint32_t* stage_kv, uint32_t* stage_val, uint32_t at,
+                                hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  return launch(k_stage_encoded, grid_for(n, kThreads), kThreads, stream, nullptr, kv, vals, n,
+                stage_kv, stage_val, at);
+}
+
+hipError_t launch_check_keys(const uint32_t* keys, uint32_t n, uint32_t limit_bits, int encoded,
                              uint32_t* err, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   return launch(k_check_keys, grid_for(n, kThreads), kThreads, stream, nullptr, keys, n,
-                limit_bits, err);
+                limit_bits, encoded, err);
 }
 
 hipError_t launch_fill_runs(uint32_t* a_kv, uint32_t* a_val, uint32_t* b_kv, uint32_t* b_val,
@@ -847,10 +869,11 @@ hipError_t launch_scan(const uint32_t* counts, uint32_t nq, uint64_t* offsets,
 
 hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi,
                              uint32_t nq, const uint64_t* offsets, uint32_t* out_keys,
-                             uint32_t* out_vals, hipStream_t stream, const KTimer* t) {
+                             uint32_t* out_vals, uint64_t cap, hipStream_t stream,
+                             const KTimer* t) {
   if (nq == 0) return hipSuccess;
   return launch(k_range_emit, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi,
-                nq, offsets, out_keys, out_vals);
+                nq, offsets, out_keys, out_vals, cap);
 }
 
 }  // namespace lsm

@@ -81,6 +81,8 @@ _SIGNATURES = {
     "lsm_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Stats)]),
     "lsm_submit": (ctypes.c_int, [_vp, _vp, _vp, _u32, ctypes.c_int]),
     "lsm_flush": (ctypes.c_int, [_vp]),
+    "lsm_submit_encoded": (ctypes.c_int, [_vp, _vp, _vp, _u32]),
+    "lsm_range_async": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _u64]),
     "lsm_pending": (_u32, [_vp]),
     "lsm_set_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lsm_autotune": (ctypes.c_int, [_vp, _u32, _u32]),
@@ -212,6 +214,21 @@ class LSM:
         vp = _dev(vals, "vals") if (vals is not None and not delete) else None
         _check(self._lib.lsm_submit(self._h, _dev(keys, "keys"), vp, n, 1 if delete else 0),
                "lsm_submit")
+
+    def submit_encoded(self, kv: torch.Tensor, vals: torch.Tensor) -> None:
+        """Arrival-ordered operations as key variables (key << 1 | status,
+        status 0 = delete) with values."""
+        if kv.numel() != vals.numel():
+            raise ValueError("kv and vals differ in length")
+        _check(self._lib.lsm_submit_encoded(self._h, _dev(kv, "kv"), _dev(vals, "vals"),
+                                            kv.numel()), "lsm_submit_encoded")
+
+    def range_async(self, lo, hi, offsets, keys, vals, cap: int) -> None:
+        _check(self._lib.lsm_range_async(self._h, _dev(lo, "lo"), _dev(hi, "hi"), lo.numel(),
+                                         _dev(offsets, "offsets", (torch.int64,)),
+                                         keys.data_ptr() if keys is not None else None,
+                                         vals.data_ptr() if vals is not None else None, int(cap)),
+               "lsm_range_async")
 
     def flush(self) -> None:
         _check(self._lib.lsm_flush(self._h), "lsm_flush")

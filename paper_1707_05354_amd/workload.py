@@ -267,3 +267,85 @@ def batching_stream(config: int = 4, n_batches: int = 4096, median: int = 4096,
         out.append((k, v, dele))
         off += n
     return out
+
+
+# ---------------------------------------------------------------- serving
+SERVING_KINDS = ("lookup", "count", "range", "insert", "delete")
+SERVING_MIX = (0.50, 0.10, 0.10, 0.25, 0.05)
+
+
+@dataclass
+class ServingRequests:
+    """Arrival-ordered requests.  Request r has kind[r] (index into
+    SERVING_KINDS), size[r] operations and arrives at t_arrive[r] seconds.
+    Payloads are laid out per kind in arrival order, so the requests of one
+    kind admitted together form one contiguous slice: lookup_keys,
+    count_lo/hi, range_lo/hi; inserts and deletes share one update stream of
+    key variables (key << 1 | 1 for an insert, key << 1 for a delete) and
+    values.  off[r] is the request's first element in its kind's stream."""
+    t_arrive: np.ndarray
+    kind: np.ndarray
+    size: np.ndarray
+    off: np.ndarray
+    lookup_keys: np.ndarray
+    count_lo: np.ndarray
+    count_hi: np.ndarray
+    range_lo: np.ndarray
+    range_hi: np.ndarray
+    upd_kv: np.ndarray
+    upd_val: np.ndarray
+    width: int
+
+    @property
+    def n(self) -> int:
+        return int(self.kind.size)
+
+
+def resident(config: int = 5, b: int = 1 << 16, R: int = 4096):
+    """The resident dictionary: R insert batches of b uniform 31-bit keys."""
+    return (uniform_keys(config, 1, 0, R * b).reshape(R, b),
+            values(config, 2, 0, R * b).reshape(R, b))
+
+
+def serving_requests(resident_keys: np.ndarray, n_requests: int, rate: float, config: int = 5,
+                     max_size: int = 8192, expected_hits: int = 32,
+                     mix=SERVING_MIX) -> ServingRequests:
+    """Poisson arrivals at `rate` requests/s; kinds drawn with probabilities
+    `mix`; sizes log-uniform in [1, max_size]; lookups half drawn from the
+    resident keys; count/range width so about `expected_hits` resident keys
+    fall inside; inserts of fresh uniform keys; deletes of resident keys."""
+    u = (splitmix64(config, 20, 0, n_requests) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    t = np.cumsum(-np.log1p(-u) / rate)
+    c = (splitmix64(config, 21, 0, n_requests) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    kind = np.searchsorted(np.cumsum(mix), c, side="right").clip(0, len(mix) - 1).astype(np.uint8)
+    s = (splitmix64(config, 22, 0, n_requests) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    size = np.clip(np.floor(np.exp(s * np.log(max_size + 1))), 1, max_size).astype(np.int64)
+    off = np.zeros(n_requests, np.int64)
+    res = resident_keys.reshape(-1)
+    width = max(1, int(round(expected_hits * KEY_DOMAIN / res.size)))
+    totals = []
+    for k in range(len(SERVING_KINDS)):
+        sel = kind == k
+        if k == 4:  # deletes share the update stream with inserts
+            continue
+        off[sel] = np.concatenate([[0], np.cumsum(size[sel])[:-1]]) if sel.any() else 0
+        totals.append(int(size[sel].sum()))
+    upd = (kind == 3) | (kind == 4)
+    off[upd] = np.concatenate([[0], np.cumsum(size[upd])[:-1]]) if upd.any() else 0
+    n_lk, n_ct, n_rg = totals[0], totals[1], totals[2]
+    pick = splitmix64(config, 23, 0, n_lk)
+    hit = (pick & np.uint64(1)).astype(bool)
+    idx = ((pick >> np.uint64(32)) * np.uint64(res.size)) >> np.uint64(32)
+    lookup_keys = np.where(hit, res[idx.astype(np.int64)], uniform_keys(config, 24, 0, n_lk))
+    starts = bounded(config, 25, 0, n_ct + n_rg, KEY_DOMAIN - width + 1).astype(np.uint32)
+    n_upd = int(size[upd].sum())
+    ins_keys = uniform_keys(config, 26, 0, n_upd)
+    del_pick = bounded(config, 27, 0, n_upd, res.size)
+    upd_is_del = np.repeat(kind[upd] == 4, size[upd])
+    upd_keys = np.where(upd_is_del, res[del_pick], ins_keys).astype(np.uint32)
+    upd_kv = (upd_keys << np.uint32(1)) | (~upd_is_del).astype(np.uint32)
+    upd_val = values(config, 28, 0, n_upd)
+    return ServingRequests(t, kind, size, off, lookup_keys.astype(np.uint32),
+                           starts[:n_ct], starts[:n_ct] + np.uint32(width - 1),
+                           starts[n_ct:], starts[n_ct:] + np.uint32(width - 1),
+                           upd_kv.astype(np.uint32), upd_val, width)

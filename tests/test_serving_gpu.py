@@ -1,0 +1,140 @@
+"""GPU tests of the serving form: every query request's answer, taken from
+the mix of concurrently admitted requests, equals (a) the map oracle
+replaying the epoch log (queries of an epoch see every update of earlier
+epochs, in arrival order, and none of their own epoch's) and (b) the same
+request served alone against a dictionary rebuilt to that state.  Integer
+results: tolerance 0."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1707_05354_amd import workload as W
+from paper_1707_05354_amd.lsm import LSM
+from paper_1707_05354_amd.serving import COUNT, DELETE, INSERT, LOOKUP, RANGE, Server
+from _gpu import dev, host, note
+
+pytestmark = pytest.mark.gpu
+
+
+def build(b, rk, rv, graphs=True):
+    g = LSM(b)
+    g.use_graphs(graphs)
+    kd, vd = dev(rk), dev(rv)
+    for i in range(rk.shape[0]):
+        g.insert(kd[i], vd[i])
+    return g
+
+
+def oracle_answer(m, reqs, q):
+    k, a, n = int(reqs.kind[q]), int(reqs.off[q]), int(reqs.size[q])
+    if k == LOOKUP:
+        return m.lookup(reqs.lookup_keys[a:a + n])
+    if k == COUNT:
+        return m.count(reqs.count_lo[a:a + n], reqs.count_hi[a:a + n])
+    off, keys, vals = m.range(reqs.range_lo[a:a + n], reqs.range_hi[a:a + n])
+    return off.astype(np.int64), keys, vals
+
+
+def apply_update(m, reqs, q):
+    a, n = int(reqs.off[q]), int(reqs.size[q])
+    kv, v = reqs.upd_kv[a:a + n], reqs.upd_val[a:a + n]
+    if reqs.kind[q] == INSERT:
+        m.insert(kv >> 1, v)
+    else:
+        m.delete(kv >> 1)
+
+
+def same(x, y):
+    if isinstance(x, tuple):
+        return all(np.array_equal(np.asarray(p).astype(np.int64), np.asarray(q).astype(np.int64))
+                   for p, q in zip(x, y))
+    return np.array_equal(np.asarray(x).astype(np.int64), np.asarray(y).astype(np.int64))
+
+
+def alone(b, rk, rv, reqs, q, upd_prefix):
+    """Serve request q by itself on a dictionary rebuilt from the resident
+    batches plus the first upd_prefix update operations."""
+    g = build(b, rk, rv, graphs=False)
+    if upd_prefix:
+        g.submit_encoded(dev(reqs.upd_kv[:upd_prefix]), dev(reqs.upd_val[:upd_prefix]))
+    k, a, n = int(reqs.kind[q]), int(reqs.off[q]), int(reqs.size[q])
+    if k == LOOKUP:
+        v, f = g.lookup(dev(reqs.lookup_keys[a:a + n]))
+        out = (host(v), host(f))
+    elif k == COUNT:
+        out = host(g.count(dev(reqs.count_lo[a:a + n]), dev(reqs.count_hi[a:a + n])))
+    else:
+        o, kk, vv = g.range(dev(reqs.range_lo[a:a + n]), dev(reqs.range_hi[a:a + n]))
+        out = (host(o).astype(np.int64), host(kk), host(vv))
+    g.sync()
+    g.close()
+    return out
+
+
+@pytest.mark.parametrize("realtime", [False, True])
+def test_mix_equals_epoch_oracle_and_alone(realtime):
+    b = 4096
+    rk, rv = W.resident(config=51, b=b, R=16)
+    reqs = W.serving_requests(rk, 600, rate=2e4, config=51, max_size=700, expected_hits=8)
+    note("serving mix realtime=%s" % realtime)
+    g = build(b, rk, rv)
+    srv = Server(g, reqs, max_epoch_ops=6000, in_flight=3, keep_results=True)
+    res = srv.run(realtime=realtime)
+    assert len(res.epochs) >= 5
+    assert np.all(np.isfinite(res.completion_s))
+    if realtime:
+        assert np.all(res.latency_s > 0)
+    m = oracle.MapOracle()
+    for i in range(rk.shape[0]):
+        m.insert(rk[i], rv[i])
+    upd_before = {}
+    done_upd = 0
+    for ep in res.epochs:
+        for q in range(ep.first, ep.last):
+            if reqs.kind[q] in (LOOKUP, COUNT, RANGE):
+                assert same(srv.results(res, q), oracle_answer(m, reqs, q)), (q, int(reqs.kind[q]))
+                upd_before[q] = done_upd
+        for q in range(ep.first, ep.last):
+            if reqs.kind[q] in (INSERT, DELETE):
+                apply_update(m, reqs, q)
+                done_upd += int(reqs.size[q])
+    # A sample of query requests, each served alone.
+    queries = sorted(upd_before)
+    rng = np.random.default_rng(3)
+    for q in rng.choice(queries, size=min(12, len(queries)), replace=False):
+        assert same(alone(b, rk, rv, reqs, int(q), upd_before[int(q)]), srv.results(res, int(q))), q
+    g.close()
+
+
+def test_result_pool_smaller_than_demand_still_exact():
+    """A result pool far smaller than the run's total range output forces
+    admission by memory (epochs wait for older ones to complete and free
+    their slots); answers stay exact."""
+    b = 2048
+    rk, rv = W.resident(config=52, b=b, R=8)
+    reqs = W.serving_requests(rk, 300, rate=1e5, config=52, max_size=300, expected_hits=4)
+    g = build(b, rk, rv)
+    cost = Server(g, reqs).range_cost
+    pool = int(cost.max()) + 10
+    note("serving small pool %d of %d" % (pool, int(cost.sum())))
+    srv = Server(g, reqs, max_epoch_ops=3000, in_flight=2, pool_elems=pool)
+    # Results are released as epochs retire, so check answers as we go via
+    # a second run that keeps results, on an identical dictionary.
+    res = srv.run(realtime=False)
+    assert len(res.epochs) > 3
+    g2 = build(b, rk, rv)
+    srv2 = Server(g2, reqs, max_epoch_ops=3000, in_flight=2, keep_results=True)
+    res2 = srv2.run(realtime=False)
+    m = oracle.MapOracle()
+    for i in range(rk.shape[0]):
+        m.insert(rk[i], rv[i])
+    for ep in res2.epochs:
+        for q in range(ep.first, ep.last):
+            if reqs.kind[q] in (LOOKUP, COUNT, RANGE):
+                assert same(srv2.results(res2, q), oracle_answer(m, reqs, q))
+        for q in range(ep.first, ep.last):
+            if reqs.kind[q] in (INSERT, DELETE):
+                apply_update(m, reqs, q)
+    g.close()
+    g2.close()
