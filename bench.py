@@ -189,6 +189,71 @@ def batching_form(torch, L, W, reps: int = 2):
     return res
 
 
+def serving_form(torch, L, W, n_requests: int = 40000, loads=(0.25, 0.5, 0.75, 0.9)):
+    """Resident dictionary of 2^28 pairs (4096 insert batches of 2^16),
+    Poisson arrivals of mixed requests (50% lookup, 10% count, 10% range of
+    width 256 (~32 hits), 25% insert, 5% delete; sizes log-uniform in
+    [1, 8192]), served by the continuous-batching loop.  First a saturation
+    run (everything arrived at t = 0) gives the capacity; then offered loads
+    at the given fractions of it.  Reports throughput and p50/p99 request
+    latency (completion - arrival) per point."""
+    from paper_1707_05354_amd import serving as S
+
+    b, R = 1 << 16, 4096
+    t0 = time.perf_counter()
+    rk, rv = W.resident(b=b, R=R)
+    reqs = W.serving_requests(rk, n_requests, rate=1.0)
+    base_t = reqs.t_arrive.copy()
+    kd = torch.from_numpy(rk.view(np.int32)).cuda()
+    vd = torch.from_numpy(rv.view(np.int32)).cuda()
+    log("serving: resident %d pairs, %d requests (%d ops) ready in %.1f s"
+        % (R * b, n_requests, int(reqs.size.sum()), time.perf_counter() - t0))
+    g = L.LSM(b)
+    g.use_graphs(True)
+    lib, h = g._lib, g._h
+    rows_k = [kd[i].data_ptr() for i in range(R)]
+    rows_v = [vd[i].data_ptr() for i in range(R)]
+
+    def rebuild():
+        g.clear()
+        for i in range(R):
+            rc = lib.lsm_insert_batch(h, rows_k[i], rows_v[i], b)
+            if rc:
+                raise L.LSMError(rc, "resident build")
+        g.sync()
+
+    def serve(realtime):
+        rebuild()
+        srv = S.Server(g, reqs, max_epoch_ops=1 << 20, in_flight=3)
+        res = srv.run(realtime=realtime)
+        span = max(res.completion_s.max() - (reqs.t_arrive[0] if realtime else 0.0), 1e-9)
+        del srv
+        return res, span
+
+    t1 = time.perf_counter()
+    reqs.t_arrive = np.zeros_like(base_t)
+    res, span = serve(False)
+    cap_rps = n_requests / span
+    sat = {"offered_rps": None, "throughput_rps": round(cap_rps), "M_ops_per_s": round(res.ops / span / 1e6, 2),
+           **{k: round(v, 3) for k, v in S.percentiles(res.latency_s).items()}, "epochs": len(res.epochs)}
+    log("serving saturation: %s" % sat)
+    points = [dict(sat, load="saturation")]
+    for f in loads:
+        rate = f * cap_rps
+        reqs.t_arrive = base_t / rate
+        res, span = serve(True)
+        p = {"load": f, "offered_rps": round(rate), "throughput_rps": round(n_requests / span),
+             "M_ops_per_s": round(res.ops / span / 1e6, 2),
+             **{k: round(v, 3) for k, v in S.percentiles(res.latency_s).items()},
+             "epochs": len(res.epochs)}
+        log("serving load %.2f: %s" % (f, p))
+        points.append(p)
+    g.close()
+    return {"resident_pairs": R * b, "requests": n_requests, "ops": int(reqs.size.sum()),
+            "mix": "50%% lookup, 10%% count, 10%% range (width %d), 25%% insert, 5%% delete" % reqs.width,
+            "points": points, "seconds": round(time.perf_counter() - t1, 1)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +265,8 @@ def main() -> int:
                     help="skip the Zipf batch-size sweep (b = 2^13..2^19 at n = 2^25)")
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the batching-form comparison (4096 log-normal user batches)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving form (resident 2^28 pairs, offered-load sweep)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 4 times (PMC byte calibration)")
     args = ap.parse_args()
@@ -397,6 +464,8 @@ def main() -> int:
         out["sweep"] = zipf_sweep(torch, L, W)
     if not args.no_batching:
         out["batching"] = batching_form(torch, L, W)
+    if not args.no_serving:
+        out["serving"] = serving_form(torch, L, W)
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w)

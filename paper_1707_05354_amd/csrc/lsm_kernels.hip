@@ -578,6 +578,28 @@ __global__ __launch_bounds__(kQueryThreads) void k_lookup(LevelSet lv, const uin
 
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;  // above every original key (< 2^31)
 
+// First index in (c, e) whose original key differs from k, where kv[c] has
+// key k: one probe for the common run of length 1, then a galloping search,
+// so long runs of one key (hot keys, padded batches) cost O(log run).
+__device__ __forceinline__ uint32_t skip_run(const uint32_t* kv, uint32_t c, uint32_t e,
+                                             uint32_t k) {
+  uint32_t lo = c + 1;  // kv[lo - 1] has key k
+  if (lo >= e || (kv[lo] >> 1) != k) return lo;
+  uint32_t step = 1;
+  // Invariant: kv[lo] has key k.
+  while (lo + step < e && (kv[lo + step] >> 1) == k) {
+    lo += step;
+    step <<= 1;
+  }
+  uint32_t hi = (lo + step < e) ? lo + step : e;  // key(hi) > k, or hi == e
+  while (hi - lo > 1) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if ((kv[mid] >> 1) == k) lo = mid;
+    else hi = mid;
+  }
+  return hi;
+}
+
 // Walk the candidate runs [lower_bound(k1), upper_bound(k2)) of all occupied
 // levels in key order.  For each distinct key the element met first is the
 // newest instance (smaller levels are newer, and inside a level a key's run
@@ -616,8 +638,8 @@ __device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, 
       ++count;
     }
     for (int l = mi; l < L; ++l) {
-      while (ck[l] == mk) {
-        ++cur[l];
+      if (ck[l] == mk) {
+        cur[l] = skip_run(lv.kv[l], cur[l], end[l], mk);
         ck[l] = cur[l] < end[l] ? (lv.kv[l][cur[l]] >> 1) : kNoKey;
       }
     }
