@@ -8,7 +8,8 @@ std::sort and std::merge), reached through ctypes with numpy arrays.
 * :class:`MapOracle` -- the dictionary of sec. I-B applied one operation at a
   time (the plain definition of every query answer).
 * :class:`CascadeOracle` -- the level layout produced by the insertion
-  algorithm of Fig. 2(a) / Fig. 3, step by step.
+  algorithm of Fig. 2(a) / Fig. 3, step by step, and by the cleanup of
+  sec. III-E / IV-D.
 
 Every function is pinned by ``tests/test_oracle_pins.py`` against brute force
 on tiny inputs, a closed form of the layout, the building invariants of
@@ -60,12 +61,15 @@ def _load():
             "om_lookup": (None, [vp, _u32p, ctypes.c_uint64, _u32p, _u8p]),
             "om_count": (None, [vp, _u32p, _u32p, ctypes.c_uint64, _u32p]),
             "om_range": (ctypes.c_uint64, [vp, _u32p, _u32p, ctypes.c_uint64, _u64p, _u32p, _u32p, ctypes.c_uint64]),
+            "om_successor": (None, [vp, _u32p, ctypes.c_uint64, _u32p, _u32p, _u8p]),
+            "om_predecessor": (None, [vp, _u32p, ctypes.c_uint64, _u32p, _u32p, _u8p]),
             "om_size": (ctypes.c_uint64, [vp]),
             "om_items": (None, [vp, _u32p, _u32p]),
             "oc_create": (vp, [ctypes.c_uint32]),
             "oc_destroy": (None, [vp]),
             "oc_insert": (ctypes.c_int, [vp, _u32p, _u32p, _u8p, ctypes.c_uint32]),
             "oc_insert_ordered": (ctypes.c_int, [vp, _u32p, _u32p, _u8p, ctypes.c_uint32]),
+            "oc_cleanup": (ctypes.c_uint64, [vp]),
             "oc_num_batches": (ctypes.c_uint64, [vp]),
             "oc_merged_last": (ctypes.c_uint64, [vp]),
             "oc_merged_total": (ctypes.c_uint64, [vp]),
@@ -145,6 +149,22 @@ class MapOracle:
                                offsets.ctypes.data_as(_u64p), _p32(keys), _p32(vals), total)
         return offsets, keys, vals
 
+    def _order(self, fn, q):
+        q = _u32(q)
+        keys = np.zeros(q.size, np.uint32)
+        vals = np.zeros(q.size, np.uint32)
+        found = np.zeros(q.size, np.uint8)
+        fn(self._h, _p32(q), q.size, _p32(keys), _p32(vals), found.ctypes.data_as(_u8p))
+        return keys, vals, found
+
+    def successor(self, q):
+        """(keys, vals, found): the pair with the smallest key > q."""
+        return self._order(self._lib.om_successor, q)
+
+    def predecessor(self, q):
+        """(keys, vals, found): the pair with the largest key < q."""
+        return self._order(self._lib.om_predecessor, q)
+
     def __len__(self) -> int:
         return int(self._lib.om_size(self._h))
 
@@ -192,6 +212,10 @@ class CascadeOracle:
         rc = self._lib.oc_insert_ordered(self._h, _p32(k), _p32(v), s.ctypes.data_as(_u8p), k.size)
         if rc != 0:
             raise ValueError("batch size must be in [1, b]")
+
+    def cleanup(self) -> int:
+        """Cleanup of sec. III-E / IV-D; returns the number of valid elements."""
+        return int(self._lib.oc_cleanup(self._h))
 
     @property
     def r(self) -> int:

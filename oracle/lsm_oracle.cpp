@@ -38,7 +38,15 @@
 //     order into one batch of b) must instead behave like its user batches
 //     applied one after another: it is sorted on the original key alone, the
 //     later position first, so the newest operation on a key wins whatever
-//     its type (oc_insert_ordered).
+//     its type (oc_insert_ordered);
+//   - successor(k) is the pair with the smallest key strictly greater than k
+//     and predecessor(k) the pair with the largest key strictly smaller than
+//     k (the order queries the footnote of sec. I-B names); none: not found;
+//   - cleanup's placebo elements (sec. IV-D footnote) are tombstones of the
+//     largest encodable key, 2^31 - 1, i.e. key variable 0xFFFFFFFE with
+//     value 0 (the footnote's 2^32 - 1 would carry the regular status bit);
+//     the redistributed list fills the occupied levels of the new batch count
+//     from the smallest level up, so smaller keys land in smaller levels.
 //
 // Build: g++ -O2 -std=c++17 -shared -fPIC lsm_oracle.cpp -o liblsm_oracle.so
 #include <algorithm>
@@ -158,6 +166,33 @@ uint64_t om_range(void* h, const uint32_t* lo, const uint32_t* hi, uint64_t nq,
   return total;
 }
 
+// Order queries (footnote of sec. I-B): successor = smallest key > k,
+// predecessor = largest key < k.  found = 0 leaves key and value 0.
+void om_successor(void* h, const uint32_t* q, uint64_t nq, uint32_t* keys, uint32_t* vals,
+                  uint8_t* found) {
+  const auto& m = static_cast<MapOracle*>(h)->m;
+  for (uint64_t i = 0; i < nq; ++i) {
+    auto it = m.upper_bound(q[i]);
+    const bool f = it != m.end();
+    found[i] = f ? 1 : 0;
+    keys[i] = f ? it->first : 0u;
+    vals[i] = f ? it->second : 0u;
+  }
+}
+
+void om_predecessor(void* h, const uint32_t* q, uint64_t nq, uint32_t* keys, uint32_t* vals,
+                    uint8_t* found) {
+  const auto& m = static_cast<MapOracle*>(h)->m;
+  for (uint64_t i = 0; i < nq; ++i) {
+    auto it = m.lower_bound(q[i]);
+    const bool f = it != m.begin();
+    if (f) --it;
+    found[i] = f ? 1 : 0;
+    keys[i] = f ? it->first : 0u;
+    vals[i] = f ? it->second : 0u;
+  }
+}
+
 uint64_t om_size(void* h) { return static_cast<MapOracle*>(h)->m.size(); }
 
 // All live pairs in ascending key order.
@@ -249,6 +284,45 @@ int oc_insert(void* h, const uint32_t* keys, const uint32_t* vals, const uint8_t
 int oc_insert_ordered(void* h, const uint32_t* keys, const uint32_t* vals, const uint8_t* status,
                       uint32_t n) {
   return insert_impl(h, keys, vals, status, n, false);
+}
+
+// CLEANUP (sec. III-E), by the bulk strategy of sec. IV-D: (1) merge the
+// occupied levels from the smallest to the largest, the accumulated newer
+// run first on equal original keys; (2) mark every element that is not the
+// first of its key run, and every tombstone, as stale; (3) compact the
+// valid elements, order kept; (4) pad with fewer than b placebos up to a
+// multiple of b; (5) slice the list into the levels of the new batch count.
+// Returns the number of valid elements.
+uint64_t oc_cleanup(void* h) {
+  auto* c = static_cast<CascadeOracle*>(h);
+  const uint64_t b = c->b;
+  std::vector<Elem> acc;
+  for (size_t i = 0; i < c->level.size(); ++i) {
+    if (((c->r >> i) & 1u) == 0) continue;
+    std::vector<Elem> out(acc.size() + c->level[i].size());
+    std::merge(acc.begin(), acc.end(), c->level[i].begin(), c->level[i].end(), out.begin(),
+               [](const Elem& x, const Elem& y) { return orig_key(x) < orig_key(y); });
+    acc.swap(out);
+  }
+  std::vector<Elem> valid;
+  for (size_t p = 0; p < acc.size(); ++p) {
+    const bool first = p == 0 || orig_key(acc[p - 1]) != orig_key(acc[p]);
+    if (first && (acc[p].kv & 1u)) valid.push_back(acc[p]);
+  }
+  const uint64_t v = valid.size();
+  const uint64_t r2 = (v + b - 1) / b;
+  valid.resize(r2 * b, Elem{0xFFFFFFFEu, 0u});
+  c->level.assign(64, std::vector<Elem>());
+  uint64_t off = 0;
+  for (int i = 0; i < 64 && (r2 >> i) != 0; ++i) {
+    if (((r2 >> i) & 1u) == 0) continue;
+    const uint64_t len = b << i;
+    c->level[i].assign(valid.begin() + off, valid.begin() + off + len);
+    off += len;
+  }
+  c->r = r2;
+  c->merged_elems_last = 0;
+  return v;
 }
 
 uint64_t oc_num_batches(void* h) { return static_cast<CascadeOracle*>(h)->r; }

@@ -10,6 +10,10 @@ what the paper fixes, small enough to check by eye:
   base = (r >> (i+1)) << (i+1) (the binary-counter picture of sec. III-B),
   ordered by original key, then newest batch first, then tombstone first,
   then later batch position first (building invariants of sec. III-D).
+* :func:`cleanup_layout` gives the levels right after a cleanup (sec. III-E,
+  IV-D) straight from the live set: its pairs in key order as regular
+  elements, padded with placebo tombstones of key 2^31 - 1 to a multiple of b,
+  then cut into the levels of the new batch count, smallest level first.
 * :func:`lookup_over_levels` / :func:`count_over_levels` /
   :func:`range_over_levels` read a layout the way sec. III-D and III-E (with
   the five count stages of sec. IV-C) describe, so a layout that breaks the
@@ -51,6 +55,25 @@ class LogBrute:
             return 0
         return sum(self.lookup(k)[1] for k in range(int(k1), min(int(k2), domain - 1) + 1))
 
+    def successor(self, k, domain):
+        """Smallest live key > k (scanning the domain upwards), or None."""
+        for x in range(int(k) + 1, domain):
+            v, f = self.lookup(x)
+            if f:
+                return x, v
+        return None
+
+    def predecessor(self, k, domain):
+        """Largest live key < k (scanning the domain downwards), or None."""
+        for x in range(min(int(k), domain) - 1, -1, -1):
+            v, f = self.lookup(x)
+            if f:
+                return x, v
+        return None
+
+    def live(self, domain):
+        return [(k, self.lookup(k)[0]) for k in range(domain) if self.lookup(k)[1]]
+
     def range(self, k1, k2, domain):
         out = []
         if k1 > k2:
@@ -91,6 +114,25 @@ def closed_form_levels(batches, b, status_in_sort=True):
             levels[i] = [((k << 1) | s, v) for (k, _t, _s, _p, s, v) in elems]
         i += 1
     return levels
+
+
+PLACEBO_KV = 0xFFFFFFFE                          # key 2^31 - 1, tombstone
+
+
+def cleanup_layout(live, b):
+    """live: [(key, val)] ascending by key.  Returns (r, {level: (kv, vals)})."""
+    r = -(-len(live) // b)
+    flat = [((k << 1) | 1, v) for k, v in live]
+    flat += [(PLACEBO_KV, 0)] * (r * b - len(live))
+    levels, off, i = {}, 0, 0
+    while (r >> i) != 0:
+        if (r >> i) & 1:
+            part = flat[off:off + (b << i)]
+            levels[i] = ([kv for kv, _ in part], [v for _, v in part])
+            off += b << i
+        i += 1
+    assert off == len(flat)
+    return r, levels
 
 
 def lookup_over_levels(levels, k):

@@ -32,6 +32,22 @@ MUTATIONS = [
     ("ordered_batch_sorts_on_status",
      "    const uint32_t kx = status_in_sort ? x.e.kv : (x.e.kv >> 1);",
      "    const uint32_t kx = x.e.kv;"),
+    ("cleanup_keeps_last_of_run",
+     "const bool first = p == 0 || orig_key(acc[p - 1]) != orig_key(acc[p]);",
+     "const bool first = p + 1 == acc.size() || orig_key(acc[p + 1]) != orig_key(acc[p]);"),
+    ("cleanup_merges_older_first",
+     "std::merge(acc.begin(), acc.end(), c->level[i].begin(), c->level[i].end(), out.begin(),",
+     "std::merge(c->level[i].begin(), c->level[i].end(), acc.begin(), acc.end(), out.begin(),"),
+    ("cleanup_placebo_regular", "valid.resize(r2 * b, Elem{0xFFFFFFFEu, 0u});",
+     "valid.resize(r2 * b, Elem{0xFFFFFFFFu, 0u});"),
+    ("cleanup_keeps_tombstones", "if (first && (acc[p].kv & 1u)) valid.push_back(acc[p]);",
+     "if (first) valid.push_back(acc[p]);"),
+    ("cleanup_large_keys_in_small_levels",
+     "c->level[i].assign(valid.begin() + off, valid.begin() + off + len);",
+     "c->level[i].assign(valid.end() - off - len, valid.end() - off);"),
+    ("successor_not_strict", "auto it = m.upper_bound(q[i]);", "auto it = m.lower_bound(q[i]);"),
+    ("predecessor_off_by_one", "    const bool f = it != m.begin();\n    if (f) --it;",
+     "    const bool f = it != m.end();"),
     ("lookup_miss_value", "      vals[i] = 0;\n      found[i] = 0;", "      vals[i] = 1;\n      found[i] = 0;"),
 ]
 

@@ -13,8 +13,8 @@ import numpy as np
 import pytest
 
 import oracle
-from _brute import (LogBrute, closed_form_levels, count_over_levels,
-                    lookup_over_levels, range_over_levels)
+from _brute import (PLACEBO_KV, LogBrute, cleanup_layout, closed_form_levels,
+                    count_over_levels, lookup_over_levels, range_over_levels)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -332,3 +332,136 @@ def test_coalesced_insert_after_delete_in_one_batch():
     casc2 = oracle.CascadeOracle(4)
     casc2.insert([5, 5, 2, 7], [0, 99, 1, 2], [0, 1, 1, 1])
     assert lookup_over_levels(_layout(casc2), 5) == (0, 0)
+
+
+# ------------------------------------------------------------ order queries
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_successor_predecessor_vs_log_brute(seed):
+    rng = np.random.default_rng(500 + seed)
+    domain = 24
+    ops = _rand_ops(rng, 4, 10, domain, p_delete=0.35, p_mixed=0.1)
+    m, brute, _c, _h = _apply(ops, 4)
+    q = np.arange(0, domain + 3, dtype=np.uint32)
+    sk, sv, sf = m.successor(q)
+    pk, pv, pf = m.predecessor(q)
+    for i, k in enumerate(q.tolist()):
+        s = brute.successor(k, domain)
+        assert (int(sf[i]), int(sk[i]), int(sv[i])) == ((1, s[0], s[1]) if s else (0, 0, 0)), k
+        p = brute.predecessor(k, domain)
+        assert (int(pf[i]), int(pk[i]), int(pv[i])) == ((1, p[0], p[1]) if p else (0, 0, 0)), k
+
+
+def test_order_queries_at_the_ends_of_the_key_space():
+    m = oracle.MapOracle()
+    top = 2**31 - 1
+    m.insert([0, 5, top], [10, 50, 70])
+    k, v, f = m.successor([top, top - 1, 0, 2**32 - 1])
+    assert f.tolist() == [0, 1, 1, 0] and k.tolist() == [0, top, 5, 0] and v.tolist() == [0, 70, 50, 0]
+    k, v, f = m.predecessor([0, 1, 6, 2**32 - 1])
+    assert f.tolist() == [0, 1, 1, 1] and k.tolist() == [0, 0, 5, top] and v.tolist() == [0, 10, 50, 70]
+
+
+# ------------------------------------------------------------ cleanup
+def _cleanup_case(seed, b, nbatch, domain):
+    rng = np.random.default_rng(seed)
+    ops = _rand_ops(rng, b, nbatch, domain, p_delete=0.3, p_mixed=0.1)
+    return _apply(ops, b)
+
+
+@pytest.mark.parametrize("b", [1, 2, 3, 4, 5])
+def test_cleanup_layout_is_the_live_set_sliced(b):
+    for seed in range(8):
+        m, brute, casc, _h = _cleanup_case(700 + 10 * b + seed, b, 9 + seed, 20)
+        live = brute.live(20)
+        v = casc.cleanup()
+        assert v == len(live) == len(m)
+        r, expect = cleanup_layout(live, b)
+        assert casc.r == r
+        assert _layout(casc) == {i: (kv, vals) for i, (kv, vals) in expect.items()}
+        for i in range(64):
+            if i not in expect:
+                assert casc.level(i)[0].size == 0
+
+
+@pytest.mark.parametrize("b", [2, 3, 4])
+def test_cleanup_keeps_every_answer_and_later_batches_still_work(b):
+    domain = 20
+    for seed in range(6):
+        rng = np.random.default_rng(900 + 7 * b + seed)
+        ops = _rand_ops(rng, b, 11, domain, p_delete=0.3, p_mixed=0.1)
+        m, brute, casc, _h = _apply(ops, b)
+        casc.cleanup()
+        more = _rand_ops(rng, b, 7, domain, p_delete=0.3, p_mixed=0.1)
+        for step in range(len(more) + 1):
+            lay = {i: casc.level(i) for i in casc.occupied()}
+            lay = {i: (kv.tolist(), v.tolist()) for i, (kv, v) in lay.items()}
+            for k in range(domain):
+                assert lookup_over_levels(lay, k) == brute.lookup(k), (seed, step, k)
+            for k1 in range(0, domain, 3):
+                for k2 in range(k1, domain + 2, 4):
+                    assert range_over_levels(lay, k1, k2) == brute.range(k1, k2, domain)
+            for i, (kv, _v) in lay.items():
+                keys = [x >> 1 for x in kv]
+                assert keys == sorted(keys) and len(kv) == b << i
+            if step == len(more):
+                break
+            kind, keys, vals, dele = more[step]
+            if kind == "insert":
+                brute.insert(keys, vals); casc.insert(keys, vals)
+            elif kind == "delete":
+                brute.delete(keys); casc.delete(keys)
+            else:
+                brute.mixed(keys, vals, dele); casc.insert(keys, vals, (1 - dele).astype(np.uint8))
+
+
+def test_cleanup_structure_properties():
+    """No stale element survives, placebos are fewer than b and sit at the end
+    of the largest level, and smaller keys lie in smaller levels."""
+    b = 8
+    m, brute, casc, _h = _cleanup_case(31, b, 40, 200)
+    casc.cleanup()
+    occ = casc.occupied()
+    assert occ and casc.r == -(-len(m) // b)
+    prev_max = -1
+    placebos = 0
+    for i in occ:
+        kv, v = casc.level(i)
+        real = kv[kv != PLACEBO_KV]
+        if i != occ[-1]:
+            assert real.size == kv.size
+        else:
+            tail = kv[real.size:]
+            assert np.all(tail == PLACEBO_KV) and np.all(v[real.size:] == 0)
+            placebos = tail.size
+        assert np.all(real & 1 == 1)
+        keys = (real >> 1).astype(np.int64)
+        assert np.all(np.diff(keys) > 0)
+        assert keys.size == 0 or keys[0] > prev_max
+        if keys.size:
+            prev_max = keys[-1]
+    assert placebos < b
+    assert placebos == casc.r * b - len(m)
+
+
+def test_cleanup_special_cases():
+    b = 4
+    c = oracle.CascadeOracle(b)
+    assert c.cleanup() == 0 and c.r == 0 and c.occupied() == []
+    c.insert([1, 2, 3], [7, 8, 9])
+    c.delete([3, 2, 1])
+    assert c.cleanup() == 0 and c.r == 0 and c.occupied() == []
+    # A live key 2^31 - 1 is not hidden by the placebos of its own key.
+    top = 2**31 - 1
+    c.insert([top, 4], [11, 12])
+    assert c.cleanup() == 2 and c.r == 1
+    kv, v = c.level(0)
+    assert kv.tolist() == [(4 << 1) | 1, (top << 1) | 1, PLACEBO_KV, PLACEBO_KV]
+    assert v.tolist() == [12, 11, 0, 0]
+    lay = {0: (kv.tolist(), v.tolist())}
+    assert lookup_over_levels(lay, top) == (11, 1)
+    assert count_over_levels(lay, 0, top) == 2
+    # After a newer delete of that key, it is gone.
+    c.delete([top])
+    lay = {i: tuple(a.tolist() for a in c.level(i)) for i in c.occupied()}
+    assert lookup_over_levels(lay, top) == (0, 0)
+    assert count_over_levels(lay, 0, top) == 1
