@@ -116,6 +116,138 @@ def zipf_sweep(torch, L, W, reps: int = 2):
     return res
 
 
+def cleanup_form(torch, L, W, reps: int = 2):
+    """Cleanup (sec. III-E / IV-D) at the sizes of sec. V-E: n = 63 b with
+    b = 2^20 and n = 127 b with b = 2^19, 10 % and 50 % of the resident
+    elements stale (replaced duplicates); elements processed per second =
+    resident elements / cleanup time (whole call, host read-back included).
+    Then the query effect at b = 2^18, n = 127 b, 10 % stale: 2^25 lookups
+    before, cleanup, the same lookups after."""
+    res = {"points": []}
+    for lb, R, stale in ((20, 63, 0.1), (20, 63, 0.5), (19, 127, 0.1), (19, 127, 0.5)):
+        b = 1 << lb
+        w = W.cleanup_build(b, R, stale, nq=1 << 10)
+        kd = torch.from_numpy(w.keys.view(np.int32)).cuda()
+        vd = torch.from_numpy(w.vals.view(np.int32)).cuda()
+        g = L.LSM(b)
+        best, v = None, 0
+        for rep in range(reps + 1):
+            g.clear()
+            for i in range(R):
+                g.insert(kd[i], vd[i])
+            g.sync()
+            torch.cuda.synchronize()
+            if rep == reps:
+                g.profile(True)
+                g.profile_read(reset=True)
+            t0 = time.perf_counter()
+            v = g.cleanup()
+            dt = time.perf_counter() - t0
+            if rep < reps:
+                best = dt if best is None else min(best, dt)
+        prof = g.profile_read(reset=True)
+        g.profile(False)
+        ks = {}
+        for k, name in enumerate(L.KERNEL_NAMES):
+            if prof.launches[k]:
+                ks[name] = {"launches": int(prof.launches[k]), "ms": round(prof.kernel_ms[k], 3),
+                            "GB_per_s": round(prof.kernel_bytes[k] / max(1e-12, prof.kernel_ms[k] * 1e-3) / 1e9, 1)}
+        byts = sum(prof.kernel_bytes)
+        kms = sum(prof.kernel_ms)
+        res["points"].append({
+            "b": b, "batches": R, "resident": R * b, "valid": v,
+            "removed_frac": round(1 - v / (R * b), 4), "levels_after": g.occupied(),
+            "ms": round(best * 1e3, 3), "M_elements_per_s": round(R * b / best / 1e6, 1),
+            "kernel_ms": round(kms, 3), "algorithmic_GB_per_s": round(byts / max(1e-12, kms * 1e-3) / 1e9, 1),
+            "kernels": ks})
+        log("cleanup: %s" % res["points"][-1])
+        g.close()
+        del kd, vd
+    b, R = 1 << 18, 127
+    w = W.cleanup_build(b, R, 0.1, nq=1 << 25)
+    kd = torch.from_numpy(w.keys.view(np.int32)).cuda()
+    vd = torch.from_numpy(w.vals.view(np.int32)).cuda()
+    qd = torch.from_numpy(w.lookups.view(np.int32)).cuda()
+    lv = torch.empty(qd.numel(), dtype=torch.int32, device="cuda")
+    lf = torch.empty(qd.numel(), dtype=torch.uint8, device="cuda")
+    g = L.LSM(b)
+    for i in range(R):
+        g.insert(kd[i], vd[i])
+    g.lookup(qd, out=(lv, lf))
+    g.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.lookup(qd, out=(lv, lf))
+    torch.cuda.synchronize()
+    before = time.perf_counter() - t0
+    f_before = lf.clone()
+    levels_before = g.occupied()
+    t0 = time.perf_counter()
+    g.cleanup()
+    clean = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g.lookup(qd, out=(lv, lf))
+    torch.cuda.synchronize()
+    after = time.perf_counter() - t0
+    assert bool(torch.equal(f_before, lf))
+    res["lookups"] = {"b": b, "batches": R, "lookups": qd.numel(), "levels_before": levels_before,
+                      "levels_after": g.occupied(), "before_ms": round(before * 1e3, 3),
+                      "cleanup_ms": round(clean * 1e3, 3), "after_ms": round(after * 1e3, 3),
+                      "speedup_incl_cleanup": round(before / (clean + after), 2),
+                      "hit_rate": round(float(lf.float().mean().item()), 4)}
+    log("cleanup lookups: %s" % res["lookups"])
+    g.close()
+    res["context"] = ("paper (K40c): cleanup 1870.2 / 1828.2 M elements/s at n=63*2^20 with "
+                      "10 / 50 % removed; 1842.5 / 1794.3 at n=127*2^19; at b=2^18, n=127b, "
+                      "32 M lookups 4.8x faster after cleanup, cleanup time included")
+    return res
+
+
+def bulk_form(torch, L, W, reps: int = 2):
+    """Bulk build (sec. V-B): n uniform pairs loaded into an empty dictionary
+    with one lsm_bulk_insert call (b = 2^16; n = 2^26 and the 2^28 resident
+    set of the serving form), against the same pairs as 1024 / 4096
+    sequential insert batches.  Elements per second, whole call."""
+    res = []
+    for R in (1024, 4096):
+        b = 1 << 16
+        n = R * b
+        kd = torch.from_numpy(W.uniform_keys(7, 1, 0, n).view(np.int32)).cuda()
+        vd = torch.from_numpy(W.values(7, 2, 0, n).view(np.int32)).cuda()
+        g = L.LSM(b)
+        lib, h = g._lib, g._h
+        best_bulk, best_seq = None, None
+        for _ in range(reps):
+            g.clear()
+            g.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.bulk_insert(kd, vd)
+            dt = time.perf_counter() - t0
+            best_bulk = dt if best_bulk is None else min(best_bulk, dt)
+            levels = g.occupied()
+            g.clear()
+            g.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(R):
+                rc = lib.lsm_insert_batch(h, kd.data_ptr() + 4 * i * b, vd.data_ptr() + 4 * i * b, b)
+                if rc:
+                    raise L.LSMError(rc, "insert")
+            g.sync()
+            dt = time.perf_counter() - t0
+            best_seq = dt if best_seq is None else min(best_seq, dt)
+        res.append({"b": b, "pairs": n, "levels": levels,
+                    "bulk_ms": round(best_bulk * 1e3, 3),
+                    "bulk_M_elements_per_s": round(n / best_bulk / 1e6, 1),
+                    "sequential_ms": round(best_seq * 1e3, 3),
+                    "sequential_M_elements_per_s": round(n / best_seq / 1e6, 1)})
+        log("bulk: %s" % res[-1])
+        g.close()
+        del kd, vd
+    return {"points": res, "context": "paper (K40c): bulk build 770 M elements/s (key-value radix sort)"}
+
+
 def batching_form(torch, L, W, reps: int = 2):
     """4096 user batches, log-normal sizes (median 4096, sigma 1, clipped to
     [256, 65536]), uniform keys, every tenth a delete batch: the plain path
@@ -267,6 +399,8 @@ def main() -> int:
                     help="skip the batching-form comparison (4096 log-normal user batches)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving form (resident 2^28 pairs, offered-load sweep)")
+    ap.add_argument("--no-cleanup", action="store_true",
+                    help="skip the cleanup measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 4 times (PMC byte calibration)")
     args = ap.parse_args()
@@ -383,6 +517,29 @@ def main() -> int:
     g.sync()
     log("profiled step: %.1f ms" % ev[0].elapsed_time(ev[4]))
 
+    # Order queries (successor / predecessor) on the final state, same keys
+    # as the lookups; best of two runs each, outside the step.
+    ok_ = torch.empty(nq, dtype=torch.int32, device="cuda")
+    ov_ = torch.empty(nq, dtype=torch.int32, device="cuda")
+    of_ = torch.empty(nq, dtype=torch.uint8, device="cuda")
+    order = {}
+    for name in ("successor", "predecessor"):
+        fn = getattr(lib, "lsm_" + name)
+        best = None
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rc = fn(h, q_d.data_ptr(), nq, ok_.data_ptr(), ov_.data_ptr(), of_.data_ptr())
+            e1.record()
+            torch.cuda.synchronize()
+            if rc:
+                raise L.LSMError(rc, name)
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        order[name] = {"value": round(nq / (best * 1e-3) / 1e6, 2), "unit": "M queries/s",
+                       "found_rate": round(float(of_.float().mean().item()), 4)}
+    log("order queries: %s" % order)
+
     K = args.steps
     upd_ms, lk_ms, ct_ms, rg_ms = (phase / K).tolist()
     n_upd = w.R * w.b
@@ -406,6 +563,20 @@ def main() -> int:
     dom = max(range(len(L.KERNEL_NAMES)), key=lambda k: prof.kernel_ms[k])
     dom_bytes, dom_ms, dom_n = prof.kernel_bytes[dom], prof.kernel_ms[dom], int(prof.launches[dom])
     dom_gbs = dom_bytes / (dom_ms * 1e-3) / 1e9
+    # HBM bytes per launch from the committed counter summary, when it was
+    # taken with the current kernel source (else null).
+    from paper_1707_05354_amd import profsum
+    tr = profsum.load_traffic(os.path.join(ROOT, "profiles", "paper_scale_b65536_hbm_traffic.md"))
+    traffic, traffic_detail = None, None
+    if tr is not None and L.KERNEL_NAMES[dom] in tr["kernels"]:
+        kt = tr["kernels"][L.KERNEL_NAMES[dom]]
+        traffic = round(kt["fetch_bytes_per_launch"] + kt["write_bytes_per_launch"])
+        traffic_detail = {"unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                  "copy-calibrated)",
+                          "fetch": round(kt["fetch_bytes_per_launch"]),
+                          "write": round(kt["write_bytes_per_launch"]),
+                          "algorithmic": round(dom_bytes / max(1, dom_n)),
+                          "traffic_over_algorithmic": round(traffic / max(1.0, dom_bytes / max(1, dom_n)), 3)}
     merge_gbs = prof.kernel_bytes[2] / max(1e-12, prof.kernel_ms[2] * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -432,6 +603,7 @@ def main() -> int:
                    "mean_count": round(mean_count, 3)},
         "ranges": {"value": round(nr / (rg_ms * 1e-3) / 1e6, 2), "unit": "M ranges/s",
                    "pairs_returned": range_total},
+        "order_queries": order,
         "update_latency_ms": {"p50": round(prof.update_p50_ms, 4),
                               "p99": round(prof.update_p99_ms, 4),
                               "max": round(prof.update_max_ms, 4)},
@@ -446,7 +618,8 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_detail": traffic_detail,
             "launches": dom_n,
             "avg_launch_us": round(dom_ms / max(1, dom_n) * 1e3, 3),
             "bytes_per_launch": round(dom_bytes / max(1, dom_n)),
@@ -466,6 +639,9 @@ def main() -> int:
         out["batching"] = batching_form(torch, L, W)
     if not args.no_serving:
         out["serving"] = serving_form(torch, L, W)
+    if not args.no_cleanup:
+        out["cleanup"] = cleanup_form(torch, L, W)
+        out["bulk"] = bulk_form(torch, L, W)
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w)

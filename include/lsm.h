@@ -224,6 +224,61 @@ LSM_API lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_
                        uint32_t* d_vals, uint64_t cap, uint64_t* h_total);
 
 /*
+ * lsm_bulk_insert -- many insert batches in one call (the bulk build of
+ * sec. V-B and its footnote on inserting several batches into a non-empty
+ * structure): the n pairs (d_keys[i], d_vals[i]) are exactly ceil(n / b)
+ * consecutive insert batches of b elements in array order, the last one
+ * partial (padded as lsm_insert_batch pads), so the resulting levels are
+ * byte for byte those of the equivalent lsm_insert_batch calls.  Each level
+ * of the new batch count that receives new batches is built once: its new
+ * batches are sorted together, then merged with the old levels it takes
+ * over.  From an empty dictionary this is a sort per level and no merge.
+ *   d_keys, d_vals : n keys and values (device), read only.
+ * n == 0 is a no-op.  Allocates scratch for the call (the sort's ping-pong
+ * and look-back words for the largest level built, two merge buffers when
+ * old levels are taken over) and frees it before returning; synchronises
+ * the stream.  LSM_EINVAL, LSM_EKEY (checked mode; nothing changed),
+ * LSM_ENOMEM (nothing changed), LSM_ECAPACITY (n >= 2^32 or a level above
+ * 2^31 elements), LSM_EHIP.
+ */
+LSM_API lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals,
+                                     uint64_t n);
+
+/*
+ * lsm_successor / lsm_predecessor -- the order queries that the footnote of
+ * sec. I-B names as straightforward extensions: for each of nq query keys,
+ * the live pair with the smallest key strictly greater than d_q[i]
+ * (successor) or the largest key strictly smaller than d_q[i]
+ * (predecessor).  Stale elements and tombstones are skipped exactly as
+ * COUNT skips them (sec. III-E).
+ *   d_q     : nq query keys (device; any 32-bit value).
+ *   d_keys  : nq outputs; the key found, or 0.
+ *   d_vals  : nq outputs; its value, or 0.
+ *   d_found : nq outputs; 1 when a pair exists, else 0.
+ * nq == 0 is a no-op.  Asynchronous.  LSM_EINVAL, LSM_EHIP.
+ */
+LSM_API lsm_status_t lsm_successor(lsm_t h, const uint32_t* d_q, uint32_t nq,
+                                   uint32_t* d_keys, uint32_t* d_vals, uint8_t* d_found);
+LSM_API lsm_status_t lsm_predecessor(lsm_t h, const uint32_t* d_q, uint32_t nq,
+                                     uint32_t* d_keys, uint32_t* d_vals, uint8_t* d_found);
+
+/*
+ * lsm_cleanup -- CLEANUP (sec. III-E) by the bulk strategy of sec. IV-D:
+ * removes every tombstone, every deleted element and every replaced
+ * duplicate, then rebuilds the levels.  The valid pairs, in ascending key
+ * order, are padded with fewer than b placebo elements (tombstones of key
+ * 2^31 - 1, which hide nothing) to r' = ceil(valid / b) batches and sliced
+ * into the levels of r' from the smallest level up, so smaller keys land in
+ * smaller levels.  Every query answer is unchanged; later batches insert on
+ * top of r' as usual.
+ *   h_valid : HOST pointer (may be NULL); receives the number of valid pairs.
+ * Allocates scratch of up to 2 r b (key, value) pairs for the call and frees
+ * it before returning; synchronises the stream.  LSM_EINVAL, LSM_ENOMEM
+ * (nothing changed), LSM_ECAPACITY (r b >= 2^32), LSM_EHIP.
+ */
+LSM_API lsm_status_t lsm_cleanup(lsm_t h, uint64_t* h_valid);
+
+/*
  * lsm_clear -- empty the dictionary (r = 0) and keep every allocation, so a
  * rebuild reuses the level memory.  Work already enqueued is unaffected.
  */
@@ -302,14 +357,17 @@ LSM_API lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out);
  * the events and returns the sums since the last reset.
  *
  * Kernel index k: 0 batch-sort histogram, 1 batch-sort digit pass, 2 level
- * merge, 3 lookup, 4 count, 5 range offset scan, 6 range emission.
+ * merge, 3 lookup, 4 count, 5 range offset scan, 6 range emission,
+ * 7 successor / predecessor, 8 cleanup mark-and-compact.
  * kernel_bytes[k] is the algorithmic traffic of those launches: 8 B per
  * batch element for the histogram (key and value read), 16 B per element
  * for a digit pass (key and value read and written), 16 B per merge output
- * element, 12 B per scanned count; 0 for the search kernels, which are
+ * element, 12 B per scanned count; for cleanup 4 B per merged element to
+ * count, 8 B per merged element read plus 8 B per valid element written to
+ * scatter, 8 B per placebo; 0 for the search kernels, which are
  * latency-bound.
  */
-#define LSM_PROF_KERNELS 7
+#define LSM_PROF_KERNELS 9
 typedef struct {
   uint64_t update_calls;                   /* update calls (n > 0)          */
   uint64_t query_calls[3];                 /* lookup, count, range calls    */

@@ -20,6 +20,8 @@
 
 using namespace lsm;
 
+static_assert(LSM_PROF_KERNELS == kNumKernelKinds, "profile kernel kinds out of step");
+
 struct lsm_s {
   uint32_t b = 0;
   uint32_t flags = 0;
@@ -30,6 +32,7 @@ struct lsm_s {
 
   uint32_t* lvl_kv[kMaxLevels] = {};
   uint32_t* lvl_val[kMaxLevels] = {};
+  uint32_t* lvl_fence[kMaxLevels] = {};
 
   uint32_t* tmp_kv[2] = {};  // radix ping-pong, b elements each
   uint32_t* tmp_val[2] = {};
@@ -133,6 +136,7 @@ LevelSet occupied_levels(const lsm_t h) {
     if ((h->r >> i) & 1u) {
       s.kv[s.count] = h->lvl_kv[i];
       s.val[s.count] = h->lvl_val[i];
+      s.fence[s.count] = h->lvl_fence[i];
       s.len[s.count] = static_cast<uint32_t>(level_len(h, i));
       ++s.count;
     }
@@ -143,16 +147,20 @@ LevelSet occupied_levels(const lsm_t h) {
 lsm_status_t ensure_level(lsm_t h, int j) {
   if (h->lvl_kv[j] != nullptr) return LSM_OK;
   const size_t bytes = level_len(h, j) * sizeof(uint32_t);
-  void *k = nullptr, *v = nullptr;
+  const size_t fbytes = fence_len(level_len(h, j)) * sizeof(uint32_t);
+  void *k = nullptr, *v = nullptr, *f = nullptr;
   lsm_status_t s = dev_alloc(h, &k, bytes);
   if (s != LSM_OK) return s;
   s = dev_alloc(h, &v, bytes);
+  if (s == LSM_OK) s = dev_alloc(h, &f, fbytes);
   if (s != LSM_OK) {
     dev_free(h, k, bytes);
+    dev_free(h, v, bytes);
     return s;
   }
   h->lvl_kv[j] = static_cast<uint32_t*>(k);
   h->lvl_val[j] = static_cast<uint32_t*>(v);
+  h->lvl_fence[j] = static_cast<uint32_t*>(f);
   return LSM_OK;
 }
 
@@ -220,6 +228,7 @@ void release_all(lsm_t h) {
   for (int i = 0; i < kMaxLevels; ++i) {
     dev_free(h, h->lvl_kv[i], level_len(h, i) * sizeof(uint32_t));
     dev_free(h, h->lvl_val[i], level_len(h, i) * sizeof(uint32_t));
+    dev_free(h, h->lvl_fence[i], fence_len(level_len(h, i)) * sizeof(uint32_t));
   }
   for (int i = 0; i < 2; ++i) {
     dev_free(h, h->tmp_kv[i], bb);
@@ -317,6 +326,7 @@ SortArgs sort_args(lsm_t h, const BatchSrc& src, int j) {
   sa.tmp_val[1] = h->tmp_val[1];
   sa.out_kv = (j == 0) ? h->lvl_kv[0] : h->buf_kv;
   sa.out_val = (j == 0) ? h->lvl_val[0] : h->buf_val;
+  sa.out_fence = (j == 0) ? h->lvl_fence[0] : nullptr;
   return sa;
 }
 
@@ -334,7 +344,8 @@ hipError_t enqueue_cascade(lsm_t h, const SortArgs& sa, int j, hipStream_t s, Ti
     Timed mt;
     const KTimer* t = (last != nullptr) ? timer(h, mt, kKMerge, 2ull * len, 16.0 * 2.0 * len) : nullptr;
     const hipError_t e = launch_merge(cur_kv, cur_val, len, h->lvl_kv[i], h->lvl_val[i], len,
-                                      o_kv, o_val, h->merge_variant[i], s, t);
+                                      o_kv, o_val, (i == j - 1) ? h->lvl_fence[j] : nullptr,
+                                      h->merge_variant[i], s, t);
     if (e != hipSuccess) return e;
     if (t != nullptr) *last = mt;
     merged += 2ull * len;
@@ -379,7 +390,8 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
   Timed st[1 + kMaxPasses];
   KTimer sort_t[1 + kMaxPasses];
   bool timed = h->prof;
-  for (int p = 0; p <= sa.passes && timed; ++p) {
+  const int nk = sort_kernel_count(sa);
+  for (int p = 0; p < nk && timed; ++p) {
     const KTimer* t = (p == 0) ? timer(h, st[p], kKSortHist, h->b, 8.0 * h->b)
                                : timer(h, st[p], kKSortPass, h->b, 16.0 * h->b);
     if (t == nullptr) timed = false;
@@ -388,7 +400,7 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
   const hipError_t se = launch_sort(sa, h->stream, timed ? sort_t : nullptr);
   h->hist_parity ^= 1;  // the histogram kernel cleared the other buffer for the next sort
   if (se != hipSuccess) return LSM_EHIP;
-  Timed last = st[sa.passes];
+  Timed last = st[nk - 1];
 
   if (checked) {
     if (hipMemcpyAsync(h->h_pinned, sa.meta.err, sizeof(uint32_t), hipMemcpyDeviceToHost,
@@ -573,6 +585,309 @@ lsm_status_t lsm_count(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   if (launch_count(lv, d_lo, d_hi, nq, d_counts, nullptr, 0, h->stream, t) != hipSuccess)
     return LSM_EHIP;
   if (t != nullptr) call_span(h, 12, tc, tc, nq);
+  return LSM_OK;
+}
+
+static lsm_status_t order_query(lsm_t h, const uint32_t* d_q, uint32_t nq, uint32_t* d_keys,
+                         uint32_t* d_vals, uint8_t* d_found, bool successor) {
+  if (h == nullptr) return LSM_EINVAL;
+  if (nq == 0) return LSM_OK;
+  if (d_q == nullptr || d_keys == nullptr || d_vals == nullptr || d_found == nullptr)
+    return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  const lsm_status_t fs = flush_staged(h);
+  if (fs != LSM_OK) return fs;
+  const LevelSet lv = occupied_levels(h);
+  Timed to;
+  const KTimer* t = timer(h, to, kKOrder, nq, 0.0);
+  const hipError_t e = successor
+                           ? launch_successor(lv, d_q, nq, d_keys, d_vals, d_found, h->stream, t)
+                           : launch_predecessor(lv, d_q, nq, d_keys, d_vals, d_found, h->stream, t);
+  return e == hipSuccess ? LSM_OK : LSM_EHIP;
+}
+
+lsm_status_t lsm_successor(lsm_t h, const uint32_t* d_q, uint32_t nq, uint32_t* d_keys,
+                           uint32_t* d_vals, uint8_t* d_found) {
+  return order_query(h, d_q, nq, d_keys, d_vals, d_found, true);
+}
+
+lsm_status_t lsm_predecessor(lsm_t h, const uint32_t* d_q, uint32_t nq, uint32_t* d_keys,
+                             uint32_t* d_vals, uint8_t* d_found) {
+  return order_query(h, d_q, nq, d_keys, d_vals, d_found, false);
+}
+
+// Multi-batch insert (sec. V-B, bulk build and its footnote): n pairs as
+// ceil(n / b) consecutive insert batches of b, the last one padded.  Each
+// level of the new batch count r1 = r + k that holds a new batch is built
+// once: the new batches of its batch range are sorted together (read back to
+// front, stable, as one batch), then merged with the old levels its range
+// takes over, newest first.  Levels are produced from the largest down, so
+// an old level is always read before a smaller new level overwrites it.
+lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals, uint64_t n) {
+  if (h == nullptr) return LSM_EINVAL;
+  if (n == 0) return LSM_OK;
+  if (d_keys == nullptr || d_vals == nullptr) return LSM_EINVAL;
+  if (n > 0xFFFFFFFFull) return LSM_ECAPACITY;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  lsm_status_t s = flush_staged(h);
+  if (s != LSM_OK) return s;
+  const uint64_t b = h->b;
+  const uint64_t k = (n + b - 1) / b;
+  const uint64_t r0 = h->r, r1 = r0 + k;
+  if ((r1 >> kMaxLevels) != 0) return LSM_ECAPACITY;
+
+  struct Plan {
+    int level;
+    uint64_t first_new;  // first new batch in the level's range
+    uint64_t end;        // end of the range (batch number)
+    int old[kMaxLevels];
+    int n_old;
+  };
+  Plan plan[kMaxLevels];
+  int np = 0;
+  uint64_t max_new = 0, max_level = 0;
+  bool merges = false;
+  for (int i = kMaxLevels - 1; i >= 0; --i) {
+    if (((r1 >> i) & 1u) == 0) continue;
+    const uint64_t lo = (r1 >> (i + 1)) << (i + 1), hi = lo + (1ull << i);
+    if (hi <= r0) continue;  // the same range as old level i: unchanged
+    if (level_len(h, i) > (1ull << 31)) return LSM_ECAPACITY;
+    Plan& p = plan[np++];
+    p.level = i;
+    p.first_new = lo > r0 ? lo : r0;
+    p.end = hi;
+    p.n_old = 0;
+    for (int j = 0; j < i; ++j) {
+      if (((r0 >> j) & 1u) == 0) continue;
+      if (((r0 >> (j + 1)) << (j + 1)) >= lo) p.old[p.n_old++] = j;  // newest first
+    }
+    max_new = std::max(max_new, (p.end - p.first_new) * b);
+    max_level = std::max(max_level, level_len(h, i));
+    merges = merges || p.n_old > 0;
+  }
+
+  if (h->flags & LSM_CHECKED) {
+    const SortMeta m = sort_meta_carve(h->meta, h->b, 0);
+    if (hipMemsetAsync(m.err, 0, sizeof(uint32_t), h->stream) != hipSuccess ||
+        launch_check_keys(d_keys, static_cast<uint32_t>(n), h->key_bits, 0, m.err, h->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(h->h_pinned, m.err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return LSM_EHIP;
+    if (*reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u) return LSM_EKEY;
+  }
+
+  // Scratch: the sort's ping-pong and look-back words for the largest new
+  // part; two merge buffers when a level takes over old levels.
+  const size_t meta_bytes = sort_meta_words(static_cast<uint32_t>(max_new)) * sizeof(uint32_t);
+  void* st[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [buffer][kv, val]
+  void* mg[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  void* meta = nullptr;
+  auto release = [&]() {
+    for (int q = 0; q < 2; ++q)
+      for (int c = 0; c < 2; ++c) {
+        dev_free(h, st[q][c], max_new * sizeof(uint32_t));
+        dev_free(h, mg[q][c], max_level * sizeof(uint32_t));
+      }
+    dev_free(h, meta, meta_bytes);
+  };
+  for (int q = 0; q < 2 && s == LSM_OK; ++q)
+    for (int c = 0; c < 2 && s == LSM_OK; ++c) {
+      s = dev_alloc(h, &st[q][c], max_new * sizeof(uint32_t));
+      if (s == LSM_OK && merges) s = dev_alloc(h, &mg[q][c], max_level * sizeof(uint32_t));
+    }
+  if (s == LSM_OK) s = dev_alloc(h, &meta, meta_bytes);
+  for (int q = 0; q < np && s == LSM_OK; ++q) s = ensure_level(h, plan[q].level);
+  if (s != LSM_OK) {
+    release();
+    return s;
+  }
+  auto u32 = [](void* p) { return static_cast<uint32_t*>(p); };
+  hipError_t e = hipMemsetAsync(meta, 0, meta_bytes, h->stream);
+  uint64_t merged = 0, sorted = 0;
+  int parity = 0;
+  for (int q = 0; q < np && e == hipSuccess; ++q) {
+    const Plan& p = plan[q];
+    const int i = p.level;
+    const uint64_t e0 = (p.first_new - r0) * b;          // first input element
+    const uint64_t len = (p.end - p.first_new) * b;      // padded length
+    const uint64_t avail = n - e0 < len ? n - e0 : len;  // real elements
+    SortArgs sa;
+    sa.src = BatchSrc{d_keys + e0, d_vals + e0, nullptr, static_cast<uint32_t>(avail),
+                      static_cast<uint32_t>(len), static_cast<int>(kInsert)};
+    sa.lo_bit = 1;
+    sa.passes = sort_passes(h->key_bits, 1);
+    sa.key_limit_bits = h->key_bits;
+    sa.checked = 0;
+    sa.meta = sort_meta_carve(u32(meta), static_cast<uint32_t>(len), parity);
+    parity ^= 1;
+    sa.tmp_kv[0] = u32(st[0][0]);
+    sa.tmp_val[0] = u32(st[0][1]);
+    sa.tmp_kv[1] = u32(st[1][0]);
+    sa.tmp_val[1] = u32(st[1][1]);
+    sa.out_kv = p.n_old == 0 ? h->lvl_kv[i] : u32(mg[0][0]);
+    sa.out_val = p.n_old == 0 ? h->lvl_val[i] : u32(mg[0][1]);
+    sa.out_fence = p.n_old == 0 ? h->lvl_fence[i] : nullptr;
+    Timed ts[1 + kMaxPasses];
+    KTimer tt[1 + kMaxPasses];
+    const int nk = sort_kernel_count(sa);
+    bool timed = h->prof;
+    for (int x = 0; x < nk && timed; ++x) {
+      const KTimer* t = (x == 0) ? timer(h, ts[x], kKSortHist, len, 8.0 * len)
+                                 : timer(h, ts[x], kKSortPass, len, 16.0 * len);
+      if (t == nullptr) timed = false;
+      else tt[x] = *t;
+    }
+    e = launch_sort(sa, h->stream, timed ? tt : nullptr);
+    sorted += len;
+    const uint32_t* ak = sa.out_kv;
+    const uint32_t* av = sa.out_val;
+    uint64_t alen = len;
+    for (int x = 0; x < p.n_old && e == hipSuccess; ++x) {
+      const int j = p.old[x];
+      const bool last = x == p.n_old - 1;
+      uint32_t* ok = last ? h->lvl_kv[i] : u32(mg[(x + 1) & 1][0]);
+      uint32_t* ov = last ? h->lvl_val[i] : u32(mg[(x + 1) & 1][1]);
+      const uint64_t lj = level_len(h, j);
+      Timed mt;
+      e = launch_merge(ak, av, static_cast<uint32_t>(alen), h->lvl_kv[j], h->lvl_val[j],
+                       static_cast<uint32_t>(lj), ok, ov, last ? h->lvl_fence[i] : nullptr,
+                       h->merge_variant[j], h->stream,
+                       timer(h, mt, kKMerge, alen + lj, 16.0 * (alen + lj)));
+      ak = ok;
+      av = ov;
+      alen += lj;
+      merged += alen;
+    }
+  }
+  const hipError_t e2 = hipStreamSynchronize(h->stream);
+  release();
+  if (e != hipSuccess || e2 != hipSuccess) return LSM_EHIP;
+  h->r = r1;
+  h->merged_last = merged;
+  h->merged_total += merged;
+  h->sorted_total += sorted;
+  return LSM_OK;
+}
+
+// Cleanup (sec. III-E) by the bulk strategy of sec. IV-D.  Stage 1 merges
+// the occupied levels from the smallest up into scratch (the accumulated,
+// newer run first on equal keys), so the redistribution never writes a level
+// it still reads; stages 2-5 count the valid elements per tile, scan the
+// counts, and after one read-back of the total scatter the valid elements
+// straight into the levels of the new batch count and pad with placebos.
+lsm_status_t lsm_cleanup(lsm_t h, uint64_t* h_valid) {
+  if (h == nullptr) return LSM_EINVAL;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  lsm_status_t s = flush_staged(h);
+  if (s != LSM_OK) return s;
+  if (h_valid != nullptr) *h_valid = 0;
+  if (h->r == 0) return LSM_OK;
+  const uint64_t total = h->r * static_cast<uint64_t>(h->b);
+  if (total > 0xFFFFFFFFull) return LSM_ECAPACITY;
+  const uint32_t n = static_cast<uint32_t>(total);
+  int occ[kMaxLevels];
+  int m = 0;
+  for (int i = 0; i < kMaxLevels; ++i)
+    if ((h->r >> i) & 1u) occ[m++] = i;
+
+  // Scratch: one or two merge buffers (kv + val), the tiles' offsets.
+  const size_t bytes = total * sizeof(uint32_t);
+  const uint32_t tiles = clean_tiles(n);
+  void* tk[2] = {nullptr, nullptr};
+  void* tv[2] = {nullptr, nullptr};
+  void* toff = nullptr;
+  const int nbuf = m >= 3 ? 2 : 1;
+  auto release = [&]() {
+    for (int q = 0; q < 2; ++q) {
+      dev_free(h, tk[q], bytes);
+      dev_free(h, tv[q], bytes);
+    }
+    dev_free(h, toff, (tiles + 1ull) * sizeof(uint64_t));
+  };
+  for (int q = 0; q < nbuf && s == LSM_OK; ++q) {
+    s = dev_alloc(h, &tk[q], bytes);
+    if (s == LSM_OK) s = dev_alloc(h, &tv[q], bytes);
+  }
+  if (s == LSM_OK) s = dev_alloc(h, &toff, (tiles + 1ull) * sizeof(uint64_t));
+  if (s == LSM_OK) s = ensure_query_scratch(h, tiles);
+  if (s != LSM_OK) {
+    release();
+    return s;
+  }
+  hipError_t e = hipSuccess;
+  const uint32_t* ak = h->lvl_kv[occ[0]];
+  const uint32_t* av = h->lvl_val[occ[0]];
+  uint64_t alen = level_len(h, occ[0]);
+  if (m == 1) {
+    e = hipMemcpyAsync(tk[0], ak, bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(tv[0], av, bytes, hipMemcpyDeviceToDevice, h->stream);
+    ak = static_cast<uint32_t*>(tk[0]);
+    av = static_cast<uint32_t*>(tv[0]);
+  }
+  for (int k = 1; k < m && e == hipSuccess; ++k) {
+    const int i = occ[k];
+    const uint64_t len = level_len(h, i);
+    uint32_t* ok = static_cast<uint32_t*>(tk[(k - 1) & 1]);
+    uint32_t* ov = static_cast<uint32_t*>(tv[(k - 1) & 1]);
+    Timed mt;
+    e = launch_merge(ak, av, static_cast<uint32_t>(alen), h->lvl_kv[i], h->lvl_val[i],
+                     static_cast<uint32_t>(len), ok, ov, nullptr, kDefaultMergeVariant, h->stream,
+                     timer(h, mt, kKMerge, alen + len, 16.0 * (alen + len)));
+    ak = ok;
+    av = ov;
+    alen += len;
+  }
+  uint64_t* tile_off = static_cast<uint64_t*>(toff);
+  Timed t1, t2;
+  if (e == hipSuccess)
+    e = launch_clean_count(ak, n, h->q_counts, h->q_status, scan_status_words(tiles), h->stream,
+                           timer(h, t1, kKClean, total, 4.0 * total));
+  if (e == hipSuccess)
+    e = launch_scan(h->q_counts, tiles, tile_off, h->q_status, h->fault, h->stream,
+                    timer(h, t2, kKScan, tiles, 12.0 * tiles));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->h_pinned, tile_off + tiles, sizeof(uint64_t), hipMemcpyDeviceToHost,
+                       h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(h->stream);
+    release();
+    return LSM_EHIP;
+  }
+  const uint64_t v = *reinterpret_cast<volatile uint64_t*>(h->h_pinned);
+  const uint64_t r2 = (v + h->b - 1) / h->b;
+  for (int i = 0; i < kMaxLevels && s == LSM_OK; ++i)
+    if ((r2 >> i) & 1u) s = ensure_level(h, i);
+  if (s != LSM_OK) {
+    release();
+    return s;
+  }
+  LevelDst d{};
+  for (int i = 0; i < kMaxLevels; ++i) {
+    if (((r2 >> i) & 1u) == 0) continue;
+    d.kv[d.count] = h->lvl_kv[i];
+    d.val[d.count] = h->lvl_val[i];
+    d.fence[d.count] = h->lvl_fence[i];
+    d.start[d.count] = static_cast<uint64_t>(h->b) * (r2 & ((1ull << i) - 1ull));
+    ++d.count;
+  }
+  Timed t3, t4;
+  e = launch_clean_scatter(ak, av, n, tile_off, d, h->stream,
+                           timer(h, t3, kKClean, total, 8.0 * total + 8.0 * v));
+  if (e == hipSuccess)
+    e = launch_clean_pad(d, v, r2 * h->b, h->stream,
+                         timer(h, t4, kKClean, r2 * h->b - v, 8.0 * (r2 * h->b - v)));
+  const hipError_t e2 = hipStreamSynchronize(h->stream);
+  release();
+  if (e != hipSuccess || e2 != hipSuccess) return LSM_EHIP;
+  h->r = r2;
+  h->merged_last = 0;
+  if (h_valid != nullptr) *h_valid = v;
   return LSM_OK;
 }
 
@@ -783,13 +1098,13 @@ lsm_status_t lsm_autotune(lsm_t h, uint32_t max_level, uint32_t reps) {
     int best = kDefaultMergeVariant;
     float best_us = 0.f;
     for (int v = 0; v < kMergeVariants && s == LSM_OK; ++v) {
-      if (launch_merge(ak, av, len, bk, bv, len, ok, ov, v, h->stream, nullptr) != hipSuccess ||
+      if (launch_merge(ak, av, len, bk, bv, len, ok, ov, nullptr, v, h->stream, nullptr) != hipSuccess ||
           hipEventRecord(e0, h->stream) != hipSuccess) {
         s = LSM_EHIP;
         break;
       }
       for (uint32_t k = 0; k < reps; ++k)
-        if (launch_merge(ak, av, len, bk, bv, len, ok, ov, v, h->stream, nullptr) != hipSuccess)
+        if (launch_merge(ak, av, len, bk, bv, len, ok, ov, nullptr, v, h->stream, nullptr) != hipSuccess)
           s = LSM_EHIP;
       float ms = 0.f;
       if (s != LSM_OK || hipEventRecord(e1, h->stream) != hipSuccess ||

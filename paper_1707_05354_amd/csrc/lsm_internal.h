@@ -21,6 +21,11 @@ constexpr int kSortTile = kThreads * kSortItems;
 constexpr int kMaxPasses = 4;
 // The histogram kernel uses at most this many work-groups (tile-strided).
 constexpr int kMaxHistBlocks = 512;
+// Batches of at most kMsdMaxTiles tiles use the three-kernel MSD sort (top
+// digit scatter, then per-bucket sort); buckets of up to kLocalCap
+// elements are sorted in LDS.
+constexpr int kMsdMaxTiles = 512;
+constexpr int kLocalCap = 8192;
 
 // Merge variants (autotuned per level): items per thread x work-group cap.
 // Variant v uses kMergeItemsOf[v % 3] items per thread (tiles of 256 x that)
@@ -38,10 +43,23 @@ constexpr int kScanTile = kThreads * kScanItems;
 // Query kernels: one thread per query.
 constexpr int kQueryThreads = 256;
 
+// Every level keeps a fence array: the original key of every kFenceStride-th
+// element (the first key of each 128-byte line of key variables), written by
+// the kernel that writes the level.  Searches go through the fences first
+// and finish inside one line of keys.
+constexpr int kFenceStride = 32;
+inline uint64_t fence_len(uint64_t n) { return (n + kFenceStride - 1) / kFenceStride; }
+
+// Placebo element of cleanup (sec. IV-D footnote): a tombstone of the largest
+// encodable key, 2^31 - 1.  It sorts after every other element and hides
+// nothing: a live element of that key precedes it in the same level.
+constexpr uint32_t kPlaceboKv = 0xFFFFFFFEu;
+
 // The occupied levels, newest (smallest) first, passed by value.
 struct LevelSet {
   const uint32_t* kv[kMaxLevels];
   const uint32_t* val[kMaxLevels];
+  const uint32_t* fence[kMaxLevels];
   uint32_t len[kMaxLevels];
   int count;
 };
@@ -69,6 +87,7 @@ struct SortMeta {
   uint32_t* tile_ctr;     // [kMaxPasses] dynamic tile ids of each pass
   uint32_t* err;          // [0] key-range violation (checked mode),
                           // [1] sticky device fault (a bounded wait expired)
+  uint32_t* tile_cnt;     // [num_sort_tiles][256] top-digit counts (MSD sort)
   uint32_t num_sort_tiles;
   int parity;
 };
@@ -84,6 +103,7 @@ struct SortArgs {
   uint32_t* tmp_val[2];
   uint32_t* out_kv;         // sorted batch
   uint32_t* out_val;
+  uint32_t* out_fence;      // fences of the output when it is a level, else null
 };
 
 // Optional per-launch timing: when start is non-null the kernel is launched
@@ -96,7 +116,18 @@ struct KTimer {
 // Kernel kinds of the profile (indices of lsm_profile_t's per-kernel arrays).
 enum KernelKind : int {
   kKSortHist = 0, kKSortPass = 1, kKMerge = 2, kKLookup = 3, kKCount = 4, kKScan = 5,
-  kKRangeEmit = 6, kNumKernelKinds = 7
+  kKRangeEmit = 6, kKOrder = 7, kKClean = 8, kNumKernelKinds = 9
+};
+
+// Destination of cleanup's redistribution: the occupied levels of the new
+// batch count, smallest first; level l receives the list positions
+// [start[l], start[l] + length of level l).
+struct LevelDst {
+  uint32_t* kv[kMaxLevels];
+  uint32_t* val[kMaxLevels];
+  uint32_t* fence[kMaxLevels];
+  uint64_t start[kMaxLevels];
+  int count;
 };
 
 size_t sort_meta_words(uint32_t b);
@@ -104,16 +135,18 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity);
 
 // Sorts one batch into (out_kv, out_val): key variables ascending over bits
 // [lo_bit, lo_bit + 8 * passes), equal key variables with the later batch
-// position first.  timers (optional) holds 1 + passes entries: the
-// histogram kernel, then each digit pass.
+// position first.  timers (optional) holds sort_kernel_count(a) entries,
+// one per kernel launched.
 hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers);
+// Number of kernels launch_sort issues (and timers it uses) for a.
+int sort_kernel_count(const SortArgs& a);
 
 // Stable merge of a newer run (first on equal original keys) with an older
 // run into out (na + nb elements), with merge variant `variant`.
 hipError_t launch_merge(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na,
                         const uint32_t* b_kv, const uint32_t* b_val, uint32_t nb,
-                        uint32_t* out_kv, uint32_t* out_val, int variant, hipStream_t stream,
-                        const KTimer* t);
+                        uint32_t* out_kv, uint32_t* out_val, uint32_t* out_fence, int variant,
+                        hipStream_t stream, const KTimer* t);
 
 // Coalescer: encodes n keys of one user batch as key variables (status 0
 // for a deletion, value 0) into staging[at .. at + n).
@@ -154,6 +187,31 @@ hipError_t launch_scan(const uint32_t* counts, uint32_t nq, uint64_t* offsets,
 
 // Range emission pass: writes each query's live pairs at offsets[q], for
 // the queries whose pairs end at or before cap.
+// Order queries: per query the live pair with the smallest key > q
+// (successor) or the largest key < q (predecessor); found = 0 leaves key and
+// value 0.
+hipError_t launch_successor(const LevelSet& lv, const uint32_t* q, uint32_t nq, uint32_t* out_key,
+                            uint32_t* out_val, uint8_t* out_found, hipStream_t stream,
+                            const KTimer* t);
+hipError_t launch_predecessor(const LevelSet& lv, const uint32_t* q, uint32_t nq,
+                              uint32_t* out_key, uint32_t* out_val, uint8_t* out_found,
+                              hipStream_t stream, const KTimer* t);
+
+// Cleanup over the merged list (kv, val) of n elements: per-tile counts of
+// valid elements (first of their key run and regular; also clears the scan's
+// look-back words), then the scatter of valid elements to their level
+// positions given the tiles' exclusive offsets, then the placebo padding of
+// positions [v, total).
+uint32_t clean_tiles(uint32_t n);
+hipError_t launch_clean_count(const uint32_t* kv, uint32_t n, uint32_t* tile_cnt,
+                              uint64_t* scan_status, size_t scan_words, hipStream_t stream,
+                              const KTimer* t);
+hipError_t launch_clean_scatter(const uint32_t* kv, const uint32_t* val, uint32_t n,
+                                const uint64_t* tile_off, const LevelDst& d, hipStream_t stream,
+                                const KTimer* t);
+hipError_t launch_clean_pad(const LevelDst& d, uint64_t v, uint64_t total, hipStream_t stream,
+                            const KTimer* t);
+
 hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi,
                              uint32_t nq, const uint64_t* offsets, uint32_t* out_keys,
                              uint32_t* out_vals, uint64_t cap, hipStream_t stream,

@@ -10,6 +10,11 @@
 //       look-back.  The batch is read back to front, so among equal key
 //       variables the later batch position comes first (the last duplicate
 //       wins), and padded with copies of its last element (sec. IV-A).
+//   k_msd_hist / k_msd_scatter / k_local_sort : the same stable order for
+//       batches of at most 512 tiles: one scatter on the top digit, then one
+//       work-group sorts each top-digit bucket in LDS.
+//   Every kernel that writes a level also writes its fences (the original
+//       key of every 32nd element), which the searches use first.
 //   k_merge : merge of a newer run with an older run on the original key,
 //       the newer element first on equal keys (sec. IV-A), merge-path
 //       partitioned with a 64-ary wave search.
@@ -21,6 +26,11 @@
 //       (sec. III-E, IV-C, IV-D).
 //   k_scan : single-pass exclusive scan with decoupled look-back for the
 //       range output offsets (stage 2 of sec. IV-C).
+//   k_successor / k_predecessor : the order queries of the sec. I-B
+//       footnote, the same walk as count stopped at the first live key.
+//   k_clean_count / k_clean_scatter / k_clean_pad : cleanup (sec. III-E,
+//       IV-D) after the levels are merged: mark stale elements, compact the
+//       valid ones straight into the new levels, pad with placebos.
 #include <hip/hip_ext.h>
 
 #include "lsm_internal.h"
@@ -90,27 +100,41 @@ __device__ __forceinline__ void st_dev64(uint64_t* p, uint64_t v) {
 }
 
 // ------------------------------------------------------------ searches
-// First index i in [0, n) with (kv[i] >> 1) >= k, or n.  Branch-free.
-__device__ __forceinline__ uint32_t lower_bound_key(const uint32_t* kv, uint32_t n, uint32_t k) {
+// Lower / upper bound through the level's fences: a bound search over the
+// fences (n / 32 entries, cache-resident) picks the one 128-byte line of
+// keys that holds the answer, and a search inside that line finishes it.
+// Returns the first index whose original key is >= k (upper: > k), or n.
+__device__ __forceinline__ uint32_t fenced_bound(const uint32_t* kv, const uint32_t* fence,
+                                                 uint32_t n, uint32_t k, bool upper) {
   if (n == 0) return 0;
-  uint32_t base = 0, len = n;
+  const uint32_t nf = (n + kFenceStride - 1) / kFenceStride;
+  // g = first fence whose key is >= k (lower) or > k (upper).
+  uint32_t base = 0, len = nf;
   while (len > 1) {
     const uint32_t half = len >> 1;
-    base = ((kv[base + half] >> 1) < k) ? base + half : base;
+    const uint32_t f = fence[base + half];
+    base = (upper ? f <= k : f < k) ? base + half : base;
     len -= half;
   }
-  return base + ((kv[base] >> 1) < k ? 1u : 0u);
+  const uint32_t f0 = fence[base];
+  const uint32_t g = base + ((upper ? f0 <= k : f0 < k) ? 1u : 0u);
+  if (g == 0) return 0;
+  // The answer lies in (32 (g - 1), 32 g]; position 32 g (if it exists)
+  // qualifies by its fence, so search positions 32 (g - 1) + 1 .. 32 g - 1.
+  uint32_t lo = (g - 1) * kFenceStride + 1;
+  uint32_t hi = g * kFenceStride < n ? g * kFenceStride : n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    const uint32_t x = kv[mid] >> 1;
+    if (upper ? x <= k : x < k) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
 }
-// First index i in [0, n) with (kv[i] >> 1) > k, or n.
-__device__ __forceinline__ uint32_t upper_bound_key(const uint32_t* kv, uint32_t n, uint32_t k) {
-  if (n == 0) return 0;
-  uint32_t base = 0, len = n;
-  while (len > 1) {
-    const uint32_t half = len >> 1;
-    base = ((kv[base + half] >> 1) <= k) ? base + half : base;
-    len -= half;
-  }
-  return base + ((kv[base] >> 1) <= k ? 1u : 0u);
+
+// Records the fence of output position o when it starts a fence group.
+__device__ __forceinline__ void put_fence(uint32_t* fence, uint64_t o, uint32_t kv) {
+  if (fence != nullptr && (o & (kFenceStride - 1)) == 0) fence[o / kFenceStride] = kv >> 1;
 }
 
 // ------------------------------------------------------------ radix sort
@@ -173,8 +197,8 @@ __device__ __forceinline__ uint32_t tile_pos(uint32_t wave, int i, uint32_t lane
 // write consecutive output addresses.
 __device__ void sort_tile_pass(const uint32_t (&kv)[kSortItems], const uint32_t (&val)[kSortItems],
                                uint32_t tile, uint32_t b, int shift, uint32_t* st,
-                               uint32_t* out_kv, uint32_t* out_val, bool coherent_out,
-                               uint32_t* fault, SortLds& L) {
+                               uint32_t* out_kv, uint32_t* out_val, uint32_t* out_fence,
+                               bool coherent_out, uint32_t* fault, SortLds& L) {
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t tbase = tile * kSortTile;
   for (uint32_t i = tid; i < kWaves * kRadix; i += kThreads) (&L.wcnt[0][0])[i] = 0u;
@@ -275,6 +299,7 @@ __device__ void sort_tile_pass(const uint32_t (&kv)[kSortItems], const uint32_t 
         } else {
           out_kv[o] = k;
           out_val[o] = L.val[x];
+          put_fence(out_fence, o, k);
         }
       }
     }
@@ -370,8 +395,291 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(SortArgs a, int pass) {
   const uint32_t tile = s_tile;
   if (tile != blockIdx.x) load_tile(tile);
   uint32_t* st = m.status + static_cast<size_t>(pass) * m.num_sort_tiles * kRadix;
-  sort_tile_pass(kv, val, tile, b, a.lo_bit + kRadixBits * pass, st, o_kv, o_val, false,
-                 &m.err[1], L);
+  sort_tile_pass(kv, val, tile, b, a.lo_bit + kRadixBits * pass, st, o_kv, o_val,
+                 (pass == a.passes - 1) ? a.out_fence : nullptr, false, &m.err[1], L);
+}
+
+// ------------------------------------------------------------ MSD sort
+// For batches of at most kMsdMaxTiles tiles the sort exchanges data across
+// the device only once: a histogram of the top 8-bit digit, one stable MSD
+// scatter into 256 buckets, then each bucket sorted on its own by one
+// work-group on the remaining bits (in LDS when it fits, streaming through
+// the bucket's global range otherwise).  Three kernels instead of
+// 1 + passes, and no look-back chains.
+
+// Stable ranking of one item per lane by digit d among the valid lanes of
+// the wave: returns the item's position after the entries already counted
+// in wcnt[d], and adds the wave's count of d to wcnt[d].
+__device__ __forceinline__ uint32_t wave_rank1(uint32_t d, bool valid, uint32_t* wcnt) {
+  uint64_t peers = ballot(valid);
+#pragma unroll
+  for (int bit = 0; bit < kRadixBits; ++bit) {
+    const bool set = (d >> bit) & 1u;
+    const uint64_t m = ballot(set);
+    peers &= set ? m : ~m;
+  }
+  const uint32_t r = count_below(peers);
+  uint32_t prev = 0;
+  if (valid) prev = wcnt[d];
+  if (valid && r == 0) wcnt[d] = prev + static_cast<uint32_t>(__popcll(peers));
+  return prev + r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_msd_hist(SortArgs a, int top_shift) {
+  __shared__ uint32_t s_h[kRadix];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const SortMeta& m = a.meta;
+  const uint32_t b = a.src.b;
+  const uint32_t tile = blockIdx.x;
+  const size_t gid = static_cast<size_t>(blockIdx.x) * kThreads + tid;
+  uint32_t* other = m.hist + static_cast<size_t>(m.parity ^ 1) * kMaxPasses * kRadix;
+  // Clear all of the other buffer whatever the grid size: the next sort on
+  // this scratch may be a digit-pass sort that uses every pass's counts.
+  for (size_t i = gid; i < static_cast<size_t>(kMaxPasses) * kRadix;
+       i += static_cast<size_t>(gridDim.x) * kThreads)
+    other[i] = 0u;
+  s_h[tid] = 0u;
+  uint32_t kv[kSortItems], key[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const uint32_t e = tile * kSortTile + tile_pos(wave, i, lane);
+    uint32_t val;
+    kv[i] = 0u;
+    key[i] = 0u;
+    if (e < b) batch_elem(a.src, e, kv[i], val, key[i]);
+  }
+  __syncthreads();
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    if (tile * kSortTile + tile_pos(wave, i, lane) >= b) continue;
+    if (a.checked) bad |= (key[i] >> a.key_limit_bits) != 0u;
+    atomicAdd(&s_h[(kv[i] >> top_shift) & (kRadix - 1)], 1u);
+  }
+  __syncthreads();
+  m.tile_cnt[static_cast<size_t>(tile) * kRadix + tid] = s_h[tid];
+  uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
+  if (s_h[tid] != 0u) atomicAdd(&mine[tid], s_h[tid]);
+  if (a.checked && bad) atomicOr(&m.err[0], 1u);
+}
+
+__global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_shift) {
+  __shared__ uint32_t s_kv[kSortTile];
+  __shared__ uint32_t s_val[kSortTile];
+  __shared__ uint32_t s_wcnt[kWaves][kRadix];
+  __shared__ uint32_t s_local[kRadix];
+  __shared__ uint32_t s_gbase[kRadix];
+  __shared__ uint32_t s_tmp[kWaves];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const SortMeta& m = a.meta;
+  const uint32_t b = a.src.b;
+  const uint32_t tile = blockIdx.x;
+  const uint32_t tbase = tile * kSortTile;
+  const uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
+  const uint32_t gtotal = mine[tid];
+  // Elements of this digit in earlier tiles (independent loads).
+  uint32_t before = 0;
+  for (uint32_t t = 0; t < tile; ++t) before += m.tile_cnt[static_cast<size_t>(t) * kRadix + tid];
+  for (uint32_t i = tid; i < kWaves * kRadix; i += kThreads) (&s_wcnt[0][0])[i] = 0u;
+  uint32_t kv[kSortItems], val[kSortItems], off[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const uint32_t e = tbase + tile_pos(wave, i, lane);
+    uint32_t key;
+    kv[i] = 0u;
+    val[i] = 0u;
+    if (e < b) batch_elem(a.src, e, kv[i], val[i], key);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i)
+    off[i] = wave_rank1((kv[i] >> top_shift) & (kRadix - 1), tbase + tile_pos(wave, i, lane) < b,
+                        s_wcnt[wave]);
+  __syncthreads();
+  uint32_t tile_count = 0;
+  for (uint32_t w = 0; w < kWaves; ++w) {
+    const uint32_t c = s_wcnt[w][tid];
+    s_wcnt[w][tid] = tile_count;
+    tile_count += c;
+  }
+  s_local[tid] = block_excl_scan(tile_count, s_tmp);
+  s_gbase[tid] = block_excl_scan(gtotal, s_tmp) + before;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    if (tbase + tile_pos(wave, i, lane) < b) {
+      const uint32_t dd = (kv[i] >> top_shift) & (kRadix - 1);
+      const uint32_t pos = s_local[dd] + s_wcnt[wave][dd] + off[i];
+      s_kv[pos] = kv[i];
+      s_val[pos] = val[i];
+    }
+  }
+  __syncthreads();
+  const uint32_t tile_n = (b - tbase) < static_cast<uint32_t>(kSortTile) ? (b - tbase) : kSortTile;
+  for (uint32_t x = tid; x < tile_n; x += kThreads) {
+    const uint32_t k = s_kv[x];
+    const uint32_t dd = (k >> top_shift) & (kRadix - 1);
+    const uint32_t o = s_gbase[dd] + (x - s_local[dd]);
+    if (o < b) {
+      a.tmp_kv[0][o] = k;
+      a.tmp_val[0][o] = s_val[x];
+    }
+  }
+}
+
+struct LocalLds {
+  uint32_t k[2][kLocalCap];
+  uint32_t v[2][kLocalCap];
+  uint32_t wcnt[kWaves][kRadix];
+  uint32_t tmp[kWaves];
+};
+
+// One stable counting pass over n <= kLocalCap elements in LDS, from
+// buffer `from` to buffer 1 - from, on the digit at `shift`.  Wave w owns
+// positions [w*S, (w+1)*S) in (item, lane) order, S a multiple of 64.
+__device__ void lds_pass(LocalLds& L, int from, uint32_t n, int shift) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t S = ((n + kThreads - 1) / kThreads) * 64;
+  const uint32_t* sk = L.k[from];
+  const uint32_t* sv = L.v[from];
+  uint32_t* dk = L.k[1 - from];
+  uint32_t* dv = L.v[1 - from];
+  for (uint32_t i = tid; i < kWaves * kRadix; i += kThreads) (&L.wcnt[0][0])[i] = 0u;
+  __syncthreads();
+  for (uint32_t it = 0; it < S / 64; ++it) {
+    const uint32_t pos = wave * S + it * 64 + lane;
+    const bool valid = pos < n;
+    (void)wave_rank1(valid ? (sk[pos] >> shift) & (kRadix - 1) : 0u, valid, L.wcnt[wave]);
+  }
+  __syncthreads();
+  uint32_t tot = 0;
+  for (uint32_t w = 0; w < kWaves; ++w) {
+    const uint32_t c = L.wcnt[w][tid];
+    L.wcnt[w][tid] = tot;
+    tot += c;
+  }
+  const uint32_t local = block_excl_scan(tot, L.tmp);
+  for (uint32_t w = 0; w < kWaves; ++w) L.wcnt[w][tid] += local;
+  __syncthreads();
+  for (uint32_t it = 0; it < S / 64; ++it) {
+    const uint32_t pos = wave * S + it * 64 + lane;
+    const bool valid = pos < n;
+    const uint32_t x = valid ? sk[pos] : 0u;
+    const uint32_t o = wave_rank1((x >> shift) & (kRadix - 1), valid, L.wcnt[wave]);
+    if (valid) {
+      dk[o] = x;
+      dv[o] = sv[pos];
+    }
+  }
+  __syncthreads();
+}
+
+// Bucket d (= blockIdx.x) of the MSD scatter, sorted on the digits below
+// the top one; written to the sort output at the bucket's own range.
+__global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit, int passes) {
+  __shared__ LocalLds L;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const SortMeta& m = a.meta;
+  const uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
+  const uint32_t cnt = mine[tid];
+  const uint32_t start = block_excl_scan(cnt, L.tmp);
+  if (tid == blockIdx.x) {
+    L.tmp[0] = start;
+    L.tmp[1] = cnt;
+  }
+  __syncthreads();
+  const uint32_t s = L.tmp[0], n = L.tmp[1];
+  __syncthreads();
+  if (n == 0) return;
+  const uint32_t* src_k = a.tmp_kv[0] + s;
+  const uint32_t* src_v = a.tmp_val[0] + s;
+  uint32_t* out_k = a.out_kv + s;
+  uint32_t* out_v = a.out_val + s;
+  if (n <= static_cast<uint32_t>(kLocalCap)) {
+    for (uint32_t x = tid; x < n; x += kThreads) {
+      L.k[0][x] = src_k[x];
+      L.v[0][x] = src_v[x];
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int p = 0; p < passes; ++p) {
+      lds_pass(L, cur, n, lo_bit + kRadixBits * p);
+      cur = 1 - cur;
+    }
+    for (uint32_t x = tid; x < n; x += kThreads) {
+      out_k[x] = L.k[cur][x];
+      out_v[x] = L.v[cur][x];
+      put_fence(a.out_fence, s + x, L.k[cur][x]);
+    }
+    return;
+  }
+  // Oversized bucket: stable passes streaming through the bucket's range,
+  // chunk by chunk in order, ping-ponging between the two scratch buffers.
+  if (passes == 0) {
+    for (uint32_t x = tid; x < n; x += kThreads) {
+      const uint32_t k = src_k[x];
+      out_k[x] = k;
+      out_v[x] = src_v[x];
+      put_fence(a.out_fence, s + x, k);
+    }
+    return;
+  }
+  uint32_t* run = L.k[0];       // running output position per digit
+  uint32_t* chunk_cnt = L.k[1];
+  for (int p = 0; p < passes; ++p) {
+    const int shift = lo_bit + kRadixBits * p;
+    const uint32_t* ik = ((p & 1) == 0 ? a.tmp_kv[0] : a.tmp_kv[1]) + s;
+    const uint32_t* iv = ((p & 1) == 0 ? a.tmp_val[0] : a.tmp_val[1]) + s;
+    uint32_t* ok = (p == passes - 1) ? out_k : ((p & 1) == 0 ? a.tmp_kv[1] : a.tmp_kv[0]) + s;
+    uint32_t* ov = (p == passes - 1) ? out_v : ((p & 1) == 0 ? a.tmp_val[1] : a.tmp_val[0]) + s;
+    run[tid] = 0u;
+    __syncthreads();
+    for (uint32_t x = tid; x < n; x += kThreads) atomicAdd(&run[(ik[x] >> shift) & (kRadix - 1)], 1u);
+    __syncthreads();
+    const uint32_t c = run[tid];
+    __syncthreads();
+    run[tid] = block_excl_scan(c, L.tmp);
+    __syncthreads();
+    for (uint32_t cb = 0; cb < n; cb += kSortTile) {
+      uint32_t kv[kSortItems], vv[kSortItems], off[kSortItems];
+#pragma unroll
+      for (int i = 0; i < kSortItems; ++i) {
+        const uint32_t e = cb + tile_pos(wave, i, lane);
+        kv[i] = e < n ? ik[e] : 0u;
+        vv[i] = e < n ? iv[e] : 0u;
+      }
+      for (uint32_t i = tid; i < kWaves * kRadix; i += kThreads) (&L.wcnt[0][0])[i] = 0u;
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < kSortItems; ++i)
+        off[i] = wave_rank1((kv[i] >> shift) & (kRadix - 1), cb + tile_pos(wave, i, lane) < n,
+                            L.wcnt[wave]);
+      __syncthreads();
+      uint32_t tot = 0;
+      for (uint32_t w = 0; w < kWaves; ++w) {
+        const uint32_t cc = L.wcnt[w][tid];
+        L.wcnt[w][tid] = tot;
+        tot += cc;
+      }
+      chunk_cnt[tid] = tot;
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < kSortItems; ++i) {
+        if (cb + tile_pos(wave, i, lane) < n) {
+          const uint32_t dd = (kv[i] >> shift) & (kRadix - 1);
+          const uint32_t o = run[dd] + L.wcnt[wave][dd] + off[i];
+          if (o < n) {
+            ok[o] = kv[i];
+            ov[o] = vv[i];
+            if (p == passes - 1) put_fence(a.out_fence, s + o, kv[i]);
+          }
+        }
+      }
+      __syncthreads();
+      run[tid] += chunk_cnt[tid];
+      __syncthreads();
+    }
+  }
 }
 
 // ------------------------------------------------------------ merge
@@ -435,7 +743,7 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
                                                     uint32_t na, const uint32_t* b_kv,
                                                     const uint32_t* b_val, uint32_t nb,
                                                     uint32_t* out_kv, uint32_t* out_val,
-                                                    uint32_t tiles_per_wg) {
+                                                    uint32_t* out_fence, uint32_t tiles_per_wg) {
   constexpr uint32_t kMergeTile = kThreads * kMergeItems;
   __shared__ uint32_t s_kv[2 * kMergeTile];
   __shared__ uint32_t s_val[2 * kMergeTile];
@@ -499,6 +807,7 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
     for (uint32_t x = tid; x < n; x += kThreads) {
       out_kv[d + x] = s_kv[x];
       out_val[d + x] = s_val[x];
+      put_fence(out_fence, d + x, s_kv[x]);
     }
     const uint32_t la = s_split;
     a0 += la;
@@ -560,7 +869,7 @@ __global__ __launch_bounds__(kQueryThreads) void k_lookup(LevelSet lv, const uin
   for (int l = 0; l < lv.count; ++l) {
     const uint32_t* kv = lv.kv[l];
     const uint32_t n = lv.len[l];
-    const uint32_t p = lower_bound_key(kv, n, k);
+    const uint32_t p = fenced_bound(kv, lv.fence[l], n, k, false);
     if (p < n) {
       const uint32_t x = kv[p];
       if ((x >> 1) == k) {
@@ -614,8 +923,8 @@ __device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, 
   for (int l = 0; l < L; ++l) {
     const uint32_t* kv = lv.kv[l];
     const uint32_t n = lv.len[l];
-    cur[l] = lower_bound_key(kv, n, k1);
-    end[l] = upper_bound_key(kv, n, k2);
+    cur[l] = fenced_bound(kv, lv.fence[l], n, k1, false);
+    end[l] = fenced_bound(kv, lv.fence[l], n, k2, true);
     ck[l] = cur[l] < end[l] ? (kv[cur[l]] >> 1) : kNoKey;
   }
   uint32_t count = 0;
@@ -756,6 +1065,191 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* counts, uint3
   if (tile == tiles - 1 && tid == kThreads - 1) offsets[nq] = s_prefix + tile_total;
 }
 
+// ------------------------------------------------------------ order queries
+constexpr uint32_t kMaxKey = 0x7FFFFFFFu;  // largest encodable original key
+
+// Successor: walk the level runs that start at upper_bound(q) in key order
+// (as range_walk does); the first key whose newest instance is a regular
+// element is the answer.
+__global__ __launch_bounds__(kQueryThreads) void k_successor(LevelSet lv, const uint32_t* q,
+                                                             uint32_t nq, uint32_t* out_key,
+                                                             uint32_t* out_val,
+                                                             uint8_t* out_found) {
+  const uint32_t i = blockIdx.x * kQueryThreads + threadIdx.x;
+  if (i >= nq) return;
+  const uint32_t k = q[i];
+  uint32_t rk = 0u, rv = 0u;
+  uint8_t f = 0;
+  if (k < kMaxKey) {
+    uint32_t cur[kMaxLevels], ck[kMaxLevels];
+    const int L = lv.count;
+    for (int l = 0; l < L; ++l) {
+      cur[l] = fenced_bound(lv.kv[l], lv.fence[l], lv.len[l], k, true);
+      ck[l] = cur[l] < lv.len[l] ? (lv.kv[l][cur[l]] >> 1) : kNoKey;
+    }
+    for (;;) {
+      uint32_t mk = kNoKey;
+      int mi = -1;
+      for (int l = 0; l < L; ++l) {
+        if (ck[l] < mk) {
+          mk = ck[l];
+          mi = l;
+        }
+      }
+      if (mi < 0) break;
+      if (lv.kv[mi][cur[mi]] & 1u) {
+        rk = mk;
+        rv = lv.val[mi][cur[mi]];
+        f = 1;
+        break;
+      }
+      for (int l = mi; l < L; ++l) {
+        if (ck[l] == mk) {
+          cur[l] = skip_run(lv.kv[l], cur[l], lv.len[l], mk);
+          ck[l] = cur[l] < lv.len[l] ? (lv.kv[l][cur[l]] >> 1) : kNoKey;
+        }
+      }
+    }
+  }
+  out_key[i] = rk;
+  out_val[i] = rv;
+  out_found[i] = f;
+}
+
+// Predecessor: the mirror walk, downwards from lower_bound(q).  For the
+// largest remaining key, the newest instance is the first element of its run
+// in the smallest level holding it; a tombstone there discards the key, and
+// every level then drops its run of that key.
+__global__ __launch_bounds__(kQueryThreads) void k_predecessor(LevelSet lv, const uint32_t* q,
+                                                               uint32_t nq, uint32_t* out_key,
+                                                               uint32_t* out_val,
+                                                               uint8_t* out_found) {
+  const uint32_t i = blockIdx.x * kQueryThreads + threadIdx.x;
+  if (i >= nq) return;
+  const uint32_t k = q[i];
+  uint32_t rk = 0u, rv = 0u;
+  uint8_t f = 0;
+  if (k > 0u) {
+    uint32_t e[kMaxLevels], ck[kMaxLevels];  // ck = key just below e, or kNoKey
+    const int L = lv.count;
+    for (int l = 0; l < L; ++l) {
+      e[l] = fenced_bound(lv.kv[l], lv.fence[l], lv.len[l], k, false);
+      ck[l] = e[l] > 0u ? (lv.kv[l][e[l] - 1u] >> 1) : kNoKey;
+    }
+    for (;;) {
+      uint32_t mk = 0u;
+      int mi = -1;
+      for (int l = 0; l < L; ++l) {
+        if (ck[l] != kNoKey && (mi < 0 || ck[l] > mk)) {
+          mk = ck[l];
+          mi = l;
+        }
+      }
+      if (mi < 0) break;
+      bool done = false;
+      for (int l = mi; l < L; ++l) {
+        if (ck[l] != mk) continue;
+        const uint32_t s = fenced_bound(lv.kv[l], lv.fence[l], e[l], mk, false);
+        if (l == mi && (lv.kv[l][s] & 1u)) {
+          rk = mk;
+          rv = lv.val[l][s];
+          f = 1;
+          done = true;
+          break;
+        }
+        e[l] = s;
+        ck[l] = s > 0u ? (lv.kv[l][s - 1u] >> 1) : kNoKey;
+      }
+      if (done) break;
+    }
+  }
+  out_key[i] = rk;
+  out_val[i] = rv;
+  out_found[i] = f;
+}
+
+// ------------------------------------------------------------ cleanup
+// Stages 2-5 of the bulk cleanup of sec. IV-D over the merged list (stage 1
+// is a chain of ordinary merges).  A tile is kThreads x kCleanItems
+// consecutive elements, each thread holding kCleanItems consecutive ones.
+constexpr int kCleanItems = 8;
+constexpr uint32_t kCleanTile = kThreads * kCleanItems;
+
+// Valid flags of the thread's elements [e0, e0 + kCleanItems): the first
+// element of a key run, when regular (stage 2: everything else is stale).
+__device__ __forceinline__ uint32_t clean_flags(const uint32_t* kv, uint32_t n, uint32_t e0,
+                                                uint32_t (&x)[kCleanItems]) {
+  uint32_t prev = (e0 > 0u && e0 < n) ? (kv[e0 - 1u] >> 1) : kNoKey;
+  uint32_t mask = 0u;
+#pragma unroll
+  for (int j = 0; j < kCleanItems; ++j) {
+    const uint32_t e = e0 + j;
+    x[j] = e < n ? kv[e] : 0u;
+    if (e < n && (x[j] & 1u) && (x[j] >> 1) != prev) mask |= 1u << j;
+    prev = x[j] >> 1;
+  }
+  return mask;
+}
+
+__global__ __launch_bounds__(kThreads) void k_clean_count(const uint32_t* kv, uint32_t n,
+                                                          uint32_t* tile_cnt,
+                                                          uint64_t* scan_status,
+                                                          uint64_t scan_words) {
+  __shared__ uint32_t tmp[kWaves];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t gi = static_cast<uint64_t>(blockIdx.x) * kThreads + tid;
+  for (uint64_t w = gi; w < scan_words; w += static_cast<uint64_t>(gridDim.x) * kThreads)
+    scan_status[w] = 0ull;
+  const uint32_t e0 = blockIdx.x * kCleanTile + tid * kCleanItems;
+  uint32_t x[kCleanItems];
+  const uint32_t c = __popc(clean_flags(kv, n, e0, x));
+  const uint32_t pre = block_excl_scan(c, tmp);
+  if (tid == kThreads - 1) tile_cnt[blockIdx.x] = pre + c;
+}
+
+// Position p of the redistributed list -> (level slot, index in the level).
+__device__ __forceinline__ int dst_level(const LevelDst& d, uint64_t p, int l) {
+  while (l + 1 < d.count && d.start[l + 1] <= p) ++l;
+  return l;
+}
+
+__device__ __forceinline__ void dst_write(const LevelDst& d, int l, uint64_t p, uint32_t x,
+                                          uint32_t v) {
+  const uint64_t o = p - d.start[l];
+  d.kv[l][o] = x;
+  d.val[l][o] = v;
+  put_fence(d.fence[l], o, x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_clean_scatter(const uint32_t* kv,
+                                                            const uint32_t* val, uint32_t n,
+                                                            const uint64_t* tile_off,
+                                                            LevelDst d) {
+  __shared__ uint32_t tmp[kWaves];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t e0 = blockIdx.x * kCleanTile + tid * kCleanItems;
+  uint32_t x[kCleanItems];
+  const uint32_t mask = clean_flags(kv, n, e0, x);
+  const uint32_t pre = block_excl_scan(__popc(mask), tmp);
+  if (mask == 0u) return;
+  uint64_t p = tile_off[blockIdx.x] + pre;
+  int l = dst_level(d, p, 0);
+#pragma unroll
+  for (int j = 0; j < kCleanItems; ++j) {
+    if (mask & (1u << j)) {
+      l = dst_level(d, p, l);
+      dst_write(d, l, p, x[j], val[e0 + j]);
+      ++p;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_clean_pad(LevelDst d, uint64_t v, uint64_t total) {
+  const uint64_t p = v + static_cast<uint64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (p >= total) return;
+  dst_write(d, dst_level(d, p, 0), p, kPlaceboKv, 0u);
+}
+
 inline unsigned grid_for(uint64_t n, uint64_t per) { return static_cast<unsigned>((n + per - 1) / per); }
 
 template <typename Kernel, typename... Args>
@@ -774,7 +1268,7 @@ hipError_t launch(Kernel k, unsigned grid, unsigned block, hipStream_t s, const 
 size_t sort_meta_words(uint32_t b) {
   const size_t ns = grid_for(b, kSortTile);
   return static_cast<size_t>(2) * kMaxPasses * kRadix + static_cast<size_t>(kMaxPasses) * ns * kRadix +
-         kMaxPasses + 2;
+         kMaxPasses + 2 + ns * kRadix;
 }
 
 SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
@@ -784,12 +1278,30 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
   m.status = m.hist + static_cast<size_t>(2) * kMaxPasses * kRadix;
   m.tile_ctr = m.status + static_cast<size_t>(kMaxPasses) * m.num_sort_tiles * kRadix;
   m.err = m.tile_ctr + kMaxPasses;
+  m.tile_cnt = m.err + 2;
   m.parity = parity;
   return m;
 }
 
+int sort_kernel_count(const SortArgs& a) {
+  return a.meta.num_sort_tiles <= static_cast<uint32_t>(kMsdMaxTiles) ? 3 : 1 + a.passes;
+}
+
 hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers) {
   const uint32_t tiles = a.meta.num_sort_tiles;
+  if (tiles <= static_cast<uint32_t>(kMsdMaxTiles)) {
+    // Top digit: the highest 8 of the sorted bits [lo_bit, lo_bit + 8 * passes).
+    const int hi_bit = a.lo_bit + kRadixBits * a.passes;
+    const int top = hi_bit - kRadixBits > a.lo_bit ? hi_bit - kRadixBits : a.lo_bit;
+    const int local_passes = (top - a.lo_bit + kRadixBits - 1) / kRadixBits;
+    hipError_t e = launch(k_msd_hist, tiles, kThreads, stream, timers ? &timers[0] : nullptr, a, top);
+    if (e == hipSuccess)
+      e = launch(k_msd_scatter, tiles, kThreads, stream, timers ? &timers[1] : nullptr, a, top);
+    if (e == hipSuccess)
+      e = launch(k_local_sort, kRadix, kThreads, stream, timers ? &timers[2] : nullptr, a, a.lo_bit,
+                 local_passes);
+    return e;
+  }
   const uint32_t hist_grid = tiles < static_cast<uint32_t>(kMaxHistBlocks) ? tiles : kMaxHistBlocks;
   hipError_t e = launch(k_sort_hist, hist_grid, kThreads, stream, timers ? &timers[0] : nullptr, a);
   if (e != hipSuccess) return e;
@@ -803,33 +1315,33 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* time
 template <int kItems>
 hipError_t launch_merge_items(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na,
                               const uint32_t* b_kv, const uint32_t* b_val, uint32_t nb,
-                              uint32_t* out_kv, uint32_t* out_val, uint32_t max_blocks,
-                              hipStream_t stream, const KTimer* t) {
+                              uint32_t* out_kv, uint32_t* out_val, uint32_t* out_fence,
+                              uint32_t max_blocks, hipStream_t stream, const KTimer* t) {
   const uint64_t total = static_cast<uint64_t>(na) + nb;
   const uint64_t tile = static_cast<uint64_t>(kThreads) * kItems;
   const uint64_t tiles = (total + tile - 1) / tile;
   const uint32_t per = static_cast<uint32_t>((tiles + max_blocks - 1) / max_blocks);
   return launch(k_merge<kItems>, grid_for(tiles, per), kThreads, stream, t, a_kv, a_val, na, b_kv,
-                b_val, nb, out_kv, out_val, per);
+                b_val, nb, out_kv, out_val, out_fence, per);
 }
 
 hipError_t launch_merge(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na,
                         const uint32_t* b_kv, const uint32_t* b_val, uint32_t nb,
-                        uint32_t* out_kv, uint32_t* out_val, int variant, hipStream_t stream,
-                        const KTimer* t) {
+                        uint32_t* out_kv, uint32_t* out_val, uint32_t* out_fence, int variant,
+                        hipStream_t stream, const KTimer* t) {
   const uint64_t total = static_cast<uint64_t>(na) + nb;
   if (total == 0) return hipSuccess;
   if (variant < 0 || variant >= kMergeVariants) variant = kDefaultMergeVariant;
   const uint32_t blocks = static_cast<uint32_t>(kMergeBlocksOf[variant / 3]);
   switch (kMergeItemsOf[variant % 3]) {
     case 4:
-      return launch_merge_items<4>(a_kv, a_val, na, b_kv, b_val, nb, out_kv, out_val, blocks,
+      return launch_merge_items<4>(a_kv, a_val, na, b_kv, b_val, nb, out_kv, out_val, out_fence, blocks,
                                    stream, t);
     case 16:
-      return launch_merge_items<16>(a_kv, a_val, na, b_kv, b_val, nb, out_kv, out_val, blocks,
+      return launch_merge_items<16>(a_kv, a_val, na, b_kv, b_val, nb, out_kv, out_val, out_fence, blocks,
                                     stream, t);
     default:
-      return launch_merge_items<8>(a_kv, a_val, na, b_kv, b_val, nb, out_kv, out_val, blocks,
+      return launch_merge_items<8>(a_kv, a_val, na, b_kv, b_val, nb, out_kv, out_val, out_fence, blocks,
                                    stream, t);
   }
 }
@@ -887,6 +1399,45 @@ hipError_t launch_scan(const uint32_t* counts, uint32_t nq, uint64_t* offsets,
   if (nq == 0) return hipSuccess;
   return launch(k_scan, grid_for(nq, kScanTile), kThreads, stream, t, counts, nq, offsets,
                 scan_status, fault);
+}
+
+hipError_t launch_successor(const LevelSet& lv, const uint32_t* q, uint32_t nq, uint32_t* out_key,
+                            uint32_t* out_val, uint8_t* out_found, hipStream_t stream,
+                            const KTimer* t) {
+  if (nq == 0) return hipSuccess;
+  return launch(k_successor, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, q, nq,
+                out_key, out_val, out_found);
+}
+
+hipError_t launch_predecessor(const LevelSet& lv, const uint32_t* q, uint32_t nq,
+                              uint32_t* out_key, uint32_t* out_val, uint8_t* out_found,
+                              hipStream_t stream, const KTimer* t) {
+  if (nq == 0) return hipSuccess;
+  return launch(k_predecessor, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, q, nq,
+                out_key, out_val, out_found);
+}
+
+uint32_t clean_tiles(uint32_t n) { return grid_for(n, kCleanTile); }
+
+hipError_t launch_clean_count(const uint32_t* kv, uint32_t n, uint32_t* tile_cnt,
+                              uint64_t* scan_status, size_t scan_words, hipStream_t stream,
+                              const KTimer* t) {
+  if (n == 0) return hipSuccess;
+  return launch(k_clean_count, clean_tiles(n), kThreads, stream, t, kv, n, tile_cnt, scan_status,
+                static_cast<uint64_t>(scan_words));
+}
+
+hipError_t launch_clean_scatter(const uint32_t* kv, const uint32_t* val, uint32_t n,
+                                const uint64_t* tile_off, const LevelDst& d, hipStream_t stream,
+                                const KTimer* t) {
+  if (n == 0 || d.count == 0) return hipSuccess;
+  return launch(k_clean_scatter, clean_tiles(n), kThreads, stream, t, kv, val, n, tile_off, d);
+}
+
+hipError_t launch_clean_pad(const LevelDst& d, uint64_t v, uint64_t total, hipStream_t stream,
+                            const KTimer* t) {
+  if (total <= v || d.count == 0) return hipSuccess;
+  return launch(k_clean_pad, grid_for(total - v, kThreads), kThreads, stream, t, d, v, total);
 }
 
 hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi,

@@ -40,7 +40,7 @@ class Stats(ctypes.Structure):
 
 
 KERNEL_NAMES = ("k_sort_hist", "k_sort_pass", "k_merge", "k_lookup", "k_count", "k_scan",
-                "k_range_emit")
+                "k_range_emit", "k_order", "k_clean")
 _NK = len(KERNEL_NAMES)
 
 
@@ -67,6 +67,10 @@ _SIGNATURES = {
     "lsm_lookup": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
     "lsm_count": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp]),
     "lsm_range": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _u64, ctypes.POINTER(_u64)]),
+    "lsm_successor": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
+    "lsm_predecessor": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
+    "lsm_cleanup": (ctypes.c_int, [_vp, ctypes.POINTER(_u64)]),
+    "lsm_bulk_insert": (ctypes.c_int, [_vp, _vp, _vp, _u64]),
     "lsm_destroy": (ctypes.c_int, [_vp]),
     "lsm_clear": (ctypes.c_int, [_vp]),
     "lsm_sync": (ctypes.c_int, [_vp]),
@@ -264,6 +268,39 @@ class LSM:
         _check(self._lib.lsm_lookup(self._h, _dev(q, "q"), nq, _dev(vals, "vals"),
                                     _dev(found, "found", (torch.uint8, torch.bool))), "lsm_lookup")
         return vals, found
+
+    def _order(self, fn, name, q):
+        nq = q.numel()
+        keys = torch.empty(nq, dtype=torch.int32, device=q.device)
+        vals = torch.empty(nq, dtype=torch.int32, device=q.device)
+        found = torch.empty(nq, dtype=torch.uint8, device=q.device)
+        _check(fn(self._h, _dev(q, "q"), nq, _dev(keys, "keys"), _dev(vals, "vals"),
+                  _dev(found, "found", (torch.uint8,))), name)
+        return keys, vals, found
+
+    def successor(self, q: torch.Tensor):
+        """(keys, vals, found): per query the live pair with the smallest key > q."""
+        return self._order(self._lib.lsm_successor, "lsm_successor", q)
+
+    def predecessor(self, q: torch.Tensor):
+        """(keys, vals, found): per query the live pair with the largest key < q."""
+        return self._order(self._lib.lsm_predecessor, "lsm_predecessor", q)
+
+    def bulk_insert(self, keys: torch.Tensor, vals: torch.Tensor) -> None:
+        """keys.numel() pairs as consecutive insert batches of b (the last one
+        partial); synchronises the stream."""
+        n = keys.numel()
+        if vals.numel() != n:
+            raise ValueError("keys and vals differ in length")
+        _check(self._lib.lsm_bulk_insert(self._h, _dev(keys, "keys"), _dev(vals, "vals"), n),
+               "lsm_bulk_insert")
+
+    def cleanup(self) -> int:
+        """Cleanup (drop stale elements, rebuild the levels); returns the
+        number of valid pairs.  Synchronises the stream."""
+        v = _u64(0)
+        _check(self._lib.lsm_cleanup(self._h, ctypes.byref(v)), "lsm_cleanup")
+        return int(v.value)
 
     def count(self, lo: torch.Tensor, hi: torch.Tensor, out: Optional[torch.Tensor] = None):
         nq = lo.numel()

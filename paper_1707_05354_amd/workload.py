@@ -232,6 +232,35 @@ def zipf_sweep(b: int, config: int = 3, n_total: int = 1 << 25, nq: int = 1 << 2
 
 
 # ---------------------------------------------------------------- batching
+def cleanup_build(b: int, R: int, stale: float, config: int = 6, nq: int = 1 << 22):
+    """R insert batches of b uniform 31-bit keys in which each element, with
+    probability `stale`, re-inserts a key of an earlier batch (a uniformly
+    drawn earlier slot), so that about that fraction of the resident
+    elements are replaced duplicates when the build ends; the cleanup
+    measurements of sec. V-E remove 10 % and 50 %.  Followed by nq lookups
+    of which half hit (keys drawn from the build).  Streams: 1 keys, 2
+    values, 3 re-insert choice, 4 earlier slot, 6 lookups."""
+    keys = uniform_keys(config, 1, 0, R * b).reshape(R, b)
+    vals = values(config, 2, 0, R * b).reshape(R, b)
+    flat = keys.reshape(-1)
+    u = splitmix64(config, 3, 0, R * b).reshape(R, b)
+    thresh = np.uint64(min(int(stale * 2.0**64), 2**64 - 1))
+    for i in range(1, R):
+        pick = np.nonzero(u[i] < thresh)[0]
+        if pick.size:
+            src = bounded(config, 4, i * b, pick.size, i * b)
+            keys[i, pick] = flat[src]
+    hit = flat[bounded(config, 6, 0, nq, R * b)]
+    miss = uniform_keys(config, 6, 1 << 40, nq)
+    half = bounded(config, 6, 1 << 41, nq, 2).astype(bool)
+    look = np.where(half, hit, miss).astype(np.uint32)
+    return PlainWorkload(name="cleanup b=%d R=%d stale=%.2f" % (b, R, stale), b=b, keys=keys,
+                         vals=vals, is_delete=np.zeros(R, bool), lookups=look,
+                         count_lo=np.zeros(0, np.uint32), count_hi=np.zeros(0, np.uint32),
+                         range_lo=np.zeros(0, np.uint32), range_hi=np.zeros(0, np.uint32),
+                         width=0, meta={"stale_target": stale})
+
+
 def batching_stream(config: int = 4, n_batches: int = 4096, median: int = 4096,
                     sigma: float = 1.0, lo: int = 256, hi: int = 65536, b: int = 1 << 16):
     """User batches for the batching form: sizes round(exp(N(ln median,

@@ -43,21 +43,51 @@ class Trio:
         self.m = oracle.MapOracle()
         self.c = oracle.CascadeOracle(b)
         self.b = b
+        self.merge_count_comparable = True  # false after a bulk call
 
     def insert(self, keys, vals):
+        self.merge_count_comparable = True
         self.g.insert(dev(keys), dev(vals))
         self.m.insert(keys, vals)
         self.c.insert(keys, vals)
 
     def delete(self, keys):
+        self.merge_count_comparable = True
         self.g.delete(dev(keys))
         self.m.delete(keys)
         self.c.delete(keys)
 
     def mixed(self, keys, vals, is_delete):
+        self.merge_count_comparable = True
         self.g.update(dev(keys), dev(vals), dev_u8(is_delete))
         self.m.mixed(keys, vals, is_delete)
         self.c.insert(keys, vals, (1 - np.asarray(is_delete, np.uint8)).astype(np.uint8))
+
+    def bulk(self, keys, vals):
+        """One bulk insert on the GPU; the oracles take the same pairs as
+        consecutive insert batches of b.  The call's merge count covers all
+        its merges, so it is not compared with the oracle's last batch."""
+        self.merge_count_comparable = False
+        self.g.bulk_insert(dev(keys), dev(vals))
+        for a in range(0, len(keys), self.b):
+            self.m.insert(keys[a:a + self.b], vals[a:a + self.b])
+            self.c.insert(keys[a:a + self.b], vals[a:a + self.b])
+
+    def cleanup(self):
+        v = self.g.cleanup()
+        ov = self.c.cleanup()
+        assert v == ov == len(self.m), (v, ov, len(self.m))
+        return v
+
+    def check_order(self, q):
+        q = np.asarray(q, np.uint32)
+        for name in ("successor", "predecessor"):
+            gk, gv, gf = getattr(self.g, name)(dev(q))
+            torch.cuda.synchronize()
+            ok, ov, of = getattr(self.m, name)(q)
+            assert np.array_equal(host(gf), of), name + " found flags differ"
+            assert np.array_equal(host(gk), ok), name + " keys differ"
+            assert np.array_equal(host(gv), ov), name + " values differ"
 
     def check_levels(self):
         self.g.sync()
@@ -74,7 +104,8 @@ class Trio:
                                      "gpu %d oracle %d" % (i, bad.size, bad[0], gk[bad[0]], okv[bad[0]]))
             assert np.array_equal(gv, ov), "level %d values differ" % i
         st = self.g.stats()
-        assert st.merged_elems_last == self.c.merged_last
+        if self.merge_count_comparable:
+            assert st.merged_elems_last == self.c.merged_last
 
     def check_queries(self, q, lo, hi):
         q, lo, hi = (np.asarray(x, np.uint32) for x in (q, lo, hi))

@@ -11,6 +11,10 @@ batches, n = 2^26 slots), in the benchmark's launch configuration.
 * Properties that hold at any size are checked on every query: count equals
   the range size, range keys ascend within their bounds, and each returned
   pair is what lookup returns for its key.
+* Cleanup at full size: the cascade oracle's cleanup gives the live set in
+  key order, which fixes every successor / predecessor answer exactly; the
+  GPU answers all 2^22 order queries before and after its own cleanup, and
+  its cleaned levels equal the oracle's byte for byte.
 """
 import numpy as np
 import pytest
@@ -73,12 +77,15 @@ def test_paper_scale_layout_and_sampled_queries():
         else:
             c.insert(w.keys[i], w.vals[i])
     okv, ov = c.level(10)
-    del c
     gkv, gv = g.level(10)
     gkv, gv = host(gkv), host(gv)
     assert np.array_equal(gkv, okv), "level 10 key variables differ"
     assert np.array_equal(gv, ov), "level 10 values differ"
-    del okv, ov
+    del okv, ov, gkv, gv
+    n_valid = c.cleanup()
+    cleaned = {i: c.level(i) for i in c.occupied()}
+    r_clean = c.r
+    del c
 
     note("paper scale: queries")
     q_d = dev(w.lookups)
@@ -120,4 +127,43 @@ def test_paper_scale_layout_and_sampled_queries():
     got_v = np.concatenate([rv[roff[j]:roff[j + 1]] for j in ri])
     assert np.array_equal(np.diff(oo.astype(np.int64)), np.diff(roff)[ri])
     assert np.array_equal(got_k, ok) and np.array_equal(got_v, oval)
+
+    # Order queries, exact for every query: the oracle's cleaned list is the
+    # live set in key order.
+    note("paper scale: order queries and cleanup")
+    flat_kv = np.concatenate([cleaned[i][0] for i in sorted(cleaned)])
+    flat_v = np.concatenate([cleaned[i][1] for i in sorted(cleaned)])
+    live_k, live_v = (flat_kv[:n_valid] >> 1).astype(np.int64), flat_v[:n_valid]
+    assert np.all(flat_kv[:n_valid] & 1 == 1) and np.all(np.diff(live_k) > 0)
+    edges = np.array([0, 1, 2**31 - 2, 2**31 - 1, 2**31, 2**32 - 1], np.uint32)
+    q = np.concatenate([w.lookups, edges, (live_k[::4099] + 1).astype(np.uint32)])
+    qi = q.astype(np.int64)
+    js = np.searchsorted(live_k, qi, side="right")
+    jp = np.searchsorted(live_k, qi, side="left") - 1
+    exp = {"successor": (js < n_valid, np.minimum(js, n_valid - 1)),
+           "predecessor": (jp >= 0, np.maximum(jp, 0))}
+
+    def check_order(stage):
+        for name, (f, j) in exp.items():
+            gk, gv2, gf = getattr(g, name)(dev(q))
+            torch.cuda.synchronize()
+            gk, gv2, gf = host(gk), host(gv2), host(gf)
+            assert np.array_equal(gf, f.astype(np.uint8)), "%s found flags differ (%s)" % (name, stage)
+            assert np.array_equal(gk, np.where(f, live_k[j], 0).astype(np.uint32)), \
+                "%s keys differ (%s)" % (name, stage)
+            assert np.array_equal(gv2, np.where(f, live_v[j], 0).astype(np.uint32)), \
+                "%s values differ (%s)" % (name, stage)
+
+    check_order("before cleanup")
+    assert g.cleanup() == n_valid
+    g.sync()
+    assert g.num_batches == r_clean and g.occupied() == sorted(cleaned)
+    for i, (okv, ov) in cleaned.items():
+        gkv, gv = g.level(i)
+        assert np.array_equal(host(gkv), okv), "cleaned level %d key variables differ" % i
+        assert np.array_equal(host(gv), ov), "cleaned level %d values differ" % i
+    check_order("after cleanup")
+    lv2, lf2 = g.lookup(q_d)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(lf2), lf) and np.array_equal(host(lv2), lv)
     g.close()

@@ -252,3 +252,22 @@ def test_merges_with_several_tiles_per_workgroup():
         t.check_levels()
     q = np.concatenate([np.array([12345], np.uint32), rng.integers(0, 1 << 30, 5000).astype(np.uint32)])
     t.check_queries(q, q[:2000], q[:2000] + 200000)
+
+
+def test_one_oversized_sort_bucket():
+    """Keys below 2^16 share one top digit, so the batch sort's whole batch
+    (98311 elements, beyond what one work-group sorts in LDS) lands in one
+    bucket and is sorted by streaming passes over global memory."""
+    b = 3 * (1 << 15) + 7
+    rng = np.random.default_rng(16)
+    note("oversized bucket b=%d" % b)
+    t = Trio(b)
+    for r in range(3):
+        k = rng.integers(0, 1 << 16, b).astype(np.uint32)
+        if r == 2:
+            t.delete(k[: b // 2])
+        else:
+            t.insert(k, rng.integers(0, 2**32, b, dtype=np.uint64).astype(np.uint32))
+        t.check_levels()
+    q = np.arange(0, 1 << 16, 7, dtype=np.uint32)
+    t.check_queries(q, q[:500], q[:500] + 300)
