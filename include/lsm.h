@@ -181,6 +181,22 @@ LSM_API lsm_status_t lsm_get_tuning(lsm_t h, uint32_t level, uint32_t* variant, 
 LSM_API lsm_status_t lsm_set_tuning(lsm_t h, uint32_t level, uint32_t variant);
 
 /*
+ * lsm_set_sort_path -- which batch sort runs (both give the same order, so
+ * results never depend on it).  LSM_SORT_TOP_DIGIT: one scatter on the top
+ * 8 sorted bits, then each bucket sorted in LDS by one work-group (batches
+ * of at most 2^20 elements; larger ones use digit passes).
+ * LSM_SORT_DIGIT_PASSES: one stable counting pass per 8-bit digit with
+ * decoupled look-back.  LSM_SORT_AUTO (the default): the top-digit sort
+ * unless the previous sort saw a top-digit bucket above 8192 elements
+ * (skewed keys, where one work-group would sort a large bucket alone).
+ * Takes effect at the next sort.  LSM_EINVAL for another mode.
+ */
+#define LSM_SORT_AUTO 0
+#define LSM_SORT_TOP_DIGIT 1
+#define LSM_SORT_DIGIT_PASSES 2
+LSM_API lsm_status_t lsm_set_sort_path(lsm_t h, int mode);
+
+/*
  * lsm_lookup -- LOOKUP(k) for nq query keys (sec. III-D, IV-B): searches
  * the occupied levels from the smallest (newest) up; a regular element
  * with key k returns its value, a tombstone with key k ends the search
@@ -345,6 +361,8 @@ typedef struct {
   uint64_t merged_elems_total; /* merge output elements since creation     */
   uint64_t sorted_elems_total; /* batch elements sorted since creation     */
   uint64_t device_bytes;       /* device memory held by the handle         */
+  uint64_t sorts_top_digit;    /* batch sorts by top-digit scatter + LDS    */
+  uint64_t sorts_digit_passes; /* batch sorts by one pass per 8-bit digit   */
 } lsm_stats_t;
 
 LSM_API lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out);

@@ -51,6 +51,13 @@ struct lsm_s {
   uint64_t q_cap = 0;
 
   uint64_t* h_pinned = nullptr;  // read-backs (range total, key check)
+  // Largest top-digit bucket of the most recent sort, written by the sort
+  // kernels into mapped host memory and read without synchronising (a
+  // stale value only affects which of two equivalent sort paths runs).
+  uint32_t* skew_host = nullptr;
+  uint32_t* skew_dev = nullptr;
+  uint64_t sorts_by_path[2] = {0, 0};
+  int sort_mode = LSM_SORT_AUTO;
 
   // Coalescer (batching form): user batches staged as key variables in
   // arrival order until b are collected.
@@ -62,8 +69,8 @@ struct lsm_s {
   // and histogram parity; recaptured whenever a buffer they name changes.
   bool graphs = false;
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph[kMaxLevels][2] = {};
-  hipGraphExec_t graph_exec[kMaxLevels][2] = {};
+  hipGraph_t graph[kMaxLevels][2][2] = {};          // [level][parity][sort path]
+  hipGraphExec_t graph_exec[kMaxLevels][2][2] = {};
 
   // Merge variant per merge input level (autotuned or set).
   int merge_variant[kMaxLevels];
@@ -211,12 +218,13 @@ lsm_status_t ensure_query_scratch(lsm_t h, uint32_t nq) {
 
 void drop_graphs(lsm_t h) {
   for (int j = 0; j < kMaxLevels; ++j)
-    for (int p = 0; p < 2; ++p) {
-      if (h->graph_exec[j][p]) (void)hipGraphExecDestroy(h->graph_exec[j][p]);
-      if (h->graph[j][p]) (void)hipGraphDestroy(h->graph[j][p]);
-      h->graph_exec[j][p] = nullptr;
-      h->graph[j][p] = nullptr;
-    }
+    for (int p = 0; p < 2; ++p)
+      for (int q = 0; q < 2; ++q) {
+        if (h->graph_exec[j][p][q]) (void)hipGraphExecDestroy(h->graph_exec[j][p][q]);
+        if (h->graph[j][p][q]) (void)hipGraphDestroy(h->graph[j][p][q]);
+        h->graph_exec[j][p][q] = nullptr;
+        h->graph[j][p][q] = nullptr;
+      }
 }
 
 void release_all(lsm_t h) {
@@ -244,6 +252,7 @@ void release_all(lsm_t h) {
     dev_free(h, h->q_status, scan_status_words(static_cast<uint32_t>(h->q_cap)) * sizeof(uint64_t));
   }
   if (h->h_pinned) (void)hipHostFree(h->h_pinned);
+  if (h->skew_host) (void)hipHostFree(h->skew_host);
 }
 
 // Two pooled events for one kernel launch (start, stop), remembered as a
@@ -312,6 +321,14 @@ lsm_status_t prepare_insert(lsm_t h, int j) {
   return LSM_OK;
 }
 
+int sort_path(lsm_t h, uint32_t tiles) {
+  int p;
+  if (h->sort_mode == LSM_SORT_DIGIT_PASSES) p = kSortLsd;
+  else if (h->sort_mode == LSM_SORT_TOP_DIGIT) p = pick_sort_path(tiles, 0u);
+  else p = pick_sort_path(tiles, *reinterpret_cast<volatile uint32_t*>(h->skew_host));
+  h->sorts_by_path[p] += 1;
+  return p;
+}
 SortArgs sort_args(lsm_t h, const BatchSrc& src, int j) {
   SortArgs sa;
   sa.src = src;
@@ -327,6 +344,8 @@ SortArgs sort_args(lsm_t h, const BatchSrc& src, int j) {
   sa.out_kv = (j == 0) ? h->lvl_kv[0] : h->buf_kv;
   sa.out_val = (j == 0) ? h->lvl_val[0] : h->buf_val;
   sa.out_fence = (j == 0) ? h->lvl_fence[0] : nullptr;
+  sa.path = sort_path(h, sa.meta.num_sort_tiles);
+  sa.skew_out = h->skew_dev;
   return sa;
 }
 
@@ -432,12 +451,13 @@ lsm_status_t insert_staged(lsm_t h, uint32_t n) {
   lsm_status_t s = prepare_insert(h, j);
   if (s != LSM_OK) return s;
   const int par = h->hist_parity;
-  if (h->graph_exec[j][par] == nullptr) {
+  const SortArgs sa =
+      sort_args(h, BatchSrc{h->stage_kv, h->stage_val, nullptr, h->b, h->b, kEncoded}, j);
+  const int path = sa.path;
+  if (h->graph_exec[j][par][path] == nullptr) {
     if (h->cap_stream == nullptr &&
         hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
       return LSM_EHIP;
-    const SortArgs sa =
-        sort_args(h, BatchSrc{h->stage_kv, h->stage_val, nullptr, h->b, h->b, kEncoded}, j);
     if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return LSM_EHIP;
     hipError_t e = launch_sort(sa, h->cap_stream, nullptr);
@@ -453,8 +473,8 @@ lsm_status_t insert_staged(lsm_t h, uint32_t n) {
       (void)hipGraphDestroy(graph);
       return LSM_EHIP;
     }
-    h->graph[j][par] = graph;
-    h->graph_exec[j][par] = exec;
+    h->graph[j][par][path] = graph;
+    h->graph_exec[j][par][path] = exec;
   }
   Timed tg;
   const KTimer* t = timer(h, tg, kKSortHist, 0, 0.0);  // whole-graph span, reported as an update
@@ -462,7 +482,7 @@ lsm_status_t insert_staged(lsm_t h, uint32_t n) {
     h->spans.pop_back();  // keep only the update-call span below
     (void)hipEventRecord(t->start, h->stream);
   }
-  if (hipGraphLaunch(h->graph_exec[j][par], h->stream) != hipSuccess) return LSM_EHIP;
+  if (hipGraphLaunch(h->graph_exec[j][par][path], h->stream) != hipSuccess) return LSM_EHIP;
   if (t != nullptr) {
     (void)hipEventRecord(t->stop, h->stream);
     call_span(h, 10, tg, tg, h->b);
@@ -524,6 +544,18 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
     void* hp = nullptr;
     if (hipHostMalloc(&hp, 64, hipHostMallocDefault) != hipSuccess) s = LSM_ENOMEM;
     else h->h_pinned = static_cast<uint64_t*>(hp);
+  }
+  if (s == LSM_OK) {
+    void* hp = nullptr;
+    void* dp = nullptr;
+    if (hipHostMalloc(&hp, 64, hipHostMallocMapped) != hipSuccess) {
+      s = LSM_ENOMEM;
+    } else {
+      h->skew_host = static_cast<uint32_t*>(hp);
+      *h->skew_host = 0u;
+      if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess) s = LSM_EHIP;
+      else h->skew_dev = static_cast<uint32_t*>(dp);
+    }
   }
   if (s != LSM_OK) {
     release_all(h);
@@ -731,6 +763,8 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
     sa.out_kv = p.n_old == 0 ? h->lvl_kv[i] : u32(mg[0][0]);
     sa.out_val = p.n_old == 0 ? h->lvl_val[i] : u32(mg[0][1]);
     sa.out_fence = p.n_old == 0 ? h->lvl_fence[i] : nullptr;
+    sa.path = sort_path(h, sa.meta.num_sort_tiles);
+    sa.skew_out = h->skew_dev;
     Timed ts[1 + kMaxPasses];
     KTimer tt[1 + kMaxPasses];
     const int nk = sort_kernel_count(sa);
@@ -1266,6 +1300,12 @@ lsm_status_t lsm_level_copy(lsm_t h, uint32_t i, uint32_t* d_kv_out, uint32_t* d
   return LSM_OK;
 }
 
+lsm_status_t lsm_set_sort_path(lsm_t h, int mode) {
+  if (h == nullptr || mode < LSM_SORT_AUTO || mode > LSM_SORT_DIGIT_PASSES) return LSM_EINVAL;
+  h->sort_mode = mode;
+  return LSM_OK;
+}
+
 lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out) {
   if (h == nullptr || out == nullptr) return LSM_EINVAL;
   out->num_batches = h->r;
@@ -1274,6 +1314,8 @@ lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out) {
   out->merged_elems_total = h->merged_total;
   out->sorted_elems_total = h->sorted_total;
   out->device_bytes = h->device_bytes;
+  out->sorts_top_digit = h->sorts_by_path[kSortMsd];
+  out->sorts_digit_passes = h->sorts_by_path[kSortLsd];
   return LSM_OK;
 }
 

@@ -92,6 +92,19 @@ struct SortMeta {
   int parity;
 };
 
+// The two sort paths: one scatter on the top digit then a per-bucket LDS
+// sort (for at most kMsdMaxTiles tiles), or one digit pass per 8 bits.  The
+// first is faster unless a top-digit bucket outgrows kLocalCap (skewed keys),
+// which its fallback handles with a single work-group; each sort records its
+// largest top-digit bucket so that the next sort can pick the path.
+enum SortPath : int { kSortMsd = 0, kSortLsd = 1 };
+inline int pick_sort_path(uint32_t tiles, uint32_t last_max_bucket) {
+  return (tiles <= static_cast<uint32_t>(kMsdMaxTiles) &&
+          last_max_bucket <= static_cast<uint32_t>(kLocalCap))
+             ? kSortMsd
+             : kSortLsd;
+}
+
 struct SortArgs {
   BatchSrc src;
   int lo_bit;               // lowest key-variable bit sorted
@@ -104,6 +117,8 @@ struct SortArgs {
   uint32_t* out_kv;         // sorted batch
   uint32_t* out_val;
   uint32_t* out_fence;      // fences of the output when it is a level, else null
+  int path;                 // SortPath; both paths give the same order
+  uint32_t* skew_out;       // optional: receives the largest top-digit bucket
 };
 
 // Optional per-launch timing: when start is non-null the kernel is launched

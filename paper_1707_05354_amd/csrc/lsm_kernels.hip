@@ -84,6 +84,23 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* tmp) {
   return pre + inc - x;
 }
 
+// Writes the largest of the work-group's 256 per-thread values to *out
+// (thread 0).  tmp holds kWaves words; two barriers, so the whole
+// work-group must call it.
+__device__ void record_max(uint32_t x, uint32_t* out, uint32_t* tmp) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = max(x, static_cast<uint32_t>(__shfl_xor(x, o, 64)));
+  if (lane == 0) tmp[wave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t r = tmp[0];
+    for (int w = 1; w < kWaves; ++w) r = max(r, tmp[w]);
+    *out = r;
+  }
+  __syncthreads();
+}
+
 // Device-scope relaxed atomics for the look-back words: each word carries
 // its own payload, so no other memory needs ordering with it.
 __device__ __forceinline__ uint32_t ld_dev(const uint32_t* p) {
@@ -394,6 +411,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(SortArgs a, int pass) {
   L.gstart[tid] = block_excl_scan(gtotal, L.tmp);  // contains the barrier publishing s_tile
   const uint32_t tile = s_tile;
   if (tile != blockIdx.x) load_tile(tile);
+  if (pass == 0 && tile == 0 && a.skew_out != nullptr)
+    record_max(mine[static_cast<size_t>(a.passes - 1) * kRadix + tid], a.skew_out, L.tmp);
   uint32_t* st = m.status + static_cast<size_t>(pass) * m.num_sort_tiles * kRadix;
   sort_tile_pass(kv, val, tile, b, a.lo_bit + kRadixBits * pass, st, o_kv, o_val,
                  (pass == a.passes - 1) ? a.out_fence : nullptr, false, &m.err[1], L);
@@ -590,6 +609,7 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
   __syncthreads();
   const uint32_t s = L.tmp[0], n = L.tmp[1];
   __syncthreads();
+  if (blockIdx.x == 0 && a.skew_out != nullptr) record_max(cnt, a.skew_out, L.tmp);
   if (n == 0) return;
   const uint32_t* src_k = a.tmp_kv[0] + s;
   const uint32_t* src_v = a.tmp_val[0] + s;
@@ -1283,13 +1303,11 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
   return m;
 }
 
-int sort_kernel_count(const SortArgs& a) {
-  return a.meta.num_sort_tiles <= static_cast<uint32_t>(kMsdMaxTiles) ? 3 : 1 + a.passes;
-}
+int sort_kernel_count(const SortArgs& a) { return a.path == kSortMsd ? 3 : 1 + a.passes; }
 
 hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers) {
   const uint32_t tiles = a.meta.num_sort_tiles;
-  if (tiles <= static_cast<uint32_t>(kMsdMaxTiles)) {
+  if (a.path == kSortMsd && tiles <= static_cast<uint32_t>(kMsdMaxTiles)) {
     // Top digit: the highest 8 of the sorted bits [lo_bit, lo_bit + 8 * passes).
     const int hi_bit = a.lo_bit + kRadixBits * a.passes;
     const int top = hi_bit - kRadixBits > a.lo_bit ? hi_bit - kRadixBits : a.lo_bit;

@@ -36,7 +36,7 @@ class LSMError(RuntimeError):
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "num_batches", "resident_elems", "merged_elems_last", "merged_elems_total",
-        "sorted_elems_total", "device_bytes")]
+        "sorted_elems_total", "device_bytes", "sorts_top_digit", "sorts_digit_passes")]
 
 
 KERNEL_NAMES = ("k_sort_hist", "k_sort_pass", "k_merge", "k_lookup", "k_count", "k_scan",
@@ -71,6 +71,7 @@ _SIGNATURES = {
     "lsm_predecessor": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
     "lsm_cleanup": (ctypes.c_int, [_vp, ctypes.POINTER(_u64)]),
     "lsm_bulk_insert": (ctypes.c_int, [_vp, _vp, _vp, _u64]),
+    "lsm_set_sort_path": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lsm_destroy": (ctypes.c_int, [_vp]),
     "lsm_clear": (ctypes.c_int, [_vp]),
     "lsm_sync": (ctypes.c_int, [_vp]),
@@ -253,6 +254,12 @@ class LSM:
         us = (ctypes.c_float * 6)()
         _check(self._lib.lsm_get_tuning(self._h, int(level), ctypes.byref(v), us), "lsm_get_tuning")
         return int(v.value), [float(x) for x in us]
+
+    SORT_AUTO, SORT_TOP_DIGIT, SORT_DIGIT_PASSES = 0, 1, 2
+
+    def set_sort_path(self, mode: int) -> None:
+        """LSM.SORT_AUTO (default), LSM.SORT_TOP_DIGIT or LSM.SORT_DIGIT_PASSES."""
+        _check(self._lib.lsm_set_sort_path(self._h, int(mode)), "lsm_set_sort_path")
 
     def set_tuning(self, level: int, variant: int) -> None:
         _check(self._lib.lsm_set_tuning(self._h, int(level), int(variant)), "lsm_set_tuning")

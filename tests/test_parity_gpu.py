@@ -262,6 +262,7 @@ def test_one_oversized_sort_bucket():
     rng = np.random.default_rng(16)
     note("oversized bucket b=%d" % b)
     t = Trio(b)
+    t.g.set_sort_path(LSM.SORT_TOP_DIGIT)
     for r in range(3):
         k = rng.integers(0, 1 << 16, b).astype(np.uint32)
         if r == 2:
@@ -271,3 +272,45 @@ def test_one_oversized_sort_bucket():
         t.check_levels()
     q = np.arange(0, 1 << 16, 7, dtype=np.uint32)
     t.check_queries(q, q[:500], q[:500] + 300)
+
+
+def test_sort_path_follows_key_skew():
+    """Automatic path choice: skewed batches (one key in 70 % of the slots)
+    move the sort to digit passes from the next batch on, uniform batches
+    move it back; every batch's level layout stays byte-exact either way."""
+    b = (1 << 15) + 5
+    rng = np.random.default_rng(61)
+    note("sort path follows skew b=%d" % b)
+    t = Trio(b)
+    paths = []
+    for r in range(7):
+        if r < 3:
+            k = rng.integers(0, 1 << 31, b, dtype=np.uint64).astype(np.uint32)
+            k[rng.random(b) < 0.7] = 123456789
+        else:
+            k = rng.integers(0, 1 << 31, b, dtype=np.uint64).astype(np.uint32)
+        before = t.g.stats()
+        t.insert(k, rng.integers(0, 2**32, b, dtype=np.uint64).astype(np.uint32))
+        t.check_levels()  # synchronises, so the next choice sees this sort
+        after = t.g.stats()
+        paths.append("top" if after.sorts_top_digit > before.sorts_top_digit else "passes")
+    assert paths == ["top", "passes", "passes", "passes", "top", "top", "top"], paths
+
+
+@pytest.mark.parametrize("mode", [LSM.SORT_TOP_DIGIT, LSM.SORT_DIGIT_PASSES])
+def test_forced_sort_paths(mode):
+    """Either path, forced, on batches of 1 to 600 tiles with partial
+    batches and mixed updates."""
+    for b, domain, R, seed in [(1, 8, 20, 71), (2047, 3000, 9, 72), (4096 * 3 + 1, 1 << 31, 6, 73),
+                               (600 * 2048 - 9, 1 << 31, 3, 74)]:
+        ops, q, lo, hi = W.random_small(seed, b, R, domain, p_delete=0.3, nq=300)
+        note("forced sort path %d b=%d" % (mode, b))
+        t = Trio(b)
+        t.g.set_sort_path(mode)
+        for kind, k, v in ops:
+            if kind == "insert":
+                t.insert(k, v)
+            else:
+                t.delete(k)
+        t.check_levels()
+        t.check_queries(q, lo, hi)
