@@ -568,13 +568,19 @@ def main() -> int:
     from paper_1707_05354_amd import profsum
     tr = profsum.load_traffic(os.path.join(ROOT, "profiles", "paper_scale_b65536_hbm_traffic.md"))
     traffic, traffic_detail = None, None
-    if tr is not None and L.KERNEL_NAMES[dom] in tr["kernels"]:
-        kt = tr["kernels"][L.KERNEL_NAMES[dom]]
-        traffic = round(kt["fetch_bytes_per_launch"] + kt["write_bytes_per_launch"])
+    names = [n for n in L.KERNEL_TRACE_NAMES.get(L.KERNEL_NAMES[dom], (L.KERNEL_NAMES[dom],))
+             if tr is not None and n in tr["kernels"]]
+    if names:
+        rows = [tr["kernels"][n] for n in names]
+        disp = sum(r["dispatches"] for r in rows)
+        fetch = sum(r["fetch_bytes_per_launch"] * r["dispatches"] for r in rows) / disp
+        write = sum(r["write_bytes_per_launch"] * r["dispatches"] for r in rows) / disp
+        traffic = round(fetch + write)
         traffic_detail = {"unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                   "copy-calibrated)",
-                          "fetch": round(kt["fetch_bytes_per_launch"]),
-                          "write": round(kt["write_bytes_per_launch"]),
+                          "kernels": names,
+                          "fetch": round(fetch),
+                          "write": round(write),
                           "algorithmic": round(dom_bytes / max(1, dom_n)),
                           "traffic_over_algorithmic": round(traffic / max(1.0, dom_bytes / max(1, dom_n)), 3)}
     merge_gbs = prof.kernel_bytes[2] / max(1e-12, prof.kernel_ms[2] * 1e-3) / 1e9
@@ -609,7 +615,7 @@ def main() -> int:
                               "max": round(prof.update_max_ms, 4)},
         "phase_ms": {"updates": round(upd_ms, 3), "lookups": round(lk_ms, 3),
                      "counts": round(ct_ms, 3), "ranges": round(rg_ms, 3),
-                     "sort_kernels": round(prof.kernel_ms[0] + prof.kernel_ms[1], 3),
+                     "sort_kernels": round(sum(prof.kernel_ms[k] for k in (0, 1, 9, 10, 11)), 3),
                      "merge_kernels": round(prof.kernel_ms[2], 3)},
         "roofline": {
             "kernel": L.KERNEL_NAMES[dom],

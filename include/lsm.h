@@ -191,6 +191,19 @@ LSM_API lsm_status_t lsm_set_tuning(lsm_t h, uint32_t level, uint32_t variant);
  * (skewed keys, where one work-group would sort a large bucket alone).
  * Takes effect at the next sort.  LSM_EINVAL for another mode.
  */
+/*
+ * lsm_set_fusion -- deepest cascade fused into the top-digit batch sort.  An
+ * insert that fills level j <= max_levels (j >= 1) is done by the sort's
+ * per-bucket work-groups: each merges its bucket of the batch with the same
+ * key range of levels 0..j-1 and writes that part of level j, in the order
+ * of the pairwise cascade (so the levels are byte for byte the same), with
+ * no merge launch.  0 disables fusion; a negative value restores the
+ * default (the largest j with b 2^j <= 2^20, at most 8).  Applies only when
+ * the top-digit sort runs.  Drops captured graphs.  LSM_EINVAL for more
+ * than 8 levels.
+ */
+LSM_API lsm_status_t lsm_set_fusion(lsm_t h, int max_levels);
+
 #define LSM_SORT_AUTO 0
 #define LSM_SORT_TOP_DIGIT 1
 #define LSM_SORT_DIGIT_PASSES 2
@@ -357,8 +370,11 @@ LSM_API lsm_status_t lsm_level_copy(lsm_t h, uint32_t i, uint32_t* d_kv_out,
 typedef struct {
   uint64_t num_batches;        /* r                                        */
   uint64_t resident_elems;     /* r * b                                    */
-  uint64_t merged_elems_last;  /* merge output elements, last update call  */
-  uint64_t merged_elems_total; /* merge output elements since creation     */
+  uint64_t merged_elems_last;  /* merge output elements of the pairwise
+                                  cascade, last update call ((2^(j+1) - 2) b
+                                  for an insert into level j; the same
+                                  figure when the cascade is fused)         */
+  uint64_t merged_elems_total; /* the same, summed since creation           */
   uint64_t sorted_elems_total; /* batch elements sorted since creation     */
   uint64_t device_bytes;       /* device memory held by the handle         */
   uint64_t sorts_top_digit;    /* batch sorts by top-digit scatter + LDS    */
@@ -374,18 +390,19 @@ LSM_API lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out);
  * own execution times.  lsm_profile_read synchronises the stream, resolves
  * the events and returns the sums since the last reset.
  *
- * Kernel index k: 0 batch-sort histogram, 1 batch-sort digit pass, 2 level
- * merge, 3 lookup, 4 count, 5 range offset scan, 6 range emission,
- * 7 successor / predecessor, 8 cleanup mark-and-compact.
- * kernel_bytes[k] is the algorithmic traffic of those launches: 8 B per
- * batch element for the histogram (key and value read), 16 B per element
- * for a digit pass (key and value read and written), 16 B per merge output
- * element, 12 B per scanned count; for cleanup 4 B per merged element to
- * count, 8 B per merged element read plus 8 B per valid element written to
- * scatter, 8 B per placebo; 0 for the search kernels, which are
- * latency-bound.
+ * Kernel index k: 0 batch-sort histogram (digit-pass path), 1 batch-sort
+ * digit pass, 2 level merge, 3 lookup, 4 count, 5 range offset scan, 6 range
+ * emission, 7 successor / predecessor, 8 cleanup mark-and-compact, 9 / 10 /
+ * 11 the top-digit sort's histogram, scatter and per-bucket sort.
+ * kernel_bytes[k] is the algorithmic traffic of those launches: 4 B per
+ * batch element for a histogram (keys read), 16 B per element for a digit
+ * pass, the top-digit scatter and the per-bucket sort (key and value read
+ * and written), 16 B per merge output element, 12 B per scanned count; for
+ * cleanup 4 B per merged element to count, 8 B per merged element read plus
+ * 8 B per valid element written to scatter, 8 B per placebo; 0 for the
+ * search kernels, which are latency-bound.
  */
-#define LSM_PROF_KERNELS 9
+#define LSM_PROF_KERNELS 12
 typedef struct {
   uint64_t update_calls;                   /* update calls (n > 0)          */
   uint64_t query_calls[3];                 /* lookup, count, range calls    */

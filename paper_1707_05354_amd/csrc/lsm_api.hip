@@ -58,6 +58,7 @@ struct lsm_s {
   uint32_t* skew_dev = nullptr;
   uint64_t sorts_by_path[2] = {0, 0};
   int sort_mode = LSM_SORT_AUTO;
+  int fuse_max = 0;  // deepest cascade fused into the top-digit sort
 
   // Coalescer (batching form): user batches staged as key variables in
   // arrival order until b are collected.
@@ -329,8 +330,45 @@ int sort_path(lsm_t h, uint32_t tiles) {
   h->sorts_by_path[p] += 1;
   return p;
 }
+// Default depth of the fused cascade: level j is fused while a bucket of
+// level j holds about 4096 elements on average (b 2^j / 256 <= 2^12).
+int default_fuse_max(uint32_t b) {
+  int J = 0;
+  while (J < kMaxFuse && (static_cast<uint64_t>(b) << (J + 1)) <= (1ull << 20)) ++J;
+  return J;
+}
+
+// Fuses the first levels of an insert's cascade into the top-digit sort:
+// levels 0..nf-1 with nf = min(j, fuse_max).  When nf = j the sort writes
+// level j; otherwise it writes the merge scratch buffer that the pairwise
+// merge of level nf then reads (see enqueue_cascade).
+void setup_fusion(lsm_t h, SortArgs& sa, int j) {
+  sa.fuse.nlev = 0;
+  const int nf = j < h->fuse_max ? j : h->fuse_max;
+  if (sa.path != kSortMsd || nf < 1 || nf > kMaxFuse || sort_top_shift(sa) < 1) return;
+  FuseArgs& f = sa.fuse;
+  f.nlev = nf;
+  f.key_shift = sort_top_shift(sa) - 1;
+  for (int l = 0; l < nf; ++l) {
+    f.kv[l] = h->lvl_kv[l];
+    f.val[l] = h->lvl_val[l];
+    f.fence[l] = h->lvl_fence[l];
+    f.len[l] = static_cast<uint32_t>(level_len(h, l));
+  }
+  f.out_len = level_len(h, nf);
+  if (nf == j) {
+    f.out_kv = h->lvl_kv[j];
+    f.out_val = h->lvl_val[j];
+    f.out_fence = h->lvl_fence[j];
+  } else {
+    f.out_kv = h->mrg_kv[(nf + 1) & 1];
+    f.out_val = h->mrg_val[(nf + 1) & 1];
+    f.out_fence = nullptr;
+  }
+}
+
 SortArgs sort_args(lsm_t h, const BatchSrc& src, int j) {
-  SortArgs sa;
+  SortArgs sa{};
   sa.src = src;
   sa.lo_bit = (src.mode == kMixed) ? 0 : 1;
   sa.passes = sort_passes(h->key_bits, sa.lo_bit);
@@ -346,17 +384,22 @@ SortArgs sort_args(lsm_t h, const BatchSrc& src, int j) {
   sa.out_fence = (j == 0) ? h->lvl_fence[0] : nullptr;
   sa.path = sort_path(h, sa.meta.num_sort_tiles);
   sa.skew_out = h->skew_dev;
+  setup_fusion(h, sa, j);
   return sa;
 }
 
 // The cascade of Fig. 2(a): while level i is full, buffer <- merge(buffer,
 // level i); the last merge writes straight into level j.  Enqueued on s.
+// The pairwise merges of an insert into level j, after the sort (and after
+// the levels the sort fused, whose output is then the first input).
 hipError_t enqueue_cascade(lsm_t h, const SortArgs& sa, int j, hipStream_t s, Timed* last,
                            uint64_t* merged_out) {
-  const uint32_t* cur_kv = sa.out_kv;
-  const uint32_t* cur_val = sa.out_val;
+  const int i0 = sa.fuse.nlev;
+  const uint32_t* cur_kv = i0 > 0 ? sa.fuse.out_kv : sa.out_kv;
+  const uint32_t* cur_val = i0 > 0 ? sa.fuse.out_val : sa.out_val;
   uint64_t merged = 0;
-  for (int i = 0; i < j; ++i) {
+  for (int l = 0; l < i0; ++l) merged += 2ull * level_len(h, l);
+  for (int i = i0; i < j; ++i) {
     uint32_t* o_kv = (i == j - 1) ? h->lvl_kv[j] : h->mrg_kv[i & 1];
     uint32_t* o_val = (i == j - 1) ? h->lvl_val[j] : h->mrg_val[i & 1];
     const uint32_t len = static_cast<uint32_t>(level_len(h, i));
@@ -411,8 +454,10 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
   bool timed = h->prof;
   const int nk = sort_kernel_count(sa);
   for (int p = 0; p < nk && timed; ++p) {
-    const KTimer* t = (p == 0) ? timer(h, st[p], kKSortHist, h->b, 8.0 * h->b)
-                               : timer(h, st[p], kKSortPass, h->b, 16.0 * h->b);
+    const double bytes = (sa.fuse.nlev > 0 && p == nk - 1)
+                             ? 16.0 * static_cast<double>(level_len(h, sa.fuse.nlev))
+                             : sort_kernel_bytes_per_elem(p) * h->b;
+    const KTimer* t = timer(h, st[p], sort_kernel_kind(sa.path, p), h->b, bytes);
     if (t == nullptr) timed = false;
     else sort_t[p] = *t;
   }
@@ -514,6 +559,7 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
   lsm_t h = new (std::nothrow) lsm_s();
   if (h == nullptr) return LSM_ENOMEM;
   h->b = b;
+  h->fuse_max = default_fuse_max(b);
   h->flags = flags;
   h->key_bits = kb;
   h->stream = static_cast<hipStream_t>(stream);
@@ -747,7 +793,7 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
     const uint64_t e0 = (p.first_new - r0) * b;          // first input element
     const uint64_t len = (p.end - p.first_new) * b;      // padded length
     const uint64_t avail = n - e0 < len ? n - e0 : len;  // real elements
-    SortArgs sa;
+    SortArgs sa{};
     sa.src = BatchSrc{d_keys + e0, d_vals + e0, nullptr, static_cast<uint32_t>(avail),
                       static_cast<uint32_t>(len), static_cast<int>(kInsert)};
     sa.lo_bit = 1;
@@ -770,8 +816,8 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
     const int nk = sort_kernel_count(sa);
     bool timed = h->prof;
     for (int x = 0; x < nk && timed; ++x) {
-      const KTimer* t = (x == 0) ? timer(h, ts[x], kKSortHist, len, 8.0 * len)
-                                 : timer(h, ts[x], kKSortPass, len, 16.0 * len);
+      const KTimer* t = timer(h, ts[x], sort_kernel_kind(sa.path, x), len,
+                              sort_kernel_bytes_per_elem(x) * len);
       if (t == nullptr) timed = false;
       else tt[x] = *t;
     }
@@ -1297,6 +1343,13 @@ lsm_status_t lsm_level_copy(lsm_t h, uint32_t i, uint32_t* d_kv_out, uint32_t* d
       hipMemcpyAsync(d_vals_out, h->lvl_val[i], n * sizeof(uint32_t), hipMemcpyDeviceToDevice,
                      h->stream) != hipSuccess)
     return LSM_EHIP;
+  return LSM_OK;
+}
+
+lsm_status_t lsm_set_fusion(lsm_t h, int max_levels) {
+  if (h == nullptr || max_levels > kMaxFuse) return LSM_EINVAL;
+  h->fuse_max = max_levels < 0 ? default_fuse_max(h->b) : max_levels;
+  drop_graphs(h);
   return LSM_OK;
 }
 

@@ -26,6 +26,9 @@ constexpr int kMaxHistBlocks = 512;
 // elements are sorted in LDS.
 constexpr int kMsdMaxTiles = 512;
 constexpr int kLocalCap = 8192;
+// Buckets of at most this many elements are sorted by ranking (every
+// element counts the elements that precede it) instead of radix passes.
+constexpr uint32_t kRankSortMax = 1024;
 
 // Merge variants (autotuned per level): items per thread x work-group cap.
 // Variant v uses kMergeItemsOf[v % 3] items per thread (tiles of 256 x that)
@@ -105,6 +108,24 @@ inline int pick_sort_path(uint32_t tiles, uint32_t last_max_bucket) {
              : kSortLsd;
 }
 
+// A small cascade fused into the top-digit sort: the work-group of bucket d
+// merges the batch's bucket with the same key range of levels 0..nlev-1
+// (bucket d holds the original keys [d << key_shift, (d + 1) << key_shift))
+// and writes that part of level nlev.  nlev = 0: no fusion.
+constexpr int kMaxFuse = 8;
+struct FuseArgs {
+  int nlev;
+  int key_shift;
+  const uint32_t* kv[kMaxFuse];
+  const uint32_t* val[kMaxFuse];
+  const uint32_t* fence[kMaxFuse];
+  uint32_t len[kMaxFuse];
+  uint32_t* out_kv;
+  uint32_t* out_val;
+  uint32_t* out_fence;
+  uint64_t out_len;
+};
+
 struct SortArgs {
   BatchSrc src;
   int lo_bit;               // lowest key-variable bit sorted
@@ -119,7 +140,14 @@ struct SortArgs {
   uint32_t* out_fence;      // fences of the output when it is a level, else null
   int path;                 // SortPath; both paths give the same order
   uint32_t* skew_out;       // optional: receives the largest top-digit bucket
+  FuseArgs fuse;            // top-digit path only
 };
+
+// Bit position of the top digit the top-digit sort scatters on.
+inline int sort_top_shift(const SortArgs& a) {
+  const int hi_bit = a.lo_bit + kRadixBits * a.passes;
+  return hi_bit - kRadixBits > a.lo_bit ? hi_bit - kRadixBits : a.lo_bit;
+}
 
 // Optional per-launch timing: when start is non-null the kernel is launched
 // with hipExtLaunchKernelGGL so the two events bracket the kernel itself.
@@ -131,8 +159,16 @@ struct KTimer {
 // Kernel kinds of the profile (indices of lsm_profile_t's per-kernel arrays).
 enum KernelKind : int {
   kKSortHist = 0, kKSortPass = 1, kKMerge = 2, kKLookup = 3, kKCount = 4, kKScan = 5,
-  kKRangeEmit = 6, kKOrder = 7, kKClean = 8, kNumKernelKinds = 9
+  kKRangeEmit = 6, kKOrder = 7, kKClean = 8, kKMsdHist = 9, kKMsdScatter = 10,
+  kKLocalSort = 11, kNumKernelKinds = 12
 };
+// Profiler kind and algorithmic bytes per element of the x-th kernel a sort
+// launches (launch_sort's order).
+inline int sort_kernel_kind(int path, int x) {
+  if (path == kSortMsd) return x == 0 ? kKMsdHist : (x == 1 ? kKMsdScatter : kKLocalSort);
+  return x == 0 ? kKSortHist : kKSortPass;
+}
+inline double sort_kernel_bytes_per_elem(int x) { return x == 0 ? 4.0 : 16.0; }
 
 // Destination of cleanup's redistribution: the occupied levels of the new
 // batch count, smallest first; level l receives the list positions

@@ -496,9 +496,18 @@ __global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_sh
   const uint32_t tbase = tile * kSortTile;
   const uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
   const uint32_t gtotal = mine[tid];
-  // Elements of this digit in earlier tiles (independent loads).
+  // Elements of this digit in earlier tiles, eight independent loads in
+  // flight at a time.
   uint32_t before = 0;
-  for (uint32_t t = 0; t < tile; ++t) before += m.tile_cnt[static_cast<size_t>(t) * kRadix + tid];
+  uint32_t t = 0;
+  for (; t + 8 <= tile; t += 8) {
+    uint32_t c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c[q] = m.tile_cnt[static_cast<size_t>(t + q) * kRadix + tid];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) before += c[q];
+  }
+  for (; t < tile; ++t) before += m.tile_cnt[static_cast<size_t>(t) * kRadix + tid];
   for (uint32_t i = tid; i < kWaves * kRadix; i += kThreads) (&s_wcnt[0][0])[i] = 0u;
   uint32_t kv[kSortItems], val[kSortItems], off[kSortItems];
 #pragma unroll
@@ -551,6 +560,9 @@ struct LocalLds {
   uint32_t v[2][kLocalCap];
   uint32_t wcnt[kWaves][kRadix];
   uint32_t tmp[kWaves];
+  uint32_t lo[kMaxFuse], hi[kMaxFuse];  // fused cascade: the digit's range per level
+  uint32_t rs[kMaxFuse + 2];            // run starts in the concatenated runs
+  uint32_t out_lo, out_hi;              // first output position (64-bit)
 };
 
 // One stable counting pass over n <= kLocalCap elements in LDS, from
@@ -595,46 +607,16 @@ __device__ void lds_pass(LocalLds& L, int from, uint32_t n, int shift) {
 
 // Bucket d (= blockIdx.x) of the MSD scatter, sorted on the digits below
 // the top one; written to the sort output at the bucket's own range.
-__global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit, int passes) {
-  __shared__ LocalLds L;
+// Stable passes over a bucket too large for LDS, streaming through the
+// bucket's range chunk by chunk in order and ping-ponging between the two
+// scratch buffers; the last pass writes out_kv / out_val at s.
+__device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, uint32_t s,
+                                     uint32_t n, LocalLds& L) {
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const SortMeta& m = a.meta;
-  const uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
-  const uint32_t cnt = mine[tid];
-  const uint32_t start = block_excl_scan(cnt, L.tmp);
-  if (tid == blockIdx.x) {
-    L.tmp[0] = start;
-    L.tmp[1] = cnt;
-  }
-  __syncthreads();
-  const uint32_t s = L.tmp[0], n = L.tmp[1];
-  __syncthreads();
-  if (blockIdx.x == 0 && a.skew_out != nullptr) record_max(cnt, a.skew_out, L.tmp);
-  if (n == 0) return;
   const uint32_t* src_k = a.tmp_kv[0] + s;
   const uint32_t* src_v = a.tmp_val[0] + s;
   uint32_t* out_k = a.out_kv + s;
   uint32_t* out_v = a.out_val + s;
-  if (n <= static_cast<uint32_t>(kLocalCap)) {
-    for (uint32_t x = tid; x < n; x += kThreads) {
-      L.k[0][x] = src_k[x];
-      L.v[0][x] = src_v[x];
-    }
-    __syncthreads();
-    int cur = 0;
-    for (int p = 0; p < passes; ++p) {
-      lds_pass(L, cur, n, lo_bit + kRadixBits * p);
-      cur = 1 - cur;
-    }
-    for (uint32_t x = tid; x < n; x += kThreads) {
-      out_k[x] = L.k[cur][x];
-      out_v[x] = L.v[cur][x];
-      put_fence(a.out_fence, s + x, L.k[cur][x]);
-    }
-    return;
-  }
-  // Oversized bucket: stable passes streaming through the bucket's range,
-  // chunk by chunk in order, ping-ponging between the two scratch buffers.
   if (passes == 0) {
     for (uint32_t x = tid; x < n; x += kThreads) {
       const uint32_t k = src_k[x];
@@ -702,6 +684,246 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
   }
 }
 
+// Bound of original key k in the sorted segment [lo, hi) of s (LDS or
+// global): first position whose key is >= k (upper: > k).
+__device__ __forceinline__ uint32_t seg_bound(const uint32_t* s, uint32_t lo, uint32_t hi,
+                                              uint32_t k, bool upper) {
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    const uint32_t x = s[mid] >> 1;
+    if (upper ? x <= k : x < k) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One work-group per top-digit bucket.  The bucket of the batch is sorted on
+// the digits below the top one: by ranking up to kRankSortMax elements, by
+// LDS radix passes up to kLocalCap, else by streaming passes over global
+// memory.  Without a fused cascade the sorted bucket is the output.
+//
+// With a fused cascade (a.fuse.nlev = j > 0), the work-group then merges
+// its bucket with the same digit's key range of levels 0..j-1 and writes
+// that part of level j.  Runs are numbered newest first (the batch, then
+// level 0, 1, ...); the output rank of an element is its position in its
+// run plus, for every newer run, the elements with a key <= its key and, for
+// every older run, the elements with a smaller key.  (key, run, position) is
+// a strict total order, so this is exactly the order of the pairwise cascade
+// (the newer run first on equal keys at every step).  A bucket whose runs fit
+// in LDS is ranked there; a larger one is ranked with searches in global
+// memory.
+__global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit, int passes) {
+  __shared__ LocalLds L;
+  const uint32_t tid = threadIdx.x;
+  const SortMeta& m = a.meta;
+  const FuseArgs& f = a.fuse;
+  const bool fused = f.nlev > 0;
+  const uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
+  const uint32_t cnt = mine[tid];
+  const uint32_t start = block_excl_scan(cnt, L.tmp);
+  if (tid == blockIdx.x) {
+    L.tmp[0] = start;
+    L.tmp[1] = cnt;
+  }
+  __syncthreads();
+  const uint32_t s = L.tmp[0], n = L.tmp[1];
+  __syncthreads();
+  if (blockIdx.x == 0 && a.skew_out != nullptr) record_max(cnt, a.skew_out, L.tmp);
+  if (n == 0 && !fused) return;
+  const uint32_t* src_k = a.tmp_kv[0] + s;
+  const uint32_t* src_v = a.tmp_val[0] + s;
+  uint32_t* out_k = a.out_kv + s;
+  uint32_t* out_v = a.out_val + s;
+
+  // ---- sort the batch's bucket; buf = LDS buffer holding it, or -1 when
+  // it was sorted in global memory (at out_k / out_v).
+  int buf = 0;
+  if (n == 0) {
+    buf = 0;
+  } else if (n <= kRankSortMax) {
+    // Stable rank sort: the rank of element x is the number of elements
+    // whose sorted field is smaller, plus those with an equal field at an
+    // earlier position; (field, position) is a strict total order, so the
+    // ranks are a permutation of [0, n) and the order equals that of the
+    // radix passes over the same bits.
+    const uint32_t fmask = (kRadixBits * passes >= 32) ? 0xFFFFFFFFu
+                                                       : ((1u << (kRadixBits * passes)) - 1u);
+    for (uint32_t x = tid; x < n; x += kThreads) {
+      const uint32_t k = src_k[x];
+      L.k[0][x] = k;
+      L.v[0][x] = src_v[x];
+      L.k[1][x] = (k >> lo_bit) & fmask;
+    }
+    __syncthreads();
+    constexpr int kPer = static_cast<int>(kRankSortMax / kThreads);
+    uint32_t fx[kPer], rank[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const uint32_t x = tid + i * kThreads;
+      fx[i] = x < n ? L.k[1][x] : 0u;
+      rank[i] = 0u;
+    }
+    for (uint32_t y = 0; y < n; ++y) {
+      const uint32_t fy = L.k[1][y];
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const uint32_t x = tid + i * kThreads;
+        rank[i] += (fy < fx[i] || (fy == fx[i] && y < x)) ? 1u : 0u;
+      }
+    }
+    uint32_t kx[kPer], vx[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const uint32_t x = tid + i * kThreads;
+      kx[i] = x < n ? L.k[0][x] : 0u;
+      vx[i] = x < n ? L.v[0][x] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      if (tid + i * kThreads < n) {
+        L.k[1][rank[i]] = kx[i];
+        L.v[1][rank[i]] = vx[i];
+      }
+    }
+    __syncthreads();
+    buf = 1;
+  } else if (n <= static_cast<uint32_t>(kLocalCap)) {
+    for (uint32_t x = tid; x < n; x += kThreads) {
+      L.k[0][x] = src_k[x];
+      L.v[0][x] = src_v[x];
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int p = 0; p < passes; ++p) {
+      lds_pass(L, cur, n, lo_bit + kRadixBits * p);
+      cur = 1 - cur;
+    }
+    buf = cur;
+  } else {
+    buf = -1;
+    local_sort_streaming(a, lo_bit, passes, s, n, L);
+  }
+
+  if (!fused) {
+    if (buf >= 0) {
+      for (uint32_t x = tid; x < n; x += kThreads) {
+        const uint32_t k = L.k[buf][x];
+        out_k[x] = k;
+        out_v[x] = L.v[buf][x];
+        put_fence(a.out_fence, s + x, k);
+      }
+    }
+    return;
+  }
+
+  // ---- fused cascade: this digit's key range in levels 0..j-1.
+  const uint32_t d = blockIdx.x;
+  const int R = f.nlev + 1;  // runs: the batch, then levels 0..j-1
+  if (tid < static_cast<uint32_t>(f.nlev)) {
+    const uint32_t l = tid;
+    const uint64_t k0 = static_cast<uint64_t>(d) << f.key_shift;
+    const uint64_t k1 = static_cast<uint64_t>(d + 1) << f.key_shift;
+    const uint32_t len = f.len[l];
+    const uint32_t lo = k0 > 0xFFFFFFFFull ? len
+                                           : fenced_bound(f.kv[l], f.fence[l], len,
+                                                          static_cast<uint32_t>(k0), false);
+    uint32_t hi = (d == kRadix - 1 || k1 > 0xFFFFFFFFull)
+                      ? len
+                      : fenced_bound(f.kv[l], f.fence[l], len, static_cast<uint32_t>(k1), false);
+    if (hi < lo) hi = lo;
+    L.lo[l] = lo;
+    L.hi[l] = hi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t o = s;
+    L.rs[0] = 0;
+    L.rs[1] = n;
+    for (int l = 0; l < f.nlev; ++l) {
+      o += L.lo[l];
+      L.rs[l + 2] = L.rs[l + 1] + (L.hi[l] - L.lo[l]);
+    }
+    L.out_lo = static_cast<uint32_t>(o);
+    L.out_hi = static_cast<uint32_t>(o >> 32);
+  }
+  __syncthreads();
+  const uint32_t T = L.rs[R];
+  const uint64_t out0 = (static_cast<uint64_t>(L.out_hi) << 32) | L.out_lo;
+  if (T == 0) return;
+
+  if (buf >= 0 && T <= static_cast<uint32_t>(kLocalCap)) {
+    uint32_t* rk = L.k[buf];
+    uint32_t* rv = L.v[buf];
+    uint32_t* ok = L.k[1 - buf];
+    uint32_t* ov = L.v[1 - buf];
+    for (int l = 0; l < f.nlev; ++l) {
+      const uint32_t base = L.rs[l + 1], c = L.rs[l + 2] - L.rs[l + 1], lo = L.lo[l];
+      for (uint32_t x = tid; x < c; x += kThreads) {
+        rk[base + x] = f.kv[l][lo + x];
+        rv[base + x] = f.val[l][lo + x];
+      }
+    }
+    __syncthreads();
+    for (uint32_t e = tid; e < T; e += kThreads) {
+      int r = 0;
+      while (r + 1 < R && L.rs[r + 1] <= e) ++r;
+      const uint32_t x = rk[e];
+      const uint32_t key = x >> 1;
+      uint32_t rank = e - L.rs[r];
+      for (int q = 0; q < R; ++q) {
+        if (q == r) continue;
+        rank += seg_bound(rk, L.rs[q], L.rs[q + 1], key, q < r) - L.rs[q];
+      }
+      ok[rank] = x;
+      ov[rank] = rv[e];
+    }
+    __syncthreads();
+    for (uint32_t x = tid; x < T; x += kThreads) {
+      const uint64_t pos = out0 + x;
+      if (pos < f.out_len) {
+        const uint32_t k = ok[x];
+        f.out_kv[pos] = k;
+        f.out_val[pos] = ov[x];
+        put_fence(f.out_fence, pos, k);
+      }
+    }
+    return;
+  }
+
+  // Runs too large for LDS: rank with searches in global memory.  The
+  // batch's bucket is put in global scratch first (it may be in LDS).
+  if (buf >= 0) {
+    for (uint32_t x = tid; x < n; x += kThreads) {
+      out_k[x] = L.k[buf][x];
+      out_v[x] = L.v[buf][x];
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (uint32_t e = tid; e < T; e += kThreads) {
+    int r = 0;
+    while (r + 1 < R && L.rs[r + 1] <= e) ++r;
+    const uint32_t p = e - L.rs[r];
+    const uint32_t* rkp = r == 0 ? out_k : f.kv[r - 1] + L.lo[r - 1];
+    const uint32_t* rvp = r == 0 ? out_v : f.val[r - 1] + L.lo[r - 1];
+    const uint32_t x = rkp[p];
+    const uint32_t key = x >> 1;
+    uint32_t rank = p;
+    for (int q = 0; q < R; ++q) {
+      if (q == r) continue;
+      const uint32_t* qk = q == 0 ? out_k : f.kv[q - 1] + L.lo[q - 1];
+      rank += seg_bound(qk, 0, L.rs[q + 1] - L.rs[q], key, q < r);
+    }
+    const uint64_t pos = out0 + rank;
+    if (pos < f.out_len) {
+      f.out_kv[pos] = x;
+      f.out_val[pos] = rvp[p];
+      put_fence(f.out_fence, pos, x);
+    }
+  }
+}
+
 // ------------------------------------------------------------ merge
 // Number of elements of a (the newer run) among the first `diag` outputs of
 // the merge, a first on equal original keys.  The whole wave searches: each
@@ -739,25 +961,35 @@ __device__ uint32_t wave_merge_path(const uint32_t* a, uint32_t na, const uint32
   return static_cast<uint32_t>(lo);
 }
 
-// Merge-path position of diagonal dt inside two LDS windows A = s[0, wa)
-// and B = s[off, off + wb): the number of A elements among the first dt
-// outputs, A first on equal original keys.
-__device__ __forceinline__ uint32_t lds_merge_path(const uint32_t* s, uint32_t wa, uint32_t off,
-                                                   uint32_t wb, uint32_t dt) {
-  uint32_t lo = dt > wb ? dt - wb : 0, hi = dt < wa ? dt : wa;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if ((s[mid] >> 1) <= (s[off + dt - 1 - mid] >> 1)) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
 
 // Each work-group merges a contiguous run of `tiles_per_wg` output tiles of
 // kMergeTile = 256 * kMergeItems elements.  Only the first tile's split is searched in global
 // memory (64-ary wave search); every later split is found inside LDS
 // windows holding the next kMergeTile elements of each input, which are the
 // elements the tile is about to consume anyway.
+// Merge-path split inside the work-group's windows, held in circular LDS
+// buffers: window a is positions [a0, a0 + wa) of run a at slots
+// (a0 + i) & mask, window b likewise.  Returns how many of the first dt
+// outputs come from a (a first on equal original keys).
+__device__ __forceinline__ uint32_t ring_merge_path(const uint32_t* sa, uint32_t a0, uint32_t wa,
+                                                    const uint32_t* sb, uint32_t b0, uint32_t wb,
+                                                    uint32_t dt, uint32_t mask) {
+  uint32_t lo = dt > wb ? dt - wb : 0, hi = dt < wa ? dt : wa;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if ((sa[(a0 + mid) & mask] >> 1) <= (sb[(b0 + dt - 1 - mid) & mask] >> 1)) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Merge of run a (newer) with run b (older) on the original key.  Each
+// work-group produces tiles_per_wg consecutive output tiles.  It finds the
+// split of its first tile with a wave search in global memory, then keeps a
+// window of each run in LDS ring buffers: a tile's outputs consume la
+// elements of a and n - la of b, and the next tile loads exactly those
+// counts, so every input element is read from HBM once.  Each thread merges
+// kMergeItems consecutive outputs and stores them with 16-byte stores.
 template <int kMergeItems>
 __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const uint32_t* a_val,
                                                     uint32_t na, const uint32_t* b_kv,
@@ -765,8 +997,10 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
                                                     uint32_t* out_kv, uint32_t* out_val,
                                                     uint32_t* out_fence, uint32_t tiles_per_wg) {
   constexpr uint32_t kMergeTile = kThreads * kMergeItems;
-  __shared__ uint32_t s_kv[2 * kMergeTile];
-  __shared__ uint32_t s_val[2 * kMergeTile];
+  constexpr uint32_t kMask = kMergeTile - 1;
+  static_assert((kMergeTile & kMask) == 0, "merge tile must be a power of two");
+  static_assert(kMergeItems % 4 == 0, "16-byte stores");
+  __shared__ uint32_t sa_k[kMergeTile], sa_v[kMergeTile], sb_k[kMergeTile], sb_v[kMergeTile];
   __shared__ uint32_t s_split;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t total = static_cast<uint64_t>(na) + nb;
@@ -781,22 +1015,25 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
   __syncthreads();
   uint32_t a0 = s_split;
   uint32_t b0 = static_cast<uint32_t>(t * kMergeTile - a0);
+  uint32_t a_end = a0, b_end = b0;  // loaded into the rings up to here
   for (; t < t_end; ++t) {
     const uint64_t d = t * kMergeTile;
     const uint32_t n = static_cast<uint32_t>((total - d) < kMergeTile ? (total - d) : kMergeTile);
     const uint32_t wa = (na - a0) < n ? (na - a0) : n;
     const uint32_t wb = (nb - b0) < n ? (nb - b0) : n;
-    for (uint32_t x = tid; x < wa; x += kThreads) {
-      s_kv[x] = a_kv[a0 + x];
-      s_val[x] = a_val[a0 + x];
+    for (uint32_t x = a_end + tid; x < a0 + wa; x += kThreads) {
+      sa_k[x & kMask] = a_kv[x];
+      sa_v[x & kMask] = a_val[x];
     }
-    for (uint32_t x = tid; x < wb; x += kThreads) {
-      s_kv[kMergeTile + x] = b_kv[b0 + x];
-      s_val[kMergeTile + x] = b_val[b0 + x];
+    for (uint32_t x = b_end + tid; x < b0 + wb; x += kThreads) {
+      sb_k[x & kMask] = b_kv[x];
+      sb_v[x & kMask] = b_val[x];
     }
+    a_end = (a0 + wa > a_end) ? a0 + wa : a_end;
+    b_end = (b0 + wb > b_end) ? b0 + wb : b_end;
     __syncthreads();
     const uint32_t dt = (tid * kMergeItems < n) ? tid * kMergeItems : n;
-    uint32_t ia = lds_merge_path(s_kv, wa, kMergeTile, wb, dt);
+    uint32_t ia = ring_merge_path(sa_k, a0, wa, sb_k, b0, wb, dt, kMask);
     uint32_t ib = dt - ia;
     uint32_t rk[kMergeItems], rv[kMergeItems];
 #pragma unroll
@@ -804,35 +1041,39 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
       rk[k] = 0u;
       rv[k] = 0u;
       if (dt + k < n) {
-        bool take_a;
-        if (ia < wa && ib < wb) take_a = (s_kv[ia] >> 1) <= (s_kv[kMergeTile + ib] >> 1);
-        else take_a = ia < wa;
-        const uint32_t src = take_a ? ia : kMergeTile + ib;
-        rk[k] = s_kv[src];
-        rv[k] = s_val[src];
+        const uint32_t ka = ia < wa ? sa_k[(a0 + ia) & kMask] : 0u;
+        const uint32_t kb = ib < wb ? sb_k[(b0 + ib) & kMask] : 0u;
+        const bool take_a = ia < wa && (ib >= wb || (ka >> 1) <= (kb >> 1));
+        rk[k] = take_a ? ka : kb;
+        rv[k] = take_a ? sa_v[(a0 + ia) & kMask] : sb_v[(b0 + ib) & kMask];
         ia += take_a ? 1u : 0u;
         ib += take_a ? 0u : 1u;
       }
     }
-    if (tid == kThreads - 1) s_split = lds_merge_path(s_kv, wa, kMergeTile, wb, n);
-    __syncthreads();
+    if (tid == kThreads - 1) s_split = ring_merge_path(sa_k, a0, wa, sb_k, b0, wb, n, kMask);
+    const uint64_t o = d + dt;
+    if (dt + kMergeItems <= n) {
 #pragma unroll
-    for (int k = 0; k < kMergeItems; ++k) {
-      if (dt + k < n) {
-        s_kv[dt + k] = rk[k];
-        s_val[dt + k] = rv[k];
+      for (int k = 0; k < kMergeItems; k += 4) {
+        *reinterpret_cast<uint4*>(out_kv + o + k) = make_uint4(rk[k], rk[k + 1], rk[k + 2], rk[k + 3]);
+        *reinterpret_cast<uint4*>(out_val + o + k) = make_uint4(rv[k], rv[k + 1], rv[k + 2], rv[k + 3]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kMergeItems; ++k) {
+        if (dt + k < n) {
+          out_kv[o + k] = rk[k];
+          out_val[o + k] = rv[k];
+        }
       }
     }
+#pragma unroll
+    for (int k = 0; k < kMergeItems; ++k)
+      if (dt + k < n) put_fence(out_fence, o + k, rk[k]);
     __syncthreads();
-    for (uint32_t x = tid; x < n; x += kThreads) {
-      out_kv[d + x] = s_kv[x];
-      out_val[d + x] = s_val[x];
-      put_fence(out_fence, d + x, s_kv[x]);
-    }
     const uint32_t la = s_split;
     a0 += la;
     b0 += n - la;
-    __syncthreads();
   }
 }
 

@@ -40,7 +40,12 @@ class Stats(ctypes.Structure):
 
 
 KERNEL_NAMES = ("k_sort_hist", "k_sort_pass", "k_merge", "k_lookup", "k_count", "k_scan",
-                "k_range_emit", "k_order", "k_clean")
+                "k_range_emit", "k_order", "k_clean", "k_msd_hist", "k_msd_scatter",
+                "k_local_sort")
+# rocprofv3 kernel names behind each profiler kind that covers several kernels.
+KERNEL_TRACE_NAMES = {"k_order": ("k_successor", "k_predecessor"),
+                      "k_clean": ("k_clean_count", "k_clean_scatter", "k_clean_pad"),
+                      "k_merge": ("k_merge<4>", "k_merge<8>", "k_merge<16>")}
 _NK = len(KERNEL_NAMES)
 
 
@@ -72,6 +77,7 @@ _SIGNATURES = {
     "lsm_cleanup": (ctypes.c_int, [_vp, ctypes.POINTER(_u64)]),
     "lsm_bulk_insert": (ctypes.c_int, [_vp, _vp, _vp, _u64]),
     "lsm_set_sort_path": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lsm_set_fusion": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lsm_destroy": (ctypes.c_int, [_vp]),
     "lsm_clear": (ctypes.c_int, [_vp]),
     "lsm_sync": (ctypes.c_int, [_vp]),
@@ -260,6 +266,10 @@ class LSM:
     def set_sort_path(self, mode: int) -> None:
         """LSM.SORT_AUTO (default), LSM.SORT_TOP_DIGIT or LSM.SORT_DIGIT_PASSES."""
         _check(self._lib.lsm_set_sort_path(self._h, int(mode)), "lsm_set_sort_path")
+
+    def set_fusion(self, max_levels: int) -> None:
+        """Deepest cascade fused into the top-digit sort (0 off, -1 default)."""
+        _check(self._lib.lsm_set_fusion(self._h, int(max_levels)), "lsm_set_fusion")
 
     def set_tuning(self, level: int, variant: int) -> None:
         _check(self._lib.lsm_set_tuning(self._h, int(level), int(variant)), "lsm_set_tuning")

@@ -300,9 +300,12 @@ def test_sort_path_follows_key_skew():
 @pytest.mark.parametrize("mode", [LSM.SORT_TOP_DIGIT, LSM.SORT_DIGIT_PASSES])
 def test_forced_sort_paths(mode):
     """Either path, forced, on batches of 1 to 600 tiles with partial
-    batches and mixed updates."""
+    batches: top-digit buckets sorted by ranking (up to 1024 elements), by
+    LDS radix passes (about 4096 at b = 2^20) and, with keys below 2^12 (one
+    bucket), by the streaming fallback."""
     for b, domain, R, seed in [(1, 8, 20, 71), (2047, 3000, 9, 72), (4096 * 3 + 1, 1 << 31, 6, 73),
-                               (600 * 2048 - 9, 1 << 31, 3, 74)]:
+                               (600 * 2048 - 9, 1 << 31, 3, 74), ((1 << 20) - 3, 1 << 31, 2, 75),
+                               (300 * 2048 + 5, 1 << 12, 2, 76)]:
         ops, q, lo, hi = W.random_small(seed, b, R, domain, p_delete=0.3, nq=300)
         note("forced sort path %d b=%d" % (mode, b))
         t = Trio(b)

@@ -1,0 +1,88 @@
+"""GPU tests of the library's per-launch profiler (lsm_profile_*): launch
+counts per kernel kind follow the path taken (the sort path's kernels, one
+merge per full level the cascade passes, as the binary counter fixes), the
+times are positive, and profiling changes no result."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1707_05354_amd.lsm import KERNEL_NAMES, LSM
+from _gpu import Trio, dev, host, note
+
+pytestmark = pytest.mark.gpu
+
+K = {n: i for i, n in enumerate(KERNEL_NAMES)}
+
+
+def ffz(r):
+    j = 0
+    while (r >> j) & 1:
+        j += 1
+    return j
+
+
+def default_fusion(b):
+    j = 0
+    while j < 8 and (b << (j + 1)) <= (1 << 20):
+        j += 1
+    return j
+
+
+@pytest.mark.parametrize("mode,fusion", [
+    (LSM.SORT_TOP_DIGIT, -1), (LSM.SORT_TOP_DIGIT, 0), (LSM.SORT_TOP_DIGIT, 2),
+    (LSM.SORT_DIGIT_PASSES, -1),
+])
+def test_profile_counts_follow_the_path(mode, fusion):
+    """Merge launches: one per level the cascade passes beyond the levels
+    fused into the top-digit sort (none fused on the digit-pass path)."""
+    b, R = 4096, 13
+    rng = np.random.default_rng(5)
+    note("profile counts mode=%d fusion=%d" % (mode, fusion))
+    t = Trio(b)
+    t.g.set_sort_path(mode)
+    t.g.set_fusion(fusion)
+    depth = 0 if mode == LSM.SORT_DIGIT_PASSES else (default_fusion(b) if fusion < 0 else fusion)
+    t.g.profile(True)
+    t.g.profile_read(reset=True)
+    for _ in range(R):
+        t.insert(rng.integers(0, 1 << 31, b, dtype=np.uint64).astype(np.uint32),
+                 rng.integers(0, 2**32, b, dtype=np.uint64).astype(np.uint32))
+    q = rng.integers(0, 1 << 31, 1000, dtype=np.uint64).astype(np.uint32)
+    t.check_queries(q, q[:300], q[:300] + 10**6)
+    t.check_order(q[:200])
+    p = t.g.profile_read(reset=True)
+    t.g.profile(False)
+    passes = 4  # 31-bit keys, status bit not sorted
+    expect = {"k_merge": sum(max(0, ffz(r) - depth) for r in range(R)), "k_lookup": 1, "k_order": 2,
+              "k_range_emit": 1, "k_scan": 1, "k_count": 2}
+    if mode == LSM.SORT_TOP_DIGIT:
+        expect.update({"k_msd_hist": R, "k_msd_scatter": R, "k_local_sort": R})
+    else:
+        expect.update({"k_sort_hist": R, "k_sort_pass": R * passes})
+    for name, n in expect.items():
+        assert int(p.launches[K[name]]) == n, (name, int(p.launches[K[name]]), n)
+        assert n == 0 or p.kernel_ms[K[name]] > 0.0, name
+    others = set(KERNEL_NAMES) - set(expect)
+    assert all(int(p.launches[K[n]]) == 0 for n in others), [n for n in others if p.launches[K[n]]]
+    assert p.update_calls == R and p.update_p50_ms > 0.0
+    t.check_levels()
+
+
+def test_profile_off_and_on_give_the_same_levels():
+    b = 3000
+    rng = np.random.default_rng(6)
+    note("profile on/off equality")
+    keys = [rng.integers(0, 5000, b).astype(np.uint32) for _ in range(9)]
+    vals = [rng.integers(0, 2**32, b, dtype=np.uint64).astype(np.uint32) for _ in range(9)]
+    out = []
+    for prof in (False, True):
+        g = LSM(b)
+        g.profile(prof)
+        for k, v in zip(keys, vals):
+            g.insert(dev(k), dev(v))
+        g.sync()
+        out.append([tuple(host(x).tobytes() for x in g.level(i)) for i in g.occupied()])
+        if prof:
+            g.profile_read(reset=True)
+        g.close()
+    assert out[0] == out[1]
