@@ -22,6 +22,13 @@ using namespace lsm;
 
 static_assert(LSM_PROF_KERNELS == kNumKernelKinds, "profile kernel kinds out of step");
 
+// Kinds of whole-call spans in the profiler, above every kernel kind.
+constexpr int kSpanUpdate = 100;
+constexpr int kSpanLookup = 101;  // then count, range
+constexpr int kSpanCount = 102;
+constexpr int kSpanRange = 103;
+static_assert(kSpanUpdate >= kNumKernelKinds, "span kinds overlap kernel kinds");
+
 struct lsm_s {
   uint32_t b = 0;
   uint32_t flags = 0;
@@ -33,6 +40,12 @@ struct lsm_s {
   uint32_t* lvl_kv[kMaxLevels] = {};
   uint32_t* lvl_val[kMaxLevels] = {};
   uint32_t* lvl_fence[kMaxLevels] = {};
+  // Top-digit index of a level: the position of the first element of each
+  // of the kTopBuckets top-digit buckets, written by the kernel that wrote the level
+  // when it sorted by that digit.  digit_shift[i] is the key shift it was
+  // built for, or -1 when level i was last written without one.
+  uint32_t* lvl_digit[kMaxLevels] = {};
+  int digit_shift[kMaxLevels];
 
   uint32_t* tmp_kv[2] = {};  // radix ping-pong, b elements each
   uint32_t* tmp_val[2] = {};
@@ -72,6 +85,7 @@ struct lsm_s {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph[kMaxLevels][2][2] = {};          // [level][parity][sort path]
   hipGraphExec_t graph_exec[kMaxLevels][2][2] = {};
+  int graph_fuse[kMaxLevels][2][2] = {};             // fused depth the graph was captured with
 
   // Merge variant per merge input level (autotuned or set).
   int merge_variant[kMaxLevels];
@@ -156,19 +170,23 @@ lsm_status_t ensure_level(lsm_t h, int j) {
   if (h->lvl_kv[j] != nullptr) return LSM_OK;
   const size_t bytes = level_len(h, j) * sizeof(uint32_t);
   const size_t fbytes = fence_len(level_len(h, j)) * sizeof(uint32_t);
-  void *k = nullptr, *v = nullptr, *f = nullptr;
+  void *k = nullptr, *v = nullptr, *f = nullptr, *dg = nullptr;
   lsm_status_t s = dev_alloc(h, &k, bytes);
   if (s != LSM_OK) return s;
   s = dev_alloc(h, &v, bytes);
   if (s == LSM_OK) s = dev_alloc(h, &f, fbytes);
+  if (s == LSM_OK) s = dev_alloc(h, &dg, kTopBuckets * sizeof(uint32_t));
   if (s != LSM_OK) {
     dev_free(h, k, bytes);
     dev_free(h, v, bytes);
+    dev_free(h, f, fbytes);
     return s;
   }
   h->lvl_kv[j] = static_cast<uint32_t*>(k);
   h->lvl_val[j] = static_cast<uint32_t*>(v);
   h->lvl_fence[j] = static_cast<uint32_t*>(f);
+  h->lvl_digit[j] = static_cast<uint32_t*>(dg);
+  h->digit_shift[j] = -1;
   return LSM_OK;
 }
 
@@ -238,6 +256,7 @@ void release_all(lsm_t h) {
     dev_free(h, h->lvl_kv[i], level_len(h, i) * sizeof(uint32_t));
     dev_free(h, h->lvl_val[i], level_len(h, i) * sizeof(uint32_t));
     dev_free(h, h->lvl_fence[i], fence_len(level_len(h, i)) * sizeof(uint32_t));
+    dev_free(h, h->lvl_digit[i], kTopBuckets * sizeof(uint32_t));
   }
   for (int i = 0; i < 2; ++i) {
     dev_free(h, h->tmp_kv[i], bb);
@@ -342,17 +361,37 @@ int default_fuse_max(uint32_t b) {
 // levels 0..nf-1 with nf = min(j, fuse_max).  When nf = j the sort writes
 // level j; otherwise it writes the merge scratch buffer that the pairwise
 // merge of level nf then reads (see enqueue_cascade).
+// Fuses the first levels of an insert's cascade into the top-digit sort:
+// levels 0..nf-1 with nf = min(j, fuse_max), cut short at the first level
+// without a top-digit index for this key shift.  When nf = j the sort
+// writes level j (and its index); otherwise it writes the merge scratch
+// buffer that the pairwise merge of level nf then reads.
 void setup_fusion(lsm_t h, SortArgs& sa, int j) {
   sa.fuse.nlev = 0;
-  const int nf = j < h->fuse_max ? j : h->fuse_max;
-  if (sa.path != kSortMsd || nf < 1 || nf > kMaxFuse || sort_top_shift(sa) < 1) return;
+  sa.out_digit = nullptr;
+  if (sa.path != kSortMsd || sort_top_shift(sa) < 1) return;
+  const int shift = sort_top_shift(sa) - 1;
+  if (j == 0) {
+    sa.out_digit = h->lvl_digit[0];
+    return;
+  }
+  int nf = j < h->fuse_max ? j : h->fuse_max;
+  if (nf > kMaxFuse) nf = kMaxFuse;
+  // Keep the fused runs of a bucket within LDS: the previous sort's largest
+  // bucket, grown 2^nf times by the levels, must fit (skewed keys otherwise
+  // leave one work-group ranking a huge bucket through global memory).
+  const uint64_t big = *reinterpret_cast<volatile uint32_t*>(h->skew_host);
+  while (nf > 0 && (big << nf) > static_cast<uint64_t>(kLocalCap)) --nf;
+  for (int l = 0; l < nf; ++l)
+    if (h->digit_shift[l] != shift) nf = l;
+  if (nf < 1) return;
   FuseArgs& f = sa.fuse;
   f.nlev = nf;
-  f.key_shift = sort_top_shift(sa) - 1;
+  f.key_shift = shift;
   for (int l = 0; l < nf; ++l) {
     f.kv[l] = h->lvl_kv[l];
     f.val[l] = h->lvl_val[l];
-    f.fence[l] = h->lvl_fence[l];
+    f.digit[l] = h->lvl_digit[l];
     f.len[l] = static_cast<uint32_t>(level_len(h, l));
   }
   f.out_len = level_len(h, nf);
@@ -360,11 +399,20 @@ void setup_fusion(lsm_t h, SortArgs& sa, int j) {
     f.out_kv = h->lvl_kv[j];
     f.out_val = h->lvl_val[j];
     f.out_fence = h->lvl_fence[j];
+    f.out_digit = h->lvl_digit[j];
   } else {
     f.out_kv = h->mrg_kv[(nf + 1) & 1];
     f.out_val = h->mrg_val[(nf + 1) & 1];
     f.out_fence = nullptr;
+    f.out_digit = nullptr;
   }
+}
+
+// Records whether the level an insert wrote carries a top-digit index.
+void note_digit_index(lsm_t h, const SortArgs& sa, int j) {
+  const bool indexed = (j == 0) ? sa.out_digit != nullptr
+                                : (sa.fuse.nlev == j && sa.fuse.out_digit != nullptr);
+  h->digit_shift[j] = indexed ? sort_top_shift(sa) - 1 : -1;
 }
 
 SortArgs sort_args(lsm_t h, const BatchSrc& src, int j) {
@@ -477,7 +525,8 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
   uint64_t merged = 0;
   if (enqueue_cascade(h, sa, j, h->stream, timed ? &last : nullptr, &merged) != hipSuccess)
     return LSM_EHIP;
-  if (timed) call_span(h, 10, st[0], last, h->b);
+  if (timed) call_span(h, kSpanUpdate, st[0], last, h->b);
+  note_digit_index(h, sa, j);
   commit_insert(h, merged);
   return LSM_OK;
 }
@@ -499,6 +548,13 @@ lsm_status_t insert_staged(lsm_t h, uint32_t n) {
   const SortArgs sa =
       sort_args(h, BatchSrc{h->stage_kv, h->stage_val, nullptr, h->b, h->b, kEncoded}, j);
   const int path = sa.path;
+  if (h->graph_exec[j][par][path] != nullptr && h->graph_fuse[j][par][path] != sa.fuse.nlev) {
+    // Captured with another fused depth (a level's digit index changed since).
+    (void)hipGraphExecDestroy(h->graph_exec[j][par][path]);
+    (void)hipGraphDestroy(h->graph[j][par][path]);
+    h->graph_exec[j][par][path] = nullptr;
+    h->graph[j][par][path] = nullptr;
+  }
   if (h->graph_exec[j][par][path] == nullptr) {
     if (h->cap_stream == nullptr &&
         hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
@@ -520,6 +576,7 @@ lsm_status_t insert_staged(lsm_t h, uint32_t n) {
     }
     h->graph[j][par][path] = graph;
     h->graph_exec[j][par][path] = exec;
+    h->graph_fuse[j][par][path] = sa.fuse.nlev;
   }
   Timed tg;
   const KTimer* t = timer(h, tg, kKSortHist, 0, 0.0);  // whole-graph span, reported as an update
@@ -530,9 +587,10 @@ lsm_status_t insert_staged(lsm_t h, uint32_t n) {
   if (hipGraphLaunch(h->graph_exec[j][par][path], h->stream) != hipSuccess) return LSM_EHIP;
   if (t != nullptr) {
     (void)hipEventRecord(t->stop, h->stream);
-    call_span(h, 10, tg, tg, h->b);
+    call_span(h, kSpanUpdate, tg, tg, h->b);
   }
   h->hist_parity ^= 1;
+  note_digit_index(h, sa, j);
   commit_insert(h, (j == 0) ? 0 : (2ull << j) * h->b - 2ull * h->b);
   h->stage_fill = 0;
   return LSM_OK;
@@ -560,6 +618,7 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
   if (h == nullptr) return LSM_ENOMEM;
   h->b = b;
   h->fuse_max = default_fuse_max(b);
+  for (int i = 0; i < kMaxLevels; ++i) h->digit_shift[i] = -1;
   h->flags = flags;
   h->key_bits = kb;
   h->stream = static_cast<hipStream_t>(stream);
@@ -644,7 +703,7 @@ lsm_status_t lsm_lookup(lsm_t h, const uint32_t* d_keys, uint32_t nq, uint32_t* 
   Timed tl;
   const KTimer* t = timer(h, tl, kKLookup, nq, 0.0);
   if (launch_lookup(lv, d_keys, nq, d_vals, d_found, h->stream, t) != hipSuccess) return LSM_EHIP;
-  if (t != nullptr) call_span(h, 11, tl, tl, nq);
+  if (t != nullptr) call_span(h, kSpanLookup, tl, tl, nq);
   return LSM_OK;
 }
 
@@ -662,7 +721,7 @@ lsm_status_t lsm_count(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   const KTimer* t = timer(h, tc, kKCount, nq, 0.0);
   if (launch_count(lv, d_lo, d_hi, nq, d_counts, nullptr, 0, h->stream, t) != hipSuccess)
     return LSM_EHIP;
-  if (t != nullptr) call_span(h, 12, tc, tc, nq);
+  if (t != nullptr) call_span(h, kSpanCount, tc, tc, nq);
   return LSM_OK;
 }
 
@@ -846,6 +905,7 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
   const hipError_t e2 = hipStreamSynchronize(h->stream);
   release();
   if (e != hipSuccess || e2 != hipSuccess) return LSM_EHIP;
+  for (int q = 0; q < np; ++q) h->digit_shift[plan[q].level] = -1;
   h->r = r1;
   h->merged_last = merged;
   h->merged_total += merged;
@@ -965,6 +1025,8 @@ lsm_status_t lsm_cleanup(lsm_t h, uint64_t* h_valid) {
   const hipError_t e2 = hipStreamSynchronize(h->stream);
   release();
   if (e != hipSuccess || e2 != hipSuccess) return LSM_EHIP;
+  for (int i = 0; i < kMaxLevels; ++i)
+    if ((r2 >> i) & 1u) h->digit_shift[i] = -1;
   h->r = r2;
   h->merged_last = 0;
   if (h_valid != nullptr) *h_valid = v;
@@ -1010,9 +1072,9 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
     if (launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, d_keys, d_vals, cap, h->stream,
                           timer(h, t3, kKRangeEmit, nq, 0.0)) != hipSuccess)
       return LSM_EHIP;
-    call_span(h, 13, t1, t3, nq);
+    call_span(h, kSpanRange, t1, t3, nq);
   } else {
-    call_span(h, 13, t1, t2, nq);
+    call_span(h, kSpanRange, t1, t2, nq);
   }
   return LSM_OK;
 }
@@ -1252,12 +1314,12 @@ lsm_status_t lsm_profile_read(lsm_t h, lsm_profile_t* out, int reset) {
       p.elems[sp.kind] += sp.items;
       p.kernel_ms[sp.kind] += ms;
       p.kernel_bytes[sp.kind] += sp.bytes;
-    } else if (sp.kind == 10) {
+    } else if (sp.kind == kSpanUpdate) {
       p.update_ms += ms;
       p.update_calls += 1;
       h->update_times.push_back(ms);
     } else {
-      const int q = sp.kind - 11;
+      const int q = sp.kind - kSpanLookup;
       p.query_ms[q] += ms;
       p.query_calls[q] += 1;
       p.query_items[q] += sp.items;

@@ -21,14 +21,18 @@ constexpr int kSortTile = kThreads * kSortItems;
 constexpr int kMaxPasses = 4;
 // The histogram kernel uses at most this many work-groups (tile-strided).
 constexpr int kMaxHistBlocks = 512;
-// Batches of at most kMsdMaxTiles tiles use the three-kernel MSD sort (top
-// digit scatter, then per-bucket sort); buckets of up to kLocalCap
-// elements are sorted in LDS.
+// Batches of at most kMsdMaxTiles tiles use the three-kernel top-digit sort:
+// a scatter on the top kTopBits bits into kTopBuckets buckets, then one
+// work-group per bucket.  Buckets (and fused runs) of up to kLocalCap
+// elements are sorted and merged in LDS.
 constexpr int kMsdMaxTiles = 512;
-constexpr int kLocalCap = 8192;
+constexpr int kTopBits = 10;
+constexpr uint32_t kTopBuckets = 1u << kTopBits;
+constexpr int kTopPer = static_cast<int>(kTopBuckets) / kThreads;  // buckets per thread
+constexpr int kLocalCap = 2048;
 // Buckets of at most this many elements are sorted by ranking (every
 // element counts the elements that precede it) instead of radix passes.
-constexpr uint32_t kRankSortMax = 1024;
+constexpr uint32_t kRankSortMax = 256;
 
 // Merge variants (autotuned per level): items per thread x work-group cap.
 // Variant v uses kMergeItemsOf[v % 3] items per thread (tiles of 256 x that)
@@ -90,7 +94,8 @@ struct SortMeta {
   uint32_t* tile_ctr;     // [kMaxPasses] dynamic tile ids of each pass
   uint32_t* err;          // [0] key-range violation (checked mode),
                           // [1] sticky device fault (a bounded wait expired)
-  uint32_t* tile_cnt;     // [num_sort_tiles][256] top-digit counts (MSD sort)
+  uint32_t* tile_cnt;     // [num_sort_tiles][kTopBuckets] top-digit counts (top-digit sort)
+  uint32_t* bucket_start; // [kTopBuckets] first position of each top-digit bucket
   uint32_t num_sort_tiles;
   int parity;
 };
@@ -118,11 +123,12 @@ struct FuseArgs {
   int key_shift;
   const uint32_t* kv[kMaxFuse];
   const uint32_t* val[kMaxFuse];
-  const uint32_t* fence[kMaxFuse];
+  const uint32_t* digit[kMaxFuse];  // each level's top-digit index
   uint32_t len[kMaxFuse];
   uint32_t* out_kv;
   uint32_t* out_val;
   uint32_t* out_fence;
+  uint32_t* out_digit;              // the output level's index, or null
   uint64_t out_len;
 };
 
@@ -138,15 +144,20 @@ struct SortArgs {
   uint32_t* out_kv;         // sorted batch
   uint32_t* out_val;
   uint32_t* out_fence;      // fences of the output when it is a level, else null
+  uint32_t* out_digit;      // top-digit index of the output level (top-digit path), or null
   int path;                 // SortPath; both paths give the same order
   uint32_t* skew_out;       // optional: receives the largest top-digit bucket
   FuseArgs fuse;            // top-digit path only
 };
 
-// Bit position of the top digit the top-digit sort scatters on.
+// Bit position of the top digit the top-digit sort scatters on: the highest
+// kTopBits bits a key variable can have (keys below 2^key_limit_bits give key
+// variables of key_limit_bits + 1 bits), so that every bucket is used.
 inline int sort_top_shift(const SortArgs& a) {
-  const int hi_bit = a.lo_bit + kRadixBits * a.passes;
-  return hi_bit - kRadixBits > a.lo_bit ? hi_bit - kRadixBits : a.lo_bit;
+  int hi_bit = a.lo_bit + kRadixBits * a.passes;
+  const int kv_bits = static_cast<int>(a.key_limit_bits) + 1;
+  if (hi_bit > kv_bits) hi_bit = kv_bits;
+  return hi_bit - kTopBits > a.lo_bit ? hi_bit - kTopBits : a.lo_bit;
 }
 
 // Optional per-launch timing: when start is non-null the kernel is launched

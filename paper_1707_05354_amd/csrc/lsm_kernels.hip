@@ -420,19 +420,20 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(SortArgs a, int pass) {
 
 // ------------------------------------------------------------ MSD sort
 // For batches of at most kMsdMaxTiles tiles the sort exchanges data across
-// the device only once: a histogram of the top 8-bit digit, one stable MSD
-// scatter into 256 buckets, then each bucket sorted on its own by one
-// work-group on the remaining bits (in LDS when it fits, streaming through
-// the bucket's global range otherwise).  Three kernels instead of
-// 1 + passes, and no look-back chains.
+// the device only once: a histogram of the top kTopBits-bit digit, one
+// stable scatter into kTopBuckets buckets, then each bucket sorted on its
+// own by one work-group on the remaining bits (in LDS when it fits,
+// streaming through the bucket's global range otherwise).  Three kernels
+// instead of 1 + passes, and no look-back chains.
 
 // Stable ranking of one item per lane by digit d among the valid lanes of
 // the wave: returns the item's position after the entries already counted
 // in wcnt[d], and adds the wave's count of d to wcnt[d].
-__device__ __forceinline__ uint32_t wave_rank1(uint32_t d, bool valid, uint32_t* wcnt) {
+template <int kBits>
+__device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint32_t* wcnt) {
   uint64_t peers = ballot(valid);
 #pragma unroll
-  for (int bit = 0; bit < kRadixBits; ++bit) {
+  for (int bit = 0; bit < kBits; ++bit) {
     const bool set = (d >> bit) & 1u;
     const uint64_t m = ballot(set);
     peers &= set ? m : ~m;
@@ -445,7 +446,9 @@ __device__ __forceinline__ uint32_t wave_rank1(uint32_t d, bool valid, uint32_t*
 }
 
 __global__ __launch_bounds__(kThreads) void k_msd_hist(SortArgs a, int top_shift) {
-  __shared__ uint32_t s_h[kRadix];
+  static_assert(kTopBuckets == static_cast<uint32_t>(kMaxPasses * kRadix),
+                "the top-digit counts use one histogram buffer");
+  __shared__ uint32_t s_h[kTopBuckets];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const SortMeta& m = a.meta;
   const uint32_t b = a.src.b;
@@ -457,7 +460,8 @@ __global__ __launch_bounds__(kThreads) void k_msd_hist(SortArgs a, int top_shift
   for (size_t i = gid; i < static_cast<size_t>(kMaxPasses) * kRadix;
        i += static_cast<size_t>(gridDim.x) * kThreads)
     other[i] = 0u;
-  s_h[tid] = 0u;
+#pragma unroll
+  for (int q = 0; q < kTopPer; ++q) s_h[tid + q * kThreads] = 0u;
   uint32_t kv[kSortItems], key[kSortItems];
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
@@ -473,21 +477,32 @@ __global__ __launch_bounds__(kThreads) void k_msd_hist(SortArgs a, int top_shift
   for (int i = 0; i < kSortItems; ++i) {
     if (tile * kSortTile + tile_pos(wave, i, lane) >= b) continue;
     if (a.checked) bad |= (key[i] >> a.key_limit_bits) != 0u;
-    atomicAdd(&s_h[(kv[i] >> top_shift) & (kRadix - 1)], 1u);
+    atomicAdd(&s_h[(kv[i] >> top_shift) & (kTopBuckets - 1)], 1u);
   }
   __syncthreads();
-  m.tile_cnt[static_cast<size_t>(tile) * kRadix + tid] = s_h[tid];
   uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
-  if (s_h[tid] != 0u) atomicAdd(&mine[tid], s_h[tid]);
+#pragma unroll
+  for (int q = 0; q < kTopPer; ++q) {
+    const uint32_t dg = tid + q * kThreads;
+    const uint32_t c = s_h[dg];
+    m.tile_cnt[static_cast<size_t>(tile) * kTopBuckets + dg] = c;
+    if (c != 0u) atomicAdd(&mine[dg], c);
+  }
   if (a.checked && bad) atomicOr(&m.err[0], 1u);
 }
 
+// Stable scatter of one tile on the top digit.  Thread t owns the digits
+// [kTopPer t, kTopPer t + kTopPer).  A digit's output base is the number of
+// batch elements with a smaller digit (scan of the global counts) plus its
+// elements in earlier tiles (summed from their counts, eight loads in flight
+// at a time); the tile is ranked in LDS and written digit-sorted.  The work-
+// group of tile 0 also publishes every bucket's first position.
 __global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_shift) {
   __shared__ uint32_t s_kv[kSortTile];
   __shared__ uint32_t s_val[kSortTile];
-  __shared__ uint32_t s_wcnt[kWaves][kRadix];
-  __shared__ uint32_t s_local[kRadix];
-  __shared__ uint32_t s_gbase[kRadix];
+  __shared__ uint32_t s_wcnt[kWaves][kTopBuckets];
+  __shared__ uint32_t s_local[kTopBuckets];
+  __shared__ uint32_t s_gbase[kTopBuckets];
   __shared__ uint32_t s_tmp[kWaves];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const SortMeta& m = a.meta;
@@ -495,20 +510,37 @@ __global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_sh
   const uint32_t tile = blockIdx.x;
   const uint32_t tbase = tile * kSortTile;
   const uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
-  const uint32_t gtotal = mine[tid];
-  // Elements of this digit in earlier tiles, eight independent loads in
-  // flight at a time.
-  uint32_t before = 0;
-  uint32_t t = 0;
-  for (; t + 8 <= tile; t += 8) {
-    uint32_t c[8];
+  const uint32_t d0 = tid * kTopPer;
+  uint32_t gtot[kTopPer], before[kTopPer];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) c[q] = m.tile_cnt[static_cast<size_t>(t + q) * kRadix + tid];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) before += c[q];
+  for (int q = 0; q < kTopPer; ++q) {
+    gtot[q] = mine[d0 + q];
+    before[q] = 0u;
   }
-  for (; t < tile; ++t) before += m.tile_cnt[static_cast<size_t>(t) * kRadix + tid];
-  for (uint32_t i = tid; i < kWaves * kRadix; i += kThreads) (&s_wcnt[0][0])[i] = 0u;
+  {
+    uint32_t t = 0;
+    for (; t + 8 <= tile; t += 8) {
+      uint4 c[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        c[r] = *reinterpret_cast<const uint4*>(m.tile_cnt + static_cast<size_t>(t + r) * kTopBuckets + d0);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        before[0] += c[r].x;
+        before[1] += c[r].y;
+        before[2] += c[r].z;
+        before[3] += c[r].w;
+      }
+    }
+    for (; t < tile; ++t) {
+      const uint4 c = *reinterpret_cast<const uint4*>(m.tile_cnt + static_cast<size_t>(t) * kTopBuckets + d0);
+      before[0] += c.x;
+      before[1] += c.y;
+      before[2] += c.z;
+      before[3] += c.w;
+    }
+  }
+  for (uint32_t i = tid; i < kWaves * kTopBuckets; i += kThreads) (&s_wcnt[0][0])[i] = 0u;
   uint32_t kv[kSortItems], val[kSortItems], off[kSortItems];
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
@@ -521,22 +553,37 @@ __global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_sh
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i)
-    off[i] = wave_rank1((kv[i] >> top_shift) & (kRadix - 1), tbase + tile_pos(wave, i, lane) < b,
-                        s_wcnt[wave]);
+    off[i] = wave_rank<kTopBits>((kv[i] >> top_shift) & (kTopBuckets - 1),
+                                 tbase + tile_pos(wave, i, lane) < b, s_wcnt[wave]);
   __syncthreads();
-  uint32_t tile_count = 0;
-  for (uint32_t w = 0; w < kWaves; ++w) {
-    const uint32_t c = s_wcnt[w][tid];
-    s_wcnt[w][tid] = tile_count;
-    tile_count += c;
+  uint32_t cnt[kTopPer], tsum = 0, gsum = 0;
+#pragma unroll
+  for (int q = 0; q < kTopPer; ++q) {
+    uint32_t c = 0;
+    for (uint32_t w = 0; w < kWaves; ++w) {
+      const uint32_t x = s_wcnt[w][d0 + q];
+      s_wcnt[w][d0 + q] = c;
+      c += x;
+    }
+    cnt[q] = c;
+    tsum += c;
+    gsum += gtot[q];
   }
-  s_local[tid] = block_excl_scan(tile_count, s_tmp);
-  s_gbase[tid] = block_excl_scan(gtotal, s_tmp) + before;
+  uint32_t lrun = block_excl_scan(tsum, s_tmp);
+  uint32_t grun = block_excl_scan(gsum, s_tmp);
+#pragma unroll
+  for (int q = 0; q < kTopPer; ++q) {
+    s_local[d0 + q] = lrun;
+    s_gbase[d0 + q] = grun + before[q];
+    if (tile == 0) m.bucket_start[d0 + q] = grun;
+    lrun += cnt[q];
+    grun += gtot[q];
+  }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
     if (tbase + tile_pos(wave, i, lane) < b) {
-      const uint32_t dd = (kv[i] >> top_shift) & (kRadix - 1);
+      const uint32_t dd = (kv[i] >> top_shift) & (kTopBuckets - 1);
       const uint32_t pos = s_local[dd] + s_wcnt[wave][dd] + off[i];
       s_kv[pos] = kv[i];
       s_val[pos] = val[i];
@@ -546,7 +593,7 @@ __global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_sh
   const uint32_t tile_n = (b - tbase) < static_cast<uint32_t>(kSortTile) ? (b - tbase) : kSortTile;
   for (uint32_t x = tid; x < tile_n; x += kThreads) {
     const uint32_t k = s_kv[x];
-    const uint32_t dd = (k >> top_shift) & (kRadix - 1);
+    const uint32_t dd = (k >> top_shift) & (kTopBuckets - 1);
     const uint32_t o = s_gbase[dd] + (x - s_local[dd]);
     if (o < b) {
       a.tmp_kv[0][o] = k;
@@ -555,7 +602,7 @@ __global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_sh
   }
 }
 
-struct LocalLds {
+struct alignas(16) LocalLds {
   uint32_t k[2][kLocalCap];
   uint32_t v[2][kLocalCap];
   uint32_t wcnt[kWaves][kRadix];
@@ -580,7 +627,7 @@ __device__ void lds_pass(LocalLds& L, int from, uint32_t n, int shift) {
   for (uint32_t it = 0; it < S / 64; ++it) {
     const uint32_t pos = wave * S + it * 64 + lane;
     const bool valid = pos < n;
-    (void)wave_rank1(valid ? (sk[pos] >> shift) & (kRadix - 1) : 0u, valid, L.wcnt[wave]);
+    (void)wave_rank<kRadixBits>(valid ? (sk[pos] >> shift) & (kRadix - 1) : 0u, valid, L.wcnt[wave]);
   }
   __syncthreads();
   uint32_t tot = 0;
@@ -596,7 +643,7 @@ __device__ void lds_pass(LocalLds& L, int from, uint32_t n, int shift) {
     const uint32_t pos = wave * S + it * 64 + lane;
     const bool valid = pos < n;
     const uint32_t x = valid ? sk[pos] : 0u;
-    const uint32_t o = wave_rank1((x >> shift) & (kRadix - 1), valid, L.wcnt[wave]);
+    const uint32_t o = wave_rank<kRadixBits>((x >> shift) & (kRadix - 1), valid, L.wcnt[wave]);
     if (valid) {
       dk[o] = x;
       dv[o] = sv[pos];
@@ -654,7 +701,7 @@ __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, 
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < kSortItems; ++i)
-        off[i] = wave_rank1((kv[i] >> shift) & (kRadix - 1), cb + tile_pos(wave, i, lane) < n,
+        off[i] = wave_rank<kRadixBits>((kv[i] >> shift) & (kRadix - 1), cb + tile_pos(wave, i, lane) < n,
                             L.wcnt[wave]);
       __syncthreads();
       uint32_t tot = 0;
@@ -684,6 +731,100 @@ __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, 
   }
 }
 
+// Stable merge in LDS of a = src[0, A) (newer) and b = src[A, A + c)
+// (older) into dst[0, A + c), a first on equal original keys.  Each thread
+// finds the merge-path split of its share of the output by binary search,
+// then merges it sequentially.  Ends with a barrier.
+__device__ void lds_merge_pair(const uint32_t* sk, const uint32_t* sv, uint32_t A, uint32_t c,
+                               uint32_t* dk, uint32_t* dv) {
+  const uint32_t total = A + c;
+  const uint32_t per = (total + kThreads - 1) / kThreads;
+  const uint32_t d0 = threadIdx.x * per < total ? threadIdx.x * per : total;
+  const uint32_t d1 = d0 + per < total ? d0 + per : total;
+  uint32_t lo = d0 > c ? d0 - c : 0, hi = d0 < A ? d0 : A;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if ((sk[mid] >> 1) <= (sk[A + d0 - 1 - mid] >> 1)) lo = mid + 1;
+    else hi = mid;
+  }
+  uint32_t ia = lo, ib = d0 - lo;
+  for (uint32_t o = d0; o < d1; ++o) {
+    const bool take_a = ia < A && (ib >= c || (sk[ia] >> 1) <= (sk[A + ib] >> 1));
+    const uint32_t src = take_a ? ia : A + ib;
+    dk[o] = sk[src];
+    dv[o] = sv[src];
+    ia += take_a ? 1u : 0u;
+    ib += take_a ? 0u : 1u;
+  }
+  __syncthreads();
+}
+
+// Stable rank sort of a bucket of n <= P * kThreads elements into
+// L.k[1] / L.v[1].  The rank of element x is the number of elements whose
+// sorted field (bits [lo_bit, lo_bit + 8 passes) of the key variable) is
+// smaller, plus those with an equal field at an earlier position; (field,
+// position) is a strict total order, so the ranks are a permutation of
+// [0, n) and the order equals that of the radix passes over the same bits.
+// The fields are read four at a time (16-byte LDS reads, two in flight);
+// the reads past n see 0xFFFFFFFF at positions above every element, which
+// never counts.
+template <int P>
+__device__ void rank_sort(LocalLds& L, const uint32_t* src_k, const uint32_t* src_v, uint32_t n,
+                          int lo_bit, int passes) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t fmask = (kRadixBits * passes >= 32) ? 0xFFFFFFFFu
+                                                     : ((1u << (kRadixBits * passes)) - 1u);
+  const uint32_t n8 = (n + 7u) & ~7u;
+  for (uint32_t x = tid; x < n8; x += kThreads) {
+    if (x < n) {
+      const uint32_t k = src_k[x];
+      L.k[0][x] = k;
+      L.v[0][x] = src_v[x];
+      L.k[1][x] = (k >> lo_bit) & fmask;
+    } else {
+      L.k[1][x] = 0xFFFFFFFFu;
+    }
+  }
+  __syncthreads();
+  uint32_t fx[P], rank[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const uint32_t x = tid + i * kThreads;
+    fx[i] = x < n ? L.k[1][x] : 0u;
+    rank[i] = 0u;
+  }
+  const uint4* f4 = reinterpret_cast<const uint4*>(L.k[1]);
+  for (uint32_t y = 0; y < n8; y += 8) {
+    const uint4 p = f4[y / 4];
+    const uint4 q = f4[y / 4 + 1];
+    const uint32_t fy[8] = {p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const uint32_t x = tid + i * kThreads;
+        rank[i] += (fy[u] < fx[i] || (fy[u] == fx[i] && y + u < x)) ? 1u : 0u;
+      }
+    }
+  }
+  uint32_t kx[P], vx[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const uint32_t x = tid + i * kThreads;
+    kx[i] = x < n ? L.k[0][x] : 0u;
+    vx[i] = x < n ? L.v[0][x] : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    if (tid + i * kThreads < n) {
+      L.k[1][rank[i]] = kx[i];
+      L.v[1][rank[i]] = vx[i];
+    }
+  }
+  __syncthreads();
+}
+
 // Bound of original key k in the sorted segment [lo, hi) of s (LDS or
 // global): first position whose key is >= k (upper: > k).
 __device__ __forceinline__ uint32_t seg_bound(const uint32_t* s, uint32_t lo, uint32_t hi,
@@ -703,15 +844,17 @@ __device__ __forceinline__ uint32_t seg_bound(const uint32_t* s, uint32_t lo, ui
 // memory.  Without a fused cascade the sorted bucket is the output.
 //
 // With a fused cascade (a.fuse.nlev = j > 0), the work-group then merges
-// its bucket with the same digit's key range of levels 0..j-1 and writes
-// that part of level j.  Runs are numbered newest first (the batch, then
-// level 0, 1, ...); the output rank of an element is its position in its
-// run plus, for every newer run, the elements with a key <= its key and, for
-// every older run, the elements with a smaller key.  (key, run, position) is
-// a strict total order, so this is exactly the order of the pairwise cascade
-// (the newer run first on equal keys at every step).  A bucket whose runs fit
-// in LDS is ranked there; a larger one is ranked with searches in global
-// memory.
+// its bucket with the same digit's key range of levels 0..j-1 (read from
+// each level's top-digit index) and writes that part of level j, recording
+// where it starts in level j's index.  Runs fitting in LDS are merged there
+// pairwise, newest first, exactly as the cascade merges whole levels.  Larger
+// ones are ranked with searches in global memory: runs are numbered newest
+// first (the batch, then level 0, 1, ...), and an element's output rank is
+// its position in its run plus, for every newer run, the elements with a key
+// <= its key and, for every older run, the elements with a smaller key;
+// (key, run, position) is a strict total order, so the order is again the
+// cascade's.  Without fusion, the sort of a level records its buckets'
+// starts as that level's top-digit index.
 __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit, int passes) {
   __shared__ LocalLds L;
   const uint32_t tid = threadIdx.x;
@@ -719,16 +862,14 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
   const FuseArgs& f = a.fuse;
   const bool fused = f.nlev > 0;
   const uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
-  const uint32_t cnt = mine[tid];
-  const uint32_t start = block_excl_scan(cnt, L.tmp);
-  if (tid == blockIdx.x) {
-    L.tmp[0] = start;
-    L.tmp[1] = cnt;
+  const uint32_t s = m.bucket_start[blockIdx.x], n = mine[blockIdx.x];
+  if (blockIdx.x == 0 && a.skew_out != nullptr) {
+    uint32_t mx = 0;
+#pragma unroll
+    for (int q = 0; q < kTopPer; ++q) mx = max(mx, mine[tid * kTopPer + q]);
+    record_max(mx, a.skew_out, L.tmp);
   }
-  __syncthreads();
-  const uint32_t s = L.tmp[0], n = L.tmp[1];
-  __syncthreads();
-  if (blockIdx.x == 0 && a.skew_out != nullptr) record_max(cnt, a.skew_out, L.tmp);
+  if (!fused && a.out_digit != nullptr && tid == 0) a.out_digit[blockIdx.x] = s;
   if (n == 0 && !fused) return;
   const uint32_t* src_k = a.tmp_kv[0] + s;
   const uint32_t* src_v = a.tmp_val[0] + s;
@@ -741,52 +882,8 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
   if (n == 0) {
     buf = 0;
   } else if (n <= kRankSortMax) {
-    // Stable rank sort: the rank of element x is the number of elements
-    // whose sorted field is smaller, plus those with an equal field at an
-    // earlier position; (field, position) is a strict total order, so the
-    // ranks are a permutation of [0, n) and the order equals that of the
-    // radix passes over the same bits.
-    const uint32_t fmask = (kRadixBits * passes >= 32) ? 0xFFFFFFFFu
-                                                       : ((1u << (kRadixBits * passes)) - 1u);
-    for (uint32_t x = tid; x < n; x += kThreads) {
-      const uint32_t k = src_k[x];
-      L.k[0][x] = k;
-      L.v[0][x] = src_v[x];
-      L.k[1][x] = (k >> lo_bit) & fmask;
-    }
-    __syncthreads();
-    constexpr int kPer = static_cast<int>(kRankSortMax / kThreads);
-    uint32_t fx[kPer], rank[kPer];
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      const uint32_t x = tid + i * kThreads;
-      fx[i] = x < n ? L.k[1][x] : 0u;
-      rank[i] = 0u;
-    }
-    for (uint32_t y = 0; y < n; ++y) {
-      const uint32_t fy = L.k[1][y];
-#pragma unroll
-      for (int i = 0; i < kPer; ++i) {
-        const uint32_t x = tid + i * kThreads;
-        rank[i] += (fy < fx[i] || (fy == fx[i] && y < x)) ? 1u : 0u;
-      }
-    }
-    uint32_t kx[kPer], vx[kPer];
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      const uint32_t x = tid + i * kThreads;
-      kx[i] = x < n ? L.k[0][x] : 0u;
-      vx[i] = x < n ? L.v[0][x] : 0u;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      if (tid + i * kThreads < n) {
-        L.k[1][rank[i]] = kx[i];
-        L.v[1][rank[i]] = vx[i];
-      }
-    }
-    __syncthreads();
+    static_assert(kRankSortMax <= static_cast<uint32_t>(kThreads), "one element per thread");
+    rank_sort<1>(L, src_k, src_v, n, lo_bit, passes);
     buf = 1;
   } else if (n <= static_cast<uint32_t>(kLocalCap)) {
     for (uint32_t x = tid; x < n; x += kThreads) {
@@ -821,17 +918,13 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
   const uint32_t d = blockIdx.x;
   const int R = f.nlev + 1;  // runs: the batch, then levels 0..j-1
   if (tid < static_cast<uint32_t>(f.nlev)) {
+    // The digit's range in level l, from the level's top-digit index.
     const uint32_t l = tid;
-    const uint64_t k0 = static_cast<uint64_t>(d) << f.key_shift;
-    const uint64_t k1 = static_cast<uint64_t>(d + 1) << f.key_shift;
     const uint32_t len = f.len[l];
-    const uint32_t lo = k0 > 0xFFFFFFFFull ? len
-                                           : fenced_bound(f.kv[l], f.fence[l], len,
-                                                          static_cast<uint32_t>(k0), false);
-    uint32_t hi = (d == kRadix - 1 || k1 > 0xFFFFFFFFull)
-                      ? len
-                      : fenced_bound(f.kv[l], f.fence[l], len, static_cast<uint32_t>(k1), false);
-    if (hi < lo) hi = lo;
+    uint32_t lo = f.digit[l][d];
+    uint32_t hi = d == kTopBuckets - 1 ? len : f.digit[l][d + 1];
+    lo = lo < len ? lo : len;
+    hi = hi < lo ? lo : (hi < len ? hi : len);
     L.lo[l] = lo;
     L.hi[l] = hi;
   }
@@ -846,6 +939,7 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
     }
     L.out_lo = static_cast<uint32_t>(o);
     L.out_hi = static_cast<uint32_t>(o >> 32);
+    if (f.out_digit != nullptr) f.out_digit[d] = static_cast<uint32_t>(o);
   }
   __syncthreads();
   const uint32_t T = L.rs[R];
@@ -853,38 +947,39 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
   if (T == 0) return;
 
   if (buf >= 0 && T <= static_cast<uint32_t>(kLocalCap)) {
-    uint32_t* rk = L.k[buf];
-    uint32_t* rv = L.v[buf];
-    uint32_t* ok = L.k[1 - buf];
-    uint32_t* ov = L.v[1 - buf];
+    // All runs side by side in buffer buf (the batch's bucket first), then
+    // a pairwise cascade in LDS: the accumulated run (newer) and the next
+    // level's run (older) are merged into the other buffer.  When the
+    // accumulated run sits in the other buffer, the next run is first
+    // copied next to it (the same offsets), so the two inputs are always
+    // adjacent and the output never overlaps an input still to be read.
     for (int l = 0; l < f.nlev; ++l) {
       const uint32_t base = L.rs[l + 1], c = L.rs[l + 2] - L.rs[l + 1], lo = L.lo[l];
       for (uint32_t x = tid; x < c; x += kThreads) {
-        rk[base + x] = f.kv[l][lo + x];
-        rv[base + x] = f.val[l][lo + x];
+        L.k[buf][base + x] = f.kv[l][lo + x];
+        L.v[buf][base + x] = f.val[l][lo + x];
       }
     }
     __syncthreads();
-    for (uint32_t e = tid; e < T; e += kThreads) {
-      int r = 0;
-      while (r + 1 < R && L.rs[r + 1] <= e) ++r;
-      const uint32_t x = rk[e];
-      const uint32_t key = x >> 1;
-      uint32_t rank = e - L.rs[r];
-      for (int q = 0; q < R; ++q) {
-        if (q == r) continue;
-        rank += seg_bound(rk, L.rs[q], L.rs[q + 1], key, q < r) - L.rs[q];
+    int acc = buf;
+    for (int q = 1; q < R; ++q) {
+      const uint32_t A = L.rs[q], c = L.rs[q + 1] - L.rs[q];
+      if (acc != buf) {
+        for (uint32_t x = tid; x < c; x += kThreads) {
+          L.k[acc][A + x] = L.k[buf][A + x];
+          L.v[acc][A + x] = L.v[buf][A + x];
+        }
+        __syncthreads();
       }
-      ok[rank] = x;
-      ov[rank] = rv[e];
+      lds_merge_pair(L.k[acc], L.v[acc], A, c, L.k[1 - acc], L.v[1 - acc]);
+      acc = 1 - acc;
     }
-    __syncthreads();
     for (uint32_t x = tid; x < T; x += kThreads) {
       const uint64_t pos = out0 + x;
       if (pos < f.out_len) {
-        const uint32_t k = ok[x];
+        const uint32_t k = L.k[acc][x];
         f.out_kv[pos] = k;
-        f.out_val[pos] = ov[x];
+        f.out_val[pos] = L.v[acc][x];
         put_fence(f.out_fence, pos, k);
       }
     }
@@ -1529,7 +1624,7 @@ hipError_t launch(Kernel k, unsigned grid, unsigned block, hipStream_t s, const 
 size_t sort_meta_words(uint32_t b) {
   const size_t ns = grid_for(b, kSortTile);
   return static_cast<size_t>(2) * kMaxPasses * kRadix + static_cast<size_t>(kMaxPasses) * ns * kRadix +
-         kMaxPasses + 2 + ns * kRadix;
+         kMaxPasses + 4 + ns * kTopBuckets + kTopBuckets;
 }
 
 SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
@@ -1539,7 +1634,8 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
   m.status = m.hist + static_cast<size_t>(2) * kMaxPasses * kRadix;
   m.tile_ctr = m.status + static_cast<size_t>(kMaxPasses) * m.num_sort_tiles * kRadix;
   m.err = m.tile_ctr + kMaxPasses;
-  m.tile_cnt = m.err + 2;
+  m.tile_cnt = m.err + 4;  // 16-byte aligned (vector loads of four counts)
+  m.bucket_start = m.tile_cnt + static_cast<size_t>(m.num_sort_tiles) * kTopBuckets;
   m.parity = parity;
   return m;
 }
@@ -1549,16 +1645,15 @@ int sort_kernel_count(const SortArgs& a) { return a.path == kSortMsd ? 3 : 1 + a
 hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers) {
   const uint32_t tiles = a.meta.num_sort_tiles;
   if (a.path == kSortMsd && tiles <= static_cast<uint32_t>(kMsdMaxTiles)) {
-    // Top digit: the highest 8 of the sorted bits [lo_bit, lo_bit + 8 * passes).
-    const int hi_bit = a.lo_bit + kRadixBits * a.passes;
-    const int top = hi_bit - kRadixBits > a.lo_bit ? hi_bit - kRadixBits : a.lo_bit;
+    // Top digit: the highest 8 bits a key variable of this handle can have.
+    const int top = sort_top_shift(a);
     const int local_passes = (top - a.lo_bit + kRadixBits - 1) / kRadixBits;
     hipError_t e = launch(k_msd_hist, tiles, kThreads, stream, timers ? &timers[0] : nullptr, a, top);
     if (e == hipSuccess)
       e = launch(k_msd_scatter, tiles, kThreads, stream, timers ? &timers[1] : nullptr, a, top);
     if (e == hipSuccess)
-      e = launch(k_local_sort, kRadix, kThreads, stream, timers ? &timers[2] : nullptr, a, a.lo_bit,
-                 local_passes);
+      e = launch(k_local_sort, kTopBuckets, kThreads, stream, timers ? &timers[2] : nullptr, a,
+                 a.lo_bit, local_passes);
     return e;
   }
   const uint32_t hist_grid = tiles < static_cast<uint32_t>(kMaxHistBlocks) ? tiles : kMaxHistBlocks;

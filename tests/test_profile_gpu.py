@@ -48,7 +48,17 @@ def test_profile_counts_follow_the_path(mode, fusion):
         t.insert(rng.integers(0, 1 << 31, b, dtype=np.uint64).astype(np.uint32),
                  rng.integers(0, 2**32, b, dtype=np.uint64).astype(np.uint32))
     q = rng.integers(0, 1 << 31, 1000, dtype=np.uint64).astype(np.uint32)
-    t.check_queries(q, q[:300], q[:300] + 10**6)
+    lo, hi = q[:300], q[:300] + 10**6
+    gv, gf = t.g.lookup(dev(q))
+    gc = t.g.count(dev(lo), dev(hi))
+    go, gk, gval = t.g.range(dev(lo), dev(hi), cap=1 << 20)  # one lsm_range call
+    torch.cuda.synchronize()
+    ov, of = t.m.lookup(q)
+    assert np.array_equal(host(gv), ov) and np.array_equal(host(gf), of)
+    assert np.array_equal(host(gc), t.m.count(lo, hi))
+    oo, ok, oval = t.m.range(lo, hi)
+    assert np.array_equal(host(go), oo) and np.array_equal(host(gk), ok)
+    assert np.array_equal(host(gval), oval)
     t.check_order(q[:200])
     p = t.g.profile_read(reset=True)
     t.g.profile(False)
