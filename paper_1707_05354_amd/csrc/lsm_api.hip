@@ -1014,6 +1014,7 @@ lsm_status_t lsm_cleanup(lsm_t h, uint64_t* h_valid) {
     d.val[d.count] = h->lvl_val[i];
     d.fence[d.count] = h->lvl_fence[i];
     d.start[d.count] = static_cast<uint64_t>(h->b) * (r2 & ((1ull << i) - 1ull));
+    d.len[d.count] = level_len(h, i);
     ++d.count;
   }
   Timed t3, t4;

@@ -50,12 +50,24 @@ constexpr int kScanTile = kThreads * kScanItems;
 // Query kernels: one thread per query.
 constexpr int kQueryThreads = 256;
 
-// Every level keeps a fence array: the original key of every kFenceStride-th
-// element (the first key of each 128-byte line of key variables), written by
-// the kernel that writes the level.  Searches go through the fences first
-// and finish inside one line of keys.
+// Every level keeps a fence tree, written by the kernel that writes the
+// level: tree level t = 1, 2, ... holds the original key of every 32^t-th
+// element (level 1: the first key of each 128-byte line of key variables).
+// Level t has ceil(n / 32^t) entries, padded to whole 128-byte lines, and
+// the levels are stored one after another up to the first with at most 32
+// entries (the root).  A search reads one line per tree level, top down,
+// then one line of key variables.
 constexpr int kFenceStride = 32;
-inline uint64_t fence_len(uint64_t n) { return (n + kFenceStride - 1) / kFenceStride; }
+__host__ __device__ inline uint64_t fence_pad(uint64_t c) { return (c + 31) & ~uint64_t(31); }
+inline uint64_t fence_len(uint64_t n) {
+  uint64_t total = 0, c = (n + 31) / 32;
+  for (;;) {
+    total += fence_pad(c);
+    if (c <= 32) break;
+    c = (c + 31) / 32;
+  }
+  return total;
+}
 
 // Placebo element of cleanup (sec. IV-D footnote): a tombstone of the largest
 // encodable key, 2^31 - 1.  It sorts after every other element and hides
@@ -189,6 +201,7 @@ struct LevelDst {
   uint32_t* val[kMaxLevels];
   uint32_t* fence[kMaxLevels];
   uint64_t start[kMaxLevels];
+  uint64_t len[kMaxLevels];
   int count;
 };
 

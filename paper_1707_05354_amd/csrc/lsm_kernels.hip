@@ -117,41 +117,80 @@ __device__ __forceinline__ void st_dev64(uint64_t* p, uint64_t v) {
 }
 
 // ------------------------------------------------------------ searches
-// Lower / upper bound through the level's fences: a bound search over the
-// fences (n / 32 entries, cache-resident) picks the one 128-byte line of
-// keys that holds the answer, and a search inside that line finishes it.
-// Returns the first index whose original key is >= k (upper: > k), or n.
-__device__ __forceinline__ uint32_t fenced_bound(const uint32_t* kv, const uint32_t* fence,
-                                                 uint32_t n, uint32_t k, bool upper) {
-  if (n == 0) return 0;
-  const uint32_t nf = (n + kFenceStride - 1) / kFenceStride;
-  // g = first fence whose key is >= k (lower) or > k (upper).
-  uint32_t base = 0, len = nf;
-  while (len > 1) {
-    const uint32_t half = len >> 1;
-    const uint32_t f = fence[base + half];
-    base = (upper ? f <= k : f < k) ? base + half : base;
-    len -= half;
+// Number of entries line[i], lo <= i < hi, that are < k (upper: <= k); the
+// 128-byte line at `line` is read whole (eight 16-byte loads in flight).
+// kv: the entries are key variables, compared by their original key.
+__device__ __forceinline__ uint32_t line_count(const uint32_t* line, uint32_t lo, uint32_t hi,
+                                               uint32_t k, bool upper, bool kv) {
+  const uint4* p = reinterpret_cast<const uint4*>(line);
+  uint4 v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = p[q];
+  uint32_t c = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t e[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t i = 4u * q + r;
+      const uint32_t x = kv ? (e[r] >> 1) : e[r];
+      c += (i >= lo && i < hi && (upper ? x <= k : x < k)) ? 1u : 0u;
+    }
   }
-  const uint32_t f0 = fence[base];
-  const uint32_t g = base + ((upper ? f0 <= k : f0 < k) ? 1u : 0u);
-  if (g == 0) return 0;
-  // The answer lies in (32 (g - 1), 32 g]; position 32 g (if it exists)
-  // qualifies by its fence, so search positions 32 (g - 1) + 1 .. 32 g - 1.
-  uint32_t lo = (g - 1) * kFenceStride + 1;
-  uint32_t hi = g * kFenceStride < n ? g * kFenceStride : n;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    const uint32_t x = kv[mid] >> 1;
-    if (upper ? x <= k : x < k) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
+  return c;
 }
 
-// Records the fence of output position o when it starts a fence group.
-__device__ __forceinline__ void put_fence(uint32_t* fence, uint64_t o, uint32_t kv) {
-  if (fence != nullptr && (o & (kFenceStride - 1)) == 0) fence[o / kFenceStride] = kv >> 1;
+// Lower / upper bound of original key k in a level of n elements through its
+// fence tree: the first index whose original key is >= k (upper: > k), or n.
+// At every tree level, g counts the entries that qualify (< k, or <= k);
+// the next level down then holds the answer among entries
+// 32 (g - 1) + 1 .. 32 g - 1 (entry 32 (g - 1) qualifies by its parent,
+// entry 32 g fails by its parent), all in one 128-byte line.
+__device__ __forceinline__ uint32_t fenced_bound(const uint32_t* kv, const uint32_t* tree,
+                                                 uint32_t n, uint32_t k, bool upper) {
+  if (n == 0) return 0;
+  // Offset and size of the root level.
+  uint64_t off = 0, c = (static_cast<uint64_t>(n) + 31) / 32;
+  int t = 1;
+  while (c > 32) {
+    off += fence_pad(c);
+    c = (c + 31) / 32;
+    ++t;
+  }
+  uint32_t g = line_count(tree + off, 0, static_cast<uint32_t>(c), k, upper, false);
+  for (--t; t >= 1; --t) {
+    if (g == 0) return 0;
+    const uint64_t ct = (static_cast<uint64_t>(n) + (1ull << (5 * t)) - 1) >> (5 * t);
+    off -= fence_pad(ct);
+    const uint32_t base = (g - 1) * 32u;
+    const uint32_t end = (base + 32u < ct) ? base + 32u : static_cast<uint32_t>(ct);
+    g = base + line_count(tree + off + base, 1, end - base, k, upper, false) + 1u;
+  }
+  if (g == 0) return 0;
+  const uint32_t base = (g - 1) * 32u;
+  if (base + 32u <= n) return base + line_count(kv + base, 1, 32, k, upper, true) + 1u;
+  // The last, partial line of the level: read only what exists.
+  uint32_t r = base + 1u;
+  for (uint32_t i = base + 1u; i < n; ++i) {
+    const uint32_t x = kv[i] >> 1;
+    r += (upper ? x <= k : x < k) ? 1u : 0u;
+  }
+  return r;
+}
+
+// Records output position o of a level of n elements in the level's fence
+// tree: in tree level t when o is a multiple of 32^t.
+__device__ __forceinline__ void put_fence(uint32_t* tree, uint64_t n, uint64_t o, uint32_t kv) {
+  if (tree == nullptr || (o & 31u) != 0) return;
+  const uint32_t key = kv >> 1;
+  uint64_t off = 0, c = (n + 31) / 32, q = o >> 5;
+  for (;;) {
+    tree[off + q] = key;
+    if (c <= 32 || (q & 31u) != 0) break;
+    off += fence_pad(c);
+    c = (c + 31) / 32;
+    q >>= 5;
+  }
 }
 
 // ------------------------------------------------------------ radix sort
@@ -316,7 +355,7 @@ __device__ void sort_tile_pass(const uint32_t (&kv)[kSortItems], const uint32_t 
         } else {
           out_kv[o] = k;
           out_val[o] = L.val[x];
-          put_fence(out_fence, o, k);
+          put_fence(out_fence, b, o, k);
         }
       }
     }
@@ -669,7 +708,7 @@ __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, 
       const uint32_t k = src_k[x];
       out_k[x] = k;
       out_v[x] = src_v[x];
-      put_fence(a.out_fence, s + x, k);
+      put_fence(a.out_fence, a.src.b, s + x, k);
     }
     return;
   }
@@ -720,7 +759,7 @@ __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, 
           if (o < n) {
             ok[o] = kv[i];
             ov[o] = vv[i];
-            if (p == passes - 1) put_fence(a.out_fence, s + o, kv[i]);
+            if (p == passes - 1) put_fence(a.out_fence, a.src.b, s + o, kv[i]);
           }
         }
       }
@@ -908,7 +947,7 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
         const uint32_t k = L.k[buf][x];
         out_k[x] = k;
         out_v[x] = L.v[buf][x];
-        put_fence(a.out_fence, s + x, k);
+        put_fence(a.out_fence, a.src.b, s + x, k);
       }
     }
     return;
@@ -980,7 +1019,7 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
         const uint32_t k = L.k[acc][x];
         f.out_kv[pos] = k;
         f.out_val[pos] = L.v[acc][x];
-        put_fence(f.out_fence, pos, k);
+        put_fence(f.out_fence, f.out_len, pos, k);
       }
     }
     return;
@@ -1014,7 +1053,7 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
     if (pos < f.out_len) {
       f.out_kv[pos] = x;
       f.out_val[pos] = rvp[p];
-      put_fence(f.out_fence, pos, x);
+      put_fence(f.out_fence, f.out_len, pos, x);
     }
   }
 }
@@ -1164,7 +1203,7 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
     }
 #pragma unroll
     for (int k = 0; k < kMergeItems; ++k)
-      if (dt + k < n) put_fence(out_fence, o + k, rk[k]);
+      if (dt + k < n) put_fence(out_fence, total, o + k, rk[k]);
     __syncthreads();
     const uint32_t la = s_split;
     a0 += la;
@@ -1505,7 +1544,9 @@ __global__ __launch_bounds__(kQueryThreads) void k_predecessor(LevelSet lv, cons
       bool done = false;
       for (int l = mi; l < L; ++l) {
         if (ck[l] != mk) continue;
-        const uint32_t s = fenced_bound(lv.kv[l], lv.fence[l], e[l], mk, false);
+        // The run of mk ends at e[l] - 1, so the bound over the whole level
+        // (the fence tree's layout is that of the whole level) is its start.
+        const uint32_t s = fenced_bound(lv.kv[l], lv.fence[l], lv.len[l], mk, false);
         if (l == mi && (lv.kv[l][s] & 1u)) {
           rk = mk;
           rv = lv.val[l][s];
@@ -1574,7 +1615,7 @@ __device__ __forceinline__ void dst_write(const LevelDst& d, int l, uint64_t p, 
   const uint64_t o = p - d.start[l];
   d.kv[l][o] = x;
   d.val[l][o] = v;
-  put_fence(d.fence[l], o, x);
+  put_fence(d.fence[l], d.len[l], o, x);
 }
 
 __global__ __launch_bounds__(kThreads) void k_clean_scatter(const uint32_t* kv,
