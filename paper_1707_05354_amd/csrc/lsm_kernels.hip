@@ -178,6 +178,51 @@ __device__ __forceinline__ uint32_t fenced_bound(const uint32_t* kv, const uint3
   return r;
 }
 
+// [lower_bound(k1), upper_bound(k2)) of a level, the two descents of its
+// fence tree in lockstep: at every tree level both lines are loaded before
+// either is examined, so the two chains of loads overlap.  A descent that
+// has reached position 0 stays there (its line loads are then harmless
+// reads of the first line).
+__device__ __forceinline__ void fenced_range(const uint32_t* kv, const uint32_t* tree, uint32_t n,
+                                             uint32_t k1, uint32_t k2, uint32_t& lo,
+                                             uint32_t& hi) {
+  lo = hi = 0;
+  if (n == 0) return;
+  uint64_t off = 0, c = (static_cast<uint64_t>(n) + 31) / 32;
+  int t = 1;
+  while (c > 32) {
+    off += fence_pad(c);
+    c = (c + 31) / 32;
+    ++t;
+  }
+  uint32_t g1 = line_count(tree + off, 0, static_cast<uint32_t>(c), k1, false, false);
+  uint32_t g2 = line_count(tree + off, 0, static_cast<uint32_t>(c), k2, true, false);
+  for (--t; t >= 1; --t) {
+    const uint64_t ct = (static_cast<uint64_t>(n) + (1ull << (5 * t)) - 1) >> (5 * t);
+    off -= fence_pad(ct);
+    const uint32_t b1 = g1 > 0 ? (g1 - 1) * 32u : 0u, b2 = g2 > 0 ? (g2 - 1) * 32u : 0u;
+    const uint32_t e1 = (b1 + 32u < ct) ? b1 + 32u : static_cast<uint32_t>(ct);
+    const uint32_t e2 = (b2 + 32u < ct) ? b2 + 32u : static_cast<uint32_t>(ct);
+    const uint32_t c1 = line_count(tree + off + b1, 1, e1 - b1, k1, false, false);
+    const uint32_t c2 = line_count(tree + off + b2, 1, e2 - b2, k2, true, false);
+    g1 = g1 > 0 ? b1 + c1 + 1u : 0u;
+    g2 = g2 > 0 ? b2 + c2 + 1u : 0u;
+  }
+  auto finish = [&](uint32_t g, uint32_t k, bool upper) -> uint32_t {
+    if (g == 0) return 0u;
+    const uint32_t base = (g - 1) * 32u;
+    if (base + 32u <= n) return base + line_count(kv + base, 1, 32, k, upper, true) + 1u;
+    uint32_t r = base + 1u;
+    for (uint32_t i = base + 1u; i < n; ++i) {
+      const uint32_t x = kv[i] >> 1;
+      r += (upper ? x <= k : x < k) ? 1u : 0u;
+    }
+    return r;
+  };
+  lo = finish(g1, k1, false);
+  hi = finish(g2, k2, true);
+}
+
 // Records output position o of a level of n elements in the level's fence
 // tree: in tree level t when o is a multiple of 32^t.
 __device__ __forceinline__ void put_fence(uint32_t* tree, uint64_t n, uint64_t o, uint32_t kv) {
@@ -1308,18 +1353,54 @@ __device__ __forceinline__ uint32_t skip_run(const uint32_t* kv, uint32_t c, uin
 // levels in key order.  For each distinct key the element met first is the
 // newest instance (smaller levels are newer, and inside a level a key's run
 // starts with its newest element); it counts when it is a regular element.
-template <bool kEmit>
+template <bool kEmit, bool kOneLevel>
 __device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, uint32_t k2,
                                                uint32_t* out_keys, uint32_t* out_vals,
                                                uint64_t limit) {
   if (k1 > k2) return 0u;
-  uint32_t cur[kMaxLevels], end[kMaxLevels], ck[kMaxLevels];
   const int L = lv.count;
+  if (kOneLevel) {
+    // One level: the first element of every key run is that key's newest
+    // instance, so the candidates are scanned in order, 16 at a time (their
+    // loads independent); a chunk that holds no run start lies inside one
+    // long run, which is skipped by galloping.
+    const uint32_t* kv = lv.kv[0];
+    uint32_t p, e;
+    fenced_range(kv, lv.fence[0], lv.len[0], k1, k2, p, e);
+    uint32_t count = 0, prev = kNoKey;
+    while (p < e) {
+      const uint32_t m = (e - p) < 16u ? (e - p) : 16u;
+      uint32_t x[16], v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        x[i] = static_cast<uint32_t>(i) < m ? kv[p + i] : 0u;
+        v[i] = (kEmit && static_cast<uint32_t>(i) < m) ? lv.val[0][p + i] : 0u;
+      }
+      bool any_start = false;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (static_cast<uint32_t>(i) < m) {
+          const uint32_t key = x[i] >> 1;
+          const bool start = key != prev;
+          if (start && (x[i] & 1u)) {
+            if (kEmit && count < limit) {
+              out_keys[count] = key;
+              out_vals[count] = v[i];
+            }
+            ++count;
+          }
+          any_start |= start;
+          prev = key;
+        }
+      }
+      p = any_start ? p + m : skip_run(kv, p + m - 1, e, prev);
+    }
+    return count;
+  } else {
+  uint32_t cur[kMaxLevels], end[kMaxLevels], ck[kMaxLevels];
   for (int l = 0; l < L; ++l) {
     const uint32_t* kv = lv.kv[l];
-    const uint32_t n = lv.len[l];
-    cur[l] = fenced_bound(kv, lv.fence[l], n, k1, false);
-    end[l] = fenced_bound(kv, lv.fence[l], n, k2, true);
+    fenced_range(kv, lv.fence[l], lv.len[l], k1, k2, cur[l], end[l]);
     ck[l] = cur[l] < end[l] ? (kv[cur[l]] >> 1) : kNoKey;
   }
   uint32_t count = 0;
@@ -1349,8 +1430,10 @@ __device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, 
     }
   }
   return count;
+  }
 }
 
+template <bool kOneLevel>
 __global__ __launch_bounds__(kQueryThreads) void k_count(LevelSet lv, const uint32_t* lo,
                                                          const uint32_t* hi, uint32_t nq,
                                                          uint32_t* counts, uint64_t* scan_status,
@@ -1361,9 +1444,10 @@ __global__ __launch_bounds__(kQueryThreads) void k_count(LevelSet lv, const uint
       scan_status[w] = 0ull;
   }
   if (gi >= nq) return;
-  counts[gi] = range_walk<false>(lv, lo[gi], hi[gi], nullptr, nullptr, 0);
+  counts[gi] = range_walk<false, kOneLevel>(lv, lo[gi], hi[gi], nullptr, nullptr, 0);
 }
 
+template <bool kOneLevel>
 __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const uint32_t* lo,
                                                               const uint32_t* hi, uint32_t nq,
                                                               const uint64_t* offsets,
@@ -1378,7 +1462,7 @@ __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const
   // guard against offsets corrupted by a timed-out scan.
   const uint64_t e = offsets[i + 1];
   if (e < o || e > offsets[nq] || e > cap) return;
-  range_walk<true>(lv, lo[i], hi[i], out_keys + o, out_vals + o, e - o);
+  range_walk<true, kOneLevel>(lv, lo[i], hi[i], out_keys + o, out_vals + o, e - o);
 }
 
 // ------------------------------------------------------------ scan
@@ -1782,7 +1866,8 @@ hipError_t launch_count(const LevelSet& lv, const uint32_t* lo, const uint32_t* 
                         uint32_t* counts, uint64_t* scan_status, size_t scan_words,
                         hipStream_t stream, const KTimer* t) {
   if (nq == 0) return hipSuccess;
-  return launch(k_count, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi, nq,
+  return launch(lv.count == 1 ? k_count<true> : k_count<false>, grid_for(nq, kQueryThreads),
+                kQueryThreads, stream, t, lv, lo, hi, nq,
                 counts, scan_status, static_cast<uint64_t>(scan_words));
 }
 
@@ -1840,7 +1925,8 @@ hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint3
                              uint32_t* out_vals, uint64_t cap, hipStream_t stream,
                              const KTimer* t) {
   if (nq == 0) return hipSuccess;
-  return launch(k_range_emit, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi,
+  return launch(lv.count == 1 ? k_range_emit<true> : k_range_emit<false>,
+                grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi,
                 nq, offsets, out_keys, out_vals, cap);
 }
 
