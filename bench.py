@@ -615,7 +615,7 @@ def main() -> int:
                               "max": round(prof.update_max_ms, 4)},
         "phase_ms": {"updates": round(upd_ms, 3), "lookups": round(lk_ms, 3),
                      "counts": round(ct_ms, 3), "ranges": round(rg_ms, 3),
-                     "sort_kernels": round(sum(prof.kernel_ms[k] for k in (0, 1, 9, 10, 11)), 3),
+                     "sort_kernels": round(sum(prof.kernel_ms[k] for k in (0, 1, 9, 10, 11, 12)), 3),
                      "merge_kernels": round(prof.kernel_ms[2], 3)},
         "roofline": {
             "kernel": L.KERNEL_NAMES[dom],

@@ -181,17 +181,6 @@ LSM_API lsm_status_t lsm_get_tuning(lsm_t h, uint32_t level, uint32_t* variant, 
 LSM_API lsm_status_t lsm_set_tuning(lsm_t h, uint32_t level, uint32_t variant);
 
 /*
- * lsm_set_sort_path -- which batch sort runs (both give the same order, so
- * results never depend on it).  LSM_SORT_TOP_DIGIT: one scatter on the top
- * 8 sorted bits, then each bucket sorted in LDS by one work-group (batches
- * of at most 2^20 elements; larger ones use digit passes).
- * LSM_SORT_DIGIT_PASSES: one stable counting pass per 8-bit digit with
- * decoupled look-back.  LSM_SORT_AUTO (the default): the top-digit sort
- * unless the previous sort saw a top-digit bucket above 8192 elements
- * (skewed keys, where one work-group would sort a large bucket alone).
- * Takes effect at the next sort.  LSM_EINVAL for another mode.
- */
-/*
  * lsm_set_fusion -- deepest cascade fused into the top-digit batch sort.  An
  * insert that fills level j <= max_levels (j >= 1) is done by the sort's
  * per-bucket work-groups: each merges its bucket of the batch with the same
@@ -204,9 +193,23 @@ LSM_API lsm_status_t lsm_set_tuning(lsm_t h, uint32_t level, uint32_t variant);
  */
 LSM_API lsm_status_t lsm_set_fusion(lsm_t h, int max_levels);
 
+/*
+ * lsm_set_sort_path -- which batch sort runs (all give the same order, so
+ * results never depend on it).  LSM_SORT_TOP_DIGIT: one scatter on the top
+ * 10 bits of the key variable into 1024 buckets, then each bucket sorted in
+ * LDS by one work-group (batches of at most 2^20 elements; larger ones use
+ * digit passes).  LSM_SORT_ONE_KERNEL: the same sort (and its fused
+ * cascade) as one kernel of 256 work-groups with two device-wide barriers
+ * instead of three kernels.  LSM_SORT_DIGIT_PASSES: one stable counting pass
+ * per 8-bit digit with decoupled look-back.  LSM_SORT_AUTO (the default):
+ * the top-digit sort unless the previous sort saw a top-digit bucket above
+ * 2048 elements (skewed keys, where one work-group would sort a large bucket
+ * alone).  Takes effect at the next sort.  LSM_EINVAL for another mode.
+ */
 #define LSM_SORT_AUTO 0
 #define LSM_SORT_TOP_DIGIT 1
 #define LSM_SORT_DIGIT_PASSES 2
+#define LSM_SORT_ONE_KERNEL 3
 LSM_API lsm_status_t lsm_set_sort_path(lsm_t h, int mode);
 
 /*
@@ -393,7 +396,8 @@ LSM_API lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out);
  * Kernel index k: 0 batch-sort histogram (digit-pass path), 1 batch-sort
  * digit pass, 2 level merge, 3 lookup, 4 count, 5 range offset scan, 6 range
  * emission, 7 successor / predecessor, 8 cleanup mark-and-compact, 9 / 10 /
- * 11 the top-digit sort's histogram, scatter and per-bucket sort.
+ * 11 the top-digit sort's histogram, scatter and per-bucket sort, 12 the
+ * top-digit sort as one kernel.
  * kernel_bytes[k] is the algorithmic traffic of those launches: 4 B per
  * batch element for a histogram (keys read), 16 B per element for a digit
  * pass, the top-digit scatter and the per-bucket sort (key and value read
@@ -402,7 +406,7 @@ LSM_API lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out);
  * 8 B per valid element written to scatter, 8 B per placebo; 0 for the
  * search kernels, which are latency-bound.
  */
-#define LSM_PROF_KERNELS 12
+#define LSM_PROF_KERNELS 13
 typedef struct {
   uint64_t update_calls;                   /* update calls (n > 0)          */
   uint64_t query_calls[3];                 /* lookup, count, range calls    */

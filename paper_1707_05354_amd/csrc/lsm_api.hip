@@ -344,7 +344,8 @@ lsm_status_t prepare_insert(lsm_t h, int j) {
 int sort_path(lsm_t h, uint32_t tiles) {
   int p;
   if (h->sort_mode == LSM_SORT_DIGIT_PASSES) p = kSortLsd;
-  else if (h->sort_mode == LSM_SORT_TOP_DIGIT) p = pick_sort_path(tiles, 0u);
+  else if (h->sort_mode == LSM_SORT_TOP_DIGIT || h->sort_mode == LSM_SORT_ONE_KERNEL)
+    p = pick_sort_path(tiles, 0u);
   else p = pick_sort_path(tiles, *reinterpret_cast<volatile uint32_t*>(h->skew_host));
   h->sorts_by_path[p] += 1;
   return p;
@@ -431,6 +432,7 @@ SortArgs sort_args(lsm_t h, const BatchSrc& src, int j) {
   sa.out_val = (j == 0) ? h->lvl_val[0] : h->buf_val;
   sa.out_fence = (j == 0) ? h->lvl_fence[0] : nullptr;
   sa.path = sort_path(h, sa.meta.num_sort_tiles);
+  sa.onepass = (sa.path == kSortMsd && h->sort_mode == LSM_SORT_ONE_KERNEL) ? 1 : 0;
   sa.skew_out = h->skew_dev;
   setup_fusion(h, sa, j);
   return sa;
@@ -505,7 +507,7 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
     const double bytes = (sa.fuse.nlev > 0 && p == nk - 1)
                              ? 16.0 * static_cast<double>(level_len(h, sa.fuse.nlev))
                              : sort_kernel_bytes_per_elem(p) * h->b;
-    const KTimer* t = timer(h, st[p], sort_kernel_kind(sa.path, p), h->b, bytes);
+    const KTimer* t = timer(h, st[p], sort_kernel_kind(sa.path, p, sa.onepass), h->b, bytes);
     if (t == nullptr) timed = false;
     else sort_t[p] = *t;
   }
@@ -875,7 +877,7 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
     const int nk = sort_kernel_count(sa);
     bool timed = h->prof;
     for (int x = 0; x < nk && timed; ++x) {
-      const KTimer* t = timer(h, ts[x], sort_kernel_kind(sa.path, x), len,
+      const KTimer* t = timer(h, ts[x], sort_kernel_kind(sa.path, x, sa.onepass), len,
                               sort_kernel_bytes_per_elem(x) * len);
       if (t == nullptr) timed = false;
       else tt[x] = *t;
@@ -1417,7 +1419,7 @@ lsm_status_t lsm_set_fusion(lsm_t h, int max_levels) {
 }
 
 lsm_status_t lsm_set_sort_path(lsm_t h, int mode) {
-  if (h == nullptr || mode < LSM_SORT_AUTO || mode > LSM_SORT_DIGIT_PASSES) return LSM_EINVAL;
+  if (h == nullptr || mode < LSM_SORT_AUTO || mode > LSM_SORT_ONE_KERNEL) return LSM_EINVAL;
   h->sort_mode = mode;
   return LSM_OK;
 }

@@ -108,6 +108,7 @@ struct SortMeta {
                           // [1] sticky device fault (a bounded wait expired)
   uint32_t* tile_cnt;     // [num_sort_tiles][kTopBuckets] top-digit counts (top-digit sort)
   uint32_t* bucket_start; // [kTopBuckets] first position of each top-digit bucket
+  uint32_t* bar;          // [2] grid barrier of the one-kernel top-digit sort
   uint32_t num_sort_tiles;
   int parity;
 };
@@ -158,6 +159,7 @@ struct SortArgs {
   uint32_t* out_fence;      // fences of the output when it is a level, else null
   uint32_t* out_digit;      // top-digit index of the output level (top-digit path), or null
   int path;                 // SortPath; both paths give the same order
+  int onepass;              // top-digit path as one kernel with grid barriers
   uint32_t* skew_out;       // optional: receives the largest top-digit bucket
   FuseArgs fuse;            // top-digit path only
 };
@@ -183,11 +185,15 @@ struct KTimer {
 enum KernelKind : int {
   kKSortHist = 0, kKSortPass = 1, kKMerge = 2, kKLookup = 3, kKCount = 4, kKScan = 5,
   kKRangeEmit = 6, kKOrder = 7, kKClean = 8, kKMsdHist = 9, kKMsdScatter = 10,
-  kKLocalSort = 11, kNumKernelKinds = 12
+  kKLocalSort = 11, kKOnePass = 12, kNumKernelKinds = 13
 };
+// Work-groups of the one-kernel top-digit sort: one per compute unit, so all
+// are resident at once (its grid barriers rely on that).
+constexpr uint32_t kOnePassGrid = 256;
 // Profiler kind and algorithmic bytes per element of the x-th kernel a sort
 // launches (launch_sort's order).
-inline int sort_kernel_kind(int path, int x) {
+inline int sort_kernel_kind(int path, int x, int onepass = 0) {
+  if (path == kSortMsd && onepass) return kKOnePass;
   if (path == kSortMsd) return x == 0 ? kKMsdHist : (x == 1 ? kKMsdScatter : kKLocalSort);
   return x == 0 ? kKSortHist : kKSortPass;
 }

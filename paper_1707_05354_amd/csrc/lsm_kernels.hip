@@ -115,6 +115,18 @@ __device__ __forceinline__ uint64_t ld_dev64(const uint64_t* p) {
 __device__ __forceinline__ void st_dev64(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Loads and stores of data that other work-groups of the same kernel write
+// or read (kC: device-coherent accesses) or that only later kernels read.
+template <bool kC>
+__device__ __forceinline__ uint32_t ldg(const uint32_t* p) {
+  if constexpr (kC) return ld_dev(p);
+  else return *p;
+}
+template <bool kC>
+__device__ __forceinline__ void stg(uint32_t* p, uint32_t v) {
+  if constexpr (kC) st_dev(p, v);
+  else *p = v;
+}
 
 // ------------------------------------------------------------ searches
 // Number of entries line[i], lo <= i < hi, that are < k (upper: <= k); the
@@ -529,21 +541,23 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint32_t* 
   return prev + r;
 }
 
-__global__ __launch_bounds__(kThreads) void k_msd_hist(SortArgs a, int top_shift) {
-  static_assert(kTopBuckets == static_cast<uint32_t>(kMaxPasses * kRadix),
-                "the top-digit counts use one histogram buffer");
-  __shared__ uint32_t s_h[kTopBuckets];
-  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const SortMeta& m = a.meta;
-  const uint32_t b = a.src.b;
-  const uint32_t tile = blockIdx.x;
-  const size_t gid = static_cast<size_t>(blockIdx.x) * kThreads + tid;
+// Clears the other digit-pass histogram buffer, whatever the grid size: the
+// next sort on this scratch may be a digit-pass sort that uses every pass's
+// counts (the buffer a sort uses starts zeroed whichever path it takes).
+__device__ __forceinline__ void clear_other_hist(const SortMeta& m) {
   uint32_t* other = m.hist + static_cast<size_t>(m.parity ^ 1) * kMaxPasses * kRadix;
-  // Clear all of the other buffer whatever the grid size: the next sort on
-  // this scratch may be a digit-pass sort that uses every pass's counts.
+  const size_t gid = static_cast<size_t>(blockIdx.x) * kThreads + threadIdx.x;
   for (size_t i = gid; i < static_cast<size_t>(kMaxPasses) * kRadix;
        i += static_cast<size_t>(gridDim.x) * kThreads)
     other[i] = 0u;
+}
+
+// Top-digit counts of one tile into tile_cnt[tile].
+template <bool kC>
+__device__ void tile_hist(const SortArgs& a, int top_shift, uint32_t tile, uint32_t* s_h) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const SortMeta& m = a.meta;
+  const uint32_t b = a.src.b;
 #pragma unroll
   for (int q = 0; q < kTopPer; ++q) s_h[tid + q * kThreads] = 0u;
   uint32_t kv[kSortItems], key[kSortItems];
@@ -564,67 +578,53 @@ __global__ __launch_bounds__(kThreads) void k_msd_hist(SortArgs a, int top_shift
     atomicAdd(&s_h[(kv[i] >> top_shift) & (kTopBuckets - 1)], 1u);
   }
   __syncthreads();
-  uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
 #pragma unroll
   for (int q = 0; q < kTopPer; ++q) {
     const uint32_t dg = tid + q * kThreads;
-    const uint32_t c = s_h[dg];
-    m.tile_cnt[static_cast<size_t>(tile) * kTopBuckets + dg] = c;
-    if (c != 0u) atomicAdd(&mine[dg], c);
+    stg<kC>(&m.tile_cnt[static_cast<size_t>(tile) * kTopBuckets + dg], s_h[dg]);
   }
   if (a.checked && bad) atomicOr(&m.err[0], 1u);
+  __syncthreads();  // s_h may be reused by the caller
+}
+
+__global__ __launch_bounds__(kThreads) void k_msd_hist(SortArgs a, int top_shift) {
+  __shared__ uint32_t s_h[kTopBuckets];
+  clear_other_hist(a.meta);
+  tile_hist<false>(a, top_shift, blockIdx.x, s_h);
 }
 
 // Stable scatter of one tile on the top digit.  Thread t owns the digits
 // [kTopPer t, kTopPer t + kTopPer).  A digit's output base is the number of
-// batch elements with a smaller digit (scan of the global counts) plus its
-// elements in earlier tiles (summed from their counts, eight loads in flight
-// at a time); the tile is ranked in LDS and written digit-sorted.  The work-
-// group of tile 0 also publishes every bucket's first position.
-__global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_shift) {
-  __shared__ uint32_t s_kv[kSortTile];
-  __shared__ uint32_t s_val[kSortTile];
-  __shared__ uint32_t s_wcnt[kWaves][kTopBuckets];
-  __shared__ uint32_t s_local[kTopBuckets];
-  __shared__ uint32_t s_gbase[kTopBuckets];
-  __shared__ uint32_t s_tmp[kWaves];
+// batch elements with a smaller digit (scan of the digit totals, summed from
+// every tile's counts) plus its elements in earlier tiles; the tile is ranked
+// in LDS and written digit-sorted.  The work-group of tile 0 also publishes
+// every bucket's first position.
+struct ScatterLds {
+  uint32_t kv[kSortTile];
+  uint32_t val[kSortTile];
+  uint32_t wcnt[kWaves][kTopBuckets];
+  uint32_t local[kTopBuckets];
+  uint32_t gbase[kTopBuckets];
+  uint32_t tmp[kWaves];
+};
+
+// Counts of this thread's four digits in a tile (one 16-byte load, or four
+// coherent loads when written by this kernel).
+template <bool kC>
+__device__ __forceinline__ uint4 tile_counts(const SortMeta& m, uint32_t t, uint32_t d0) {
+  const uint32_t* p = m.tile_cnt + static_cast<size_t>(t) * kTopBuckets + d0;
+  if constexpr (kC) return make_uint4(ld_dev(p), ld_dev(p + 1), ld_dev(p + 2), ld_dev(p + 3));
+  else return *reinterpret_cast<const uint4*>(p);
+}
+
+template <bool kC>
+__device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, ScatterLds& S) {
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const SortMeta& m = a.meta;
   const uint32_t b = a.src.b;
-  const uint32_t tile = blockIdx.x;
   const uint32_t tbase = tile * kSortTile;
-  const uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
   const uint32_t d0 = tid * kTopPer;
-  uint32_t gtot[kTopPer], before[kTopPer];
-#pragma unroll
-  for (int q = 0; q < kTopPer; ++q) {
-    gtot[q] = mine[d0 + q];
-    before[q] = 0u;
-  }
-  {
-    uint32_t t = 0;
-    for (; t + 8 <= tile; t += 8) {
-      uint4 c[8];
-#pragma unroll
-      for (int r = 0; r < 8; ++r)
-        c[r] = *reinterpret_cast<const uint4*>(m.tile_cnt + static_cast<size_t>(t + r) * kTopBuckets + d0);
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        before[0] += c[r].x;
-        before[1] += c[r].y;
-        before[2] += c[r].z;
-        before[3] += c[r].w;
-      }
-    }
-    for (; t < tile; ++t) {
-      const uint4 c = *reinterpret_cast<const uint4*>(m.tile_cnt + static_cast<size_t>(t) * kTopBuckets + d0);
-      before[0] += c.x;
-      before[1] += c.y;
-      before[2] += c.z;
-      before[3] += c.w;
-    }
-  }
-  for (uint32_t i = tid; i < kWaves * kTopBuckets; i += kThreads) (&s_wcnt[0][0])[i] = 0u;
+  static_assert(kTopPer == 4, "four digits per thread");
   uint32_t kv[kSortItems], val[kSortItems], off[kSortItems];
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
@@ -634,32 +634,56 @@ __global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_sh
     val[i] = 0u;
     if (e < b) batch_elem(a.src, e, kv[i], val[i], key);
   }
+  // Every tile's counts of this thread's digits, sixteen tiles' loads in
+  // flight at a time: the sum over earlier tiles and the total.
+  uint32_t gtot[kTopPer] = {0u, 0u, 0u, 0u}, before[kTopPer] = {0u, 0u, 0u, 0u};
+  const uint32_t ntiles = m.num_sort_tiles;
+  for (uint32_t t0 = 0; t0 < ntiles; t0 += 16) {
+    uint4 c[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      c[r] = (t0 + r < ntiles) ? tile_counts<kC>(m, t0 + r, d0) : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      gtot[0] += c[r].x;
+      gtot[1] += c[r].y;
+      gtot[2] += c[r].z;
+      gtot[3] += c[r].w;
+      if (t0 + r < tile) {
+        before[0] += c[r].x;
+        before[1] += c[r].y;
+        before[2] += c[r].z;
+        before[3] += c[r].w;
+      }
+    }
+  }
+  for (uint32_t i = tid; i < kWaves * kTopBuckets; i += kThreads) (&S.wcnt[0][0])[i] = 0u;
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i)
     off[i] = wave_rank<kTopBits>((kv[i] >> top_shift) & (kTopBuckets - 1),
-                                 tbase + tile_pos(wave, i, lane) < b, s_wcnt[wave]);
+                                 tbase + tile_pos(wave, i, lane) < b, S.wcnt[wave]);
   __syncthreads();
   uint32_t cnt[kTopPer], tsum = 0, gsum = 0;
 #pragma unroll
   for (int q = 0; q < kTopPer; ++q) {
     uint32_t c = 0;
     for (uint32_t w = 0; w < kWaves; ++w) {
-      const uint32_t x = s_wcnt[w][d0 + q];
-      s_wcnt[w][d0 + q] = c;
+      const uint32_t x = S.wcnt[w][d0 + q];
+      S.wcnt[w][d0 + q] = c;
       c += x;
     }
     cnt[q] = c;
     tsum += c;
     gsum += gtot[q];
   }
-  uint32_t lrun = block_excl_scan(tsum, s_tmp);
-  uint32_t grun = block_excl_scan(gsum, s_tmp);
+  uint32_t lrun = block_excl_scan(tsum, S.tmp);
+  uint32_t grun = block_excl_scan(gsum, S.tmp);
 #pragma unroll
   for (int q = 0; q < kTopPer; ++q) {
-    s_local[d0 + q] = lrun;
-    s_gbase[d0 + q] = grun + before[q];
-    if (tile == 0) m.bucket_start[d0 + q] = grun;
+    S.local[d0 + q] = lrun;
+    S.gbase[d0 + q] = grun + before[q];
+    if (tile == 0) stg<kC>(&m.bucket_start[d0 + q], grun);
     lrun += cnt[q];
     grun += gtot[q];
   }
@@ -668,22 +692,28 @@ __global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_sh
   for (int i = 0; i < kSortItems; ++i) {
     if (tbase + tile_pos(wave, i, lane) < b) {
       const uint32_t dd = (kv[i] >> top_shift) & (kTopBuckets - 1);
-      const uint32_t pos = s_local[dd] + s_wcnt[wave][dd] + off[i];
-      s_kv[pos] = kv[i];
-      s_val[pos] = val[i];
+      const uint32_t pos = S.local[dd] + S.wcnt[wave][dd] + off[i];
+      S.kv[pos] = kv[i];
+      S.val[pos] = val[i];
     }
   }
   __syncthreads();
   const uint32_t tile_n = (b - tbase) < static_cast<uint32_t>(kSortTile) ? (b - tbase) : kSortTile;
   for (uint32_t x = tid; x < tile_n; x += kThreads) {
-    const uint32_t k = s_kv[x];
+    const uint32_t k = S.kv[x];
     const uint32_t dd = (k >> top_shift) & (kTopBuckets - 1);
-    const uint32_t o = s_gbase[dd] + (x - s_local[dd]);
+    const uint32_t o = S.gbase[dd] + (x - S.local[dd]);
     if (o < b) {
-      a.tmp_kv[0][o] = k;
-      a.tmp_val[0][o] = s_val[x];
+      stg<kC>(&a.tmp_kv[0][o], k);
+      stg<kC>(&a.tmp_val[0][o], S.val[x]);
     }
   }
+  __syncthreads();  // the caller may reuse S
+}
+
+__global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_shift) {
+  __shared__ ScatterLds S;
+  tile_scatter<false>(a, top_shift, blockIdx.x, S);
 }
 
 struct alignas(16) LocalLds {
@@ -741,6 +771,7 @@ __device__ void lds_pass(LocalLds& L, int from, uint32_t n, int shift) {
 // Stable passes over a bucket too large for LDS, streaming through the
 // bucket's range chunk by chunk in order and ping-ponging between the two
 // scratch buffers; the last pass writes out_kv / out_val at s.
+template <bool kC>
 __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, uint32_t s,
                                      uint32_t n, LocalLds& L) {
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -750,9 +781,9 @@ __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, 
   uint32_t* out_v = a.out_val + s;
   if (passes == 0) {
     for (uint32_t x = tid; x < n; x += kThreads) {
-      const uint32_t k = src_k[x];
+      const uint32_t k = ldg<kC>(&src_k[x]);
       out_k[x] = k;
-      out_v[x] = src_v[x];
+      out_v[x] = ldg<kC>(&src_v[x]);
       put_fence(a.out_fence, a.src.b, s + x, k);
     }
     return;
@@ -767,7 +798,13 @@ __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, 
     uint32_t* ov = (p == passes - 1) ? out_v : ((p & 1) == 0 ? a.tmp_val[1] : a.tmp_val[0]) + s;
     run[tid] = 0u;
     __syncthreads();
-    for (uint32_t x = tid; x < n; x += kThreads) atomicAdd(&run[(ik[x] >> shift) & (kRadix - 1)], 1u);
+    // Pass 0 reads the scattered batch (written by other work-groups when
+    // the whole sort is one kernel); later passes read this work-group's own
+    // writes.
+    for (uint32_t x = tid; x < n; x += kThreads) {
+      const uint32_t k = (p == 0) ? ldg<kC>(&ik[x]) : ik[x];
+      atomicAdd(&run[(k >> shift) & (kRadix - 1)], 1u);
+    }
     __syncthreads();
     const uint32_t c = run[tid];
     __syncthreads();
@@ -778,8 +815,8 @@ __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, 
 #pragma unroll
       for (int i = 0; i < kSortItems; ++i) {
         const uint32_t e = cb + tile_pos(wave, i, lane);
-        kv[i] = e < n ? ik[e] : 0u;
-        vv[i] = e < n ? iv[e] : 0u;
+        kv[i] = e < n ? ((p == 0) ? ldg<kC>(&ik[e]) : ik[e]) : 0u;
+        vv[i] = e < n ? ((p == 0) ? ldg<kC>(&iv[e]) : iv[e]) : 0u;
       }
       for (uint32_t i = tid; i < kWaves * kRadix; i += kThreads) (&L.wcnt[0][0])[i] = 0u;
       __syncthreads();
@@ -852,7 +889,7 @@ __device__ void lds_merge_pair(const uint32_t* sk, const uint32_t* sv, uint32_t 
 // The fields are read four at a time (16-byte LDS reads, two in flight);
 // the reads past n see 0xFFFFFFFF at positions above every element, which
 // never counts.
-template <int P>
+template <int P, bool kC>
 __device__ void rank_sort(LocalLds& L, const uint32_t* src_k, const uint32_t* src_v, uint32_t n,
                           int lo_bit, int passes) {
   const uint32_t tid = threadIdx.x;
@@ -861,9 +898,9 @@ __device__ void rank_sort(LocalLds& L, const uint32_t* src_k, const uint32_t* sr
   const uint32_t n8 = (n + 7u) & ~7u;
   for (uint32_t x = tid; x < n8; x += kThreads) {
     if (x < n) {
-      const uint32_t k = src_k[x];
+      const uint32_t k = ldg<kC>(&src_k[x]);
       L.k[0][x] = k;
-      L.v[0][x] = src_v[x];
+      L.v[0][x] = ldg<kC>(&src_v[x]);
       L.k[1][x] = (k >> lo_bit) & fmask;
     } else {
       L.k[1][x] = 0xFFFFFFFFu;
@@ -939,21 +976,30 @@ __device__ __forceinline__ uint32_t seg_bound(const uint32_t* s, uint32_t lo, ui
 // (key, run, position) is a strict total order, so the order is again the
 // cascade's.  Without fusion, the sort of a level records its buckets'
 // starts as that level's top-digit index.
-__global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit, int passes) {
-  __shared__ LocalLds L;
+template <bool kC>
+__device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t d, LocalLds& L) {
   const uint32_t tid = threadIdx.x;
   const SortMeta& m = a.meta;
   const FuseArgs& f = a.fuse;
   const bool fused = f.nlev > 0;
-  const uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
-  const uint32_t s = m.bucket_start[blockIdx.x], n = mine[blockIdx.x];
-  if (blockIdx.x == 0 && a.skew_out != nullptr) {
+  // Bucket d spans [start[d], start[d + 1]) of the scattered batch.
+  auto bucket_end = [&](uint32_t q) {
+    return q + 1 < kTopBuckets ? ldg<kC>(&m.bucket_start[q + 1]) : a.src.b;
+  };
+  const uint32_t s = ldg<kC>(&m.bucket_start[d]);
+  const uint32_t e_s = bucket_end(d);
+  const uint32_t n = e_s > s ? e_s - s : 0u;
+  if (d == 0 && a.skew_out != nullptr) {
     uint32_t mx = 0;
 #pragma unroll
-    for (int q = 0; q < kTopPer; ++q) mx = max(mx, mine[tid * kTopPer + q]);
+    for (int q = 0; q < kTopPer; ++q) {
+      const uint32_t dq = tid * kTopPer + q;
+      const uint32_t lo = ldg<kC>(&m.bucket_start[dq]), hi = bucket_end(dq);
+      mx = max(mx, hi > lo ? hi - lo : 0u);
+    }
     record_max(mx, a.skew_out, L.tmp);
   }
-  if (!fused && a.out_digit != nullptr && tid == 0) a.out_digit[blockIdx.x] = s;
+  if (!fused && a.out_digit != nullptr && tid == 0) a.out_digit[d] = s;
   if (n == 0 && !fused) return;
   const uint32_t* src_k = a.tmp_kv[0] + s;
   const uint32_t* src_v = a.tmp_val[0] + s;
@@ -967,12 +1013,12 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
     buf = 0;
   } else if (n <= kRankSortMax) {
     static_assert(kRankSortMax <= static_cast<uint32_t>(kThreads), "one element per thread");
-    rank_sort<1>(L, src_k, src_v, n, lo_bit, passes);
+    rank_sort<1, kC>(L, src_k, src_v, n, lo_bit, passes);
     buf = 1;
   } else if (n <= static_cast<uint32_t>(kLocalCap)) {
     for (uint32_t x = tid; x < n; x += kThreads) {
-      L.k[0][x] = src_k[x];
-      L.v[0][x] = src_v[x];
+      L.k[0][x] = ldg<kC>(&src_k[x]);
+      L.v[0][x] = ldg<kC>(&src_v[x]);
     }
     __syncthreads();
     int cur = 0;
@@ -983,7 +1029,7 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
     buf = cur;
   } else {
     buf = -1;
-    local_sort_streaming(a, lo_bit, passes, s, n, L);
+    local_sort_streaming<kC>(a, lo_bit, passes, s, n, L);
   }
 
   if (!fused) {
@@ -999,7 +1045,6 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
   }
 
   // ---- fused cascade: this digit's key range in levels 0..j-1.
-  const uint32_t d = blockIdx.x;
   const int R = f.nlev + 1;  // runs: the batch, then levels 0..j-1
   if (tid < static_cast<uint32_t>(f.nlev)) {
     // The digit's range in level l, from the level's top-digit index.
@@ -1100,6 +1145,65 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit,
       f.out_val[pos] = rvp[p];
       put_fence(f.out_fence, f.out_len, pos, x);
     }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit, int passes) {
+  __shared__ LocalLds L;
+  bucket_sort<false>(a, lo_bit, passes, blockIdx.x, L);
+}
+
+// Grid-wide barrier for a kernel whose work-groups are all resident (its
+// grid is at most one work-group per compute unit, far below what the device
+// holds).  *count only ever grows: the G arrivals at one barrier read values
+// in [kG, kG + G) (no work-group reaches the next barrier before all have
+// reached this one), so each waits until the count reaches kG + G, compared
+// modulo 2^32 (G divides 2^32).  Nothing is reset, so no ordering between
+// two stores is needed.  Data handed across the barrier is written with
+// st_dev and read with ld_dev (device-coherent accesses); before arriving, a
+// work-group waits for its own memory operations.  The wait is bounded: past
+// kSpinLimit polls it records a fault (reported by lsm_sync) and goes on.
+__device__ void grid_barrier(uint32_t* count, uint32_t* fault) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t G = gridDim.x;
+    const uint32_t old = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t target = (old / G + 1u) * G;
+    uint32_t spins = 0;
+    while (static_cast<int32_t>(ld_dev(count) - target) < 0) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins == kSpinLimit) {
+        atomicOr(fault, kFaultTimeout);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// The top-digit sort as one kernel of kOnePassGrid work-groups: tile counts,
+// grid barrier, scatter, grid barrier, then every work-group sorts the
+// buckets d = blockIdx.x, blockIdx.x + kOnePassGrid, ... (with the fused
+// cascade).  Same results as the three kernels; two device-wide exchanges
+// without two kernel boundaries.
+__global__ __launch_bounds__(kThreads) void k_msd_onepass(SortArgs a, int top_shift, int lo_bit,
+                                                          int passes) {
+  __shared__ union {
+    uint32_t h[kTopBuckets];
+    ScatterLds S;
+    LocalLds L;
+  } U;
+  const SortMeta& m = a.meta;
+  clear_other_hist(m);
+  const uint32_t tiles = m.num_sort_tiles;
+  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) tile_hist<true>(a, top_shift, t, U.h);
+  grid_barrier(m.bar, m.err + 1);
+  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) tile_scatter<true>(a, top_shift, t, U.S);
+  grid_barrier(m.bar, m.err + 1);
+  for (uint32_t d = blockIdx.x; d < kTopBuckets; d += gridDim.x) {
+    bucket_sort<true>(a, lo_bit, passes, d, U.L);
+    __syncthreads();
   }
 }
 
@@ -1749,7 +1853,7 @@ hipError_t launch(Kernel k, unsigned grid, unsigned block, hipStream_t s, const 
 size_t sort_meta_words(uint32_t b) {
   const size_t ns = grid_for(b, kSortTile);
   return static_cast<size_t>(2) * kMaxPasses * kRadix + static_cast<size_t>(kMaxPasses) * ns * kRadix +
-         kMaxPasses + 4 + ns * kTopBuckets + kTopBuckets;
+         kMaxPasses + 4 + ns * kTopBuckets + kTopBuckets + 4;
 }
 
 SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
@@ -1761,11 +1865,15 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
   m.err = m.tile_ctr + kMaxPasses;
   m.tile_cnt = m.err + 4;  // 16-byte aligned (vector loads of four counts)
   m.bucket_start = m.tile_cnt + static_cast<size_t>(m.num_sort_tiles) * kTopBuckets;
+  m.bar = m.bucket_start + kTopBuckets;
   m.parity = parity;
   return m;
 }
 
-int sort_kernel_count(const SortArgs& a) { return a.path == kSortMsd ? 3 : 1 + a.passes; }
+int sort_kernel_count(const SortArgs& a) {
+  if (a.path == kSortMsd) return a.onepass ? 1 : 3;
+  return 1 + a.passes;
+}
 
 hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers) {
   const uint32_t tiles = a.meta.num_sort_tiles;
@@ -1773,6 +1881,9 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* time
     // Top digit: the highest 8 bits a key variable of this handle can have.
     const int top = sort_top_shift(a);
     const int local_passes = (top - a.lo_bit + kRadixBits - 1) / kRadixBits;
+    if (a.onepass)
+      return launch(k_msd_onepass, kOnePassGrid, kThreads, stream, timers ? &timers[0] : nullptr, a,
+                    top, a.lo_bit, local_passes);
     hipError_t e = launch(k_msd_hist, tiles, kThreads, stream, timers ? &timers[0] : nullptr, a, top);
     if (e == hipSuccess)
       e = launch(k_msd_scatter, tiles, kThreads, stream, timers ? &timers[1] : nullptr, a, top);

@@ -41,7 +41,7 @@ class Stats(ctypes.Structure):
 
 KERNEL_NAMES = ("k_sort_hist", "k_sort_pass", "k_merge", "k_lookup", "k_count", "k_scan",
                 "k_range_emit", "k_order", "k_clean", "k_msd_hist", "k_msd_scatter",
-                "k_local_sort")
+                "k_local_sort", "k_msd_onepass")
 # rocprofv3 kernel names behind each profiler kind that covers several kernels.
 KERNEL_TRACE_NAMES = {"k_order": ("k_successor", "k_predecessor"),
                       "k_clean": ("k_clean_count", "k_clean_scatter", "k_clean_pad"),
@@ -261,7 +261,7 @@ class LSM:
         _check(self._lib.lsm_get_tuning(self._h, int(level), ctypes.byref(v), us), "lsm_get_tuning")
         return int(v.value), [float(x) for x in us]
 
-    SORT_AUTO, SORT_TOP_DIGIT, SORT_DIGIT_PASSES = 0, 1, 2
+    SORT_AUTO, SORT_TOP_DIGIT, SORT_DIGIT_PASSES, SORT_ONE_KERNEL = 0, 1, 2, 3
 
     def set_sort_path(self, mode: int) -> None:
         """LSM.SORT_AUTO (default), LSM.SORT_TOP_DIGIT or LSM.SORT_DIGIT_PASSES."""

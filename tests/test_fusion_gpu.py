@@ -15,10 +15,10 @@ from _gpu import Trio, dev, host, note
 pytestmark = pytest.mark.gpu
 
 
-def run(b, batches, fusion, force_top=True):
+def run(b, batches, fusion, force_top=True, mode=LSM.SORT_TOP_DIGIT):
     t = Trio(b)
     if force_top:
-        t.g.set_sort_path(LSM.SORT_TOP_DIGIT)
+        t.g.set_sort_path(mode)
     t.g.set_fusion(fusion)
     for kind, k, v in batches:
         if kind == "insert":
@@ -71,6 +71,20 @@ def test_partly_fused_cascades(depth):
     fused = run(b, ops, depth)
     plain = run(b, ops, 0)
     assert levels(fused) == levels(plain)
+
+
+@pytest.mark.parametrize("b,R,domain", [(1, 150, 20), (64, 40, 5000), (4099, 19, 1 << 14),
+                                        (1 << 16, 17, 1 << 31), (10000, 9, 1 << 20)])
+def test_one_kernel_sort_equals_three_kernels(b, R, domain):
+    """The top-digit sort as one kernel with device-wide barriers, fused
+    cascade included, against the same inserts through three kernels (and
+    the oracle); the last case puts every key in one top digit."""
+    note("one-kernel sort b=%d R=%d" % (b, R))
+    ops = stream(3000 + b, b, R, domain)
+    one = run(b, ops, -1, mode=LSM.SORT_ONE_KERNEL)
+    three = run(b, ops, -1, mode=LSM.SORT_TOP_DIGIT)
+    assert levels(one) == levels(three)
+    assert one.g.stats().sorts_top_digit == R
 
 
 @pytest.mark.parametrize("b", [4096, 10000])
