@@ -49,13 +49,25 @@ __device__ __forceinline__ uint32_t count_below(uint64_t m) {
 }
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Inclusive scan over the wave (every lane active).  Within each row of 16
+// lanes, four DPP row shifts by 1, 2, 4 and 8 (lanes shifted in from outside
+// the row read 0); then each row adds the totals of the rows below it, read
+// from lanes 15, 31 and 47.
+template <int kCtrl>
+__device__ __forceinline__ uint32_t dpp_row_shr(uint32_t x) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(x), kCtrl, 0xf, 0xf, true));
+}
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, uint32_t lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= static_cast<uint32_t>(o)) x += y;
-  }
-  return x;
+  x += dpp_row_shr<0x111>(x);  // row_shr:1
+  x += dpp_row_shr<0x112>(x);  // row_shr:2
+  x += dpp_row_shr<0x114>(x);  // row_shr:4
+  x += dpp_row_shr<0x118>(x);  // row_shr:8
+  const uint32_t r0 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 15));
+  const uint32_t r1 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 31));
+  const uint32_t r2 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 47));
+  const uint32_t row = lane >> 4;
+  return x + (row > 0 ? r0 : 0u) + (row > 1 ? r1 : 0u) + (row > 2 ? r2 : 0u);
 }
 __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x, uint32_t lane) {
 #pragma unroll
@@ -82,6 +94,26 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* tmp) {
   for (uint32_t w = 0; w < wave; ++w) pre += tmp[w];
   __syncthreads();
   return pre + inc - x;
+}
+
+// Two exclusive scans over the work-group in one pass (the barriers of one).
+// tmp holds 2 kWaves words.
+__device__ __forceinline__ void block_excl_scan2(uint32_t& x, uint32_t& y, uint32_t* tmp) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t ix = wave_incl_scan(x, lane), iy = wave_incl_scan(y, lane);
+  if (lane == 63) {
+    tmp[wave] = ix;
+    tmp[kWaves + wave] = iy;
+  }
+  __syncthreads();
+  uint32_t px = 0, py = 0;
+  for (uint32_t w = 0; w < wave; ++w) {
+    px += tmp[w];
+    py += tmp[kWaves + w];
+  }
+  __syncthreads();
+  x = px + ix - x;
+  y = py + iy - y;
 }
 
 // Writes the largest of the work-group's 256 per-thread values to *out
@@ -264,26 +296,49 @@ constexpr uint32_t kCountMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 24;
 constexpr uint32_t kFaultTimeout = 2u;
 
+// One thread's kN items of the tile starting at tb (positions tile_pos).
 // Element e of the batch as the sort sees it: read back to front and padded
-// with copies of the caller's last element, so e = 0 .. b-n-1 are padding
-// and e = b-n .. b-1 are the caller's elements n-1 .. 0.
-__device__ __forceinline__ void batch_elem(const BatchSrc& s, uint32_t e, uint32_t& kv,
-                                           uint32_t& val, uint32_t& key) {
-  uint32_t src = s.b - 1 - e;
-  if (src > s.n - 1) src = s.n - 1;
-  if (s.mode == kEncoded) {
-    kv = s.keys[src];
-    val = s.vals[src];
-    key = kv >> 1;
-    return;
+// with copies of the caller's last element, so e = 0 .. b-n-1 are padding and
+// e = b-n .. b-1 are the caller's elements n-1 .. 0.  Written so that the
+// tile's loads are all in flight together.  Every load is issued unconditionally (the source index is
+// clamped, so each address is in bounds; deletions read their values from the
+// keys and drop them), only a mixed batch's flags sit behind a branch (on the
+// batch mode, uniform), and the key variables are formed afterwards.  Items
+// at or past b are invalid and read as 0.
+template <int kN>
+__device__ __forceinline__ void tile_items(const BatchSrc& s, uint32_t tb, uint32_t wave,
+                                           uint32_t lane, uint32_t (&kv)[kN], uint32_t (&val)[kN],
+                                           uint32_t (&key)[kN], bool (&valid)[kN]) {
+  const uint32_t* vp = s.vals != nullptr ? s.vals : s.keys;
+  uint32_t src[kN], rk[kN], rv[kN], st[kN];
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    const uint32_t e = tb + wave * 64 * kN + static_cast<uint32_t>(i) * 64 + lane;
+    valid[i] = e < s.b;
+    const uint32_t x = s.b - 1 - e;
+    src[i] = x < s.n - 1 ? x : s.n - 1;
   }
-  key = s.keys[src];
-  uint32_t st;
-  if (s.mode == kInsert) st = 1u;
-  else if (s.mode == kDelete) st = 0u;
-  else st = s.is_delete[src] ? 0u : 1u;
-  kv = (key << 1) | st;
-  val = st ? s.vals[src] : 0u;  // tombstones carry value 0
+#pragma unroll
+  for (int i = 0; i < kN; ++i) rk[i] = s.keys[src[i]];
+#pragma unroll
+  for (int i = 0; i < kN; ++i) rv[i] = vp[src[i]];
+  if (s.mode == kMixed) {
+#pragma unroll
+    for (int i = 0; i < kN; ++i) st[i] = s.is_delete[src[i]] ? 0u : 1u;
+  } else {
+    const uint32_t c = s.mode == kDelete ? 0u : 1u;
+#pragma unroll
+    for (int i = 0; i < kN; ++i) st[i] = c;
+  }
+  const bool enc = s.mode == kEncoded;
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    const uint32_t x = enc ? rk[i] : ((rk[i] << 1) | st[i]);
+    const uint32_t v = (enc || st[i] != 0u) ? rv[i] : 0u;  // tombstones carry value 0
+    kv[i] = valid[i] ? x : 0u;
+    val[i] = valid[i] ? v : 0u;
+    key[i] = valid[i] ? (enc ? rk[i] >> 1 : rk[i]) : 0u;
+  }
 }
 
 struct SortLds {
@@ -442,18 +497,12 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(SortArgs a) {
   bool bad = false;
   for (uint32_t t = blockIdx.x; t < m.num_sort_tiles; t += gridDim.x) {
     const uint32_t tb = t * kSortTile;
-    uint32_t kv[kSortItems], key[kSortItems];
-#pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {  // all loads first, then count
-      const uint32_t e = tb + tile_pos(wave, i, lane);
-      uint32_t val;
-      kv[i] = 0u;
-      key[i] = 0u;
-      if (e < b) batch_elem(a.src, e, kv[i], val, key[i]);
-    }
+    uint32_t kv[kSortItems], key[kSortItems], val[kSortItems];
+    bool valid[kSortItems];
+    tile_items<kSortItems>(a.src, tb, wave, lane, kv, val, key, valid);  // all loads, then count
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
-      if (tb + tile_pos(wave, i, lane) >= b) continue;
+      if (!valid[i]) continue;
       if (a.checked) bad |= (key[i] >> a.key_limit_bits) != 0u;
       for (int p = 0; p < a.passes; ++p)
         atomicAdd(&s_h[p * kRadix + ((kv[i] >> (a.lo_bit + kRadixBits * p)) & (kRadix - 1))], 1u);
@@ -487,20 +536,24 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(SortArgs a, int pass) {
   uint32_t kv[kSortItems], val[kSortItems];
   auto load_tile = [&](uint32_t t) {
     const uint32_t tb = t * kSortTile;
+    if (in_kv == nullptr) {
+      uint32_t key[kSortItems];
+      bool valid[kSortItems];
+      tile_items<kSortItems>(a.src, tb, wave, lane, kv, val, key, valid);
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
       const uint32_t e = tb + tile_pos(wave, i, lane);
-      kv[i] = 0u;
-      val[i] = 0u;
-      if (e < b) {
-        if (in_kv == nullptr) {
-          uint32_t key;
-          batch_elem(a.src, e, kv[i], val[i], key);
-        } else {
-          kv[i] = in_kv[e];
-          val[i] = in_val[e];
-        }
-      }
+      const uint32_t ec = e < b ? e : b - 1;  // in bounds; the item is dropped below
+      kv[i] = in_kv[ec];
+      val[i] = in_val[ec];
+    }
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+      const bool ok = tb + tile_pos(wave, i, lane) < b;
+      kv[i] = ok ? kv[i] : 0u;
+      val[i] = ok ? val[i] : 0u;
     }
   };
   load_tile(blockIdx.x);
@@ -560,20 +613,14 @@ __device__ void tile_hist(const SortArgs& a, int top_shift, uint32_t tile, uint3
   const uint32_t b = a.src.b;
 #pragma unroll
   for (int q = 0; q < kTopPer; ++q) s_h[tid + q * kThreads] = 0u;
-  uint32_t kv[kSortItems], key[kSortItems];
-#pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    const uint32_t e = tile * kSortTile + tile_pos(wave, i, lane);
-    uint32_t val;
-    kv[i] = 0u;
-    key[i] = 0u;
-    if (e < b) batch_elem(a.src, e, kv[i], val, key[i]);
-  }
+  uint32_t kv[kSortItems], key[kSortItems], val[kSortItems];
+  bool valid[kSortItems];
+  tile_items<kSortItems>(a.src, tile * kSortTile, wave, lane, kv, val, key, valid);
   __syncthreads();
   bool bad = false;
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
-    if (tile * kSortTile + tile_pos(wave, i, lane) >= b) continue;
+    if (!valid[i]) continue;
     if (a.checked) bad |= (key[i] >> a.key_limit_bits) != 0u;
     atomicAdd(&s_h[(kv[i] >> top_shift) & (kTopBuckets - 1)], 1u);
   }
@@ -605,7 +652,7 @@ struct ScatterLds {
   uint32_t wcnt[kWaves][kTopBuckets];
   uint32_t local[kTopBuckets];
   uint32_t gbase[kTopBuckets];
-  uint32_t tmp[kWaves];
+  uint32_t tmp[2 * kWaves];
 };
 
 // Counts of this thread's four digits in a tile (one 16-byte load, or four
@@ -617,6 +664,42 @@ __device__ __forceinline__ uint4 tile_counts(const SortMeta& m, uint32_t t, uint
   else return *reinterpret_cast<const uint4*>(p);
 }
 
+// Stable ranks of a wave's items among equal digits, item i of every lane
+// after item i - 1 (tile order is item-major within the wave).  The match
+// masks of all items are computed first (no memory traffic); then the leader
+// of each digit group adds the group's size to wcnt[d] with an LDS
+// fetch-and-add, items in order (one wave's LDS operations are applied in
+// issue order), and the leader's old count is broadcast to the group.  wcnt is this
+// wave's own row, so no work-group barrier is needed around the updates.
+template <int kBits, int kN>
+__device__ __forceinline__ void wave_rank_items(const uint32_t (&d)[kN], const bool (&valid)[kN],
+                                                uint32_t* wcnt, uint32_t (&off)[kN]) {
+  uint32_t r[kN], lead[kN], size[kN];
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    uint64_t peers = ballot(valid[i]);
+#pragma unroll
+    for (int bit = 0; bit < kBits; ++bit) {
+      const bool set = (d[i] >> bit) & 1u;
+      const uint64_t m = ballot(set);
+      peers &= set ? m : ~m;
+    }
+    r[i] = count_below(peers);
+    lead[i] = peers != 0 ? static_cast<uint32_t>(__builtin_ctzll(peers)) : 0u;
+    size[i] = static_cast<uint32_t>(__popcll(peers));
+  }
+  // Every lane issues the add (others add 0, so the leader's old count is the
+  // count before this item whatever order the lanes are applied in); no
+  // branch, so the kN adds are in flight together.
+  uint32_t prev[kN];
+#pragma unroll
+  for (int i = 0; i < kN; ++i)
+    prev[i] = atomicAdd(&wcnt[valid[i] ? d[i] : 0u], (valid[i] && r[i] == 0) ? size[i] : 0u);
+#pragma unroll
+  for (int i = 0; i < kN; ++i) off[i] = static_cast<uint32_t>(__shfl(static_cast<int>(prev[i]),
+                                                                      static_cast<int>(lead[i]), 64)) + r[i];
+}
+
 template <bool kC>
 __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, ScatterLds& S) {
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -625,60 +708,65 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
   const uint32_t tbase = tile * kSortTile;
   const uint32_t d0 = tid * kTopPer;
   static_assert(kTopPer == 4, "four digits per thread");
-  uint32_t kv[kSortItems], val[kSortItems], off[kSortItems];
-#pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    const uint32_t e = tbase + tile_pos(wave, i, lane);
-    uint32_t key;
-    kv[i] = 0u;
-    val[i] = 0u;
-    if (e < b) batch_elem(a.src, e, kv[i], val[i], key);
-  }
-  // Every tile's counts of this thread's digits, sixteen tiles' loads in
-  // flight at a time: the sum over earlier tiles and the total.
+  constexpr int kChunk = 32;  // tiles' counts in flight per round
+  uint32_t kv[kSortItems], val[kSortItems], off[kSortItems], dg[kSortItems], key[kSortItems];
+  bool valid[kSortItems];
+  tile_items<kSortItems>(a.src, tbase, wave, lane, kv, val, key, valid);
+  // Every tile's counts of this thread's four digits give the sum over
+  // earlier tiles and the total.  The first round of loads is issued before
+  // the ranking below, which needs only the tile's own elements.
   uint32_t gtot[kTopPer] = {0u, 0u, 0u, 0u}, before[kTopPer] = {0u, 0u, 0u, 0u};
   const uint32_t ntiles = m.num_sort_tiles;
-  for (uint32_t t0 = 0; t0 < ntiles; t0 += 16) {
-    uint4 c[16];
+  uint4 c[kChunk];
+  auto load_chunk = [&](uint32_t t0) {  // unconditional loads (clamped tile index)
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-      c[r] = (t0 + r < ntiles) ? tile_counts<kC>(m, t0 + r, d0) : make_uint4(0u, 0u, 0u, 0u);
+    for (int r = 0; r < kChunk; ++r)
+      c[r] = tile_counts<kC>(m, t0 + r < ntiles ? t0 + r : ntiles - 1, d0);
+  };
+  auto add_chunk = [&](uint32_t t0) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      gtot[0] += c[r].x;
-      gtot[1] += c[r].y;
-      gtot[2] += c[r].z;
-      gtot[3] += c[r].w;
-      if (t0 + r < tile) {
-        before[0] += c[r].x;
-        before[1] += c[r].y;
-        before[2] += c[r].z;
-        before[3] += c[r].w;
-      }
+    for (int r = 0; r < kChunk; ++r) {
+      const uint32_t in = t0 + r < ntiles ? ~0u : 0u, early = t0 + r < tile ? ~0u : 0u;
+      gtot[0] += c[r].x & in;
+      gtot[1] += c[r].y & in;
+      gtot[2] += c[r].z & in;
+      gtot[3] += c[r].w & in;
+      before[0] += c[r].x & early;
+      before[1] += c[r].y & early;
+      before[2] += c[r].z & early;
+      before[3] += c[r].w & early;
     }
-  }
-  for (uint32_t i = tid; i < kWaves * kTopBuckets; i += kThreads) (&S.wcnt[0][0])[i] = 0u;
-  __syncthreads();
+  };
+  load_chunk(0);
+  // Rank the tile: each wave clears and fills its own row of wcnt.
+  for (uint32_t i = lane; i < kTopBuckets; i += 64) S.wcnt[wave][i] = 0u;
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i)
-    off[i] = wave_rank<kTopBits>((kv[i] >> top_shift) & (kTopBuckets - 1),
-                                 tbase + tile_pos(wave, i, lane) < b, S.wcnt[wave]);
+  for (int i = 0; i < kSortItems; ++i) dg[i] = (kv[i] >> top_shift) & (kTopBuckets - 1);
+  wave_rank_items<kTopBits>(dg, valid, S.wcnt[wave], off);
+  add_chunk(0);
+  for (uint32_t t0 = kChunk; t0 < ntiles; t0 += kChunk) {
+    load_chunk(t0);
+    add_chunk(t0);
+  }
   __syncthreads();
   uint32_t cnt[kTopPer], tsum = 0, gsum = 0;
 #pragma unroll
   for (int q = 0; q < kTopPer; ++q) {
-    uint32_t c = 0;
-    for (uint32_t w = 0; w < kWaves; ++w) {
-      const uint32_t x = S.wcnt[w][d0 + q];
-      S.wcnt[w][d0 + q] = c;
-      c += x;
+    uint32_t x[kWaves];
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) x[w] = S.wcnt[w][d0 + q];
+    uint32_t run = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      S.wcnt[w][d0 + q] = run;
+      run += x[w];
     }
-    cnt[q] = c;
-    tsum += c;
+    cnt[q] = run;
+    tsum += run;
     gsum += gtot[q];
   }
-  uint32_t lrun = block_excl_scan(tsum, S.tmp);
-  uint32_t grun = block_excl_scan(gsum, S.tmp);
+  uint32_t lrun = tsum, grun = gsum;
+  block_excl_scan2(lrun, grun, S.tmp);
 #pragma unroll
   for (int q = 0; q < kTopPer; ++q) {
     S.local[d0 + q] = lrun;
@@ -690,8 +778,8 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
-    if (tbase + tile_pos(wave, i, lane) < b) {
-      const uint32_t dd = (kv[i] >> top_shift) & (kTopBuckets - 1);
+    if (valid[i]) {
+      const uint32_t dd = dg[i];
       const uint32_t pos = S.local[dd] + S.wcnt[wave][dd] + off[i];
       S.kv[pos] = kv[i];
       S.val[pos] = val[i];
