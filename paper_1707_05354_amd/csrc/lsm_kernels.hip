@@ -809,9 +809,8 @@ struct alignas(16) LocalLds {
   uint32_t v[2][kLocalCap];
   uint32_t wcnt[kWaves][kRadix];
   uint32_t tmp[kWaves];
-  uint32_t lo[kMaxFuse], hi[kMaxFuse];  // fused cascade: the digit's range per level
-  uint32_t rs[kMaxFuse + 2];            // run starts in the concatenated runs
-  uint32_t out_lo, out_hi;              // first output position (64-bit)
+  uint32_t lo[kMaxFuse];      // fused cascade: start of the digit's range per level
+  uint32_t rs[kMaxFuse + 2];  // run starts in the concatenated runs
 };
 
 // One stable counting pass over n <= kLocalCap elements in LDS, from
@@ -968,67 +967,35 @@ __device__ void lds_merge_pair(const uint32_t* sk, const uint32_t* sv, uint32_t 
   __syncthreads();
 }
 
-// Stable rank sort of a bucket of n <= P * kThreads elements into
-// L.k[1] / L.v[1].  The rank of element x is the number of elements whose
-// sorted field (bits [lo_bit, lo_bit + 8 passes) of the key variable) is
-// smaller, plus those with an equal field at an earlier position; (field,
-// position) is a strict total order, so the ranks are a permutation of
-// [0, n) and the order equals that of the radix passes over the same bits.
-// The fields are read four at a time (16-byte LDS reads, two in flight);
-// the reads past n see 0xFFFFFFFF at positions above every element, which
-// never counts.
-template <int P, bool kC>
-__device__ void rank_sort(LocalLds& L, const uint32_t* src_k, const uint32_t* src_v, uint32_t n,
-                          int lo_bit, int passes) {
+// Stable rank sort of the bucket's n <= kRankSortMax elements, held in
+// L.k[0] / L.v[0], into L.k[1] / L.v[1].  fld[0, n8) holds each element's
+// sort key (field << 8) | x, where the field is bits [lo_bit, lo_bit + 8
+// passes) of its key variable (at most 24 bits: the bits below the top
+// digit) and x its position; n8 = n rounded up to 8, with 0xFFFFFFFF past n.
+// The keys are distinct, so the rank of element x, the number of smaller
+// keys, orders by field and then by position (a stable sort, the same order
+// as the radix passes over those bits).  The keys are read four at a time
+// (16-byte LDS reads, two in flight); the entries past n are above every
+// element's key.  Waves without elements skip the count.
+__device__ void rank_sort(LocalLds& L, const uint32_t* fld, uint32_t n) {
+  static_assert(kRankSortMax <= 256u && kRankSortMax <= static_cast<uint32_t>(kThreads),
+                "positions fit 8 bits; one element per thread");
   const uint32_t tid = threadIdx.x;
-  const uint32_t fmask = (kRadixBits * passes >= 32) ? 0xFFFFFFFFu
-                                                     : ((1u << (kRadixBits * passes)) - 1u);
-  const uint32_t n8 = (n + 7u) & ~7u;
-  for (uint32_t x = tid; x < n8; x += kThreads) {
-    if (x < n) {
-      const uint32_t k = ldg<kC>(&src_k[x]);
-      L.k[0][x] = k;
-      L.v[0][x] = ldg<kC>(&src_v[x]);
-      L.k[1][x] = (k >> lo_bit) & fmask;
-    } else {
-      L.k[1][x] = 0xFFFFFFFFu;
+  if ((tid & ~63u) < n) {
+    const uint32_t n8 = (n + 7u) & ~7u;
+    const uint32_t cx = tid < n ? fld[tid] : 0u;
+    uint32_t rank = 0;
+    const uint4* f4 = reinterpret_cast<const uint4*>(fld);
+    for (uint32_t y = 0; y < n8; y += 8) {
+      const uint4 p = f4[y / 4];
+      const uint4 q = f4[y / 4 + 1];
+      rank += (p.x < cx ? 1u : 0u) + (p.y < cx ? 1u : 0u) + (p.z < cx ? 1u : 0u) +
+              (p.w < cx ? 1u : 0u) + (q.x < cx ? 1u : 0u) + (q.y < cx ? 1u : 0u) +
+              (q.z < cx ? 1u : 0u) + (q.w < cx ? 1u : 0u);
     }
-  }
-  __syncthreads();
-  uint32_t fx[P], rank[P];
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const uint32_t x = tid + i * kThreads;
-    fx[i] = x < n ? L.k[1][x] : 0u;
-    rank[i] = 0u;
-  }
-  const uint4* f4 = reinterpret_cast<const uint4*>(L.k[1]);
-  for (uint32_t y = 0; y < n8; y += 8) {
-    const uint4 p = f4[y / 4];
-    const uint4 q = f4[y / 4 + 1];
-    const uint32_t fy[8] = {p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w};
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-#pragma unroll
-      for (int i = 0; i < P; ++i) {
-        const uint32_t x = tid + i * kThreads;
-        rank[i] += (fy[u] < fx[i] || (fy[u] == fx[i] && y + u < x)) ? 1u : 0u;
-      }
-    }
-  }
-  uint32_t kx[P], vx[P];
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const uint32_t x = tid + i * kThreads;
-    kx[i] = x < n ? L.k[0][x] : 0u;
-    vx[i] = x < n ? L.v[0][x] : 0u;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    if (tid + i * kThreads < n) {
-      L.k[1][rank[i]] = kx[i];
-      L.v[1][rank[i]] = vx[i];
+    if (tid < n) {
+      L.k[1][rank] = L.k[0][tid];
+      L.v[1][rank] = L.v[0][tid];
     }
   }
   __syncthreads();
@@ -1070,58 +1037,173 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   const SortMeta& m = a.meta;
   const FuseArgs& f = a.fuse;
   const bool fused = f.nlev > 0;
-  // Bucket d spans [start[d], start[d + 1]) of the scattered batch.
-  auto bucket_end = [&](uint32_t q) {
-    return q + 1 < kTopBuckets ? ldg<kC>(&m.bucket_start[q + 1]) : a.src.b;
+  const int R = f.nlev + 1;  // runs: the batch, then levels 0..j-1
+  // Bucket d spans [start[d], start[d + 1]) of the scattered batch, the last
+  // one ending at b.  Every load of this prologue is issued unconditionally
+  // (clamped index), so the bounds, the skew hint's bounds and the levels'
+  // digit ranges are in flight together.
+  auto next_of = [](uint32_t q) { return q + 1 < kTopBuckets ? q + 1 : q; };
+  auto end_of = [&](uint32_t q, uint32_t next_start) {
+    return q + 1 < kTopBuckets ? next_start : a.src.b;
   };
   const uint32_t s = ldg<kC>(&m.bucket_start[d]);
-  const uint32_t e_s = bucket_end(d);
+  const uint32_t e_s = end_of(d, ldg<kC>(&m.bucket_start[next_of(d)]));
+  // The digit's range in each fused level, from the level's top-digit index:
+  // uniform loads, all issued before any is used (slots past j read level
+  // 0's index and are ignored).
+  uint32_t dlo[kMaxFuse], dhi[kMaxFuse], dlen[kMaxFuse];
+  if (fused) {
+#pragma unroll
+    for (int q = 0; q < kMaxFuse; ++q) {
+      const uint32_t* dp = f.digit[q < f.nlev ? q : 0];
+      dlo[q] = dp[d];
+      dhi[q] = dp[next_of(d)];
+      dlen[q] = q < f.nlev ? f.len[q] : 0u;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kMaxFuse; ++q) dlo[q] = dhi[q] = dlen[q] = 0u;
+  }
   const uint32_t n = e_s > s ? e_s - s : 0u;
   if (d == 0 && a.skew_out != nullptr) {
-    uint32_t mx = 0;
+    uint32_t lo4[kTopPer], nx4[kTopPer], mx = 0;
 #pragma unroll
     for (int q = 0; q < kTopPer; ++q) {
       const uint32_t dq = tid * kTopPer + q;
-      const uint32_t lo = ldg<kC>(&m.bucket_start[dq]), hi = bucket_end(dq);
-      mx = max(mx, hi > lo ? hi - lo : 0u);
+      lo4[q] = ldg<kC>(&m.bucket_start[dq]);
+      nx4[q] = ldg<kC>(&m.bucket_start[next_of(dq)]);
+    }
+#pragma unroll
+    for (int q = 0; q < kTopPer; ++q) {
+      const uint32_t hi = end_of(tid * kTopPer + q, nx4[q]);
+      mx = max(mx, hi > lo4[q] ? hi - lo4[q] : 0u);
     }
     record_max(mx, a.skew_out, L.tmp);
   }
   if (!fused && a.out_digit != nullptr && tid == 0) a.out_digit[d] = s;
   if (n == 0 && !fused) return;
+
+  // Run starts in the concatenation (the batch's bucket, then each level's
+  // range) and the first output position, computed by every thread (uniform
+  // values); thread 0 also keeps them in LDS for the merge code below.
+  uint32_t lo_q[kMaxFuse], rs_q[kMaxFuse + 2];
+  rs_q[0] = 0;
+  rs_q[1] = n;
+  uint64_t out0 = s;
+  uint32_t T = n;
+#pragma unroll
+  for (int q = 0; q < kMaxFuse; ++q) {
+    const bool on = q < f.nlev;
+    const uint32_t len = dlen[q];
+    const uint32_t lo = dlo[q] < len ? dlo[q] : len;
+    const uint32_t hi_d = d == kTopBuckets - 1 ? len : dhi[q];
+    const uint32_t hi = hi_d < lo ? lo : (hi_d < len ? hi_d : len);
+    lo_q[q] = lo;
+    rs_q[q + 2] = rs_q[q + 1] + (hi - lo);
+    out0 += lo;
+    T += hi - lo;
+    if (on && tid == 0) {
+      L.lo[q] = lo;
+      L.rs[q + 2] = rs_q[q + 2];
+    }
+  }
+  if (fused && tid == 0) {
+    L.rs[0] = 0;
+    L.rs[1] = n;
+    if (f.out_digit != nullptr) f.out_digit[d] = static_cast<uint32_t>(out0);
+  }
+  if (T == 0) return;
+
+  // ---- one load phase.  The batch's bucket goes to buffer 0 (the sort's
+  // input); when all runs fit in LDS, the levels' ranges go to [n, T) of
+  // buf, the buffer the sorted bucket ends in (the rank sort writes buffer
+  // 1, the radix passes alternate from buffer 0).  Up to kLocalCap / kThreads
+  // elements per thread, loads issued unconditionally (clamped position)
+  // before any is stored.
+  const bool rank_path = n <= kRankSortMax;
+  const int buf = (rank_path || (passes & 1)) ? 1 : 0;
+  const uint32_t nl = T <= static_cast<uint32_t>(kLocalCap) ? T
+                      : (n <= static_cast<uint32_t>(kLocalCap) ? n : 0u);
+  // The bits below the top digit: at most 32 - kTopBits, so 8 passes <= 24
+  // and the rank sort's (field << 8) | position fits 32 bits.
+  static_assert(32 - kTopBits <= 3 * kRadixBits, "local passes <= 3");
+  const uint32_t fmask = (kRadixBits * passes >= 24) ? 0xFFFFFFu
+                                                     : ((1u << (kRadixBits * passes)) - 1u);
+  uint32_t* fld = &L.wcnt[0][0];  // rank-sort keys
+  static_assert(kWaves * kRadix >= kRankSortMax + 8, "field scratch");
   const uint32_t* src_k = a.tmp_kv[0] + s;
   const uint32_t* src_v = a.tmp_val[0] + s;
+  if (nl > 0) {
+    constexpr int kPer = kLocalCap / kThreads;
+    uint32_t idx[kPer], rk[kPer], rv[kPer];
+    const uint32_t* pk[kPer];
+    const uint32_t* pv[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const uint32_t x = tid + i * kThreads;
+      idx[i] = x < nl ? x : nl - 1;
+      pk[i] = src_k;
+      pv[i] = src_v;
+    }
+    // Runs past the batch (nl > n only if they all fit): selects, no
+    // branches, so the argument loads of every level are issued together.
+#pragma unroll
+    for (int q = 0; q < kMaxFuse; ++q) {
+      const bool on = q < f.nlev && nl > n;
+      const uint32_t st = rs_q[q + 1], lo = lo_q[q];
+      const uint32_t* qk = f.kv[q];
+      const uint32_t* qv = f.val[q];
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const uint32_t xc = tid + i * kThreads < nl ? tid + i * kThreads : nl - 1;
+        const bool take = on & (xc >= st);
+        idx[i] = take ? xc - st + lo : idx[i];
+        pk[i] = take ? qk : pk[i];
+        pv[i] = take ? qv : pv[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      if (static_cast<uint32_t>(i) * kThreads < nl) {
+        rk[i] = ldg<kC>(pk[i] + idx[i]);
+        rv[i] = ldg<kC>(pv[i] + idx[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const uint32_t x = tid + i * kThreads;
+      if (static_cast<uint32_t>(i) * kThreads < nl && x < nl) {
+        const int to = x < n ? 0 : buf;
+        L.k[to][x] = rk[i];
+        L.v[to][x] = rv[i];
+        if (rank_path && x < n) fld[x] = (((rk[i] >> lo_bit) & fmask) << 8) | x;
+      }
+    }
+    if (rank_path && tid >= n && tid < ((n + 7u) & ~7u)) fld[tid] = 0xFFFFFFFFu;
+  }
+  __syncthreads();  // the loaded runs, fields and L.lo / L.rs
+
+  // ---- sort the batch's bucket.  sorted = true when it ends in LDS buffer
+  // buf, false when it was sorted in global memory (at out_k / out_v).
   uint32_t* out_k = a.out_kv + s;
   uint32_t* out_v = a.out_val + s;
-
-  // ---- sort the batch's bucket; buf = LDS buffer holding it, or -1 when
-  // it was sorted in global memory (at out_k / out_v).
-  int buf = 0;
+  bool sorted_lds = true;
   if (n == 0) {
-    buf = 0;
-  } else if (n <= kRankSortMax) {
-    static_assert(kRankSortMax <= static_cast<uint32_t>(kThreads), "one element per thread");
-    rank_sort<1, kC>(L, src_k, src_v, n, lo_bit, passes);
-    buf = 1;
+  } else if (rank_path) {
+    rank_sort(L, fld, n);
   } else if (n <= static_cast<uint32_t>(kLocalCap)) {
-    for (uint32_t x = tid; x < n; x += kThreads) {
-      L.k[0][x] = ldg<kC>(&src_k[x]);
-      L.v[0][x] = ldg<kC>(&src_v[x]);
-    }
-    __syncthreads();
     int cur = 0;
     for (int p = 0; p < passes; ++p) {
       lds_pass(L, cur, n, lo_bit + kRadixBits * p);
       cur = 1 - cur;
     }
-    buf = cur;
   } else {
-    buf = -1;
+    sorted_lds = false;
     local_sort_streaming<kC>(a, lo_bit, passes, s, n, L);
   }
 
   if (!fused) {
-    if (buf >= 0) {
+    if (sorted_lds) {
       for (uint32_t x = tid; x < n; x += kThreads) {
         const uint32_t k = L.k[buf][x];
         out_k[x] = k;
@@ -1132,52 +1214,13 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
     return;
   }
 
-  // ---- fused cascade: this digit's key range in levels 0..j-1.
-  const int R = f.nlev + 1;  // runs: the batch, then levels 0..j-1
-  if (tid < static_cast<uint32_t>(f.nlev)) {
-    // The digit's range in level l, from the level's top-digit index.
-    const uint32_t l = tid;
-    const uint32_t len = f.len[l];
-    uint32_t lo = f.digit[l][d];
-    uint32_t hi = d == kTopBuckets - 1 ? len : f.digit[l][d + 1];
-    lo = lo < len ? lo : len;
-    hi = hi < lo ? lo : (hi < len ? hi : len);
-    L.lo[l] = lo;
-    L.hi[l] = hi;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint64_t o = s;
-    L.rs[0] = 0;
-    L.rs[1] = n;
-    for (int l = 0; l < f.nlev; ++l) {
-      o += L.lo[l];
-      L.rs[l + 2] = L.rs[l + 1] + (L.hi[l] - L.lo[l]);
-    }
-    L.out_lo = static_cast<uint32_t>(o);
-    L.out_hi = static_cast<uint32_t>(o >> 32);
-    if (f.out_digit != nullptr) f.out_digit[d] = static_cast<uint32_t>(o);
-  }
-  __syncthreads();
-  const uint32_t T = L.rs[R];
-  const uint64_t out0 = (static_cast<uint64_t>(L.out_hi) << 32) | L.out_lo;
-  if (T == 0) return;
-
-  if (buf >= 0 && T <= static_cast<uint32_t>(kLocalCap)) {
+  if (sorted_lds && T <= static_cast<uint32_t>(kLocalCap)) {
     // All runs side by side in buffer buf (the batch's bucket first), then
     // a pairwise cascade in LDS: the accumulated run (newer) and the next
     // level's run (older) are merged into the other buffer.  When the
     // accumulated run sits in the other buffer, the next run is first
     // copied next to it (the same offsets), so the two inputs are always
     // adjacent and the output never overlaps an input still to be read.
-    for (int l = 0; l < f.nlev; ++l) {
-      const uint32_t base = L.rs[l + 1], c = L.rs[l + 2] - L.rs[l + 1], lo = L.lo[l];
-      for (uint32_t x = tid; x < c; x += kThreads) {
-        L.k[buf][base + x] = f.kv[l][lo + x];
-        L.v[buf][base + x] = f.val[l][lo + x];
-      }
-    }
-    __syncthreads();
     int acc = buf;
     for (int q = 1; q < R; ++q) {
       const uint32_t A = L.rs[q], c = L.rs[q + 1] - L.rs[q];
@@ -1205,7 +1248,7 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
 
   // Runs too large for LDS: rank with searches in global memory.  The
   // batch's bucket is put in global scratch first (it may be in LDS).
-  if (buf >= 0) {
+  if (sorted_lds) {
     for (uint32_t x = tid; x < n; x += kThreads) {
       out_k[x] = L.k[buf][x];
       out_v[x] = L.v[buf][x];
