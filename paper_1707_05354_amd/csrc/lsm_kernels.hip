@@ -605,7 +605,7 @@ __device__ __forceinline__ void clear_other_hist(const SortMeta& m) {
     other[i] = 0u;
 }
 
-// Top-digit counts of one tile into tile_cnt[tile].
+// Top-digit counts of one tile into row tile of tile_cnt (16 bits each).
 template <bool kC>
 __device__ void tile_hist(const SortArgs& a, int top_shift, uint32_t tile, uint32_t* s_h) {
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -625,10 +625,23 @@ __device__ void tile_hist(const SortArgs& a, int top_shift, uint32_t tile, uint3
     atomicAdd(&s_h[(kv[i] >> top_shift) & (kTopBuckets - 1)], 1u);
   }
   __syncthreads();
+  // Two 16-bit counts per word (a tile's count is at most kSortTile): thread
+  // t writes the words of digits 4t .. 4t+3.
+  static_assert(kSortTile < 65536 && kTopPer == 4, "packed counts");
+  {
+    const uint32_t d0 = tid * kTopPer;
+    uint32_t* row = m.tile_cnt + static_cast<size_t>(tile) * (kTopBuckets / 2);
+    stg<kC>(&row[2 * tid], s_h[d0] | (s_h[d0 + 1] << 16));
+    stg<kC>(&row[2 * tid + 1], s_h[d0 + 2] | (s_h[d0 + 3] << 16));
+  }
+  // The batch's digit totals accumulate in hist[parity] (zeroed by the
+  // previous sort, which used the other buffer).
+  static_assert(kTopBuckets <= kMaxPasses * kRadix, "totals fit one histogram buffer");
+  uint32_t* tot = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
 #pragma unroll
   for (int q = 0; q < kTopPer; ++q) {
     const uint32_t dg = tid + q * kThreads;
-    stg<kC>(&m.tile_cnt[static_cast<size_t>(tile) * kTopBuckets + dg], s_h[dg]);
+    if (s_h[dg] != 0u) atomicAdd(&tot[dg], s_h[dg]);
   }
   if (a.checked && bad) atomicOr(&m.err[0], 1u);
   __syncthreads();  // s_h may be reused by the caller
@@ -647,6 +660,7 @@ __global__ __launch_bounds__(kThreads) void k_msd_hist(SortArgs a, int top_shift
 // in LDS and written digit-sorted.  The work-group of tile 0 also publishes
 // every bucket's first position.
 struct ScatterLds {
+  uint64_t mask[kWaves][kTopBuckets + 1];  // ranking: lanes per digit, zero between items
   uint32_t kv[kSortTile];
   uint32_t val[kSortTile];
   uint32_t wcnt[kWaves][kTopBuckets];
@@ -655,42 +669,47 @@ struct ScatterLds {
   uint32_t tmp[2 * kWaves];
 };
 
-// Counts of this thread's four digits in a tile (one 16-byte load, or four
-// coherent loads when written by this kernel).
+// Packed counts of this thread's four digits in tile t (one 8-byte load, or
+// two coherent loads when written by this kernel).
 template <bool kC>
-__device__ __forceinline__ uint4 tile_counts(const SortMeta& m, uint32_t t, uint32_t d0) {
-  const uint32_t* p = m.tile_cnt + static_cast<size_t>(t) * kTopBuckets + d0;
-  if constexpr (kC) return make_uint4(ld_dev(p), ld_dev(p + 1), ld_dev(p + 2), ld_dev(p + 3));
-  else return *reinterpret_cast<const uint4*>(p);
+__device__ __forceinline__ uint2 tile_counts(const SortMeta& m, uint32_t t, uint32_t tid) {
+  const uint32_t* p = m.tile_cnt + static_cast<size_t>(t) * (kTopBuckets / 2) + 2 * tid;
+  if constexpr (kC) return make_uint2(ld_dev(p), ld_dev(p + 1));
+  else return *reinterpret_cast<const uint2*>(p);
 }
 
 // Stable ranks of a wave's items among equal digits, item i of every lane
-// after item i - 1 (tile order is item-major within the wave).  The match
-// masks of all items are computed first (no memory traffic); then the leader
-// of each digit group adds the group's size to wcnt[d] with an LDS
-// fetch-and-add, items in order (one wave's LDS operations are applied in
-// issue order), and the leader's old count is broadcast to the group.  wcnt is this
-// wave's own row, so no work-group barrier is needed around the updates.
-template <int kBits, int kN>
+// after item i - 1 (tile order is item-major within the wave).  For each
+// item, every lane ORs its lane bit into mask[d] of the wave's own table,
+// reads the mask back (the lanes of the item with digit d) and clears it;
+// the three LDS operations of all items are issued back to back (one wave's
+// LDS operations are applied in issue order, so each item sees exactly its
+// own lanes).  Invalid items use the spare entry kTopBuckets.  Then the
+// lowest lane of each digit group adds the group's size to wcnt[d] with an
+// LDS fetch-and-add, items in order, and its old count is broadcast to the
+// group.  The tables are this wave's own, so no work-group barrier is
+// needed; mask entries are zero before and after.
+template <int kN>
 __device__ __forceinline__ void wave_rank_items(const uint32_t (&d)[kN], const bool (&valid)[kN],
-                                                uint32_t* wcnt, uint32_t (&off)[kN]) {
+                                                uint64_t* mask, uint32_t* wcnt, uint32_t (&off)[kN]) {
+  const uint32_t lane = lane_id();
+  uint64_t grp[kN];
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    uint64_t* e = &mask[valid[i] ? d[i] : kTopBuckets];
+    __hip_atomic_fetch_or(e, 1ull << lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    grp[i] = *e;
+    *e = 0ull;
+  }
   uint32_t r[kN], lead[kN], size[kN];
 #pragma unroll
   for (int i = 0; i < kN; ++i) {
-    uint64_t peers = ballot(valid[i]);
-#pragma unroll
-    for (int bit = 0; bit < kBits; ++bit) {
-      const bool set = (d[i] >> bit) & 1u;
-      const uint64_t m = ballot(set);
-      peers &= set ? m : ~m;
-    }
-    r[i] = count_below(peers);
-    lead[i] = peers != 0 ? static_cast<uint32_t>(__builtin_ctzll(peers)) : 0u;
-    size[i] = static_cast<uint32_t>(__popcll(peers));
+    r[i] = count_below(grp[i]);
+    lead[i] = static_cast<uint32_t>(__builtin_ctzll(grp[i] | (1ull << 63)));
+    size[i] = static_cast<uint32_t>(__popcll(grp[i]));
   }
   // Every lane issues the add (others add 0, so the leader's old count is the
-  // count before this item whatever order the lanes are applied in); no
-  // branch, so the kN adds are in flight together.
+  // count before this item whatever order the lanes are applied in).
   uint32_t prev[kN];
 #pragma unroll
   for (int i = 0; i < kN; ++i)
@@ -708,46 +727,56 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
   const uint32_t tbase = tile * kSortTile;
   const uint32_t d0 = tid * kTopPer;
   static_assert(kTopPer == 4, "four digits per thread");
-  constexpr int kChunk = 32;  // tiles' counts in flight per round
+  constexpr int kChunk = 16;  // rows of counts in flight per round
   uint32_t kv[kSortItems], val[kSortItems], off[kSortItems], dg[kSortItems], key[kSortItems];
   bool valid[kSortItems];
   tile_items<kSortItems>(a.src, tbase, wave, lane, kv, val, key, valid);
-  // Every tile's counts of this thread's four digits give the sum over
-  // earlier tiles and the total.  The first round of loads is issued before
-  // the ranking below, which needs only the tile's own elements.
-  uint32_t gtot[kTopPer] = {0u, 0u, 0u, 0u}, before[kTopPer] = {0u, 0u, 0u, 0u};
+  // This thread's four digits: the batch totals (hist[parity], summed by
+  // the count kernel) and the sum over earlier tiles, read directly from the
+  // rows of tiles [0, tile) or, for the later half of the tiles, as the total
+  // minus the rows of [tile, ntiles): at most half the rows either way.  The
+  // first round of loads is issued before the ranking below, which needs
+  // only the tile's own elements.
   const uint32_t ntiles = m.num_sort_tiles;
-  uint4 c[kChunk];
-  auto load_chunk = [&](uint32_t t0) {  // unconditional loads (clamped tile index)
+  const uint32_t* tot = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
+  const uint4 gt = kC ? make_uint4(ld_dev(tot + d0), ld_dev(tot + d0 + 1), ld_dev(tot + d0 + 2),
+                                   ld_dev(tot + d0 + 3))
+                      : *reinterpret_cast<const uint4*>(tot + d0);
+  const bool from_end = 2 * tile >= ntiles;
+  const uint32_t r_lo = from_end ? tile : 0u, r_hi = from_end ? ntiles : tile;
+  uint32_t part[kTopPer] = {0u, 0u, 0u, 0u};
+  uint2 c[kChunk];
+  auto load_chunk = [&](uint32_t t0) {  // unconditional loads (clamped row index)
 #pragma unroll
     for (int r = 0; r < kChunk; ++r)
-      c[r] = tile_counts<kC>(m, t0 + r < ntiles ? t0 + r : ntiles - 1, d0);
+      c[r] = tile_counts<kC>(m, t0 + r < r_hi ? t0 + r : ntiles - 1, tid);
   };
   auto add_chunk = [&](uint32_t t0) {
 #pragma unroll
     for (int r = 0; r < kChunk; ++r) {
-      const uint32_t in = t0 + r < ntiles ? ~0u : 0u, early = t0 + r < tile ? ~0u : 0u;
-      gtot[0] += c[r].x & in;
-      gtot[1] += c[r].y & in;
-      gtot[2] += c[r].z & in;
-      gtot[3] += c[r].w & in;
-      before[0] += c[r].x & early;
-      before[1] += c[r].y & early;
-      before[2] += c[r].z & early;
-      before[3] += c[r].w & early;
+      const uint32_t in = t0 + r < r_hi ? ~0u : 0u;
+      part[0] += (c[r].x & 0xFFFFu) & in;
+      part[1] += (c[r].x >> 16) & in;
+      part[2] += (c[r].y & 0xFFFFu) & in;
+      part[3] += (c[r].y >> 16) & in;
     }
   };
-  load_chunk(0);
-  // Rank the tile: each wave clears and fills its own row of wcnt.
+  load_chunk(r_lo);
+  // Rank the tile: each wave clears and fills its own tables.
   for (uint32_t i = lane; i < kTopBuckets; i += 64) S.wcnt[wave][i] = 0u;
+  for (uint32_t i = lane; i <= kTopBuckets; i += 64) S.mask[wave][i] = 0ull;
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) dg[i] = (kv[i] >> top_shift) & (kTopBuckets - 1);
-  wave_rank_items<kTopBits>(dg, valid, S.wcnt[wave], off);
-  add_chunk(0);
-  for (uint32_t t0 = kChunk; t0 < ntiles; t0 += kChunk) {
+  wave_rank_items(dg, valid, S.mask[wave], S.wcnt[wave], off);
+  add_chunk(r_lo);
+  for (uint32_t t0 = r_lo + kChunk; t0 < r_hi; t0 += kChunk) {
     load_chunk(t0);
     add_chunk(t0);
   }
+  const uint32_t gtot[kTopPer] = {gt.x, gt.y, gt.z, gt.w};
+  uint32_t before[kTopPer];
+#pragma unroll
+  for (int q = 0; q < kTopPer; ++q) before[q] = from_end ? gtot[q] - part[q] : part[q];
   __syncthreads();
   uint32_t cnt[kTopPer], tsum = 0, gsum = 0;
 #pragma unroll
@@ -1994,7 +2023,7 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
   m.status = m.hist + static_cast<size_t>(2) * kMaxPasses * kRadix;
   m.tile_ctr = m.status + static_cast<size_t>(kMaxPasses) * m.num_sort_tiles * kRadix;
   m.err = m.tile_ctr + kMaxPasses;
-  m.tile_cnt = m.err + 4;  // 16-byte aligned (vector loads of four counts)
+  m.tile_cnt = m.err + 4;  // 16-byte aligned (vector loads of packed counts)
   m.bucket_start = m.tile_cnt + static_cast<size_t>(m.num_sort_tiles) * kTopBuckets;
   m.bar = m.bucket_start + kTopBuckets;
   m.parity = parity;
