@@ -1428,11 +1428,14 @@ __device__ __forceinline__ uint32_t ring_merge_path(const uint32_t* sa, uint32_t
 
 // Merge of run a (newer) with run b (older) on the original key.  Each
 // work-group produces tiles_per_wg consecutive output tiles.  It finds the
-// split of its first tile with a wave search in global memory, then keeps a
+// splits of its first tile and of the end of its range with two wave
+// searches in global memory (waves 0 and 1, side by side), then keeps a
 // window of each run in LDS ring buffers: a tile's outputs consume la
 // elements of a and n - la of b, and the next tile loads exactly those
-// counts, so every input element is read from HBM once.  Each thread merges
-// kMergeItems consecutive outputs and stores them with 16-byte stores.
+// counts; windows never extend past the work-group's end split, so every
+// input element is read from HBM once.  A window's new elements are all
+// loaded before any is stored.  Each thread merges kMergeItems consecutive
+// outputs and stores them with 16-byte stores.
 template <int kMergeItems>
 __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const uint32_t* a_val,
                                                     uint32_t na, const uint32_t* b_kv,
@@ -1444,7 +1447,7 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
   static_assert((kMergeTile & kMask) == 0, "merge tile must be a power of two");
   static_assert(kMergeItems % 4 == 0, "16-byte stores");
   __shared__ uint32_t sa_k[kMergeTile], sa_v[kMergeTile], sb_k[kMergeTile], sb_v[kMergeTile];
-  __shared__ uint32_t s_split;
+  __shared__ uint32_t s_split, s_split_end;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t total = static_cast<uint64_t>(na) + nb;
   const uint64_t tiles = (total + kMergeTile - 1) / kMergeTile;
@@ -1454,24 +1457,47 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
   if (wave == 0) {
     const uint32_t sp = wave_merge_path(a_kv, na, b_kv, nb, t * kMergeTile);
     if (lane == 0) s_split = sp;
+  } else if (wave == 1) {
+    const uint64_t de = t_end * kMergeTile;
+    const uint32_t sp = de >= total ? na : wave_merge_path(a_kv, na, b_kv, nb, de);
+    if (lane == 0) s_split_end = sp;
   }
   __syncthreads();
   uint32_t a0 = s_split;
   uint32_t b0 = static_cast<uint32_t>(t * kMergeTile - a0);
+  const uint32_t a_lim = s_split_end;  // the work-group consumes a[a0, a_lim), b[b0, b_lim)
+  const uint32_t b_lim = static_cast<uint32_t>(
+      (t_end * kMergeTile < total ? t_end * kMergeTile : total) - a_lim);
   uint32_t a_end = a0, b_end = b0;  // loaded into the rings up to here
+  // New window elements [from, to) of one run into its ring: at most
+  // kMergeTile, so kMergeItems per thread; loads at clamped positions first.
+  auto fill = [&](const uint32_t* gk, const uint32_t* gv, uint32_t from, uint32_t to,
+                  uint32_t* rk_s, uint32_t* rv_s) {
+    if (from >= to) return;
+    uint32_t k[kMergeItems], v[kMergeItems];
+#pragma unroll
+    for (int j = 0; j < kMergeItems; ++j) {
+      const uint32_t x = from + tid + static_cast<uint32_t>(j) * kThreads;
+      const uint32_t xc = x < to ? x : to - 1;
+      k[j] = gk[xc];
+      v[j] = gv[xc];
+    }
+#pragma unroll
+    for (int j = 0; j < kMergeItems; ++j) {
+      const uint32_t x = from + tid + static_cast<uint32_t>(j) * kThreads;
+      if (x < to) {
+        rk_s[x & kMask] = k[j];
+        rv_s[x & kMask] = v[j];
+      }
+    }
+  };
   for (; t < t_end; ++t) {
     const uint64_t d = t * kMergeTile;
     const uint32_t n = static_cast<uint32_t>((total - d) < kMergeTile ? (total - d) : kMergeTile);
-    const uint32_t wa = (na - a0) < n ? (na - a0) : n;
-    const uint32_t wb = (nb - b0) < n ? (nb - b0) : n;
-    for (uint32_t x = a_end + tid; x < a0 + wa; x += kThreads) {
-      sa_k[x & kMask] = a_kv[x];
-      sa_v[x & kMask] = a_val[x];
-    }
-    for (uint32_t x = b_end + tid; x < b0 + wb; x += kThreads) {
-      sb_k[x & kMask] = b_kv[x];
-      sb_v[x & kMask] = b_val[x];
-    }
+    const uint32_t wa = (a_lim - a0) < n ? (a_lim - a0) : n;
+    const uint32_t wb = (b_lim - b0) < n ? (b_lim - b0) : n;
+    fill(a_kv, a_val, a_end, a0 + wa, sa_k, sa_v);
+    fill(b_kv, b_val, b_end, b0 + wb, sb_k, sb_v);
     a_end = (a0 + wa > a_end) ? a0 + wa : a_end;
     b_end = (b0 + wb > b_end) ? b0 + wb : b_end;
     __syncthreads();
