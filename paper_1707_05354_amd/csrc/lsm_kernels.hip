@@ -149,6 +149,13 @@ __device__ __forceinline__ void st_dev64(uint64_t* p, uint64_t v) {
 }
 // Loads and stores of data that other work-groups of the same kernel write
 // or read (kC: device-coherent accesses) or that only later kernels read.
+// A pointer known to address global memory (loads through it are global,
+// not flat, loads).
+__device__ __forceinline__ const __attribute__((address_space(1))) uint32_t* as_global(
+    const uint32_t* p) {
+  return (const __attribute__((address_space(1))) uint32_t*)(p);
+}
+
 template <bool kC>
 __device__ __forceinline__ uint32_t ldg(const uint32_t* p) {
   if constexpr (kC) return ld_dev(p);
@@ -840,6 +847,9 @@ struct alignas(16) LocalLds {
   uint32_t tmp[kWaves];
   uint32_t lo[kMaxFuse];      // fused cascade: start of the digit's range per level
   uint32_t rs[kMaxFuse + 2];  // run starts in the concatenated runs
+  const uint32_t* run_k[kMaxFuse + 1];  // fused load: source of each run
+  const uint32_t* run_v[kMaxFuse + 1];
+  uint32_t run_delta[kMaxFuse + 1];
 };
 
 // One stable counting pass over n <= kLocalCap elements in LDS, from
@@ -1144,11 +1154,13 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   if (T == 0) return;
 
   // ---- one load phase.  The batch's bucket goes to buffer 0 (the sort's
-  // input); when all runs fit in LDS, the levels' ranges go to [n, T) of
-  // buf, the buffer the sorted bucket ends in (the rank sort writes buffer
-  // 1, the radix passes alternate from buffer 0).  Up to kLocalCap / kThreads
-  // elements per thread, loads issued unconditionally (clamped position)
-  // before any is stored.
+  // input); when all runs fit in LDS, level l's range goes to its place in
+  // [n, T) of buffer buf (l even) or 1 - buf (l odd), buf being the buffer
+  // the sorted bucket ends in (the rank sort writes buffer 1, the radix
+  // passes alternate from buffer 0): the cascade below then finds each run
+  // next to the accumulated one.  Up to kLocalCap / kThreads elements per
+  // thread, loads issued unconditionally (clamped position) before any is
+  // stored.
   const bool rank_path = n <= kRankSortMax;
   const int buf = (rank_path || (passes & 1)) ? 1 : 0;
   const uint32_t nl = T <= static_cast<uint32_t>(kLocalCap) ? T
@@ -1162,47 +1174,62 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   static_assert(kWaves * kRadix >= kRankSortMax + 8, "field scratch");
   const uint32_t* src_k = a.tmp_kv[0] + s;
   const uint32_t* src_v = a.tmp_val[0] + s;
+  const bool levels_in_lds = nl > n;  // fused, and all runs fit
+  if (levels_in_lds) {
+    // Run table: run 0 is the batch's bucket, run q + 1 level q; element x
+    // of run r is source position x + delta[r].
+    if (tid == 0) {
+      L.run_k[0] = src_k;
+      L.run_v[0] = src_v;
+      L.run_delta[0] = 0;
+#pragma unroll
+      for (int q = 0; q < kMaxFuse; ++q) {
+        if (q < f.nlev) {
+          L.run_k[q + 1] = f.kv[q];
+          L.run_v[q + 1] = f.val[q];
+          L.run_delta[q + 1] = lo_q[q] - rs_q[q + 1];
+        }
+      }
+    }
+    __syncthreads();
+  }
   if (nl > 0) {
     constexpr int kPer = kLocalCap / kThreads;
-    uint32_t idx[kPer], rk[kPer], rv[kPer];
-    const uint32_t* pk[kPer];
-    const uint32_t* pv[kPer];
+    uint32_t rk[kPer], rv[kPer], run[kPer];
+    // Each element's run (the number of level starts at or below it),
+    // then its source from the run table; loads issued before any store.
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const uint32_t x = tid + i * kThreads;
-      idx[i] = x < nl ? x : nl - 1;
-      pk[i] = src_k;
-      pv[i] = src_v;
-    }
-    // Runs past the batch (nl > n only if they all fit): selects, no
-    // branches, so the argument loads of every level are issued together.
+      const uint32_t xc = x < nl ? x : nl - 1;
+      run[i] = 0;
+      if (levels_in_lds) {
 #pragma unroll
-    for (int q = 0; q < kMaxFuse; ++q) {
-      const bool on = q < f.nlev && nl > n;
-      const uint32_t st = rs_q[q + 1], lo = lo_q[q];
-      const uint32_t* qk = f.kv[q];
-      const uint32_t* qv = f.val[q];
-#pragma unroll
-      for (int i = 0; i < kPer; ++i) {
-        const uint32_t xc = tid + i * kThreads < nl ? tid + i * kThreads : nl - 1;
-        const bool take = on & (xc >= st);
-        idx[i] = take ? xc - st + lo : idx[i];
-        pk[i] = take ? qk : pk[i];
-        pv[i] = take ? qv : pv[i];
+        for (int q = 1; q <= kMaxFuse; ++q) run[i] += (q <= f.nlev && xc >= rs_q[q]) ? 1u : 0u;
       }
     }
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       if (static_cast<uint32_t>(i) * kThreads < nl) {
-        rk[i] = ldg<kC>(pk[i] + idx[i]);
-        rv[i] = ldg<kC>(pv[i] + idx[i]);
+        const uint32_t x = tid + i * kThreads;
+        const uint32_t xc = x < nl ? x : nl - 1;
+        const uint32_t* pk = levels_in_lds ? L.run_k[run[i]] : src_k;
+        const uint32_t* pv = levels_in_lds ? L.run_v[run[i]] : src_v;
+        const uint32_t at = xc + (levels_in_lds ? L.run_delta[run[i]] : 0u);
+        if constexpr (kC) {
+          rk[i] = ld_dev(pk + at);
+          rv[i] = ld_dev(pv + at);
+        } else {
+          rk[i] = as_global(pk)[at];
+          rv[i] = as_global(pv)[at];
+        }
       }
     }
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const uint32_t x = tid + i * kThreads;
       if (static_cast<uint32_t>(i) * kThreads < nl && x < nl) {
-        const int to = x < n ? 0 : buf;
+        const int to = x < n ? 0 : ((run[i] & 1u) ? buf : 1 - buf);
         L.k[to][x] = rk[i];
         L.v[to][x] = rv[i];
         if (rank_path && x < n) fld[x] = (((rk[i] >> lo_bit) & fmask) << 8) | x;
@@ -1244,22 +1271,13 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   }
 
   if (sorted_lds && T <= static_cast<uint32_t>(kLocalCap)) {
-    // All runs side by side in buffer buf (the batch's bucket first), then
-    // a pairwise cascade in LDS: the accumulated run (newer) and the next
-    // level's run (older) are merged into the other buffer.  When the
-    // accumulated run sits in the other buffer, the next run is first
-    // copied next to it (the same offsets), so the two inputs are always
-    // adjacent and the output never overlaps an input still to be read.
+    // A pairwise cascade in LDS: the accumulated run (newer, [0, rs[q]))
+    // and the next level's run (older, [rs[q], rs[q + 1]), loaded into the
+    // same buffer) are merged into [0, rs[q + 1]) of the other buffer, which
+    // holds no run still to be read there.
     int acc = buf;
     for (int q = 1; q < R; ++q) {
       const uint32_t A = L.rs[q], c = L.rs[q + 1] - L.rs[q];
-      if (acc != buf) {
-        for (uint32_t x = tid; x < c; x += kThreads) {
-          L.k[acc][A + x] = L.k[buf][A + x];
-          L.v[acc][A + x] = L.v[buf][A + x];
-        }
-        __syncthreads();
-      }
       lds_merge_pair(L.k[acc], L.v[acc], A, c, L.k[1 - acc], L.v[1 - acc]);
       acc = 1 - acc;
     }
