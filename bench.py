@@ -332,9 +332,11 @@ def serving_form(torch, L, W, n_requests: int = 40000, loads=(0.25, 0.5, 0.75, 0
     Poisson arrivals of mixed requests (50% lookup, 10% count, 10% range of
     width 256 (~32 hits), 25% insert, 5% delete; sizes log-uniform in
     [1, 8192]), served by the continuous-batching loop.  First a saturation
-    run (everything arrived at t = 0) gives the capacity; then offered loads
-    at the given fractions of it.  Reports throughput and p50/p99 request
-    latency (completion - arrival) per point."""
+    run (everything arrived at t = 0) gives the capacity, once with full
+    batches launched kernel by kernel and once replayed as hipGraphs; the
+    faster mode serves the offered loads at the given fractions of it.
+    Reports throughput and p50/p99 request latency (completion - arrival)
+    per point."""
     from paper_1707_05354_amd import serving as S
 
     b, R = 1 << 16, 4096
@@ -347,7 +349,6 @@ def serving_form(torch, L, W, n_requests: int = 40000, loads=(0.25, 0.5, 0.75, 0
     log("serving: resident %d pairs, %d requests (%d ops) ready in %.1f s"
         % (R * b, n_requests, int(reqs.size.sum()), time.perf_counter() - t0))
     g = L.LSM(b)
-    g.use_graphs(True)
     lib, h = g._lib, g._h
     rows_k = [kd[i].data_ptr() for i in range(R)]
     rows_v = [vd[i].data_ptr() for i in range(R)]
@@ -370,10 +371,22 @@ def serving_form(torch, L, W, n_requests: int = 40000, loads=(0.25, 0.5, 0.75, 0
 
     t1 = time.perf_counter()
     reqs.t_arrive = np.zeros_like(base_t)
-    res, span = serve(False)
+    sat_by_mode = {}
+    for graphs in (False, True):
+        g.use_graphs(graphs)
+        if graphs:
+            serve(False)  # first run captures the graphs
+        res, span = serve(False)
+        sat_by_mode[graphs] = (res, span)
+    use_graphs = sat_by_mode[True][1] < sat_by_mode[False][1]
+    res, span = sat_by_mode[use_graphs]
+    g.use_graphs(use_graphs)
     cap_rps = n_requests / span
     sat = {"offered_rps": None, "throughput_rps": round(cap_rps), "M_ops_per_s": round(res.ops / span / 1e6, 2),
-           **{k: round(v, 3) for k, v in S.percentiles(res.latency_s).items()}, "epochs": len(res.epochs)}
+           **{k: round(v, 3) for k, v in S.percentiles(res.latency_s).items()}, "epochs": len(res.epochs),
+           "graphs": use_graphs,
+           "M_ops_per_s_no_graphs": round(res.ops / sat_by_mode[False][1] / 1e6, 2),
+           "M_ops_per_s_graphs": round(res.ops / sat_by_mode[True][1] / 1e6, 2)}
     log("serving saturation: %s" % sat)
     points = [dict(sat, load="saturation")]
     for f in loads:

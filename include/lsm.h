@@ -195,12 +195,12 @@ LSM_API lsm_status_t lsm_set_fusion(lsm_t h, int max_levels);
 
 /*
  * lsm_set_sort_path -- which batch sort runs (all give the same order, so
- * results never depend on it).  LSM_SORT_TOP_DIGIT: one scatter on the top
- * 10 bits of the key variable into 1024 buckets, then each bucket sorted in
- * LDS by one work-group (batches of at most 2^20 elements; larger ones use
- * digit passes).  LSM_SORT_ONE_KERNEL: the same sort (and its fused
- * cascade) as one kernel of 256 work-groups with two device-wide barriers
- * instead of three kernels.  LSM_SORT_DIGIT_PASSES: one stable counting pass
+ * results never depend on it).  LSM_SORT_TOP_DIGIT: each tile of 2048
+ * grouped in place by the top 10 bits of the key variable, then each of the
+ * 1024 buckets gathered from every tile and sorted in LDS by one work-group
+ * (batches of at most 2^19 elements; larger ones use digit passes).
+ * LSM_SORT_ONE_KERNEL: the same sort (and its fused cascade) as one kernel
+ * of 256 work-groups with one device-wide barrier instead of two kernels.  LSM_SORT_DIGIT_PASSES: one stable counting pass
  * per 8-bit digit with decoupled look-back.  LSM_SORT_AUTO (the default):
  * the top-digit sort unless the previous sort saw a top-digit bucket above
  * 2048 elements (skewed keys, where one work-group would sort a large bucket
@@ -395,9 +395,10 @@ LSM_API lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out);
  *
  * Kernel index k: 0 batch-sort histogram (digit-pass path), 1 batch-sort
  * digit pass, 2 level merge, 3 lookup, 4 count, 5 range offset scan, 6 range
- * emission, 7 successor / predecessor, 8 cleanup mark-and-compact, 9 / 10 /
- * 11 the top-digit sort's histogram, scatter and per-bucket sort, 12 the
- * top-digit sort as one kernel.
+ * emission, 7 successor / predecessor, 8 cleanup mark-and-compact, 9 not
+ * used (no kernel of this library is counted there), 10 / 11 the top-digit
+ * sort's tile scatter and per-bucket sort, 12 the top-digit sort as one
+ * kernel.
  * kernel_bytes[k] is the algorithmic traffic of those launches: 4 B per
  * batch element for a histogram (keys read), 16 B per element for a digit
  * pass, the top-digit scatter and the per-bucket sort (key and value read

@@ -506,7 +506,7 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
   for (int p = 0; p < nk && timed; ++p) {
     const double bytes = (sa.fuse.nlev > 0 && p == nk - 1)
                              ? 16.0 * static_cast<double>(level_len(h, sa.fuse.nlev))
-                             : sort_kernel_bytes_per_elem(p) * h->b;
+                             : sort_kernel_bytes_per_elem(sa.path, p) * h->b;
     const KTimer* t = timer(h, st[p], sort_kernel_kind(sa.path, p, sa.onepass), h->b, bytes);
     if (t == nullptr) timed = false;
     else sort_t[p] = *t;
@@ -878,7 +878,7 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
     bool timed = h->prof;
     for (int x = 0; x < nk && timed; ++x) {
       const KTimer* t = timer(h, ts[x], sort_kernel_kind(sa.path, x, sa.onepass), len,
-                              sort_kernel_bytes_per_elem(x) * len);
+                              sort_kernel_bytes_per_elem(sa.path, x) * len);
       if (t == nullptr) timed = false;
       else tt[x] = *t;
     }

@@ -21,11 +21,11 @@ constexpr int kSortTile = kThreads * kSortItems;
 constexpr int kMaxPasses = 4;
 // The histogram kernel uses at most this many work-groups (tile-strided).
 constexpr int kMaxHistBlocks = 512;
-// Batches of at most kMsdMaxTiles tiles use the three-kernel top-digit sort:
-// a scatter on the top kTopBits bits into kTopBuckets buckets, then one
-// work-group per bucket.  Buckets (and fused runs) of up to kLocalCap
-// elements are sorted and merged in LDS.
-constexpr int kMsdMaxTiles = 512;
+// Batches of at most kMsdMaxTiles tiles use the two-kernel top-digit sort:
+// each tile grouped in place by its top kTopBits bits, then one work-group
+// per top-digit bucket gathers its group from every tile.  Buckets (and
+// fused runs) of up to kLocalCap elements are sorted and merged in LDS.
+constexpr int kMsdMaxTiles = 256;
 constexpr int kTopBits = 10;
 constexpr uint32_t kTopBuckets = 1u << kTopBits;
 constexpr int kTopPer = static_cast<int>(kTopBuckets) / kThreads;  // buckets per thread
@@ -99,15 +99,16 @@ struct BatchSrc {
 
 // Sort scratch layout (uint32 words) for a batch of b elements.  The global
 // digit histogram is double-buffered: a sort accumulates into hist[parity]
-// and clears hist[parity ^ 1] for the next sort (both start zeroed).
+// and clears hist[parity ^ 1] for the next sort (both start zeroed).  The
+// top-digit sort keeps its batch digit totals in hist[parity] too.
 struct SortMeta {
   uint32_t* hist;         // [2][kMaxPasses][256]
   uint32_t* status;       // [kMaxPasses][num_sort_tiles][256] look-back words
   uint32_t* tile_ctr;     // [kMaxPasses] dynamic tile ids of each pass
   uint32_t* err;          // [0] key-range violation (checked mode),
                           // [1] sticky device fault (a bounded wait expired)
-  uint32_t* tile_cnt;     // [num_sort_tiles][kTopBuckets] top-digit counts (top-digit sort)
-  uint32_t* bucket_start; // [kTopBuckets] first position of each top-digit bucket
+  uint32_t* tile_cnt;     // [num_sort_tiles][kTopBuckets / 2] each tile's digit-group starts
+                          // (top-digit sort; two 16-bit starts per word)
   uint32_t* bar;          // [2] grid barrier of the one-kernel top-digit sort
   uint32_t num_sort_tiles;
   int parity;
@@ -194,10 +195,12 @@ constexpr uint32_t kOnePassGrid = 256;
 // launches (launch_sort's order).
 inline int sort_kernel_kind(int path, int x, int onepass = 0) {
   if (path == kSortMsd && onepass) return kKOnePass;
-  if (path == kSortMsd) return x == 0 ? kKMsdHist : (x == 1 ? kKMsdScatter : kKLocalSort);
+  if (path == kSortMsd) return x == 0 ? kKMsdScatter : kKLocalSort;
   return x == 0 ? kKSortHist : kKSortPass;
 }
-inline double sort_kernel_bytes_per_elem(int x) { return x == 0 ? 4.0 : 16.0; }
+inline double sort_kernel_bytes_per_elem(int path, int x) {
+  return (path == kSortLsd && x == 0) ? 4.0 : 16.0;
+}
 
 // Destination of cleanup's redistribution: the occupied levels of the new
 // batch count, smallest first; level l receives the list positions

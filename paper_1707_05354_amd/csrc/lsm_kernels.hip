@@ -10,9 +10,9 @@
 //       look-back.  The batch is read back to front, so among equal key
 //       variables the later batch position comes first (the last duplicate
 //       wins), and padded with copies of its last element (sec. IV-A).
-//   k_msd_hist / k_msd_scatter / k_local_sort : the same stable order for
-//       batches of at most 512 tiles: one scatter on the top digit, then one
-//       work-group sorts each top-digit bucket in LDS.
+//   k_msd_scatter / k_local_sort : the same stable order for batches of at
+//       most 256 tiles: each tile grouped by its top digit in place, then one
+//       work-group gathers and sorts each top-digit bucket in LDS.
 //   Every kernel that writes a level also writes its fences (the original
 //       key of every 32nd element), which the searches use first.
 //   k_merge : merge of a newer run with an older run on the original key,
@@ -490,7 +490,6 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(SortArgs a) {
   __shared__ uint32_t s_h[kMaxPasses * kRadix];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const SortMeta& m = a.meta;
-  const uint32_t b = a.src.b;
   const size_t gthreads = static_cast<size_t>(gridDim.x) * kThreads;
   const size_t gid = static_cast<size_t>(blockIdx.x) * kThreads + tid;
   const size_t nstatus = static_cast<size_t>(a.passes) * m.num_sort_tiles * kRadix;
@@ -612,79 +611,6 @@ __device__ __forceinline__ void clear_other_hist(const SortMeta& m) {
     other[i] = 0u;
 }
 
-// Top-digit counts of one tile into row tile of tile_cnt (16 bits each).
-template <bool kC>
-__device__ void tile_hist(const SortArgs& a, int top_shift, uint32_t tile, uint32_t* s_h) {
-  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const SortMeta& m = a.meta;
-  const uint32_t b = a.src.b;
-#pragma unroll
-  for (int q = 0; q < kTopPer; ++q) s_h[tid + q * kThreads] = 0u;
-  uint32_t kv[kSortItems], key[kSortItems], val[kSortItems];
-  bool valid[kSortItems];
-  tile_items<kSortItems>(a.src, tile * kSortTile, wave, lane, kv, val, key, valid);
-  __syncthreads();
-  bool bad = false;
-#pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    if (!valid[i]) continue;
-    if (a.checked) bad |= (key[i] >> a.key_limit_bits) != 0u;
-    atomicAdd(&s_h[(kv[i] >> top_shift) & (kTopBuckets - 1)], 1u);
-  }
-  __syncthreads();
-  // Two 16-bit counts per word (a tile's count is at most kSortTile): thread
-  // t writes the words of digits 4t .. 4t+3.
-  static_assert(kSortTile < 65536 && kTopPer == 4, "packed counts");
-  {
-    const uint32_t d0 = tid * kTopPer;
-    uint32_t* row = m.tile_cnt + static_cast<size_t>(tile) * (kTopBuckets / 2);
-    stg<kC>(&row[2 * tid], s_h[d0] | (s_h[d0 + 1] << 16));
-    stg<kC>(&row[2 * tid + 1], s_h[d0 + 2] | (s_h[d0 + 3] << 16));
-  }
-  // The batch's digit totals accumulate in hist[parity] (zeroed by the
-  // previous sort, which used the other buffer).
-  static_assert(kTopBuckets <= kMaxPasses * kRadix, "totals fit one histogram buffer");
-  uint32_t* tot = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
-#pragma unroll
-  for (int q = 0; q < kTopPer; ++q) {
-    const uint32_t dg = tid + q * kThreads;
-    if (s_h[dg] != 0u) atomicAdd(&tot[dg], s_h[dg]);
-  }
-  if (a.checked && bad) atomicOr(&m.err[0], 1u);
-  __syncthreads();  // s_h may be reused by the caller
-}
-
-__global__ __launch_bounds__(kThreads) void k_msd_hist(SortArgs a, int top_shift) {
-  __shared__ uint32_t s_h[kTopBuckets];
-  clear_other_hist(a.meta);
-  tile_hist<false>(a, top_shift, blockIdx.x, s_h);
-}
-
-// Stable scatter of one tile on the top digit.  Thread t owns the digits
-// [kTopPer t, kTopPer t + kTopPer).  A digit's output base is the number of
-// batch elements with a smaller digit (scan of the digit totals, summed from
-// every tile's counts) plus its elements in earlier tiles; the tile is ranked
-// in LDS and written digit-sorted.  The work-group of tile 0 also publishes
-// every bucket's first position.
-struct ScatterLds {
-  uint64_t mask[kWaves][kTopBuckets + 1];  // ranking: lanes per digit, zero between items
-  uint32_t kv[kSortTile];
-  uint32_t val[kSortTile];
-  uint32_t wcnt[kWaves][kTopBuckets];
-  uint32_t local[kTopBuckets];
-  uint32_t gbase[kTopBuckets];
-  uint32_t tmp[2 * kWaves];
-};
-
-// Packed counts of this thread's four digits in tile t (one 8-byte load, or
-// two coherent loads when written by this kernel).
-template <bool kC>
-__device__ __forceinline__ uint2 tile_counts(const SortMeta& m, uint32_t t, uint32_t tid) {
-  const uint32_t* p = m.tile_cnt + static_cast<size_t>(t) * (kTopBuckets / 2) + 2 * tid;
-  if constexpr (kC) return make_uint2(ld_dev(p), ld_dev(p + 1));
-  else return *reinterpret_cast<const uint2*>(p);
-}
-
 // Stable ranks of a wave's items among equal digits, item i of every lane
 // after item i - 1 (tile order is item-major within the wave).  For each
 // item, every lane ORs its lane bit into mask[d] of the wave's own table,
@@ -726,6 +652,24 @@ __device__ __forceinline__ void wave_rank_items(const uint32_t (&d)[kN], const b
                                                                       static_cast<int>(lead[i]), 64)) + r[i];
 }
 
+// Stable scatter of one tile on the top digit, tile-major: the tile's
+// elements, grouped by digit (stable within a digit), go back to the tile's
+// own range of tmp_kv[0] / tmp_val[0] with coalesced writes.  The tile also
+// records where each digit's group starts (two 16-bit starts per word; a
+// tile holds at most kSortTile elements) and adds its digit counts into the
+// batch totals hist[parity] (zeroed by the previous sort, which used the
+// other buffer).  A bucket's elements are then its digit's group in every
+// tile, in tile order.  Thread t owns the digits [kTopPer t, kTopPer t +
+// kTopPer).
+struct ScatterLds {
+  uint64_t mask[kWaves][kTopBuckets + 1];  // ranking: lanes per digit, zero between items
+  uint32_t kv[kSortTile];
+  uint32_t val[kSortTile];
+  uint32_t wcnt[kWaves][kTopBuckets];
+  uint32_t local[kTopBuckets];
+  uint32_t tmp[2 * kWaves];
+};
+
 template <bool kC>
 __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, ScatterLds& S) {
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -733,59 +677,23 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
   const uint32_t b = a.src.b;
   const uint32_t tbase = tile * kSortTile;
   const uint32_t d0 = tid * kTopPer;
-  static_assert(kTopPer == 4, "four digits per thread");
-  constexpr int kChunk = 16;  // rows of counts in flight per round
+  static_assert(kTopPer == 4 && kSortTile < 65536, "four digits per thread, 16-bit starts");
   uint32_t kv[kSortItems], val[kSortItems], off[kSortItems], dg[kSortItems], key[kSortItems];
   bool valid[kSortItems];
   tile_items<kSortItems>(a.src, tbase, wave, lane, kv, val, key, valid);
-  // This thread's four digits: the batch totals (hist[parity], summed by
-  // the count kernel) and the sum over earlier tiles, read directly from the
-  // rows of tiles [0, tile) or, for the later half of the tiles, as the total
-  // minus the rows of [tile, ntiles): at most half the rows either way.  The
-  // first round of loads is issued before the ranking below, which needs
-  // only the tile's own elements.
-  const uint32_t ntiles = m.num_sort_tiles;
-  const uint32_t* tot = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
-  const uint4 gt = kC ? make_uint4(ld_dev(tot + d0), ld_dev(tot + d0 + 1), ld_dev(tot + d0 + 2),
-                                   ld_dev(tot + d0 + 3))
-                      : *reinterpret_cast<const uint4*>(tot + d0);
-  const bool from_end = 2 * tile >= ntiles;
-  const uint32_t r_lo = from_end ? tile : 0u, r_hi = from_end ? ntiles : tile;
-  uint32_t part[kTopPer] = {0u, 0u, 0u, 0u};
-  uint2 c[kChunk];
-  auto load_chunk = [&](uint32_t t0) {  // unconditional loads (clamped row index)
-#pragma unroll
-    for (int r = 0; r < kChunk; ++r)
-      c[r] = tile_counts<kC>(m, t0 + r < r_hi ? t0 + r : ntiles - 1, tid);
-  };
-  auto add_chunk = [&](uint32_t t0) {
-#pragma unroll
-    for (int r = 0; r < kChunk; ++r) {
-      const uint32_t in = t0 + r < r_hi ? ~0u : 0u;
-      part[0] += (c[r].x & 0xFFFFu) & in;
-      part[1] += (c[r].x >> 16) & in;
-      part[2] += (c[r].y & 0xFFFFu) & in;
-      part[3] += (c[r].y >> 16) & in;
-    }
-  };
-  load_chunk(r_lo);
   // Rank the tile: each wave clears and fills its own tables.
   for (uint32_t i = lane; i < kTopBuckets; i += 64) S.wcnt[wave][i] = 0u;
   for (uint32_t i = lane; i <= kTopBuckets; i += 64) S.mask[wave][i] = 0ull;
+  bool bad = false;
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) dg[i] = (kv[i] >> top_shift) & (kTopBuckets - 1);
-  wave_rank_items(dg, valid, S.mask[wave], S.wcnt[wave], off);
-  add_chunk(r_lo);
-  for (uint32_t t0 = r_lo + kChunk; t0 < r_hi; t0 += kChunk) {
-    load_chunk(t0);
-    add_chunk(t0);
+  for (int i = 0; i < kSortItems; ++i) {
+    dg[i] = (kv[i] >> top_shift) & (kTopBuckets - 1);
+    if (a.checked && valid[i]) bad |= (key[i] >> a.key_limit_bits) != 0u;
   }
-  const uint32_t gtot[kTopPer] = {gt.x, gt.y, gt.z, gt.w};
-  uint32_t before[kTopPer];
-#pragma unroll
-  for (int q = 0; q < kTopPer; ++q) before[q] = from_end ? gtot[q] - part[q] : part[q];
+  if (a.checked && bad) atomicOr(&m.err[0], 1u);
+  wave_rank_items(dg, valid, S.mask[wave], S.wcnt[wave], off);
   __syncthreads();
-  uint32_t cnt[kTopPer], tsum = 0, gsum = 0;
+  uint32_t cnt[kTopPer], tsum = 0;
 #pragma unroll
   for (int q = 0; q < kTopPer; ++q) {
     uint32_t x[kWaves];
@@ -799,18 +707,23 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
     }
     cnt[q] = run;
     tsum += run;
-    gsum += gtot[q];
   }
-  uint32_t lrun = tsum, grun = gsum;
-  block_excl_scan2(lrun, grun, S.tmp);
+  uint32_t lrun = block_excl_scan(tsum, S.tmp);
+  uint32_t start[kTopPer];
 #pragma unroll
   for (int q = 0; q < kTopPer; ++q) {
+    start[q] = lrun;
     S.local[d0 + q] = lrun;
-    S.gbase[d0 + q] = grun + before[q];
-    if (tile == 0) stg<kC>(&m.bucket_start[d0 + q], grun);
     lrun += cnt[q];
-    grun += gtot[q];
   }
+  uint32_t* row = m.tile_cnt + static_cast<size_t>(tile) * (kTopBuckets / 2);
+  stg<kC>(&row[2 * tid], start[0] | (start[1] << 16));
+  stg<kC>(&row[2 * tid + 1], start[2] | (start[3] << 16));
+  uint32_t* tot = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
+  static_assert(kTopBuckets <= kMaxPasses * kRadix, "totals fit one histogram buffer");
+#pragma unroll
+  for (int q = 0; q < kTopPer; ++q)
+    if (cnt[q] != 0u) atomicAdd(&tot[d0 + q], cnt[q]);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
@@ -824,19 +737,15 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
   __syncthreads();
   const uint32_t tile_n = (b - tbase) < static_cast<uint32_t>(kSortTile) ? (b - tbase) : kSortTile;
   for (uint32_t x = tid; x < tile_n; x += kThreads) {
-    const uint32_t k = S.kv[x];
-    const uint32_t dd = (k >> top_shift) & (kTopBuckets - 1);
-    const uint32_t o = S.gbase[dd] + (x - S.local[dd]);
-    if (o < b) {
-      stg<kC>(&a.tmp_kv[0][o], k);
-      stg<kC>(&a.tmp_val[0][o], S.val[x]);
-    }
+    stg<kC>(&a.tmp_kv[0][tbase + x], S.kv[x]);
+    stg<kC>(&a.tmp_val[0][tbase + x], S.val[x]);
   }
   __syncthreads();  // the caller may reuse S
 }
 
 __global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_shift) {
   __shared__ ScatterLds S;
+  clear_other_hist(a.meta);
   tile_scatter<false>(a, top_shift, blockIdx.x, S);
 }
 
@@ -844,7 +753,7 @@ struct alignas(16) LocalLds {
   uint32_t k[2][kLocalCap];
   uint32_t v[2][kLocalCap];
   uint32_t wcnt[kWaves][kRadix];
-  uint32_t tmp[kWaves];
+  uint32_t tmp[2 * kWaves + 2];  // scans; then the bucket's start and size
   uint32_t lo[kMaxFuse];      // fused cascade: start of the digit's range per level
   uint32_t rs[kMaxFuse + 2];  // run starts in the concatenated runs
   const uint32_t* run_k[kMaxFuse + 1];  // fused load: source of each run
@@ -892,43 +801,49 @@ __device__ void lds_pass(LocalLds& L, int from, uint32_t n, int shift) {
   __syncthreads();
 }
 
-// Bucket d (= blockIdx.x) of the MSD scatter, sorted on the digits below
-// the top one; written to the sort output at the bucket's own range.
-// Stable passes over a bucket too large for LDS, streaming through the
-// bucket's range chunk by chunk in order and ping-ponging between the two
-// scratch buffers; the last pass writes out_kv / out_val at s.
+// Stable passes over a bucket too large for LDS.  The bucket is first
+// gathered from the tile-major scatter (group table segb / segp over ntiles
+// tiles) into one of two global buffers at the bucket's own range: the
+// output (out_kv at s) or the second scratch buffer (tmp_kv[1] at s), chosen
+// so that the passes, ping-ponging between the two, end in the output.
+// Nothing else reads either range.
 template <bool kC>
 __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, uint32_t s,
-                                     uint32_t n, LocalLds& L) {
+                                     uint32_t n, LocalLds& L, const uint32_t* segb,
+                                     const uint32_t* segp, uint32_t ntiles) {
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t* src_k = a.tmp_kv[0] + s;
-  const uint32_t* src_v = a.tmp_val[0] + s;
-  uint32_t* out_k = a.out_kv + s;
-  uint32_t* out_v = a.out_val + s;
-  if (passes == 0) {
-    for (uint32_t x = tid; x < n; x += kThreads) {
-      const uint32_t k = ldg<kC>(&src_k[x]);
-      out_k[x] = k;
-      out_v[x] = ldg<kC>(&src_v[x]);
-      put_fence(a.out_fence, a.src.b, s + x, k);
+  uint32_t* bk[2] = {a.out_kv + s, a.tmp_kv[1] + s};
+  uint32_t* bv[2] = {a.out_val + s, a.tmp_val[1] + s};
+  const int first = passes & 1;
+  for (uint32_t x = tid; x < n; x += kThreads) {
+    uint32_t g = 0;
+    for (uint32_t step = 1u << (31 - __builtin_clz(ntiles)); step > 0; step >>= 1) {
+      const uint32_t probe = g + step;
+      if (probe < ntiles && segp[probe] <= x) g = probe;
     }
-    return;
+    const uint32_t at = segb[g] + (x - segp[g]);
+    const uint32_t k = ldg<kC>(&a.tmp_kv[0][at]);
+    bk[first][x] = k;
+    bv[first][x] = ldg<kC>(&a.tmp_val[0][at]);
+    if (passes == 0) put_fence(a.out_fence, a.src.b, s + x, k);
   }
+  if (passes == 0) return;
+  __threadfence_block();
+  __syncthreads();
   uint32_t* run = L.k[0];       // running output position per digit
   uint32_t* chunk_cnt = L.k[1];
   for (int p = 0; p < passes; ++p) {
     const int shift = lo_bit + kRadixBits * p;
-    const uint32_t* ik = ((p & 1) == 0 ? a.tmp_kv[0] : a.tmp_kv[1]) + s;
-    const uint32_t* iv = ((p & 1) == 0 ? a.tmp_val[0] : a.tmp_val[1]) + s;
-    uint32_t* ok = (p == passes - 1) ? out_k : ((p & 1) == 0 ? a.tmp_kv[1] : a.tmp_kv[0]) + s;
-    uint32_t* ov = (p == passes - 1) ? out_v : ((p & 1) == 0 ? a.tmp_val[1] : a.tmp_val[0]) + s;
+    const int cur = first ^ (p & 1);  // the last pass writes buffer 0, the output
+    const uint32_t* ik = bk[cur];
+    const uint32_t* iv = bv[cur];
+    uint32_t* ok = bk[cur ^ 1];
+    uint32_t* ov = bv[cur ^ 1];
     run[tid] = 0u;
     __syncthreads();
-    // Pass 0 reads the scattered batch (written by other work-groups when
-    // the whole sort is one kernel); later passes read this work-group's own
-    // writes.
+    // Every pass reads this work-group's own writes.
     for (uint32_t x = tid; x < n; x += kThreads) {
-      const uint32_t k = (p == 0) ? ldg<kC>(&ik[x]) : ik[x];
+      const uint32_t k = ik[x];
       atomicAdd(&run[(k >> shift) & (kRadix - 1)], 1u);
     }
     __syncthreads();
@@ -941,8 +856,8 @@ __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, 
 #pragma unroll
       for (int i = 0; i < kSortItems; ++i) {
         const uint32_t e = cb + tile_pos(wave, i, lane);
-        kv[i] = e < n ? ((p == 0) ? ldg<kC>(&ik[e]) : ik[e]) : 0u;
-        vv[i] = e < n ? ((p == 0) ? ldg<kC>(&iv[e]) : iv[e]) : 0u;
+        kv[i] = e < n ? ik[e] : 0u;
+        vv[i] = e < n ? iv[e] : 0u;
       }
       for (uint32_t i = tid; i < kWaves * kRadix; i += kThreads) (&L.wcnt[0][0])[i] = 0u;
       __syncthreads();
@@ -1077,16 +992,21 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   const FuseArgs& f = a.fuse;
   const bool fused = f.nlev > 0;
   const int R = f.nlev + 1;  // runs: the batch, then levels 0..j-1
-  // Bucket d spans [start[d], start[d + 1]) of the scattered batch, the last
-  // one ending at b.  Every load of this prologue is issued unconditionally
-  // (clamped index), so the bounds, the skew hint's bounds and the levels'
-  // digit ranges are in flight together.
+  // Bucket d is digit d's group in every tile of the tile-major scatter, in
+  // tile order; its sorted output starts at s, the number of batch elements
+  // with a smaller digit.  Every load of this prologue is issued
+  // unconditionally (clamped index), so the batch totals, each tile's group
+  // bounds and the levels' digit ranges are in flight together.
   auto next_of = [](uint32_t q) { return q + 1 < kTopBuckets ? q + 1 : q; };
-  auto end_of = [&](uint32_t q, uint32_t next_start) {
-    return q + 1 < kTopBuckets ? next_start : a.src.b;
-  };
-  const uint32_t s = ldg<kC>(&m.bucket_start[d]);
-  const uint32_t e_s = end_of(d, ldg<kC>(&m.bucket_start[next_of(d)]));
+  const uint32_t ntiles = m.num_sort_tiles;
+  static_assert(kMsdMaxTiles <= kThreads, "one tile per thread");
+  const uint32_t* tot = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
+  uint32_t gt[kTopPer];
+#pragma unroll
+  for (int q = 0; q < kTopPer; ++q) gt[q] = ldg<kC>(tot + tid * kTopPer + q);
+  const uint32_t* row = m.tile_cnt + static_cast<size_t>(tid < ntiles ? tid : 0) * (kTopBuckets / 2);
+  const uint32_t seg_w0 = ldg<kC>(&row[d >> 1]);
+  const uint32_t seg_w1 = ldg<kC>(&row[next_of(d) >> 1]);
   // The digit's range in each fused level, from the level's top-digit index:
   // uniform loads, all issued before any is used (slots past j read level
   // 0's index and are ignored).
@@ -1103,22 +1023,42 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
 #pragma unroll
     for (int q = 0; q < kMaxFuse; ++q) dlo[q] = dhi[q] = dlen[q] = 0u;
   }
-  const uint32_t n = e_s > s ? e_s - s : 0u;
-  if (d == 0 && a.skew_out != nullptr) {
-    uint32_t lo4[kTopPer], nx4[kTopPer], mx = 0;
-#pragma unroll
-    for (int q = 0; q < kTopPer; ++q) {
-      const uint32_t dq = tid * kTopPer + q;
-      lo4[q] = ldg<kC>(&m.bucket_start[dq]);
-      nx4[q] = ldg<kC>(&m.bucket_start[next_of(dq)]);
-    }
-#pragma unroll
-    for (int q = 0; q < kTopPer; ++q) {
-      const uint32_t hi = end_of(tid * kTopPer + q, nx4[q]);
-      mx = max(mx, hi > lo4[q] ? hi - lo4[q] : 0u);
-    }
-    record_max(mx, a.skew_out, L.tmp);
+  // The group of digit d in tile t = tid: [start_t[d], start_t[d + 1]) of
+  // the tile (the last digit's ends at the tile's size).
+  const uint32_t g_st = (d & 1) ? seg_w0 >> 16 : seg_w0 & 0xFFFFu;
+  const uint32_t tile_n =
+      tid < ntiles ? min(a.src.b - tid * kSortTile, static_cast<uint32_t>(kSortTile)) : 0u;
+  const uint32_t g_en = d + 1 < kTopBuckets ? (((d + 1) & 1) ? seg_w1 >> 16 : seg_w1 & 0xFFFFu)
+                                            : tile_n;
+  const uint32_t g_c = (tid < ntiles && g_en > g_st) ? g_en - g_st : 0u;
+  // One pass of two scans: the digit totals (bucket starts) and the group
+  // sizes (each group's first position in the bucket).
+  uint32_t tsum = gt[0] + gt[1] + gt[2] + gt[3], csum = g_c;
+  block_excl_scan2(tsum, csum, L.tmp);
+  uint32_t* segb = &L.wcnt[0][0] + (kRankSortMax + 8);  // group sources in the batch
+  uint32_t* segp = segb + kMsdMaxTiles;                  // group starts in the bucket
+  static_assert(kRankSortMax + 8 + 2 * kMsdMaxTiles <= kWaves * kRadix,
+                "group tables fit beside the rank-sort keys");
+  if (tid < ntiles) {
+    segb[tid] = tid * kSortTile + g_st;
+    segp[tid] = csum;
   }
+  if ((d >> 2) == tid) {
+    uint32_t pre = tsum;
+#pragma unroll
+    for (int q = 0; q < kTopPer; ++q) {
+      if (static_cast<uint32_t>(q) == (d & 3)) {
+        L.tmp[2 * kWaves] = pre;
+        L.tmp[2 * kWaves + 1] = gt[q];
+      }
+      pre += gt[q];
+    }
+  }
+  if (d == 0 && a.skew_out != nullptr)
+    record_max(max(max(gt[0], gt[1]), max(gt[2], gt[3])), a.skew_out, L.tmp);
+  __syncthreads();
+  const uint32_t s = L.tmp[2 * kWaves];
+  const uint32_t n = L.tmp[2 * kWaves + 1];
   if (!fused && a.out_digit != nullptr && tid == 0) a.out_digit[d] = s;
   if (n == 0 && !fused) return;
 
@@ -1172,15 +1112,14 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
                                                      : ((1u << (kRadixBits * passes)) - 1u);
   uint32_t* fld = &L.wcnt[0][0];  // rank-sort keys
   static_assert(kWaves * kRadix >= kRankSortMax + 8, "field scratch");
-  const uint32_t* src_k = a.tmp_kv[0] + s;
-  const uint32_t* src_v = a.tmp_val[0] + s;
   const bool levels_in_lds = nl > n;  // fused, and all runs fit
   if (levels_in_lds) {
-    // Run table: run 0 is the batch's bucket, run q + 1 level q; element x
-    // of run r is source position x + delta[r].
+    // Run table: run q + 1 is level q, whose element x is source position
+    // x + delta[q + 1]; run 0, the batch's bucket, is read through the
+    // group table instead.
     if (tid == 0) {
-      L.run_k[0] = src_k;
-      L.run_v[0] = src_v;
+      L.run_k[0] = a.tmp_kv[0];
+      L.run_v[0] = a.tmp_val[0];
       L.run_delta[0] = 0;
 #pragma unroll
       for (int q = 0; q < kMaxFuse; ++q) {
@@ -1196,8 +1135,13 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   if (nl > 0) {
     constexpr int kPer = kLocalCap / kThreads;
     uint32_t rk[kPer], rv[kPer], run[kPer];
-    // Each element's run (the number of level starts at or below it),
-    // then its source from the run table; loads issued before any store.
+    // Each element's run (the number of level starts at or below it); a
+    // batch element's position in the scattered batch comes from its
+    // tile's group (the last group starting at or below it, by a search
+    // over the group starts, the searches of a thread's elements in
+    // lockstep), a level element's from the run table; loads issued before
+    // any store.
+    uint32_t bidx[kPer];
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const uint32_t x = tid + i * kThreads;
@@ -1207,15 +1151,33 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
 #pragma unroll
         for (int q = 1; q <= kMaxFuse; ++q) run[i] += (q <= f.nlev && xc >= rs_q[q]) ? 1u : 0u;
       }
+      bidx[i] = 0;
+    }
+    if (n > 0) {
+      for (uint32_t step = 1u << (31 - __builtin_clz(ntiles)); step > 0; step >>= 1) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+          if (static_cast<uint32_t>(i) * kThreads < nl) {
+            const uint32_t x = tid + i * kThreads;
+            const uint32_t xb = x < n ? x : n - 1;
+            const uint32_t probe = bidx[i] + step;
+            const uint32_t pc = probe < ntiles ? probe : ntiles - 1;
+            bidx[i] = (probe < ntiles && segp[pc] <= xb) ? probe : bidx[i];
+          }
+        }
+      }
     }
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       if (static_cast<uint32_t>(i) * kThreads < nl) {
         const uint32_t x = tid + i * kThreads;
         const uint32_t xc = x < nl ? x : nl - 1;
-        const uint32_t* pk = levels_in_lds ? L.run_k[run[i]] : src_k;
-        const uint32_t* pv = levels_in_lds ? L.run_v[run[i]] : src_v;
-        const uint32_t at = xc + (levels_in_lds ? L.run_delta[run[i]] : 0u);
+        const uint32_t xb = x < n ? x : (n > 0 ? n - 1 : 0u);
+        const bool in_batch = run[i] == 0;
+        const uint32_t* pk = in_batch ? a.tmp_kv[0] : L.run_k[run[i]];
+        const uint32_t* pv = in_batch ? a.tmp_val[0] : L.run_v[run[i]];
+        const uint32_t at = in_batch ? segb[bidx[i]] + (xb - segp[bidx[i]])
+                                     : xc + L.run_delta[run[i]];
         if constexpr (kC) {
           rk[i] = ld_dev(pk + at);
           rv[i] = ld_dev(pv + at);
@@ -1255,7 +1217,7 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
     }
   } else {
     sorted_lds = false;
-    local_sort_streaming<kC>(a, lo_bit, passes, s, n, L);
+    local_sort_streaming<kC>(a, lo_bit, passes, s, n, L, segb, segp, ntiles);
   }
 
   if (!fused) {
@@ -1360,23 +1322,20 @@ __device__ void grid_barrier(uint32_t* count, uint32_t* fault) {
   __syncthreads();
 }
 
-// The top-digit sort as one kernel of kOnePassGrid work-groups: tile counts,
-// grid barrier, scatter, grid barrier, then every work-group sorts the
-// buckets d = blockIdx.x, blockIdx.x + kOnePassGrid, ... (with the fused
-// cascade).  Same results as the three kernels; two device-wide exchanges
-// without two kernel boundaries.
+// The top-digit sort as one kernel of kOnePassGrid work-groups: the tile
+// scatter, a grid barrier, then every work-group sorts the buckets
+// d = blockIdx.x, blockIdx.x + kOnePassGrid, ... (with the fused cascade).
+// Same results as the two kernels, with one device-wide exchange and no
+// kernel boundary.
 __global__ __launch_bounds__(kThreads) void k_msd_onepass(SortArgs a, int top_shift, int lo_bit,
                                                           int passes) {
   __shared__ union {
-    uint32_t h[kTopBuckets];
     ScatterLds S;
     LocalLds L;
   } U;
   const SortMeta& m = a.meta;
   clear_other_hist(m);
   const uint32_t tiles = m.num_sort_tiles;
-  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) tile_hist<true>(a, top_shift, t, U.h);
-  grid_barrier(m.bar, m.err + 1);
   for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) tile_scatter<true>(a, top_shift, t, U.S);
   grid_barrier(m.bar, m.err + 1);
   for (uint32_t d = blockIdx.x; d < kTopBuckets; d += gridDim.x) {
@@ -2068,14 +2027,13 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
   m.tile_ctr = m.status + static_cast<size_t>(kMaxPasses) * m.num_sort_tiles * kRadix;
   m.err = m.tile_ctr + kMaxPasses;
   m.tile_cnt = m.err + 4;  // 16-byte aligned (vector loads of packed counts)
-  m.bucket_start = m.tile_cnt + static_cast<size_t>(m.num_sort_tiles) * kTopBuckets;
-  m.bar = m.bucket_start + kTopBuckets;
+  m.bar = m.tile_cnt + static_cast<size_t>(m.num_sort_tiles) * kTopBuckets;
   m.parity = parity;
   return m;
 }
 
 int sort_kernel_count(const SortArgs& a) {
-  if (a.path == kSortMsd) return a.onepass ? 1 : 3;
+  if (a.path == kSortMsd) return a.onepass ? 1 : 2;
   return 1 + a.passes;
 }
 
@@ -2088,11 +2046,9 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* time
     if (a.onepass)
       return launch(k_msd_onepass, kOnePassGrid, kThreads, stream, timers ? &timers[0] : nullptr, a,
                     top, a.lo_bit, local_passes);
-    hipError_t e = launch(k_msd_hist, tiles, kThreads, stream, timers ? &timers[0] : nullptr, a, top);
+    hipError_t e = launch(k_msd_scatter, tiles, kThreads, stream, timers ? &timers[0] : nullptr, a, top);
     if (e == hipSuccess)
-      e = launch(k_msd_scatter, tiles, kThreads, stream, timers ? &timers[1] : nullptr, a, top);
-    if (e == hipSuccess)
-      e = launch(k_local_sort, kTopBuckets, kThreads, stream, timers ? &timers[2] : nullptr, a,
+      e = launch(k_local_sort, kTopBuckets, kThreads, stream, timers ? &timers[1] : nullptr, a,
                  a.lo_bit, local_passes);
     return e;
   }

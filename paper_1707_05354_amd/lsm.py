@@ -40,7 +40,7 @@ class Stats(ctypes.Structure):
 
 
 KERNEL_NAMES = ("k_sort_hist", "k_sort_pass", "k_merge", "k_lookup", "k_count", "k_scan",
-                "k_range_emit", "k_order", "k_clean", "k_msd_hist", "k_msd_scatter",
+                "k_range_emit", "k_order", "k_clean", "(unused)", "k_msd_scatter",
                 "k_local_sort", "k_msd_onepass")
 # rocprofv3 kernel names behind each profiler kind that covers several kernels.
 KERNEL_TRACE_NAMES = {"k_order": ("k_successor", "k_predecessor"),
