@@ -35,6 +35,8 @@
 
 #include "lsm_internal.h"
 
+#include <type_traits>
+
 namespace lsm {
 namespace {
 
@@ -716,14 +718,6 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
     S.local[d0 + q] = lrun;
     lrun += cnt[q];
   }
-  uint32_t* row = m.tile_cnt + static_cast<size_t>(tile) * (kTopBuckets / 2);
-  stg<kC>(&row[2 * tid], start[0] | (start[1] << 16));
-  stg<kC>(&row[2 * tid + 1], start[2] | (start[3] << 16));
-  uint32_t* tot = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
-  static_assert(kTopBuckets <= kMaxPasses * kRadix, "totals fit one histogram buffer");
-#pragma unroll
-  for (int q = 0; q < kTopPer; ++q)
-    if (cnt[q] != 0u) atomicAdd(&tot[d0 + q], cnt[q]);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
@@ -735,6 +729,16 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
     }
   }
   __syncthreads();
+  // Global writes last, so that no barrier waits for them: the group starts,
+  // the totals and the grouped tile.
+  uint32_t* row = m.tile_cnt + static_cast<size_t>(tile) * (kTopBuckets / 2);
+  stg<kC>(&row[2 * tid], start[0] | (start[1] << 16));
+  stg<kC>(&row[2 * tid + 1], start[2] | (start[3] << 16));
+  uint32_t* tot = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
+  static_assert(kTopBuckets <= kMaxPasses * kRadix, "totals fit one histogram buffer");
+#pragma unroll
+  for (int q = 0; q < kTopPer; ++q)
+    if (cnt[q] != 0u) atomicAdd(&tot[d0 + q], cnt[q]);
   const uint32_t tile_n = (b - tbase) < static_cast<uint32_t>(kSortTile) ? (b - tbase) : kSortTile;
   for (uint32_t x = tid; x < tile_n; x += kThreads) {
     stg<kC>(&a.tmp_kv[0][tbase + x], S.kv[x]);
@@ -1054,6 +1058,11 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
       pre += gt[q];
     }
   }
+  if (tid == 0) {  // run 0 of the load table: the scattered batch
+    L.run_k[0] = a.tmp_kv[0];
+    L.run_v[0] = a.tmp_val[0];
+    L.run_delta[0] = 0;
+  }
   if (d == 0 && a.skew_out != nullptr)
     record_max(max(max(gt[0], gt[1]), max(gt[2], gt[3])), a.skew_out, L.tmp);
   __syncthreads();
@@ -1115,12 +1124,9 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   const bool levels_in_lds = nl > n;  // fused, and all runs fit
   if (levels_in_lds) {
     // Run table: run q + 1 is level q, whose element x is source position
-    // x + delta[q + 1]; run 0, the batch's bucket, is read through the
-    // group table instead.
+    // x + delta[q + 1]; run 0, the batch's bucket (written in the
+    // prologue), is read through the group table instead.
     if (tid == 0) {
-      L.run_k[0] = a.tmp_kv[0];
-      L.run_v[0] = a.tmp_val[0];
-      L.run_delta[0] = 0;
 #pragma unroll
       for (int q = 0; q < kMaxFuse; ++q) {
         if (q < f.nlev) {
@@ -1132,8 +1138,10 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
     }
     __syncthreads();
   }
-  if (nl > 0) {
-    constexpr int kPer = kLocalCap / kThreads;
+  // The load phase for at most kPer items per thread (instantiated for 1,
+  // 4 and 8, so that a small bucket does not search for absent items).
+  auto load_phase = [&](auto per_c) {
+    constexpr int kPer = decltype(per_c)::value;
     uint32_t rk[kPer], rv[kPer], run[kPer];
     // Each element's run (the number of level starts at or below it); a
     // batch element's position in the scattered batch comes from its
@@ -1153,37 +1161,45 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
       }
       bidx[i] = 0;
     }
-    if (n > 0) {
-      for (uint32_t step = 1u << (31 - __builtin_clz(ntiles)); step > 0; step >>= 1) {
+    // Straight-line searches and table reads for every item (positions
+    // clamped, results of items past nl unused), so that the LDS reads of
+    // all items are in flight together and the loads below issue back to
+    // back.
+    const uint32_t xbmax = n > 0 ? n - 1 : 0u;
+    for (uint32_t step = 1u << (31 - __builtin_clz(ntiles)); step > 0; step >>= 1) {
 #pragma unroll
-        for (int i = 0; i < kPer; ++i) {
-          if (static_cast<uint32_t>(i) * kThreads < nl) {
-            const uint32_t x = tid + i * kThreads;
-            const uint32_t xb = x < n ? x : n - 1;
-            const uint32_t probe = bidx[i] + step;
-            const uint32_t pc = probe < ntiles ? probe : ntiles - 1;
-            bidx[i] = (probe < ntiles && segp[pc] <= xb) ? probe : bidx[i];
-          }
-        }
+      for (int i = 0; i < kPer; ++i) {
+        const uint32_t x = tid + i * kThreads;
+        const uint32_t xb = x < xbmax ? x : xbmax;
+        const uint32_t probe = bidx[i] + step;
+        const uint32_t pc = probe < ntiles ? probe : ntiles - 1;
+        const uint32_t v = segp[pc];
+        bidx[i] = ((probe < ntiles) & (v <= xb)) ? probe : bidx[i];
       }
+    }
+    const uint32_t* pk[kPer];
+    const uint32_t* pv[kPer];
+    uint32_t at[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const uint32_t x = tid + i * kThreads;
+      const uint32_t xc = x < nl ? x : nl - 1;
+      const uint32_t xb = x < xbmax ? x : xbmax;
+      const uint32_t r = levels_in_lds ? run[i] : 0u;
+      const uint32_t gb = segb[bidx[i]], gp = segp[bidx[i]];
+      pk[i] = L.run_k[r];
+      pv[i] = L.run_v[r];
+      at[i] = r == 0 ? gb + (xb - gp) : xc + L.run_delta[r];
     }
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       if (static_cast<uint32_t>(i) * kThreads < nl) {
-        const uint32_t x = tid + i * kThreads;
-        const uint32_t xc = x < nl ? x : nl - 1;
-        const uint32_t xb = x < n ? x : (n > 0 ? n - 1 : 0u);
-        const bool in_batch = run[i] == 0;
-        const uint32_t* pk = in_batch ? a.tmp_kv[0] : L.run_k[run[i]];
-        const uint32_t* pv = in_batch ? a.tmp_val[0] : L.run_v[run[i]];
-        const uint32_t at = in_batch ? segb[bidx[i]] + (xb - segp[bidx[i]])
-                                     : xc + L.run_delta[run[i]];
         if constexpr (kC) {
-          rk[i] = ld_dev(pk + at);
-          rv[i] = ld_dev(pv + at);
+          rk[i] = ld_dev(pk[i] + at[i]);
+          rv[i] = ld_dev(pv[i] + at[i]);
         } else {
-          rk[i] = as_global(pk)[at];
-          rv[i] = as_global(pv)[at];
+          rk[i] = as_global(pk[i])[at[i]];
+          rv[i] = as_global(pv[i])[at[i]];
         }
       }
     }
@@ -1198,6 +1214,14 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
       }
     }
     if (rank_path && tid >= n && tid < ((n + 7u) & ~7u)) fld[tid] = 0xFFFFFFFFu;
+  };
+  if (nl > 0) {
+    if (nl <= static_cast<uint32_t>(kThreads))
+      load_phase(std::integral_constant<int, 1>{});
+    else if (nl <= static_cast<uint32_t>(4 * kThreads))
+      load_phase(std::integral_constant<int, 4>{});
+    else
+      load_phase(std::integral_constant<int, kLocalCap / kThreads>{});
   }
   __syncthreads();  // the loaded runs, fields and L.lo / L.rs
 
