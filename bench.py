@@ -310,7 +310,7 @@ def batching_form(torch, L, W, reps: int = 2):
     run(gb, True)  # first run captures the graphs
     graph_ms, batch_r = run(gb, True)
     gb.close()
-    use_graphs = graph_ms < eager_ms
+    use_graphs = bool(graph_ms < eager_ms)
     batch_ms = min(graph_ms, eager_ms)
     res = {
         "user_batches": len(ub), "user_ops": n_ops,
@@ -378,7 +378,7 @@ def serving_form(torch, L, W, n_requests: int = 40000, loads=(0.25, 0.5, 0.75, 0
             serve(False)  # first run captures the graphs
         res, span = serve(False)
         sat_by_mode[graphs] = (res, span)
-    use_graphs = sat_by_mode[True][1] < sat_by_mode[False][1]
+    use_graphs = bool(sat_by_mode[True][1] < sat_by_mode[False][1])
     res, span = sat_by_mode[use_graphs]
     g.use_graphs(use_graphs)
     cap_rps = n_requests / span
