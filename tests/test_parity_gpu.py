@@ -299,13 +299,14 @@ def test_sort_path_follows_key_skew():
 
 @pytest.mark.parametrize("mode", [LSM.SORT_TOP_DIGIT, LSM.SORT_DIGIT_PASSES, LSM.SORT_ONE_KERNEL])
 def test_forced_sort_paths(mode):
-    """Either path, forced, on batches of 1 to 600 tiles with partial
-    batches: top-digit buckets sorted by ranking (up to 1024 elements), by
-    LDS radix passes (about 4096 at b = 2^20) and, with keys below 2^12 (one
-    bucket), by the streaming fallback."""
+    """Either path, forced, on batches of 1 to 256 tiles (the top-digit
+    sort's limit) with partial batches: top-digit buckets sorted by ranking
+    (up to 256 elements), by LDS radix passes (about 500 at 255 tiles) and,
+    with keys below 2^12 (one bucket), by the streaming fallback.  A forced
+    top-digit sort above 256 tiles runs the digit passes (600 tiles)."""
     for b, domain, R, seed in [(1, 8, 20, 71), (2047, 3000, 9, 72), (4096 * 3 + 1, 1 << 31, 6, 73),
-                               (600 * 2048 - 9, 1 << 31, 3, 74), ((1 << 20) - 3, 1 << 31, 2, 75),
-                               (300 * 2048 + 5, 1 << 12, 2, 76)]:
+                               (255 * 2048 - 9, 1 << 31, 3, 74), ((1 << 19) - 3, 1 << 31, 2, 75),
+                               (200 * 2048 + 5, 1 << 12, 2, 76), (600 * 2048 - 9, 1 << 31, 2, 77)]:
         ops, q, lo, hi = W.random_small(seed, b, R, domain, p_delete=0.3, nq=300)
         note("forced sort path %d b=%d" % (mode, b))
         t = Trio(b)
