@@ -1165,18 +1165,27 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
     // clamped, results of items past nl unused), so that the LDS reads of
     // all items are in flight together and the loads below issue back to
     // back.
+    // Only items that can hold batch elements search (all kPer, or just the
+    // first when the bucket fits one item per thread).
     const uint32_t xbmax = n > 0 ? n - 1 : 0u;
-    for (uint32_t step = 1u << (31 - __builtin_clz(ntiles)); step > 0; step >>= 1) {
+    auto search = [&](auto cnt_c) {
+      constexpr int kS = decltype(cnt_c)::value;
+      for (uint32_t step = 1u << (31 - __builtin_clz(ntiles)); step > 0; step >>= 1) {
 #pragma unroll
-      for (int i = 0; i < kPer; ++i) {
-        const uint32_t x = tid + i * kThreads;
-        const uint32_t xb = x < xbmax ? x : xbmax;
-        const uint32_t probe = bidx[i] + step;
-        const uint32_t pc = probe < ntiles ? probe : ntiles - 1;
-        const uint32_t v = segp[pc];
-        bidx[i] = ((probe < ntiles) & (v <= xb)) ? probe : bidx[i];
+        for (int i = 0; i < kS; ++i) {
+          const uint32_t x = tid + i * kThreads;
+          const uint32_t xb = x < xbmax ? x : xbmax;
+          const uint32_t probe = bidx[i] + step;
+          const uint32_t pc = probe < ntiles ? probe : ntiles - 1;
+          const uint32_t v = segp[pc];
+          bidx[i] = ((probe < ntiles) & (v <= xb)) ? probe : bidx[i];
+        }
       }
-    }
+    };
+    if (n <= static_cast<uint32_t>(kThreads))
+      search(std::integral_constant<int, 1>{});
+    else
+      search(std::integral_constant<int, kPer>{});
     const uint32_t* pk[kPer];
     const uint32_t* pv[kPer];
     uint32_t at[kPer];
