@@ -512,7 +512,7 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
     else sort_t[p] = *t;
   }
   const hipError_t se = launch_sort(sa, h->stream, timed ? sort_t : nullptr);
-  h->hist_parity ^= 1;  // the histogram kernel cleared the other buffer for the next sort
+  h->hist_parity ^= 1;  // the sort cleared the other histogram buffer for the next sort
   if (se != hipSuccess) return LSM_EHIP;
   Timed last = st[nk - 1];
 
