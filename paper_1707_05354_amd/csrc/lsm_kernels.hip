@@ -577,10 +577,11 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(SortArgs a, int pass) {
 
 // ------------------------------------------------------------ MSD sort
 // For batches of at most kMsdMaxTiles tiles the sort exchanges data across
-// the device only once: a histogram of the top kTopBits-bit digit, one
-// stable scatter into kTopBuckets buckets, then each bucket sorted on its
-// own by one work-group on the remaining bits (in LDS when it fits,
-// streaming through the bucket's global range otherwise).  Three kernels
+// the device only once: each tile grouped in place by its top kTopBits-bit
+// digit (with the batch's digit totals and each tile's group starts), then
+// each of the kTopBuckets buckets gathered from every tile and sorted on
+// its own by one work-group on the remaining bits (in LDS when it fits,
+// streaming through the bucket's global range otherwise).  Two kernels
 // instead of 1 + passes, and no look-back chains.
 
 // Stable ranking of one item per lane by digit d among the valid lanes of
@@ -972,10 +973,12 @@ __device__ __forceinline__ uint32_t seg_bound(const uint32_t* s, uint32_t lo, ui
   return lo;
 }
 
-// One work-group per top-digit bucket.  The bucket of the batch is sorted on
-// the digits below the top one: by ranking up to kRankSortMax elements, by
-// LDS radix passes up to kLocalCap, else by streaming passes over global
-// memory.  Without a fused cascade the sorted bucket is the output.
+// One work-group per top-digit bucket d.  The bucket is digit d's group in
+// every tile of the tile-major scatter, gathered in tile order (the batch's
+// order), and is sorted on the digits below the top one: by ranking up to
+// kRankSortMax elements, by LDS radix passes up to kLocalCap, else by
+// streaming passes over global memory.  Without a fused cascade the sorted
+// bucket is the output.
 //
 // With a fused cascade (a.fuse.nlev = j > 0), the work-group then merges
 // its bucket with the same digit's key range of levels 0..j-1 (read from
