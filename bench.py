@@ -252,10 +252,8 @@ def batching_form(torch, L, W, reps: int = 2):
     """4096 user batches, log-normal sizes (median 4096, sigma 1, clipped to
     [256, 65536]), uniform keys, every tenth a delete batch: the plain path
     (one padded LSM batch of b = 2^16 per user batch) against the batching
-    form (coalescer packing into ~426 LSM batches, autotuned merges; full
-    batches launched kernel by kernel and replayed as captured hipGraphs,
-    the faster reported, both times kept).  Best of `reps` runs of each; user
-    ops per second."""
+    form (coalescer packing into ~426 LSM batches, autotuned merges).  Best
+    of `reps` runs of each; user ops per second."""
     b = 1 << 16
     t0 = time.perf_counter()
     ub = W.batching_stream(b=b)
@@ -305,22 +303,16 @@ def batching_form(torch, L, W, reps: int = 2):
     gb.autotune(max_level=8, reps=3)
     tune_s = time.perf_counter() - t0
     tuning = [gb.tuning(i)[0] for i in range(9)]
-    eager_ms, _ = run(gb, True)  # full batches launched kernel by kernel
-    gb.use_graphs(True)
-    run(gb, True)  # first run captures the graphs
-    graph_ms, batch_r = run(gb, True)
+    batch_ms, batch_r = run(gb, True)
     gb.close()
-    use_graphs = bool(graph_ms < eager_ms)
-    batch_ms = min(graph_ms, eager_ms)
     res = {
         "user_batches": len(ub), "user_ops": n_ops,
         "plain": {"lsm_batches": plain_r, "ms": round(plain_ms, 3),
                   "M_user_ops_per_s": round(n_ops / (plain_ms * 1e-3) / 1e6, 2)},
         "batched": {"lsm_batches": batch_r, "ms": round(batch_ms, 3),
                     "M_user_ops_per_s": round(n_ops / (batch_ms * 1e-3) / 1e6, 2),
-                    "graphs": use_graphs, "merge_variant_by_level": tuning,
-                    "autotune_s": round(tune_s, 2),
-                    "ms_graphs": round(graph_ms, 3), "ms_no_graphs": round(eager_ms, 3)},
+                    "merge_variant_by_level": tuning,
+                    "autotune_s": round(tune_s, 2)},
         "speedup": round(plain_ms / batch_ms, 2),
     }
     log("batching: %s" % res)
@@ -332,9 +324,8 @@ def serving_form(torch, L, W, n_requests: int = 40000, loads=(0.25, 0.5, 0.75, 0
     Poisson arrivals of mixed requests (50% lookup, 10% count, 10% range of
     width 256 (~32 hits), 25% insert, 5% delete; sizes log-uniform in
     [1, 8192]), served by the continuous-batching loop.  First a saturation
-    run (everything arrived at t = 0) gives the capacity, once with full
-    batches launched kernel by kernel and once replayed as hipGraphs; the
-    faster mode serves the offered loads at the given fractions of it.
+    run (everything arrived at t = 0) gives the capacity; the offered loads
+    are then the given fractions of it.
     Reports throughput and p50/p99 request latency (completion - arrival)
     per point."""
     from paper_1707_05354_amd import serving as S
@@ -371,22 +362,10 @@ def serving_form(torch, L, W, n_requests: int = 40000, loads=(0.25, 0.5, 0.75, 0
 
     t1 = time.perf_counter()
     reqs.t_arrive = np.zeros_like(base_t)
-    sat_by_mode = {}
-    for graphs in (False, True):
-        g.use_graphs(graphs)
-        if graphs:
-            serve(False)  # first run captures the graphs
-        res, span = serve(False)
-        sat_by_mode[graphs] = (res, span)
-    use_graphs = bool(sat_by_mode[True][1] < sat_by_mode[False][1])
-    res, span = sat_by_mode[use_graphs]
-    g.use_graphs(use_graphs)
+    res, span = serve(False)
     cap_rps = n_requests / span
     sat = {"offered_rps": None, "throughput_rps": round(cap_rps), "M_ops_per_s": round(res.ops / span / 1e6, 2),
-           **{k: round(v, 3) for k, v in S.percentiles(res.latency_s).items()}, "epochs": len(res.epochs),
-           "graphs": use_graphs,
-           "M_ops_per_s_no_graphs": round(res.ops / sat_by_mode[False][1] / 1e6, 2),
-           "M_ops_per_s_graphs": round(res.ops / sat_by_mode[True][1] / 1e6, 2)}
+           **{k: round(v, 3) for k, v in S.percentiles(res.latency_s).items()}, "epochs": len(res.epochs)}
     log("serving saturation: %s" % sat)
     points = [dict(sat, load="saturation")]
     for f in loads:

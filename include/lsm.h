@@ -93,6 +93,10 @@ LSM_API lsm_status_t lsm_set_stream(lsm_t h, void* stream);
  *                    with n < b is padded with copies of its last pair
  *                    (sec. IV-A), so it still occupies b slots.
  * Duplicate keys inside one batch: the last one in batch order wins.
+ * Elements staged by lsm_submit / lsm_submit_mixed are older than this batch:
+ * when any are pending they are inserted first, as their own padded batch,
+ * once everything this batch can be refused for (size, allocations, keys in
+ * checked mode) has been checked.
  * LSM_EBATCH if n > b; LSM_EKEY (checked mode); LSM_ENOMEM; LSM_ECAPACITY;
  * LSM_EHIP.
  */
@@ -144,28 +148,24 @@ LSM_API lsm_status_t lsm_submit(lsm_t h, const uint32_t* d_keys, const uint32_t*
                                 uint32_t n, int is_delete);
 
 /*
- * lsm_submit_encoded -- stage n operations already encoded as key
- * variables (original key << 1 | status; status 0 deletes), in arrival
- * order, with their values (ignored for deletions).  One call can carry
- * many user requests of both types; the packing rules of lsm_submit apply.
+ * lsm_submit_mixed -- stage n operations of both types in arrival order:
+ * element j deletes d_keys[j] when d_is_delete[j] != 0 (its value is then
+ * ignored) and inserts (d_keys[j], d_vals[j]) otherwise.  One call can carry
+ * many user requests; the packing rules of lsm_submit apply, so the newest
+ * operation on a key wins whatever its type.  The library encodes each
+ * operation as a key variable (sec. IV-A) while staging it.
+ *   d_keys, d_vals : n keys and values (device).
+ *   d_is_delete    : n flags (device, uint8).
+ * Same errors as lsm_submit.
  */
-LSM_API lsm_status_t lsm_submit_encoded(lsm_t h, const uint32_t* d_kv, const uint32_t* d_vals,
-                                        uint32_t n);
+LSM_API lsm_status_t lsm_submit_mixed(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals,
+                                      const uint8_t* d_is_delete, uint32_t n);
 
 /* lsm_flush -- insert the staged elements as one (padded) batch, if any. */
 LSM_API lsm_status_t lsm_flush(lsm_t h);
 
 /* Number of elements staged and not yet inserted. */
 LSM_API uint32_t lsm_pending(lsm_t h);
-
-/*
- * lsm_set_graphs -- when on, every full staged batch is inserted by
- * replaying a hipGraph captured (on a private stream, at first use) for its
- * first empty level and histogram buffer; graphs are recaptured whenever a
- * buffer they name is reallocated or a merge variant changes.  Not
- * available with LSM_CHECKED (LSM_EINVAL).
- */
-LSM_API lsm_status_t lsm_set_graphs(lsm_t h, int on);
 
 /*
  * Merge-kernel autotuner.  Variant v in [0, 6) merges with 4, 8 or 16
@@ -188,7 +188,7 @@ LSM_API lsm_status_t lsm_set_tuning(lsm_t h, uint32_t level, uint32_t variant);
  * of the pairwise cascade (so the levels are byte for byte the same), with
  * no merge launch.  0 disables fusion; a negative value restores the
  * default (the largest j with b 2^j <= 2^20, at most 8).  Applies only when
- * the top-digit sort runs.  Drops captured graphs.  LSM_EINVAL for more
+ * the top-digit sort runs.  LSM_EINVAL for more
  * than 8 levels.
  */
 LSM_API lsm_status_t lsm_set_fusion(lsm_t h, int max_levels);
@@ -199,8 +199,7 @@ LSM_API lsm_status_t lsm_set_fusion(lsm_t h, int max_levels);
  * grouped in place by the top 10 bits of the key variable, then each of the
  * 1024 buckets gathered from every tile and sorted in LDS by one work-group
  * (batches of at most 2^19 elements; larger ones use digit passes).
- * LSM_SORT_ONE_KERNEL: the same sort (and its fused cascade) as one kernel
- * of 256 work-groups with one device-wide barrier instead of two kernels.  LSM_SORT_DIGIT_PASSES: one stable counting pass
+ * LSM_SORT_DIGIT_PASSES: one stable counting pass
  * per 8-bit digit with decoupled look-back.  LSM_SORT_AUTO (the default):
  * the top-digit sort unless the previous sort saw a top-digit bucket above
  * 2048 elements (skewed keys, where one work-group would sort a large bucket
@@ -209,7 +208,6 @@ LSM_API lsm_status_t lsm_set_fusion(lsm_t h, int max_levels);
 #define LSM_SORT_AUTO 0
 #define LSM_SORT_TOP_DIGIT 1
 #define LSM_SORT_DIGIT_PASSES 2
-#define LSM_SORT_ONE_KERNEL 3
 LSM_API lsm_status_t lsm_set_sort_path(lsm_t h, int mode);
 
 /*
@@ -397,8 +395,7 @@ LSM_API lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out);
  * digit pass, 2 level merge, 3 lookup, 4 count, 5 range offset scan, 6 range
  * emission, 7 successor / predecessor, 8 cleanup mark-and-compact, 9 not
  * used (no kernel of this library is counted there), 10 / 11 the top-digit
- * sort's tile scatter and per-bucket sort, 12 the top-digit sort as one
- * kernel.
+ * sort's tile scatter and per-bucket sort, 12 not used.
  * kernel_bytes[k] is the algorithmic traffic of those launches: 4 B per
  * batch element for a histogram (keys read), 16 B per element for a digit
  * pass, the top-digit scatter and the per-bucket sort (key and value read

@@ -79,14 +79,6 @@ struct lsm_s {
   uint32_t* stage_val = nullptr;
   uint32_t stage_fill = 0;
 
-  // Captured insertion graphs for full staged batches, by first empty level
-  // and histogram parity; recaptured whenever a buffer they name changes.
-  bool graphs = false;
-  hipStream_t cap_stream = nullptr;
-  hipGraph_t graph[kMaxLevels][2][2] = {};          // [level][parity][sort path]
-  hipGraphExec_t graph_exec[kMaxLevels][2][2] = {};
-  int graph_fuse[kMaxLevels][2][2] = {};             // fused depth the graph was captured with
-
   // Merge variant per merge input level (autotuned or set).
   int merge_variant[kMaxLevels];
   float tune_us[kMaxLevels][kMergeVariants] = {};
@@ -110,8 +102,6 @@ struct lsm_s {
 };
 
 namespace {
-
-void drop_graphs(lsm_t h);
 
 struct DeviceGuard {
   int prev = -1;
@@ -200,7 +190,6 @@ lsm_status_t ensure_merge_scratch(lsm_t h, uint64_t elems) {
       return LSM_ENOMEM;
     }
   }
-  drop_graphs(h);  // captured graphs name the old buffers
   const size_t old = h->mrg_cap * sizeof(uint32_t);
   for (int i = 0; i < 2; ++i) {
     dev_free(h, h->mrg_kv[i], old);
@@ -235,20 +224,7 @@ lsm_status_t ensure_query_scratch(lsm_t h, uint32_t nq) {
   return LSM_OK;
 }
 
-void drop_graphs(lsm_t h) {
-  for (int j = 0; j < kMaxLevels; ++j)
-    for (int p = 0; p < 2; ++p)
-      for (int q = 0; q < 2; ++q) {
-        if (h->graph_exec[j][p][q]) (void)hipGraphExecDestroy(h->graph_exec[j][p][q]);
-        if (h->graph[j][p][q]) (void)hipGraphDestroy(h->graph[j][p][q]);
-        h->graph_exec[j][p][q] = nullptr;
-        h->graph[j][p][q] = nullptr;
-      }
-}
-
 void release_all(lsm_t h) {
-  drop_graphs(h);
-  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   dev_free(h, h->stage_kv, static_cast<size_t>(h->b) * sizeof(uint32_t));
   dev_free(h, h->stage_val, static_cast<size_t>(h->b) * sizeof(uint32_t));
   const size_t bb = static_cast<size_t>(h->b) * sizeof(uint32_t);
@@ -344,8 +320,7 @@ lsm_status_t prepare_insert(lsm_t h, int j) {
 int sort_path(lsm_t h, uint32_t tiles) {
   int p;
   if (h->sort_mode == LSM_SORT_DIGIT_PASSES) p = kSortLsd;
-  else if (h->sort_mode == LSM_SORT_TOP_DIGIT || h->sort_mode == LSM_SORT_ONE_KERNEL)
-    p = pick_sort_path(tiles, 0u);
+  else if (h->sort_mode == LSM_SORT_TOP_DIGIT) p = pick_sort_path(tiles, 0u);
   else p = pick_sort_path(tiles, *reinterpret_cast<volatile uint32_t*>(h->skew_host));
   h->sorts_by_path[p] += 1;
   return p;
@@ -358,10 +333,6 @@ int default_fuse_max(uint32_t b) {
   return J;
 }
 
-// Fuses the first levels of an insert's cascade into the top-digit sort:
-// levels 0..nf-1 with nf = min(j, fuse_max).  When nf = j the sort writes
-// level j; otherwise it writes the merge scratch buffer that the pairwise
-// merge of level nf then reads (see enqueue_cascade).
 // Fuses the first levels of an insert's cascade into the top-digit sort:
 // levels 0..nf-1 with nf = min(j, fuse_max), cut short at the first level
 // without a top-digit index for this key shift.  When nf = j the sort
@@ -432,16 +403,15 @@ SortArgs sort_args(lsm_t h, const BatchSrc& src, int j) {
   sa.out_val = (j == 0) ? h->lvl_val[0] : h->buf_val;
   sa.out_fence = (j == 0) ? h->lvl_fence[0] : nullptr;
   sa.path = sort_path(h, sa.meta.num_sort_tiles);
-  sa.onepass = (sa.path == kSortMsd && h->sort_mode == LSM_SORT_ONE_KERNEL) ? 1 : 0;
   sa.skew_out = h->skew_dev;
   setup_fusion(h, sa, j);
   return sa;
 }
 
 // The cascade of Fig. 2(a): while level i is full, buffer <- merge(buffer,
-// level i); the last merge writes straight into level j.  Enqueued on s.
-// The pairwise merges of an insert into level j, after the sort (and after
-// the levels the sort fused, whose output is then the first input).
+// level i); the last merge writes straight into level j.  Enqueued on s,
+// after the sort and after the levels the sort fused (whose output is then
+// the first input).
 hipError_t enqueue_cascade(lsm_t h, const SortArgs& sa, int j, hipStream_t s, Timed* last,
                            uint64_t* merged_out) {
   const int i0 = sa.fuse.nlev;
@@ -507,12 +477,16 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
     const double bytes = (sa.fuse.nlev > 0 && p == nk - 1)
                              ? 16.0 * static_cast<double>(level_len(h, sa.fuse.nlev))
                              : sort_kernel_bytes_per_elem(sa.path, p) * h->b;
-    const KTimer* t = timer(h, st[p], sort_kernel_kind(sa.path, p, sa.onepass), h->b, bytes);
+    const KTimer* t = timer(h, st[p], sort_kernel_kind(sa.path, p), h->b, bytes);
     if (t == nullptr) timed = false;
     else sort_t[p] = *t;
   }
-  const hipError_t se = launch_sort(sa, h->stream, timed ? sort_t : nullptr);
-  h->hist_parity ^= 1;  // the sort cleared the other histogram buffer for the next sort
+  int launched = 0;
+  const hipError_t se = launch_sort(sa, h->stream, timed ? sort_t : nullptr, &launched);
+  // The sort's first kernel clears the other histogram buffer for the next
+  // sort; once it has been launched, the next sort must use that buffer
+  // whether or not the rest of the sort was launched.
+  if (launched > 0) h->hist_parity ^= 1;
   if (se != hipSuccess) return LSM_EHIP;
   Timed last = st[nk - 1];
 
@@ -533,74 +507,60 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
   return LSM_OK;
 }
 
-// Inserts the staged batch (n elements, padded when n < b).  A full staged
-// batch replays the graph captured for (ffz(r), parity) when graphs are on.
+// Inserts the staged batch (n elements, padded when n < b).
 lsm_status_t insert_staged(lsm_t h, uint32_t n) {
-  if (!h->graphs || n != h->b) {
-    const lsm_status_t s = update_batch(h, h->stage_kv, h->stage_val, nullptr, n, kEncoded);
-    if (s == LSM_OK) h->stage_fill = 0;
-    return s;
-  }
-  DeviceGuard g(h->device);
-  if (!g.ok) return LSM_EHIP;
-  const int j = __builtin_ctzll(~h->r);
-  lsm_status_t s = prepare_insert(h, j);
-  if (s != LSM_OK) return s;
-  const int par = h->hist_parity;
-  const SortArgs sa =
-      sort_args(h, BatchSrc{h->stage_kv, h->stage_val, nullptr, h->b, h->b, kEncoded}, j);
-  const int path = sa.path;
-  if (h->graph_exec[j][par][path] != nullptr && h->graph_fuse[j][par][path] != sa.fuse.nlev) {
-    // Captured with another fused depth (a level's digit index changed since).
-    (void)hipGraphExecDestroy(h->graph_exec[j][par][path]);
-    (void)hipGraphDestroy(h->graph[j][par][path]);
-    h->graph_exec[j][par][path] = nullptr;
-    h->graph[j][par][path] = nullptr;
-  }
-  if (h->graph_exec[j][par][path] == nullptr) {
-    if (h->cap_stream == nullptr &&
-        hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
-      return LSM_EHIP;
-    if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-      return LSM_EHIP;
-    hipError_t e = launch_sort(sa, h->cap_stream, nullptr);
-    if (e == hipSuccess) e = enqueue_cascade(h, sa, j, h->cap_stream, nullptr, nullptr);
-    hipGraph_t graph = nullptr;
-    const hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
-    if (e != hipSuccess || ec != hipSuccess || graph == nullptr) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return LSM_EHIP;
-    }
-    hipGraphExec_t exec = nullptr;
-    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      return LSM_EHIP;
-    }
-    h->graph[j][par][path] = graph;
-    h->graph_exec[j][par][path] = exec;
-    h->graph_fuse[j][par][path] = sa.fuse.nlev;
-  }
-  Timed tg;
-  const KTimer* t = timer(h, tg, kKSortHist, 0, 0.0);  // whole-graph span, reported as an update
-  if (t != nullptr) {
-    h->spans.pop_back();  // keep only the update-call span below
-    (void)hipEventRecord(t->start, h->stream);
-  }
-  if (hipGraphLaunch(h->graph_exec[j][par][path], h->stream) != hipSuccess) return LSM_EHIP;
-  if (t != nullptr) {
-    (void)hipEventRecord(t->stop, h->stream);
-    call_span(h, kSpanUpdate, tg, tg, h->b);
-  }
-  h->hist_parity ^= 1;
-  note_digit_index(h, sa, j);
-  commit_insert(h, (j == 0) ? 0 : (2ull << j) * h->b - 2ull * h->b);
-  h->stage_fill = 0;
-  return LSM_OK;
+  const lsm_status_t s = update_batch(h, h->stage_kv, h->stage_val, nullptr, n, kEncoded);
+  if (s == LSM_OK) h->stage_fill = 0;
+  return s;
 }
 
 lsm_status_t flush_staged(lsm_t h) {
   if (h->stage_fill == 0) return LSM_OK;
   return insert_staged(h, h->stage_fill);
+}
+
+// Sets *bad when any of n keys is >= 2^key_bits (checked mode); synchronises.
+lsm_status_t check_keys(lsm_t h, const uint32_t* keys, uint32_t n, bool* bad) {
+  const SortMeta m = sort_meta_carve(h->meta, h->b, 0);
+  if (hipMemsetAsync(m.err, 0, sizeof(uint32_t), h->stream) != hipSuccess ||
+      launch_check_keys(keys, n, h->key_bits, 0, m.err, h->stream) != hipSuccess ||
+      hipMemcpyAsync(h->h_pinned, m.err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return LSM_EHIP;
+  *bad = *reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u;
+  return LSM_OK;
+}
+
+// A batch handed to lsm_insert_batch / lsm_delete_batch / lsm_update_batch.
+// Elements staged by the coalescer are older than it, so they are inserted
+// first, as their own (padded) batch.  Everything the direct batch can be
+// refused for (arguments, allocations for both insertions, keys in checked
+// mode) is settled before the staged batch goes in.
+lsm_status_t direct_update(lsm_t h, const uint32_t* keys, const uint32_t* vals,
+                           const uint8_t* is_delete, uint32_t n, BatchMode mode) {
+  if (h == nullptr) return LSM_EINVAL;
+  if (n == 0) return LSM_OK;
+  if (n > h->b) return LSM_EBATCH;
+  if (keys == nullptr || (mode != kDelete && vals == nullptr) ||
+      (mode == kMixed && is_delete == nullptr))
+    return LSM_EINVAL;
+  if (h->stage_fill > 0) {
+    DeviceGuard g(h->device);
+    if (!g.ok) return LSM_EHIP;
+    lsm_status_t s = prepare_insert(h, __builtin_ctzll(~h->r));
+    if (s == LSM_OK) s = prepare_insert(h, __builtin_ctzll(~(h->r + 1)));
+    if (s != LSM_OK) return s;
+    if (h->flags & LSM_CHECKED) {
+      bool bad = false;
+      s = check_keys(h, keys, n, &bad);
+      if (s != LSM_OK) return s;
+      if (bad) return LSM_EKEY;
+    }
+    s = flush_staged(h);
+    if (s != LSM_OK) return s;
+  }
+  return update_batch(h, keys, vals, is_delete, n, mode);
 }
 
 }  // namespace
@@ -680,16 +640,16 @@ lsm_status_t lsm_set_stream(lsm_t h, void* stream) {
 }
 
 lsm_status_t lsm_insert_batch(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals, uint32_t n) {
-  return update_batch(h, d_keys, d_vals, nullptr, n, kInsert);
+  return direct_update(h, d_keys, d_vals, nullptr, n, kInsert);
 }
 
 lsm_status_t lsm_delete_batch(lsm_t h, const uint32_t* d_keys, uint32_t n) {
-  return update_batch(h, d_keys, nullptr, nullptr, n, kDelete);
+  return direct_update(h, d_keys, nullptr, nullptr, n, kDelete);
 }
 
 lsm_status_t lsm_update_batch(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals,
                               const uint8_t* d_is_delete, uint32_t n) {
-  return update_batch(h, d_keys, d_vals, d_is_delete, n, kMixed);
+  return direct_update(h, d_keys, d_vals, d_is_delete, n, kMixed);
 }
 
 lsm_status_t lsm_lookup(lsm_t h, const uint32_t* d_keys, uint32_t nq, uint32_t* d_vals,
@@ -877,12 +837,13 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
     const int nk = sort_kernel_count(sa);
     bool timed = h->prof;
     for (int x = 0; x < nk && timed; ++x) {
-      const KTimer* t = timer(h, ts[x], sort_kernel_kind(sa.path, x, sa.onepass), len,
+      const KTimer* t = timer(h, ts[x], sort_kernel_kind(sa.path, x), len,
                               sort_kernel_bytes_per_elem(sa.path, x) * len);
       if (t == nullptr) timed = false;
       else tt[x] = *t;
     }
-    e = launch_sort(sa, h->stream, timed ? tt : nullptr);
+    int launched = 0;
+    e = launch_sort(sa, h->stream, timed ? tt : nullptr, &launched);
     sorted += len;
     const uint32_t* ak = sa.out_kv;
     const uint32_t* av = sa.out_val;
@@ -1082,30 +1043,26 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   return LSM_OK;
 }
 
-lsm_status_t lsm_submit(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals, uint32_t n,
-                        int is_delete) {
-  if (h == nullptr) return LSM_EINVAL;
-  if (n == 0) return LSM_OK;
-  if (d_keys == nullptr || (!is_delete && d_vals == nullptr)) return LSM_EINVAL;
+// Coalescer: packs n operations, in arrival order, into the staging batch;
+// every b staged elements are inserted as one LSM batch.  is_delete[j] (or
+// all_delete) makes element j a deletion.
+static lsm_status_t submit(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals,
+                           const uint8_t* d_is_delete, int all_delete, uint32_t n) {
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
   if (h->flags & LSM_CHECKED) {
     // Validate the whole user batch before staging any of it.
-    const SortMeta m = sort_meta_carve(h->meta, h->b, 0);
-    if (hipMemsetAsync(m.err, 0, sizeof(uint32_t), h->stream) != hipSuccess ||
-        launch_check_keys(d_keys, n, h->key_bits, 0, m.err, h->stream) != hipSuccess ||
-        hipMemcpyAsync(h->h_pinned, m.err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(h->stream) != hipSuccess)
-      return LSM_EHIP;
-    if (*reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u) return LSM_EKEY;
+    bool bad = false;
+    const lsm_status_t s = check_keys(h, d_keys, n, &bad);
+    if (s != LSM_OK) return s;
+    if (bad) return LSM_EKEY;
   }
-  // Pack in arrival order; every b staged elements form one LSM batch.
   uint32_t done = 0;
   while (done < n) {
     const uint32_t take = (n - done) < (h->b - h->stage_fill) ? (n - done) : (h->b - h->stage_fill);
-    if (launch_stage(d_keys + done, is_delete ? nullptr : d_vals + done, take, is_delete,
-                     h->stage_kv, h->stage_val, h->stage_fill, h->stream) != hipSuccess)
+    if (launch_stage(d_keys + done, d_vals ? d_vals + done : nullptr,
+                     d_is_delete ? d_is_delete + done : nullptr, all_delete, take, h->stage_kv,
+                     h->stage_val, h->stage_fill, h->stream) != hipSuccess)
       return LSM_EHIP;
     h->stage_fill += take;
     done += take;
@@ -1117,37 +1074,20 @@ lsm_status_t lsm_submit(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals,
   return LSM_OK;
 }
 
-lsm_status_t lsm_submit_encoded(lsm_t h, const uint32_t* d_kv, const uint32_t* d_vals,
-                                uint32_t n) {
+lsm_status_t lsm_submit(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals, uint32_t n,
+                        int is_delete) {
   if (h == nullptr) return LSM_EINVAL;
   if (n == 0) return LSM_OK;
-  if (d_kv == nullptr || d_vals == nullptr) return LSM_EINVAL;
-  DeviceGuard g(h->device);
-  if (!g.ok) return LSM_EHIP;
-  if (h->flags & LSM_CHECKED) {
-    const SortMeta m = sort_meta_carve(h->meta, h->b, 0);
-    if (hipMemsetAsync(m.err, 0, sizeof(uint32_t), h->stream) != hipSuccess ||
-        launch_check_keys(d_kv, n, h->key_bits, 1, m.err, h->stream) != hipSuccess ||
-        hipMemcpyAsync(h->h_pinned, m.err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(h->stream) != hipSuccess)
-      return LSM_EHIP;
-    if (*reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u) return LSM_EKEY;
-  }
-  uint32_t done = 0;
-  while (done < n) {
-    const uint32_t take = (n - done) < (h->b - h->stage_fill) ? (n - done) : (h->b - h->stage_fill);
-    if (launch_stage_encoded(d_kv + done, d_vals + done, take, h->stage_kv, h->stage_val,
-                             h->stage_fill, h->stream) != hipSuccess)
-      return LSM_EHIP;
-    h->stage_fill += take;
-    done += take;
-    if (h->stage_fill == h->b) {
-      const lsm_status_t s = insert_staged(h, h->b);
-      if (s != LSM_OK) return s;
-    }
-  }
-  return LSM_OK;
+  if (d_keys == nullptr || (!is_delete && d_vals == nullptr)) return LSM_EINVAL;
+  return submit(h, d_keys, is_delete ? nullptr : d_vals, nullptr, is_delete ? 1 : 0, n);
+}
+
+lsm_status_t lsm_submit_mixed(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals,
+                              const uint8_t* d_is_delete, uint32_t n) {
+  if (h == nullptr) return LSM_EINVAL;
+  if (n == 0) return LSM_OK;
+  if (d_keys == nullptr || d_vals == nullptr || d_is_delete == nullptr) return LSM_EINVAL;
+  return submit(h, d_keys, d_vals, d_is_delete, 0, n);
 }
 
 lsm_status_t lsm_range_async(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint32_t nq,
@@ -1186,21 +1126,11 @@ lsm_status_t lsm_flush(lsm_t h) {
 
 uint32_t lsm_pending(lsm_t h) { return h ? h->stage_fill : 0; }
 
-lsm_status_t lsm_set_graphs(lsm_t h, int on) {
-  if (h == nullptr) return LSM_EINVAL;
-  if (on && (h->flags & LSM_CHECKED)) return LSM_EINVAL;
-  h->graphs = on != 0;
-  return LSM_OK;
-}
-
 lsm_status_t lsm_set_tuning(lsm_t h, uint32_t level, uint32_t variant) {
   if (h == nullptr || level >= static_cast<uint32_t>(kMaxLevels) ||
       variant >= static_cast<uint32_t>(kMergeVariants))
     return LSM_EINVAL;
-  if (h->merge_variant[level] != static_cast<int>(variant)) {
-    h->merge_variant[level] = static_cast<int>(variant);
-    drop_graphs(h);
-  }
+  h->merge_variant[level] = static_cast<int>(variant);
   return LSM_OK;
 }
 
@@ -1270,7 +1200,6 @@ lsm_status_t lsm_autotune(lsm_t h, uint32_t max_level, uint32_t reps) {
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(h->stream);
   for (int i = 0; i < 6; ++i) dev_free(h, buf[i], sz[i]);
-  drop_graphs(h);
   return s;
 }
 
@@ -1414,12 +1343,11 @@ lsm_status_t lsm_level_copy(lsm_t h, uint32_t i, uint32_t* d_kv_out, uint32_t* d
 lsm_status_t lsm_set_fusion(lsm_t h, int max_levels) {
   if (h == nullptr || max_levels > kMaxFuse) return LSM_EINVAL;
   h->fuse_max = max_levels < 0 ? default_fuse_max(h->b) : max_levels;
-  drop_graphs(h);
   return LSM_OK;
 }
 
 lsm_status_t lsm_set_sort_path(lsm_t h, int mode) {
-  if (h == nullptr || mode < LSM_SORT_AUTO || mode > LSM_SORT_ONE_KERNEL) return LSM_EINVAL;
+  if (h == nullptr || mode < LSM_SORT_AUTO || mode > LSM_SORT_DIGIT_PASSES) return LSM_EINVAL;
   h->sort_mode = mode;
   return LSM_OK;
 }

@@ -109,7 +109,6 @@ struct SortMeta {
                           // [1] sticky device fault (a bounded wait expired)
   uint32_t* tile_cnt;     // [num_sort_tiles][kTopBuckets / 2] each tile's digit-group starts
                           // (top-digit sort; two 16-bit starts per word)
-  uint32_t* bar;          // [2] grid barrier of the one-kernel top-digit sort
   uint32_t num_sort_tiles;
   int parity;
 };
@@ -160,7 +159,6 @@ struct SortArgs {
   uint32_t* out_fence;      // fences of the output when it is a level, else null
   uint32_t* out_digit;      // top-digit index of the output level (top-digit path), or null
   int path;                 // SortPath; both paths give the same order
-  int onepass;              // top-digit path as one kernel with grid barriers
   uint32_t* skew_out;       // optional: receives the largest top-digit bucket
   FuseArgs fuse;            // top-digit path only
 };
@@ -186,15 +184,11 @@ struct KTimer {
 enum KernelKind : int {
   kKSortHist = 0, kKSortPass = 1, kKMerge = 2, kKLookup = 3, kKCount = 4, kKScan = 5,
   kKRangeEmit = 6, kKOrder = 7, kKClean = 8, kKMsdHist = 9, kKMsdScatter = 10,
-  kKLocalSort = 11, kKOnePass = 12, kNumKernelKinds = 13
+  kKLocalSort = 11, kKSortStep = 12, kNumKernelKinds = 13
 };
-// Work-groups of the one-kernel top-digit sort: one per compute unit, so all
-// are resident at once (its grid barriers rely on that).
-constexpr uint32_t kOnePassGrid = 256;
 // Profiler kind and algorithmic bytes per element of the x-th kernel a sort
 // launches (launch_sort's order).
-inline int sort_kernel_kind(int path, int x, int onepass = 0) {
-  if (path == kSortMsd && onepass) return kKOnePass;
+inline int sort_kernel_kind(int path, int x) {
   if (path == kSortMsd) return x == 0 ? kKMsdScatter : kKLocalSort;
   return x == 0 ? kKSortHist : kKSortPass;
 }
@@ -220,8 +214,10 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity);
 // Sorts one batch into (out_kv, out_val): key variables ascending over bits
 // [lo_bit, lo_bit + 8 * passes), equal key variables with the later batch
 // position first.  timers (optional) holds sort_kernel_count(a) entries,
-// one per kernel launched.
-hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers);
+// one per kernel launched.  *launched receives the number of kernels that
+// were launched (all of them unless an error is returned).
+hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers,
+                       int* launched);
 // Number of kernels launch_sort issues (and timers it uses) for a.
 int sort_kernel_count(const SortArgs& a);
 
@@ -232,17 +228,12 @@ hipError_t launch_merge(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na
                         uint32_t* out_kv, uint32_t* out_val, uint32_t* out_fence, int variant,
                         hipStream_t stream, const KTimer* t);
 
-// Coalescer: encodes n keys of one user batch as key variables (status 0
-// for a deletion, value 0) into staging[at .. at + n).
-hipError_t launch_stage(const uint32_t* keys, const uint32_t* vals, uint32_t n, int is_delete,
-                        uint32_t* stage_kv, uint32_t* stage_val, uint32_t at,
-                        hipStream_t stream);
-
-// Coalescer: copies n pre-encoded key variables (and values; 0 for
-// tombstones) into staging[at .. at + n).
-hipError_t launch_stage_encoded(const uint32_t* kv, const uint32_t* vals, uint32_t n,
-                                uint32_t* stage_kv, uint32_t* stage_val, uint32_t at,
-                                hipStream_t stream);
+// Coalescer: encodes n operations as key variables (status 0 for a
+// deletion, value 0) into staging[at .. at + n).  Element i deletes when
+// all_delete is set or is_delete[i] != 0 (is_delete may be null).
+hipError_t launch_stage(const uint32_t* keys, const uint32_t* vals, const uint8_t* is_delete,
+                        int all_delete, uint32_t n, uint32_t* stage_kv, uint32_t* stage_val,
+                        uint32_t at, hipStream_t stream);
 
 // Sets err |= 1 when any of n keys (key variables when encoded) is
 // >= 2^limit_bits.

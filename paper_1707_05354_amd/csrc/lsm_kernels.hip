@@ -149,8 +149,6 @@ __device__ __forceinline__ uint64_t ld_dev64(const uint64_t* p) {
 __device__ __forceinline__ void st_dev64(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Loads and stores of data that other work-groups of the same kernel write
-// or read (kC: device-coherent accesses) or that only later kernels read.
 // A pointer known to address global memory (loads through it are global,
 // not flat, loads).
 __device__ __forceinline__ const __attribute__((address_space(1))) uint32_t* as_global(
@@ -158,16 +156,6 @@ __device__ __forceinline__ const __attribute__((address_space(1))) uint32_t* as_
   return (const __attribute__((address_space(1))) uint32_t*)(p);
 }
 
-template <bool kC>
-__device__ __forceinline__ uint32_t ldg(const uint32_t* p) {
-  if constexpr (kC) return ld_dev(p);
-  else return *p;
-}
-template <bool kC>
-__device__ __forceinline__ void stg(uint32_t* p, uint32_t v) {
-  if constexpr (kC) st_dev(p, v);
-  else *p = v;
-}
 
 // ------------------------------------------------------------ searches
 // Number of entries line[i], lo <= i < hi, that are < k (upper: <= k); the
@@ -673,7 +661,6 @@ struct ScatterLds {
   uint32_t tmp[2 * kWaves];
 };
 
-template <bool kC>
 __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, ScatterLds& S) {
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const SortMeta& m = a.meta;
@@ -733,8 +720,8 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
   // Global writes last, so that no barrier waits for them: the group starts,
   // the totals and the grouped tile.
   uint32_t* row = m.tile_cnt + static_cast<size_t>(tile) * (kTopBuckets / 2);
-  stg<kC>(&row[2 * tid], start[0] | (start[1] << 16));
-  stg<kC>(&row[2 * tid + 1], start[2] | (start[3] << 16));
+  row[2 * tid] = start[0] | (start[1] << 16);
+  row[2 * tid + 1] = start[2] | (start[3] << 16);
   uint32_t* tot = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
   static_assert(kTopBuckets <= kMaxPasses * kRadix, "totals fit one histogram buffer");
 #pragma unroll
@@ -742,8 +729,8 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
     if (cnt[q] != 0u) atomicAdd(&tot[d0 + q], cnt[q]);
   const uint32_t tile_n = (b - tbase) < static_cast<uint32_t>(kSortTile) ? (b - tbase) : kSortTile;
   for (uint32_t x = tid; x < tile_n; x += kThreads) {
-    stg<kC>(&a.tmp_kv[0][tbase + x], S.kv[x]);
-    stg<kC>(&a.tmp_val[0][tbase + x], S.val[x]);
+    a.tmp_kv[0][tbase + x] = S.kv[x];
+    a.tmp_val[0][tbase + x] = S.val[x];
   }
   __syncthreads();  // the caller may reuse S
 }
@@ -751,7 +738,7 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
 __global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_shift) {
   __shared__ ScatterLds S;
   clear_other_hist(a.meta);
-  tile_scatter<false>(a, top_shift, blockIdx.x, S);
+  tile_scatter(a, top_shift, blockIdx.x, S);
 }
 
 struct alignas(16) LocalLds {
@@ -812,7 +799,6 @@ __device__ void lds_pass(LocalLds& L, int from, uint32_t n, int shift) {
 // output (out_kv at s) or the second scratch buffer (tmp_kv[1] at s), chosen
 // so that the passes, ping-ponging between the two, end in the output.
 // Nothing else reads either range.
-template <bool kC>
 __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, uint32_t s,
                                      uint32_t n, LocalLds& L, const uint32_t* segb,
                                      const uint32_t* segp, uint32_t ntiles) {
@@ -827,9 +813,9 @@ __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, 
       if (probe < ntiles && segp[probe] <= x) g = probe;
     }
     const uint32_t at = segb[g] + (x - segp[g]);
-    const uint32_t k = ldg<kC>(&a.tmp_kv[0][at]);
+    const uint32_t k = a.tmp_kv[0][at];
     bk[first][x] = k;
-    bv[first][x] = ldg<kC>(&a.tmp_val[0][at]);
+    bv[first][x] = a.tmp_val[0][at];
     if (passes == 0) put_fence(a.out_fence, a.src.b, s + x, k);
   }
   if (passes == 0) return;
@@ -992,7 +978,6 @@ __device__ __forceinline__ uint32_t seg_bound(const uint32_t* s, uint32_t lo, ui
 // (key, run, position) is a strict total order, so the order is again the
 // cascade's.  Without fusion, the sort of a level records its buckets'
 // starts as that level's top-digit index.
-template <bool kC>
 __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t d, LocalLds& L) {
   const uint32_t tid = threadIdx.x;
   const SortMeta& m = a.meta;
@@ -1010,10 +995,10 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   const uint32_t* tot = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
   uint32_t gt[kTopPer];
 #pragma unroll
-  for (int q = 0; q < kTopPer; ++q) gt[q] = ldg<kC>(tot + tid * kTopPer + q);
+  for (int q = 0; q < kTopPer; ++q) gt[q] = *(tot + tid * kTopPer + q);
   const uint32_t* row = m.tile_cnt + static_cast<size_t>(tid < ntiles ? tid : 0) * (kTopBuckets / 2);
-  const uint32_t seg_w0 = ldg<kC>(&row[d >> 1]);
-  const uint32_t seg_w1 = ldg<kC>(&row[next_of(d) >> 1]);
+  const uint32_t seg_w0 = row[d >> 1];
+  const uint32_t seg_w1 = row[next_of(d) >> 1];
   // The digit's range in each fused level, from the level's top-digit index:
   // uniform loads, all issued before any is used (slots past j read level
   // 0's index and are ignored).
@@ -1206,13 +1191,8 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       if (static_cast<uint32_t>(i) * kThreads < nl) {
-        if constexpr (kC) {
-          rk[i] = ld_dev(pk[i] + at[i]);
-          rv[i] = ld_dev(pv[i] + at[i]);
-        } else {
-          rk[i] = as_global(pk[i])[at[i]];
-          rv[i] = as_global(pv[i])[at[i]];
-        }
+        rk[i] = as_global(pk[i])[at[i]];
+        rv[i] = as_global(pv[i])[at[i]];
       }
     }
 #pragma unroll
@@ -1253,7 +1233,7 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
     }
   } else {
     sorted_lds = false;
-    local_sort_streaming<kC>(a, lo_bit, passes, s, n, L, segb, segp, ntiles);
+    local_sort_streaming(a, lo_bit, passes, s, n, L, segb, segp, ntiles);
   }
 
   if (!fused) {
@@ -1326,58 +1306,7 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
 
 __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit, int passes) {
   __shared__ LocalLds L;
-  bucket_sort<false>(a, lo_bit, passes, blockIdx.x, L);
-}
-
-// Grid-wide barrier for a kernel whose work-groups are all resident (its
-// grid is at most one work-group per compute unit, far below what the device
-// holds).  *count only ever grows: the G arrivals at one barrier read values
-// in [kG, kG + G) (no work-group reaches the next barrier before all have
-// reached this one), so each waits until the count reaches kG + G, compared
-// modulo 2^32 (G divides 2^32).  Nothing is reset, so no ordering between
-// two stores is needed.  Data handed across the barrier is written with
-// st_dev and read with ld_dev (device-coherent accesses); before arriving, a
-// work-group waits for its own memory operations.  The wait is bounded: past
-// kSpinLimit polls it records a fault (reported by lsm_sync) and goes on.
-__device__ void grid_barrier(uint32_t* count, uint32_t* fault) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t G = gridDim.x;
-    const uint32_t old = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t target = (old / G + 1u) * G;
-    uint32_t spins = 0;
-    while (static_cast<int32_t>(ld_dev(count) - target) < 0) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins == kSpinLimit) {
-        atomicOr(fault, kFaultTimeout);
-        break;
-      }
-    }
-  }
-  __syncthreads();
-}
-
-// The top-digit sort as one kernel of kOnePassGrid work-groups: the tile
-// scatter, a grid barrier, then every work-group sorts the buckets
-// d = blockIdx.x, blockIdx.x + kOnePassGrid, ... (with the fused cascade).
-// Same results as the two kernels, with one device-wide exchange and no
-// kernel boundary.
-__global__ __launch_bounds__(kThreads) void k_msd_onepass(SortArgs a, int top_shift, int lo_bit,
-                                                          int passes) {
-  __shared__ union {
-    ScatterLds S;
-    LocalLds L;
-  } U;
-  const SortMeta& m = a.meta;
-  clear_other_hist(m);
-  const uint32_t tiles = m.num_sort_tiles;
-  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) tile_scatter<true>(a, top_shift, t, U.S);
-  grid_barrier(m.bar, m.err + 1);
-  for (uint32_t d = blockIdx.x; d < kTopBuckets; d += gridDim.x) {
-    bucket_sort<true>(a, lo_bit, passes, d, U.L);
-    __syncthreads();
-  }
+  bucket_sort(a, lo_bit, passes, blockIdx.x, L);
 }
 
 // ------------------------------------------------------------ merge
@@ -1560,24 +1489,18 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
 }
 
 // ------------------------------------------------------------ coalescer
+// Step a1 for the coalescer: encodes n operations as key variables (status
+// 0 for a deletion, whose value is 0) into staging[at .. at + n).  Element i
+// deletes when all_delete is set or is_delete[i] != 0.
 __global__ __launch_bounds__(kThreads) void k_stage(const uint32_t* keys, const uint32_t* vals,
-                                                    uint32_t n, int is_delete, uint32_t* stage_kv,
+                                                    const uint8_t* is_delete, int all_delete,
+                                                    uint32_t n, uint32_t* stage_kv,
                                                     uint32_t* stage_val, uint32_t at) {
   const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
-  const uint32_t st = is_delete ? 0u : 1u;
-  stage_kv[at + i] = (keys[i] << 1) | st;
-  stage_val[at + i] = st ? vals[i] : 0u;
-}
-
-__global__ __launch_bounds__(kThreads) void k_stage_encoded(const uint32_t* kv, const uint32_t* vals,
-                                                            uint32_t n, uint32_t* stage_kv,
-                                                            uint32_t* stage_val, uint32_t at) {
-  const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t x = kv[i];
-  stage_kv[at + i] = x;
-  stage_val[at + i] = (x & 1u) ? vals[i] : 0u;  // tombstones carry value 0
+  const bool del = all_delete != 0 || (is_delete != nullptr && is_delete[i] != 0);
+  stage_kv[at + i] = (keys[i] << 1) | (del ? 0u : 1u);
+  stage_val[at + i] = del ? 0u : vals[i];
 }
 
 __global__ __launch_bounds__(kThreads) void k_check_keys(const uint32_t* keys, uint32_t n,
@@ -2063,37 +1986,39 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
   m.tile_ctr = m.status + static_cast<size_t>(kMaxPasses) * m.num_sort_tiles * kRadix;
   m.err = m.tile_ctr + kMaxPasses;
   m.tile_cnt = m.err + 4;  // 16-byte aligned (vector loads of packed counts)
-  m.bar = m.tile_cnt + static_cast<size_t>(m.num_sort_tiles) * kTopBuckets;
   m.parity = parity;
   return m;
 }
 
 int sort_kernel_count(const SortArgs& a) {
-  if (a.path == kSortMsd) return a.onepass ? 1 : 2;
+  if (a.path == kSortMsd) return 2;
   return 1 + a.passes;
 }
 
-hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers) {
+hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers,
+                       int* launched) {
   const uint32_t tiles = a.meta.num_sort_tiles;
+  *launched = 0;
   if (a.path == kSortMsd && tiles <= static_cast<uint32_t>(kMsdMaxTiles)) {
     // Top digit: the highest 8 bits a key variable of this handle can have.
     const int top = sort_top_shift(a);
     const int local_passes = (top - a.lo_bit + kRadixBits - 1) / kRadixBits;
-    if (a.onepass)
-      return launch(k_msd_onepass, kOnePassGrid, kThreads, stream, timers ? &timers[0] : nullptr, a,
-                    top, a.lo_bit, local_passes);
     hipError_t e = launch(k_msd_scatter, tiles, kThreads, stream, timers ? &timers[0] : nullptr, a, top);
-    if (e == hipSuccess)
-      e = launch(k_local_sort, kTopBuckets, kThreads, stream, timers ? &timers[1] : nullptr, a,
-                 a.lo_bit, local_passes);
+    if (e != hipSuccess) return e;
+    *launched = 1;
+    e = launch(k_local_sort, kTopBuckets, kThreads, stream, timers ? &timers[1] : nullptr, a,
+               a.lo_bit, local_passes);
+    if (e == hipSuccess) *launched = 2;
     return e;
   }
   const uint32_t hist_grid = tiles < static_cast<uint32_t>(kMaxHistBlocks) ? tiles : kMaxHistBlocks;
   hipError_t e = launch(k_sort_hist, hist_grid, kThreads, stream, timers ? &timers[0] : nullptr, a);
   if (e != hipSuccess) return e;
+  *launched = 1;
   for (int p = 0; p < a.passes; ++p) {
     e = launch(k_sort_pass, tiles, kThreads, stream, timers ? &timers[1 + p] : nullptr, a, p);
     if (e != hipSuccess) return e;
+    *launched += 1;
   }
   return hipSuccess;
 }
@@ -2132,20 +2057,12 @@ hipError_t launch_merge(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na
   }
 }
 
-hipError_t launch_stage(const uint32_t* keys, const uint32_t* vals, uint32_t n, int is_delete,
-                        uint32_t* stage_kv, uint32_t* stage_val, uint32_t at,
-                        hipStream_t stream) {
+hipError_t launch_stage(const uint32_t* keys, const uint32_t* vals, const uint8_t* is_delete,
+                        int all_delete, uint32_t n, uint32_t* stage_kv, uint32_t* stage_val,
+                        uint32_t at, hipStream_t stream) {
   if (n == 0) return hipSuccess;
-  return launch(k_stage, grid_for(n, kThreads), kThreads, stream, nullptr, keys, vals, n, is_delete,
-                stage_kv, stage_val, at);
-}
-
-hipError_t launch_stage_encoded(const uint32_t* kv, const uint32_t* vals, uint32_t n,
-                                uint32_t* stage_kv, uint32_t* stage_val, uint32_t at,
-                                hipStream_t stream) {
-  if (n == 0) return hipSuccess;
-  return launch(k_stage_encoded, grid_for(n, kThreads), kThreads, stream, nullptr, kv, vals, n,
-                stage_kv, stage_val, at);
+  return launch(k_stage, grid_for(n, kThreads), kThreads, stream, nullptr, keys, vals, is_delete,
+                all_delete, n, stage_kv, stage_val, at);
 }
 
 hipError_t launch_check_keys(const uint32_t* keys, uint32_t n, uint32_t limit_bits, int encoded,

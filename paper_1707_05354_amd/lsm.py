@@ -8,9 +8,11 @@ there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import re
+import weakref
 from typing import Optional, Tuple
 
 import torch
@@ -41,7 +43,7 @@ class Stats(ctypes.Structure):
 
 KERNEL_NAMES = ("k_sort_hist", "k_sort_pass", "k_merge", "k_lookup", "k_count", "k_scan",
                 "k_range_emit", "k_order", "k_clean", "(unused)", "k_msd_scatter",
-                "k_local_sort", "k_msd_onepass")
+                "k_local_sort", "(unused)")
 # rocprofv3 kernel names behind each profiler kind that covers several kernels.
 KERNEL_TRACE_NAMES = {"k_order": ("k_successor", "k_predecessor"),
                       "k_clean": ("k_clean_count", "k_clean_scatter", "k_clean_pad"),
@@ -92,10 +94,9 @@ _SIGNATURES = {
     "lsm_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Stats)]),
     "lsm_submit": (ctypes.c_int, [_vp, _vp, _vp, _u32, ctypes.c_int]),
     "lsm_flush": (ctypes.c_int, [_vp]),
-    "lsm_submit_encoded": (ctypes.c_int, [_vp, _vp, _vp, _u32]),
+    "lsm_submit_mixed": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32]),
     "lsm_range_async": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _u64]),
     "lsm_pending": (_u32, [_vp]),
-    "lsm_set_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lsm_autotune": (ctypes.c_int, [_vp, _u32, _u32]),
     "lsm_get_tuning": (ctypes.c_int, [_vp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float)]),
     "lsm_set_tuning": (ctypes.c_int, [_vp, _u32, _u32]),
@@ -145,6 +146,21 @@ def _check(rc: int, where: str) -> None:
         raise LSMError(rc, where)
 
 
+# Every open handle, so that the ones still open when the interpreter exits
+# are destroyed by an atexit hook, while the HIP runtime is still fully up,
+# instead of by __del__ during interpreter teardown.
+_OPEN = weakref.WeakSet()
+
+
+@atexit.register
+def _close_open_handles() -> None:
+    for g in list(_OPEN):
+        try:
+            g.close()
+        except Exception:
+            pass
+
+
 class LSM:
     """A batched LSM dictionary resident on one GPU (see include/lsm.h)."""
 
@@ -160,10 +176,12 @@ class LSM:
                "lsm_create")
         self._h = h
         self._last_total = 0
+        _OPEN.add(self)
 
     # -- lifetime -----------------------------------------------------------
     def close(self) -> None:
         h, self._h = getattr(self, "_h", None), None
+        _OPEN.discard(self)
         if h:
             _check(self._lib.lsm_destroy(h), "lsm_destroy")
 
@@ -226,13 +244,16 @@ class LSM:
         _check(self._lib.lsm_submit(self._h, _dev(keys, "keys"), vp, n, 1 if delete else 0),
                "lsm_submit")
 
-    def submit_encoded(self, kv: torch.Tensor, vals: torch.Tensor) -> None:
-        """Arrival-ordered operations as key variables (key << 1 | status,
-        status 0 = delete) with values."""
-        if kv.numel() != vals.numel():
-            raise ValueError("kv and vals differ in length")
-        _check(self._lib.lsm_submit_encoded(self._h, _dev(kv, "kv"), _dev(vals, "vals"),
-                                            kv.numel()), "lsm_submit_encoded")
+    def submit_mixed(self, keys: torch.Tensor, vals: torch.Tensor,
+                     is_delete: torch.Tensor) -> None:
+        """Arrival-ordered operations of both types: element j deletes
+        keys[j] when is_delete[j] != 0, else inserts (keys[j], vals[j])."""
+        if not (keys.numel() == vals.numel() == is_delete.numel()):
+            raise ValueError("keys, vals and is_delete differ in length")
+        _check(self._lib.lsm_submit_mixed(
+            self._h, _dev(keys, "keys"), _dev(vals, "vals"),
+            _dev(is_delete, "is_delete", (torch.uint8, torch.bool)), keys.numel()),
+            "lsm_submit_mixed")
 
     def range_async(self, lo, hi, offsets, keys, vals, cap: int) -> None:
         _check(self._lib.lsm_range_async(self._h, _dev(lo, "lo"), _dev(hi, "hi"), lo.numel(),
@@ -248,9 +269,6 @@ class LSM:
     def pending(self) -> int:
         return int(self._lib.lsm_pending(self._h))
 
-    def use_graphs(self, on: bool = True) -> None:
-        _check(self._lib.lsm_set_graphs(self._h, 1 if on else 0), "lsm_set_graphs")
-
     def autotune(self, max_level: int, reps: int = 5) -> None:
         _check(self._lib.lsm_autotune(self._h, int(max_level), int(reps)), "lsm_autotune")
 
@@ -261,7 +279,7 @@ class LSM:
         _check(self._lib.lsm_get_tuning(self._h, int(level), ctypes.byref(v), us), "lsm_get_tuning")
         return int(v.value), [float(x) for x in us]
 
-    SORT_AUTO, SORT_TOP_DIGIT, SORT_DIGIT_PASSES, SORT_ONE_KERNEL = 0, 1, 2, 3
+    SORT_AUTO, SORT_TOP_DIGIT, SORT_DIGIT_PASSES = 0, 1, 2
 
     def set_sort_path(self, mode: int) -> None:
         """LSM.SORT_AUTO (default), LSM.SORT_TOP_DIGIT or LSM.SORT_DIGIT_PASSES."""

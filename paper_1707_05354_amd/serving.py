@@ -12,7 +12,8 @@ queries and updates run in separate phases):
      one lsm_lookup, one lsm_count and one lsm_range_async over the epoch's
      contiguous slices (each kind's payloads are laid out in arrival order);
   3. enqueue the epoch's updates, in arrival order, through the coalescer
-     (lsm_submit_encoded) and flush, so the next epoch sees them.
+     (lsm_submit_mixed: keys, values and delete flags, encoded by the
+     library) and flush, so the next epoch sees them.
 
 Epochs are enqueued without waiting for earlier ones (up to `in_flight`
 epochs on the device), so requests that arrive while an epoch runs are
@@ -140,7 +141,8 @@ class Server:
 
     def __init__(self, g: "L.LSM", reqs: ServingRequests, max_epoch_ops: int = 1 << 20,
                  in_flight: int = 2, pool_elems: Optional[int] = None,
-                 hbm_fraction: float = 0.25, keep_results: bool = False):
+                 hbm_fraction: float = 0.25, keep_results: bool = False,
+                 capture_ranges=False):
         self.g = g
         self.r = reqs
         self.max_epoch_ops = int(max_epoch_ops)
@@ -156,7 +158,8 @@ class Server:
         self.lk = up(reqs.lookup_keys)
         self.clo, self.chi = up(reqs.count_lo), up(reqs.count_hi)
         self.rlo, self.rhi = up(reqs.range_lo), up(reqs.range_hi)
-        self.ukv, self.uval = up(reqs.upd_kv), up(reqs.upd_val)
+        self.ukey, self.uval = up(reqs.upd_keys), up(reqs.upd_val)
+        self.udel = up(reqs.upd_is_del, torch.uint8)
         self.lk_val = torch.empty(max(1, reqs.lookup_keys.size), dtype=torch.int32, device=dev)
         self.lk_found = torch.empty(max(1, reqs.lookup_keys.size), dtype=torch.uint8, device=dev)
         self.cnt = torch.empty(max(1, reqs.count_lo.size), dtype=torch.int32, device=dev)
@@ -176,6 +179,12 @@ class Server:
             pool_elems = max(pool_elems, int(self.range_cost.sum()))
         self.pool = RangePool(pool_elems)
         self.keep = keep_results
+        # capture_ranges: each epoch's range output is copied to the host
+        # when the epoch retires, before its result slot can be reused (True:
+        # every epoch; a callable (first, last) -> bool: the epochs of
+        # requests [first, last) it accepts).
+        self.capture = capture_ranges
+        self.captured = {}
         self.rk = torch.empty(max(1, pool_elems), dtype=torch.int32, device=dev)
         self.rv = torch.empty(max(1, pool_elems), dtype=torch.int32, device=dev)
         n_rq = int(reqs.range_lo.size)
@@ -218,9 +227,10 @@ class Server:
             sel = np.nonzero(upd)[0]
             ua = int(r.off[i + sel[0]])
             ue = int(r.off[i + sel[-1]] + r.size[i + sel[-1]])
-            L._check(lib.lsm_submit_encoded(h, self.ukv.data_ptr() + 4 * ua,
-                                            self.uval.data_ptr() + 4 * ua, ue - ua),
-                     "lsm_submit_encoded")
+            L._check(lib.lsm_submit_mixed(h, self.ukey.data_ptr() + 4 * ua,
+                                          self.uval.data_ptr() + 4 * ua,
+                                          self.udel.data_ptr() + ua, ue - ua),
+                     "lsm_submit_mixed")
             L._check(lib.lsm_flush(h), "lsm_flush")
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
@@ -287,7 +297,15 @@ class Server:
                            {"epochs": len(epochs), "pool_elems": self.pool.capacity})
 
     def _retire(self, pending: List[Epoch]) -> None:
-        pending.pop(0)
+        """Called once the oldest pending epoch has completed."""
+        ep = pending.pop(0)
+        want = self.capture(ep.first, ep.last) if callable(self.capture) else self.capture
+        if want and ep.n_range_q:
+            off = self.roff[ep.range_off_base: ep.range_off_base + ep.n_range_q + 1].cpu().numpy()
+            n = int(off[-1])
+            self.captured[ep.first] = (
+                off, self.rk[ep.range_base: ep.range_base + n].cpu().numpy().view(np.uint32),
+                self.rv[ep.range_base: ep.range_base + n].cpu().numpy().view(np.uint32))
         if not self.keep:
             self.pool.release_oldest()
 
@@ -308,6 +326,14 @@ class Server:
             kinds = r.kind[ep.first:ep.last]
             first_q = int(r.off[ep.first + np.nonzero(kinds == RANGE)[0][0]])
             qa = a - first_q
+            if ep.first in self.captured:
+                eo, ek, ev = self.captured[ep.first]
+                off = eo[qa: qa + n + 1]
+                s, e = int(off[0]), int(off[-1])
+                return off - off[0], ek[s:e], ev[s:e]
+            if not self.keep:
+                raise RuntimeError("range results were released; serve with keep_results "
+                                   "or capture_ranges")
             off = self.roff[ep.range_off_base + qa: ep.range_off_base + qa + n + 1].cpu().numpy()
             s, e = int(off[0]), int(off[-1])
             keys = self.rk[ep.range_base + s: ep.range_base + e].cpu().numpy().view(np.uint32)

@@ -97,23 +97,85 @@ def _delete_batch_keys(config, keys, is_delete, b):
         keys[i] = keys[rows, idx % b]
 
 
-def _queries(config, keys, is_delete, nq, ncount, expected_hits, domain):
-    ins = keys[~is_delete].reshape(-1)
+def _key_classes(flat, bidx, dele):
+    """Classes of a stream's keys fixed by the stream itself, by set
+    membership alone.  flat: the keys of every operation in order, bidx:
+    each operation's batch number (non-decreasing), dele: whether it
+    deletes.  Returns `sure_live`, inserted keys that no deletion names
+    (present at the end whatever the order of operations), `sure_dead`,
+    deleted keys all of whose insertions come before their first deletion
+    (absent at the end), and `inserted`, every inserted key (sorted,
+    distinct)."""
+    flat = flat.astype(np.uint64)
+    bidx = bidx.astype(np.uint64)
+    ins = ~dele
+    # (key, batch) packed in 64 bits and sorted: per key, batches ascending.
+    iz = np.sort((flat[ins] << np.uint64(32)) | bidx[ins])
+    ik = (iz >> np.uint64(32)).astype(np.uint32)
+    last = np.append(ik[1:] != ik[:-1], True)          # last insertion of each key
+    inserted, ins_last = ik[last], (iz[last] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    if not dele.any():
+        return ik, np.zeros(0, np.uint32), inserted
+    dz = np.sort((flat[dele] << np.uint64(32)) | bidx[dele])
+    dk = (dz >> np.uint64(32)).astype(np.uint32)
+    first = np.insert(dk[1:] != dk[:-1], 0, True)       # first deletion of each key
+    dkeys, del_first = dk[first], (dz[first] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    j = np.minimum(np.searchsorted(inserted, dkeys), inserted.size - 1)
+    had = inserted[j] == dkeys
+    sure_dead = dkeys[~had | (ins_last[j] < del_first)]
+    j = np.minimum(np.searchsorted(dkeys, ik), dkeys.size - 1)
+    return ik[dkeys[j] != ik], sure_dead, inserted
+
+
+def query_set(config, flat, bidx, dele, nq, ncount, expected_hits, domain=KEY_DOMAIN):
+    """Queries over a stream of operations (see _key_classes for the stream's
+    arrays).  Lookups: half hits drawn from the keys sure to be present, half
+    misses (half of those deleted keys, half keys never inserted).  Count /
+    range widths expect `expected_hits` present keys, from the estimated
+    number of present keys (inserted keys minus those sure to be deleted).
+    Returns (lookups, count_lo, count_hi, range_lo, range_hi, width)."""
+    live, dead, inserted = _key_classes(flat, bidx, dele)
     pick = splitmix64(config, 4, 0, nq)
     hit = (pick & np.uint64(1)).astype(bool)
-    idx = ((pick >> np.uint64(32)) * np.uint64(ins.size)) >> np.uint64(32)
-    miss = (splitmix64(config, 6, 0, nq) % np.uint64(domain)).astype(np.uint32)
-    lookups = np.where(hit, ins[idx.astype(np.int64)], miss).astype(np.uint32)
-    width = max(1, int(round(expected_hits * domain / max(1, ins.size))))
+    idx = ((pick >> np.uint64(32)) * np.uint64(live.size)) >> np.uint64(32)
+    # Misses: a uniform draw, rejected while it names an inserted key
+    # (redrawn from later positions of the stream).
+    miss = np.zeros(nq, np.uint32)
+    todo = np.arange(nq)
+    start = 0
+    while todo.size:
+        cand = (splitmix64(config, 6, start, todo.size) % np.uint64(domain)).astype(np.uint32)
+        start += todo.size
+        o = np.argsort(cand)  # sorted probes search much faster
+        j = np.empty(cand.size, np.int64)
+        j[o] = np.searchsorted(inserted, cand[o])
+        clash = (j < inserted.size) & (inserted[np.minimum(j, inserted.size - 1)] == cand)
+        miss[todo[~clash]] = cand[~clash]
+        todo = todo[clash]
+    if dead.size:
+        dpick = splitmix64(config, 6, 1 << 40, nq)
+        use_dead = (dpick & np.uint64(1)).astype(bool)
+        didx = ((dpick >> np.uint64(32)) * np.uint64(dead.size)) >> np.uint64(32)
+        miss = np.where(use_dead, dead[didx.astype(np.int64)], miss)
+    lookups = np.where(hit, live[idx.astype(np.int64)], miss).astype(np.uint32)
+    present = max(1, inserted.size - dead.size)
+    width = max(1, int(round(expected_hits * domain / present)))
     starts = bounded(config, 5, 0, 2 * ncount, domain - width + 1).astype(np.uint32)
     c_lo, r_lo = starts[:ncount], starts[ncount:]
     return lookups, c_lo, (c_lo + np.uint32(width - 1)), r_lo, (r_lo + np.uint32(width - 1)), width
 
 
+def _queries(config, keys, is_delete, nq, ncount, expected_hits, domain):
+    """query_set over R batches of b (keys [R, b], is_delete [R])."""
+    R, b = keys.shape
+    return query_set(config, keys.reshape(-1), np.repeat(np.arange(R), b),
+                     np.repeat(is_delete, b), nq, ncount, expected_hits, domain)
+
+
 def tiny(config: int = 1) -> PlainWorkload:
     """b = 1024: 16 insert batches, then 4 delete batches of keys drawn from
-    the inserted ones; 4096 lookups (half drawn from inserted keys), 1024
-    count and 1024 range queries whose width expects about 8 hits."""
+    the inserted ones; 4096 lookups (half hits), 1024 count and 1024 range
+    queries whose width expects about 8 hits."""
     b, R = 1024, 20
     is_delete = np.array([False] * 16 + [True] * 4)
     keys = uniform_keys(config, 1, 0, R * b).reshape(R, b)
@@ -128,8 +190,8 @@ def paper_scale(config: int = 2, b: int = 1 << 16, R: int = 1024, nq: int = 1 <<
                 ncount: int = 1 << 20, expected_hits: int = 16) -> PlainWorkload:
     """b = 2^16, R = 1024 batches (n = 2^26 slots), uniform 31-bit keys;
     batch i deletes iff i mod 10 == 9 (keys drawn from earlier inserts).
-    Then 2^22 lookups (half drawn from inserted keys), 2^20 count and 2^20
-    range queries of a width that expects 16 hits."""
+    Then 2^22 lookups (half hits), 2^20 count and 2^20 range queries of a
+    width that expects 16 hits."""
     is_delete = (np.arange(R) % 10) == 9
     keys = uniform_keys(config, 1, 0, R * b).reshape(R, b)
     vals = values(config, 2, 0, R * b).reshape(R, b)
@@ -310,8 +372,8 @@ class ServingRequests:
     Payloads are laid out per kind in arrival order, so the requests of one
     kind admitted together form one contiguous slice: lookup_keys,
     count_lo/hi, range_lo/hi; inserts and deletes share one update stream of
-    key variables (key << 1 | 1 for an insert, key << 1 for a delete) and
-    values.  off[r] is the request's first element in its kind's stream."""
+    keys, values and delete flags (1 for a delete).  off[r] is the
+    request's first element in its kind's stream."""
     t_arrive: np.ndarray
     kind: np.ndarray
     size: np.ndarray
@@ -321,8 +383,9 @@ class ServingRequests:
     count_hi: np.ndarray
     range_lo: np.ndarray
     range_hi: np.ndarray
-    upd_kv: np.ndarray
+    upd_keys: np.ndarray
     upd_val: np.ndarray
+    upd_is_del: np.ndarray
     width: int
 
     @property
@@ -372,9 +435,19 @@ def serving_requests(resident_keys: np.ndarray, n_requests: int, rate: float, co
     del_pick = bounded(config, 27, 0, n_upd, res.size)
     upd_is_del = np.repeat(kind[upd] == 4, size[upd])
     upd_keys = np.where(upd_is_del, res[del_pick], ins_keys).astype(np.uint32)
-    upd_kv = (upd_keys << np.uint32(1)) | (~upd_is_del).astype(np.uint32)
     upd_val = values(config, 28, 0, n_upd)
     return ServingRequests(t, kind, size, off, lookup_keys.astype(np.uint32),
                            starts[:n_ct], starts[:n_ct] + np.uint32(width - 1),
                            starts[n_ct:], starts[n_ct:] + np.uint32(width - 1),
-                           upd_kv.astype(np.uint32), upd_val, width)
+                           upd_keys, upd_val, upd_is_del.astype(np.uint8), width)
+
+
+def batching_queries(user_batches, config: int = 4, nq: int = 1 << 20, ncount: int = 1 << 16,
+                     expected_hits: int = 16):
+    """Queries for the batching form's user batches: query_set over the
+    concatenated operations, each user batch its own batch number."""
+    sizes = [u[0].size for u in user_batches]
+    flat = np.concatenate([u[0] for u in user_batches])
+    bidx = np.repeat(np.arange(len(user_batches)), sizes)
+    dele = np.repeat(np.array([bool(u[2]) for u in user_batches]), sizes)
+    return query_set(config, flat, bidx, dele, nq, ncount, expected_hits)

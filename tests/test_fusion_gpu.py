@@ -73,20 +73,6 @@ def test_partly_fused_cascades(depth):
     assert levels(fused) == levels(plain)
 
 
-@pytest.mark.parametrize("b,R,domain", [(1, 150, 20), (64, 40, 5000), (4099, 19, 1 << 14),
-                                        (1 << 16, 17, 1 << 31), (10000, 9, 1 << 20)])
-def test_one_kernel_sort_equals_three_kernels(b, R, domain):
-    """The top-digit sort as one kernel with device-wide barriers, fused
-    cascade included, against the same inserts through three kernels (and
-    the oracle); the last case puts every key in one top digit."""
-    note("one-kernel sort b=%d R=%d" % (b, R))
-    ops = stream(3000 + b, b, R, domain)
-    one = run(b, ops, -1, mode=LSM.SORT_ONE_KERNEL)
-    three = run(b, ops, -1, mode=LSM.SORT_TOP_DIGIT)
-    assert levels(one) == levels(three)
-    assert one.g.stats().sorts_top_digit == R
-
-
 @pytest.mark.parametrize("b", [4096, 10000])
 def test_fused_cascade_with_one_top_digit(b):
     """Keys below 2^20 share the top digit: one bucket holds every element,

@@ -297,7 +297,7 @@ def test_sort_path_follows_key_skew():
     assert paths == ["top", "passes", "passes", "passes", "top", "top", "top"], paths
 
 
-@pytest.mark.parametrize("mode", [LSM.SORT_TOP_DIGIT, LSM.SORT_DIGIT_PASSES, LSM.SORT_ONE_KERNEL])
+@pytest.mark.parametrize("mode", [LSM.SORT_TOP_DIGIT, LSM.SORT_DIGIT_PASSES])
 def test_forced_sort_paths(mode):
     """Either path, forced, on batches of 1 to 256 tiles (the top-digit
     sort's limit) with partial batches: top-digit buckets sorted by ranking

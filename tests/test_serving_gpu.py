@@ -17,9 +17,8 @@ from _gpu import dev, host, note
 pytestmark = pytest.mark.gpu
 
 
-def build(b, rk, rv, graphs=True):
+def build(b, rk, rv):
     g = LSM(b)
-    g.use_graphs(graphs)
     kd, vd = dev(rk), dev(rv)
     for i in range(rk.shape[0]):
         g.insert(kd[i], vd[i])
@@ -38,11 +37,12 @@ def oracle_answer(m, reqs, q):
 
 def apply_update(m, reqs, q):
     a, n = int(reqs.off[q]), int(reqs.size[q])
-    kv, v = reqs.upd_kv[a:a + n], reqs.upd_val[a:a + n]
+    k, v = reqs.upd_keys[a:a + n], reqs.upd_val[a:a + n]
+    assert np.all(reqs.upd_is_del[a:a + n] == (1 if reqs.kind[q] == DELETE else 0))
     if reqs.kind[q] == INSERT:
-        m.insert(kv >> 1, v)
+        m.insert(k, v)
     else:
-        m.delete(kv >> 1)
+        m.delete(k)
 
 
 def same(x, y):
@@ -55,9 +55,10 @@ def same(x, y):
 def alone(b, rk, rv, reqs, q, upd_prefix):
     """Serve request q by itself on a dictionary rebuilt from the resident
     batches plus the first upd_prefix update operations."""
-    g = build(b, rk, rv, graphs=False)
+    g = build(b, rk, rv)
     if upd_prefix:
-        g.submit_encoded(dev(reqs.upd_kv[:upd_prefix]), dev(reqs.upd_val[:upd_prefix]))
+        g.submit_mixed(dev(reqs.upd_keys[:upd_prefix]), dev(reqs.upd_val[:upd_prefix]),
+                       torch.from_numpy(reqs.upd_is_del[:upd_prefix].copy()).cuda())
     k, a, n = int(reqs.kind[q]), int(reqs.off[q]), int(reqs.size[q])
     if k == LOOKUP:
         v, f = g.lookup(dev(reqs.lookup_keys[a:a + n]))
@@ -110,7 +111,10 @@ def test_mix_equals_epoch_oracle_and_alone(realtime):
 def test_result_pool_smaller_than_demand_still_exact():
     """A result pool far smaller than the run's total range output forces
     admission by memory (epochs wait for older ones to complete and free
-    their slots); answers stay exact."""
+    their slots, which are then reused).  Every answer of that run is
+    checked against the epoch-log oracle: lookups and counts from their
+    own (unpooled) outputs, ranges from each epoch's slot as copied to the
+    host when the epoch retired, before its slot could be reused."""
     b = 2048
     rk, rv = W.resident(config=52, b=b, R=8)
     reqs = W.serving_requests(rk, 300, rate=1e5, config=52, max_size=300, expected_hits=4)
@@ -118,23 +122,21 @@ def test_result_pool_smaller_than_demand_still_exact():
     cost = Server(g, reqs).range_cost
     pool = int(cost.max()) + 10
     note("serving small pool %d of %d" % (pool, int(cost.sum())))
-    srv = Server(g, reqs, max_epoch_ops=3000, in_flight=2, pool_elems=pool)
-    # Results are released as epochs retire, so check answers as we go via
-    # a second run that keeps results, on an identical dictionary.
+    assert cost.sum() > 4 * pool
+    srv = Server(g, reqs, max_epoch_ops=3000, in_flight=2, pool_elems=pool, capture_ranges=True)
     res = srv.run(realtime=False)
     assert len(res.epochs) > 3
-    g2 = build(b, rk, rv)
-    srv2 = Server(g2, reqs, max_epoch_ops=3000, in_flight=2, keep_results=True)
-    res2 = srv2.run(realtime=False)
     m = oracle.MapOracle()
     for i in range(rk.shape[0]):
         m.insert(rk[i], rv[i])
-    for ep in res2.epochs:
+    n_checked = 0
+    for ep in res.epochs:
         for q in range(ep.first, ep.last):
             if reqs.kind[q] in (LOOKUP, COUNT, RANGE):
-                assert same(srv2.results(res2, q), oracle_answer(m, reqs, q))
+                assert same(srv.results(res, q), oracle_answer(m, reqs, q)), (q, int(reqs.kind[q]))
+                n_checked += int(reqs.kind[q] == RANGE)
         for q in range(ep.first, ep.last):
             if reqs.kind[q] in (INSERT, DELETE):
                 apply_update(m, reqs, q)
+    assert n_checked == int((reqs.kind == RANGE).sum())
     g.close()
-    g2.close()
