@@ -395,16 +395,21 @@ LSM_API lsm_status_t lsm_get_stats(lsm_t h, lsm_stats_t* out);
  * digit pass, 2 level merge, 3 lookup, 4 count, 5 range offset scan, 6 range
  * emission, 7 successor / predecessor, 8 cleanup mark-and-compact, 9 not
  * used (no kernel of this library is counted there), 10 / 11 the top-digit
- * sort's tile scatter and per-bucket sort, 12 not used.
+ * sort's tile scatter and per-bucket sort, 12 the pipelined top-digit sort
+ * step (the bucket sort of one batch and the tile scatter of the next in one
+ * launch).
  * kernel_bytes[k] is the algorithmic traffic of those launches: 4 B per
  * batch element for a histogram (keys read), 16 B per element for a digit
  * pass, the top-digit scatter and the per-bucket sort (key and value read
- * and written), 16 B per merge output element, 12 B per scanned count; for
+ * and written; a per-bucket sort with a fused cascade adds 16 B per element
+ * of the levels it takes over), the sum of both for a pipelined step, 16 B
+ * per merge output element, 12 B per scanned count; for
  * cleanup 4 B per merged element to count, 8 B per merged element read plus
  * 8 B per valid element written to scatter, 8 B per placebo; 0 for the
  * search kernels, which are latency-bound.
  */
 #define LSM_PROF_KERNELS 13
+#define LSM_PROF_SIZES 40
 typedef struct {
   uint64_t update_calls;                   /* update calls (n > 0)          */
   uint64_t query_calls[3];                 /* lookup, count, range calls    */
@@ -418,9 +423,19 @@ typedef struct {
   double update_p99_ms;
   double update_max_ms;
   double query_ms[3];    /* lookup, count, range: first start to last end    */
+  /* Level merges (kernel 2) by output size: entry k sums the launches whose
+     output holds 2^(k-1) + 1 .. 2^k elements (the cascade's merge into level
+     i + 1 of a handle with b = 2^m lands in entry i + 1 + m). */
+  uint64_t merge_launches_by_size[LSM_PROF_SIZES];
+  double merge_ms_by_size[LSM_PROF_SIZES];
+  double merge_bytes_by_size[LSM_PROF_SIZES];
 } lsm_profile_t;
 
 LSM_API lsm_status_t lsm_profile_enable(lsm_t h, int on);
+
+/* sizeof(lsm_stats_t) and sizeof(lsm_profile_t), so that a binding can check
+ * its copies of the two structures before passing them in. */
+LSM_API void lsm_struct_sizes(size_t* stats_size, size_t* profile_size);
 LSM_API lsm_status_t lsm_profile_read(lsm_t h, lsm_profile_t* out, int reset);
 
 #ifdef __cplusplus

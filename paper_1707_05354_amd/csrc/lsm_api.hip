@@ -49,10 +49,26 @@ struct lsm_s {
 
   uint32_t* tmp_kv[2] = {};  // radix ping-pong, b elements each
   uint32_t* tmp_val[2] = {};
+  uint32_t* scat_kv[kSortSlots] = {};  // top-digit sort: the tile-grouped batch of each slot
+  uint32_t* scat_val[kSortSlots] = {};
   uint32_t* buf_kv = nullptr;  // the sorted batch when it has to be merged
   uint32_t* buf_val = nullptr;
-  uint32_t* meta = nullptr;  // sort histograms, look-back words, barrier, error words
-  int hist_parity = 0;       // which global histogram buffer the next sort uses
+  uint32_t* meta = nullptr;  // sort histograms, look-back words, group starts, error words
+  int hist_parity = 0;       // which histogram buffer the next digit-pass sort uses
+
+  // Pipelined insertion: the newest batch sorted by the top-digit sort has
+  // had its tiles scattered (into scratch slot `slot`) but not its buckets
+  // sorted and merged; that second half runs in the same launch as the next
+  // batch's scatter, or on its own when anything needs the levels.  The
+  // batch already counts in r; it fills level j.
+  struct Pending {
+    bool on = false;
+    int slot = 0;
+    int j = 0;
+    int lo_bit = 1;
+    int passes = 0;
+  } pend;
+  int next_slot = 0;
   uint32_t* fault = nullptr; // sticky device fault word (inside meta)
 
   uint32_t* mrg_kv[2] = {};  // cascade ping-pong
@@ -89,7 +105,7 @@ struct lsm_s {
   // Profiling: events recorded on the stream between kernels, resolved on
   // lsm_profile_read.  A span is a pair of indices into `marks`.
   struct Span {
-    int kind;  // KernelKind for a kernel; 10 update call; 11..13 lookup/count/range call
+    int kind;  // KernelKind for a kernel; kSpanUpdate.. for a whole call
     uint32_t a, b;
     uint64_t items;
     double bytes;  // algorithmic bytes of a kernel launch
@@ -240,6 +256,10 @@ void release_all(lsm_t h) {
     dev_free(h, h->mrg_kv[i], h->mrg_cap * sizeof(uint32_t));
     dev_free(h, h->mrg_val[i], h->mrg_cap * sizeof(uint32_t));
   }
+  for (int i = 0; i < kSortSlots; ++i) {
+    dev_free(h, h->scat_kv[i], bb);
+    dev_free(h, h->scat_val[i], bb);
+  }
   dev_free(h, h->buf_kv, bb);
   dev_free(h, h->buf_val, bb);
   dev_free(h, h->meta, sort_meta_words(h->b) * sizeof(uint32_t));
@@ -318,12 +338,9 @@ lsm_status_t prepare_insert(lsm_t h, int j) {
 }
 
 int sort_path(lsm_t h, uint32_t tiles) {
-  int p;
-  if (h->sort_mode == LSM_SORT_DIGIT_PASSES) p = kSortLsd;
-  else if (h->sort_mode == LSM_SORT_TOP_DIGIT) p = pick_sort_path(tiles, 0u);
-  else p = pick_sort_path(tiles, *reinterpret_cast<volatile uint32_t*>(h->skew_host));
-  h->sorts_by_path[p] += 1;
-  return p;
+  if (h->sort_mode == LSM_SORT_DIGIT_PASSES) return kSortLsd;
+  if (h->sort_mode == LSM_SORT_TOP_DIGIT) return pick_sort_path(tiles, 0u);
+  return pick_sort_path(tiles, *reinterpret_cast<volatile uint32_t*>(h->skew_host));
 }
 // Default depth of the fused cascade: level j is fused while a bucket of
 // level j holds about 4096 elements on average (b 2^j / 256 <= 2^12).
@@ -387,25 +404,80 @@ void note_digit_index(lsm_t h, const SortArgs& sa, int j) {
   h->digit_shift[j] = indexed ? sort_top_shift(sa) - 1 : -1;
 }
 
-SortArgs sort_args(lsm_t h, const BatchSrc& src, int j) {
-  SortArgs sa{};
-  sa.src = src;
-  sa.lo_bit = (src.mode == kMixed) ? 0 : 1;
+// Sort parameters of a batch: single-type batches sort the key variable
+// without its (constant) status bit, mixed batches include it (sec. III-A
+// rule 5 puts a batch's tombstone of a key before its insertion).
+void sort_params(lsm_t h, int mode, SortArgs& sa) {
+  sa.lo_bit = (mode == kMixed) ? 0 : 1;
   sa.passes = sort_passes(h->key_bits, sa.lo_bit);
   sa.key_limit_bits = h->key_bits;
-  sa.checked = 0;
-  sa.meta = sort_meta_carve(h->meta, h->b, h->hist_parity);
-  sa.tmp_kv[0] = h->tmp_kv[0];
+}
+
+// Arguments of a whole (non-pipelined) sort of the batch src for an insert
+// into level j, with its fused cascade.
+SortArgs sort_args(lsm_t h, const BatchSrc& src, int j, int path) {
+  SortArgs sa{};
+  sa.src = src;
+  sort_params(h, src.mode, sa);
+  sa.meta = sort_meta_carve(h->meta, h->b, h->hist_parity, 0);
+  sa.tmp_kv[0] = path == kSortMsd ? h->scat_kv[0] : h->tmp_kv[0];
+  sa.tmp_val[0] = path == kSortMsd ? h->scat_val[0] : h->tmp_val[0];
   sa.tmp_kv[1] = h->tmp_kv[1];
-  sa.tmp_val[0] = h->tmp_val[0];
   sa.tmp_val[1] = h->tmp_val[1];
   sa.out_kv = (j == 0) ? h->lvl_kv[0] : h->buf_kv;
   sa.out_val = (j == 0) ? h->lvl_val[0] : h->buf_val;
   sa.out_fence = (j == 0) ? h->lvl_fence[0] : nullptr;
-  sa.path = sort_path(h, sa.meta.num_sort_tiles);
+  sa.path = path;
   sa.skew_out = h->skew_dev;
   setup_fusion(h, sa, j);
   return sa;
+}
+
+// Arguments of the tile scatter of the batch src into slot `slot`.
+SortArgs scatter_args(lsm_t h, const BatchSrc& src, int slot) {
+  SortArgs sa{};
+  sa.src = src;
+  sort_params(h, src.mode, sa);
+  sa.meta = sort_meta_carve(h->meta, h->b, h->hist_parity, slot);
+  sa.tmp_kv[0] = h->scat_kv[slot];
+  sa.tmp_val[0] = h->scat_val[slot];
+  sa.tmp_kv[1] = h->tmp_kv[1];
+  sa.tmp_val[1] = h->tmp_val[1];
+  sa.path = kSortMsd;
+  sa.skew_out = h->skew_dev;
+  return sa;
+}
+
+// Arguments of the bucket sort (and fused cascade) of the pending batch, for
+// the state of the levels it meets: every earlier batch's insertion has been
+// enqueued.
+SortArgs pending_args(lsm_t h) {
+  const lsm_s::Pending& p = h->pend;
+  SortArgs sa{};
+  sa.src = BatchSrc{nullptr, nullptr, nullptr, h->b, h->b, kInsert};  // read from the slot
+  sa.lo_bit = p.lo_bit;
+  sa.passes = p.passes;
+  sa.key_limit_bits = h->key_bits;
+  sa.meta = sort_meta_carve(h->meta, h->b, h->hist_parity, p.slot);
+  sa.tmp_kv[0] = h->scat_kv[p.slot];
+  sa.tmp_val[0] = h->scat_val[p.slot];
+  sa.tmp_kv[1] = h->tmp_kv[1];
+  sa.tmp_val[1] = h->tmp_val[1];
+  sa.out_kv = (p.j == 0) ? h->lvl_kv[0] : h->buf_kv;
+  sa.out_val = (p.j == 0) ? h->lvl_val[0] : h->buf_val;
+  sa.out_fence = (p.j == 0) ? h->lvl_fence[0] : nullptr;
+  sa.path = kSortMsd;
+  sa.skew_out = h->skew_dev;
+  setup_fusion(h, sa, p.j);
+  return sa;
+}
+
+// Algorithmic bytes of the bucket half of a top-digit sort: the batch's key
+// and value read and written, and with a fused cascade every element of the
+// levels it takes over read and of the level it writes written.
+double bucket_bytes(lsm_t h, const SortArgs& sa) {
+  return sa.fuse.nlev > 0 ? 16.0 * static_cast<double>(level_len(h, sa.fuse.nlev))
+                          : 16.0 * static_cast<double>(h->b);
 }
 
 // The cascade of Fig. 2(a): while level i is full, buffer <- merge(buffer,
@@ -438,15 +510,71 @@ hipError_t enqueue_cascade(lsm_t h, const SortArgs& sa, int j, hipStream_t s, Ti
   return hipSuccess;
 }
 
-void commit_insert(lsm_t h, uint64_t merged) {
+// Sets *bad when any of n keys is >= 2^key_bits (checked mode); synchronises.
+lsm_status_t check_keys(lsm_t h, const uint32_t* keys, uint32_t n, bool* bad) {
+  const SortMeta m = sort_meta_carve(h->meta, h->b, 0, 0);
+  if (hipMemsetAsync(m.err, 0, sizeof(uint32_t), h->stream) != hipSuccess ||
+      launch_check_keys(keys, n, h->key_bits, 0, m.err, h->stream) != hipSuccess ||
+      hipMemcpyAsync(h->h_pinned, m.err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return LSM_EHIP;
+  *bad = *reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u;
+  return LSM_OK;
+}
+
+void commit_insert(lsm_t h, int j) {
+  const uint64_t merged = (j == 0) ? 0 : (2ull << j) * h->b - 2ull * h->b;
   h->r += 1;
   h->merged_last = merged;
   h->merged_total += merged;
   h->sorted_total += h->b;
 }
 
+// Enqueues the second half of the pending batch's insertion (its bucket sort
+// with the fused cascade, then the remaining merges), in one launch with the
+// tile scatter `next` when given.  On failure the batch stays pending (its
+// slot is untouched, so it can be redone) and the state is unchanged.
+hipError_t launch_pending(lsm_t h, const SortArgs* next, Timed* first, Timed* last) {
+  const SortArgs bk = pending_args(h);
+  const int j = h->pend.j;
+  Timed ts;
+  const KTimer* t =
+      next != nullptr
+          ? timer(h, ts, kKSortStep, h->b, bucket_bytes(h, bk) + 16.0 * static_cast<double>(h->b))
+          : timer(h, ts, kKLocalSort, h->b, bucket_bytes(h, bk));
+  hipError_t e = next != nullptr ? launch_sort_step(bk, *next, h->stream, t)
+                                 : launch_buckets(bk, h->stream, t);
+  if (e != hipSuccess) return e;
+  if (t != nullptr) {
+    if (first) *first = ts;
+    if (last) *last = ts;
+  }
+  e = enqueue_cascade(h, bk, j, h->stream, t != nullptr ? last : nullptr, nullptr);
+  if (e != hipSuccess) return e;
+  note_digit_index(h, bk, j);
+  h->pend.on = false;
+  return hipSuccess;
+}
+
+// Completes the pending insertion, if any: everything that reads the levels
+// calls this first.
+lsm_status_t drain(lsm_t h) {
+  if (!h->pend.on) return LSM_OK;
+  Timed first, last;
+  if (launch_pending(h, nullptr, &first, &last) != hipSuccess) return LSM_EHIP;
+  return LSM_OK;
+}
+
 // One update batch (sec. III-B insertion; deletions and mixed batches are
 // insertions whose elements carry status 0 where they delete).
+//
+// Batches sorted by the top-digit sort are pipelined: this call scatters the
+// batch's tiles and, in the same launch, sorts the buckets of the previous
+// batch and merges them into that batch's level; this batch's buckets follow
+// at the next update or when anything reads the levels.  The caller's arrays
+// are read only by this call's launch.  Other batches (digit-pass sort) first
+// complete the pending one, then are sorted and merged in this call.
 lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
                           const uint8_t* is_delete, uint32_t n, BatchMode mode) {
   if (h == nullptr) return LSM_EINVAL;
@@ -458,52 +586,73 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
 
-  // First empty level j = ffz(r); the merges fill it with b * 2^j elements.
+  // First empty level j = ffz(r) (r counts the pending batch); the batch's
+  // insertion fills it with b * 2^j elements.  Everything it needs is
+  // allocated now, so the deferred half cannot fail for want of memory.
   const int j = __builtin_ctzll(~h->r);
   lsm_status_t s = prepare_insert(h, j);
   if (s != LSM_OK) return s;
+  if ((h->flags & LSM_CHECKED) && mode != kEncoded) {
+    bool bad = false;
+    s = check_keys(h, keys, n, &bad);
+    if (s != LSM_OK) return s;
+    if (bad) return LSM_EKEY;
+  }
+  const BatchSrc src{keys, vals, is_delete, n, h->b, static_cast<int>(mode)};
+  const int path = sort_path(h, sort_meta_carve(h->meta, h->b, 0, 0).num_sort_tiles);
 
-  const bool checked = (h->flags & LSM_CHECKED) != 0 && mode != kEncoded;
-  SortArgs sa = sort_args(h, BatchSrc{keys, vals, is_delete, n, h->b, static_cast<int>(mode)}, j);
-  sa.checked = checked ? 1 : 0;
-  if (checked && hipMemsetAsync(sa.meta.err, 0, sizeof(uint32_t), h->stream) != hipSuccess)
-    return LSM_EHIP;
+  if (path == kSortMsd) {
+    const int slot = h->pend.on ? (h->pend.slot ^ 1) : h->next_slot;
+    const SortArgs sc = scatter_args(h, src, slot);
+    Timed first, last;
+    hipError_t e;
+    if (h->pend.on) {
+      e = launch_pending(h, &sc, &first, &last);
+    } else {
+      const KTimer* t = timer(h, first, kKMsdScatter, h->b, 16.0 * h->b);
+      e = launch_scatter(sc, h->stream, t);
+      last = first;
+    }
+    if (e != hipSuccess) return LSM_EHIP;
+    if (h->prof) call_span(h, kSpanUpdate, first, last, h->b);
+    h->pend.on = true;
+    h->pend.slot = slot;
+    h->pend.j = j;
+    h->pend.lo_bit = sc.lo_bit;
+    h->pend.passes = sc.passes;
+    h->next_slot = slot ^ 1;
+    h->sorts_by_path[kSortMsd] += 1;
+    commit_insert(h, j);
+    return LSM_OK;
+  }
 
+  s = drain(h);
+  if (s != LSM_OK) return s;
+  SortArgs sa = sort_args(h, src, j, path);
   Timed st[1 + kMaxPasses];
   KTimer sort_t[1 + kMaxPasses];
   bool timed = h->prof;
   const int nk = sort_kernel_count(sa);
   for (int p = 0; p < nk && timed; ++p) {
-    const double bytes = (sa.fuse.nlev > 0 && p == nk - 1)
-                             ? 16.0 * static_cast<double>(level_len(h, sa.fuse.nlev))
-                             : sort_kernel_bytes_per_elem(sa.path, p) * h->b;
-    const KTimer* t = timer(h, st[p], sort_kernel_kind(sa.path, p), h->b, bytes);
+    const KTimer* t = timer(h, st[p], sort_kernel_kind(sa.path, p), h->b,
+                            sort_kernel_bytes_per_elem(sa.path, p) * h->b);
     if (t == nullptr) timed = false;
     else sort_t[p] = *t;
   }
   int launched = 0;
   const hipError_t se = launch_sort(sa, h->stream, timed ? sort_t : nullptr, &launched);
-  // The sort's first kernel clears the other histogram buffer for the next
-  // sort; once it has been launched, the next sort must use that buffer
-  // whether or not the rest of the sort was launched.
-  if (launched > 0) h->hist_parity ^= 1;
+  // The digit-pass sort's first kernel clears the other histogram buffer for
+  // the next such sort; once it has been launched, the next one must use
+  // that buffer whether or not the rest of the sort was launched.
+  if (sa.path == kSortLsd && launched > 0) h->hist_parity ^= 1;
   if (se != hipSuccess) return LSM_EHIP;
   Timed last = st[nk - 1];
-
-  if (checked) {
-    if (hipMemcpyAsync(h->h_pinned, sa.meta.err, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                       h->stream) != hipSuccess ||
-        hipStreamSynchronize(h->stream) != hipSuccess)
-      return LSM_EHIP;
-    if (*reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u) return LSM_EKEY;
-  }
-
-  uint64_t merged = 0;
-  if (enqueue_cascade(h, sa, j, h->stream, timed ? &last : nullptr, &merged) != hipSuccess)
+  if (enqueue_cascade(h, sa, j, h->stream, timed ? &last : nullptr, nullptr) != hipSuccess)
     return LSM_EHIP;
   if (timed) call_span(h, kSpanUpdate, st[0], last, h->b);
   note_digit_index(h, sa, j);
-  commit_insert(h, merged);
+  h->sorts_by_path[path] += 1;
+  commit_insert(h, j);
   return LSM_OK;
 }
 
@@ -519,17 +668,11 @@ lsm_status_t flush_staged(lsm_t h) {
   return insert_staged(h, h->stage_fill);
 }
 
-// Sets *bad when any of n keys is >= 2^key_bits (checked mode); synchronises.
-lsm_status_t check_keys(lsm_t h, const uint32_t* keys, uint32_t n, bool* bad) {
-  const SortMeta m = sort_meta_carve(h->meta, h->b, 0);
-  if (hipMemsetAsync(m.err, 0, sizeof(uint32_t), h->stream) != hipSuccess ||
-      launch_check_keys(keys, n, h->key_bits, 0, m.err, h->stream) != hipSuccess ||
-      hipMemcpyAsync(h->h_pinned, m.err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(h->stream) != hipSuccess)
-    return LSM_EHIP;
-  *bad = *reinterpret_cast<volatile uint32_t*>(h->h_pinned) != 0u;
-  return LSM_OK;
+// Before anything reads the levels: the staged elements are inserted and
+// the pending insertion completed.
+lsm_status_t settle(lsm_t h) {
+  const lsm_status_t s = flush_staged(h);
+  return s != LSM_OK ? s : drain(h);
 }
 
 // A batch handed to lsm_insert_batch / lsm_delete_batch / lsm_update_batch.
@@ -595,6 +738,10 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
     if ((s = dev_alloc(h, &p, bb)) == LSM_OK) h->tmp_kv[i] = static_cast<uint32_t*>(p);
     if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->tmp_val[i] = static_cast<uint32_t*>(p);
   }
+  for (int i = 0; i < kSortSlots && s == LSM_OK; ++i) {
+    if ((s = dev_alloc(h, &p, bb)) == LSM_OK) h->scat_kv[i] = static_cast<uint32_t*>(p);
+    if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->scat_val[i] = static_cast<uint32_t*>(p);
+  }
   for (int i = 0; i < kMaxLevels; ++i) h->merge_variant[i] = kDefaultMergeVariant;
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->stage_kv = static_cast<uint32_t*>(p);
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->stage_val = static_cast<uint32_t*>(p);
@@ -602,7 +749,7 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->buf_val = static_cast<uint32_t*>(p);
   if (s == LSM_OK && (s = dev_alloc(h, &p, sort_meta_words(b) * sizeof(uint32_t))) == LSM_OK) {
     h->meta = static_cast<uint32_t*>(p);
-    h->fault = sort_meta_carve(h->meta, b, 0).err + 1;
+    h->fault = sort_meta_carve(h->meta, b, 0, 0).err + 1;
     // Both global histogram buffers start zeroed (each sort then clears
     // the buffer of the next one).
     if (hipMemset(h->meta, 0, sort_meta_words(b) * sizeof(uint32_t)) != hipSuccess) s = LSM_EHIP;
@@ -659,7 +806,7 @@ lsm_status_t lsm_lookup(lsm_t h, const uint32_t* d_keys, uint32_t nq, uint32_t* 
   if (d_keys == nullptr || d_vals == nullptr || d_found == nullptr) return LSM_EINVAL;
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
-  lsm_status_t fs = flush_staged(h);
+  lsm_status_t fs = settle(h);
   if (fs != LSM_OK) return fs;
   const LevelSet lv = occupied_levels(h);
   Timed tl;
@@ -676,7 +823,7 @@ lsm_status_t lsm_count(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   if (d_lo == nullptr || d_hi == nullptr || d_counts == nullptr) return LSM_EINVAL;
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
-  lsm_status_t fs = flush_staged(h);
+  lsm_status_t fs = settle(h);
   if (fs != LSM_OK) return fs;
   const LevelSet lv = occupied_levels(h);
   Timed tc;
@@ -695,7 +842,7 @@ static lsm_status_t order_query(lsm_t h, const uint32_t* d_q, uint32_t nq, uint3
     return LSM_EINVAL;
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
-  const lsm_status_t fs = flush_staged(h);
+  const lsm_status_t fs = settle(h);
   if (fs != LSM_OK) return fs;
   const LevelSet lv = occupied_levels(h);
   Timed to;
@@ -730,7 +877,7 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
   if (n > 0xFFFFFFFFull) return LSM_ECAPACITY;
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
-  lsm_status_t s = flush_staged(h);
+  lsm_status_t s = settle(h);
   if (s != LSM_OK) return s;
   const uint64_t b = h->b;
   const uint64_t k = (n + b - 1) / b;
@@ -768,7 +915,7 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
   }
 
   if (h->flags & LSM_CHECKED) {
-    const SortMeta m = sort_meta_carve(h->meta, h->b, 0);
+    const SortMeta m = sort_meta_carve(h->meta, h->b, 0, 0);
     if (hipMemsetAsync(m.err, 0, sizeof(uint32_t), h->stream) != hipSuccess ||
         launch_check_keys(d_keys, static_cast<uint32_t>(n), h->key_bits, 0, m.err, h->stream) !=
             hipSuccess ||
@@ -817,12 +964,8 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
     SortArgs sa{};
     sa.src = BatchSrc{d_keys + e0, d_vals + e0, nullptr, static_cast<uint32_t>(avail),
                       static_cast<uint32_t>(len), static_cast<int>(kInsert)};
-    sa.lo_bit = 1;
-    sa.passes = sort_passes(h->key_bits, 1);
-    sa.key_limit_bits = h->key_bits;
-    sa.checked = 0;
-    sa.meta = sort_meta_carve(u32(meta), static_cast<uint32_t>(len), parity);
-    parity ^= 1;
+    sort_params(h, kInsert, sa);
+    sa.meta = sort_meta_carve(u32(meta), static_cast<uint32_t>(len), parity, 0);
     sa.tmp_kv[0] = u32(st[0][0]);
     sa.tmp_val[0] = u32(st[0][1]);
     sa.tmp_kv[1] = u32(st[1][0]);
@@ -844,6 +987,7 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
     }
     int launched = 0;
     e = launch_sort(sa, h->stream, timed ? tt : nullptr, &launched);
+    if (sa.path == kSortLsd && launched > 0) parity ^= 1;  // see update_batch
     sorted += len;
     const uint32_t* ak = sa.out_kv;
     const uint32_t* av = sa.out_val;
@@ -886,7 +1030,7 @@ lsm_status_t lsm_cleanup(lsm_t h, uint64_t* h_valid) {
   if (h == nullptr) return LSM_EINVAL;
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
-  lsm_status_t s = flush_staged(h);
+  lsm_status_t s = settle(h);
   if (s != LSM_OK) return s;
   if (h_valid != nullptr) *h_valid = 0;
   if (h->r == 0) return LSM_OK;
@@ -1010,7 +1154,7 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
     return hipMemsetAsync(d_offsets, 0, sizeof(uint64_t), h->stream) == hipSuccess ? LSM_OK
                                                                                   : LSM_EHIP;
   }
-  lsm_status_t s = flush_staged(h);
+  lsm_status_t s = settle(h);
   if (s != LSM_OK) return s;
   s = ensure_query_scratch(h, nq);
   if (s != LSM_OK) return s;
@@ -1101,7 +1245,7 @@ lsm_status_t lsm_range_async(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi
   if (nq == 0)
     return hipMemsetAsync(d_offsets, 0, sizeof(uint64_t), h->stream) == hipSuccess ? LSM_OK
                                                                                   : LSM_EHIP;
-  lsm_status_t s = flush_staged(h);
+  lsm_status_t s = settle(h);
   if (s != LSM_OK) return s;
   s = ensure_query_scratch(h, nq);
   if (s != LSM_OK) return s;
@@ -1207,6 +1351,8 @@ lsm_status_t lsm_sync(lsm_t h) {
   if (h == nullptr) return LSM_EINVAL;
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
+  const lsm_status_t ds = drain(h);
+  if (ds != LSM_OK) return ds;
   if (hipMemcpyAsync(h->h_pinned, h->fault, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream) !=
           hipSuccess ||
       hipStreamSynchronize(h->stream) != hipSuccess)
@@ -1221,10 +1367,16 @@ lsm_status_t lsm_sync(lsm_t h) {
 
 lsm_status_t lsm_clear(lsm_t h) {
   if (h == nullptr) return LSM_EINVAL;
+  h->pend.on = false;  // its half-done insertion is simply dropped
   h->r = 0;
   h->stage_fill = 0;
   h->merged_last = 0;
   return LSM_OK;
+}
+
+void lsm_struct_sizes(size_t* stats_size, size_t* profile_size) {
+  if (stats_size != nullptr) *stats_size = sizeof(lsm_stats_t);
+  if (profile_size != nullptr) *profile_size = sizeof(lsm_profile_t);
 }
 
 lsm_status_t lsm_profile_enable(lsm_t h, int on) {
@@ -1246,6 +1398,14 @@ lsm_status_t lsm_profile_read(lsm_t h, lsm_profile_t* out, int reset) {
       p.elems[sp.kind] += sp.items;
       p.kernel_ms[sp.kind] += ms;
       p.kernel_bytes[sp.kind] += sp.bytes;
+      if (sp.kind == kKMerge && sp.items > 0) {
+        // Size class: entry k holds outputs of 2^(k-1) + 1 .. 2^k elements.
+        int k = sp.items > 1 ? 64 - __builtin_clzll(sp.items - 1) : 0;
+        if (k >= LSM_PROF_SIZES) k = LSM_PROF_SIZES - 1;
+        p.merge_launches_by_size[k] += 1;
+        p.merge_ms_by_size[k] += ms;
+        p.merge_bytes_by_size[k] += sp.bytes;
+      }
     } else if (sp.kind == kSpanUpdate) {
       p.update_ms += ms;
       p.update_calls += 1;
@@ -1308,6 +1468,12 @@ uint32_t lsm_batch_size(lsm_t h) { return h ? h->b : 0; }
 lsm_status_t lsm_level_view(lsm_t h, uint32_t i, const uint32_t** d_kv, const uint32_t** d_vals,
                             uint64_t* len) {
   if (h == nullptr || d_kv == nullptr || d_vals == nullptr || len == nullptr) return LSM_EINVAL;
+  {
+    DeviceGuard g(h->device);
+    if (!g.ok) return LSM_EHIP;
+    const lsm_status_t ds = drain(h);
+    if (ds != LSM_OK) return ds;
+  }
   if (i >= static_cast<uint32_t>(kMaxLevels) || !((h->r >> i) & 1u)) {
     *d_kv = nullptr;
     *d_vals = nullptr;
@@ -1330,6 +1496,8 @@ lsm_status_t lsm_level_copy(lsm_t h, uint32_t i, uint32_t* d_kv_out, uint32_t* d
   if (d_kv_out == nullptr || d_vals_out == nullptr) return LSM_EINVAL;
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
+  const lsm_status_t ds = drain(h);
+  if (ds != LSM_OK) return ds;
   const uint64_t n = level_len(h, static_cast<int>(i));
   *len = n;
   if (hipMemcpyAsync(d_kv_out, h->lvl_kv[i], n * sizeof(uint32_t), hipMemcpyDeviceToDevice,

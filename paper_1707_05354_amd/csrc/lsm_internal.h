@@ -98,20 +98,28 @@ struct BatchSrc {
 };
 
 // Sort scratch layout (uint32 words) for a batch of b elements.  The global
-// digit histogram is double-buffered: a sort accumulates into hist[parity]
-// and clears hist[parity ^ 1] for the next sort (both start zeroed).  The
-// top-digit sort keeps its batch digit totals in hist[parity] too.
+// digit histogram of the digit-pass sort is double-buffered: a sort
+// accumulates into hist[parity] and clears hist[parity ^ 1] for the next one
+// (both start zeroed).  The top-digit sort has two slots, so that one batch
+// can be scattered while the previous one's buckets are sorted: each slot
+// holds the tiles' digit-group starts and the slot's largest-bucket record.
+constexpr int kSortSlots = 2;
 struct SortMeta {
   uint32_t* hist;         // [2][kMaxPasses][256]
   uint32_t* status;       // [kMaxPasses][num_sort_tiles][256] look-back words
   uint32_t* tile_ctr;     // [kMaxPasses] dynamic tile ids of each pass
   uint32_t* err;          // [0] key-range violation (checked mode),
                           // [1] sticky device fault (a bounded wait expired)
-  uint32_t* tile_cnt;     // [num_sort_tiles][kTopBuckets / 2] each tile's digit-group starts
-                          // (top-digit sort; two 16-bit starts per word)
+  uint32_t* tile_cnt;     // this slot's [num_sort_tiles][kTopBuckets / 2] digit-group
+                          // starts (top-digit sort; two 16-bit starts per word)
+  uint32_t* skew;         // this slot's largest top-digit bucket (top-digit sort)
   uint32_t num_sort_tiles;
   int parity;
 };
+// Bucket sizes that can change which path the next sort takes or how deep
+// it fuses (more than kLocalCap >> kMaxFuse elements); smaller largest
+// buckets are recorded as 0.
+constexpr uint32_t kSkewFloor = 8;
 
 // The two sort paths: one scatter on the top digit then a per-bucket LDS
 // sort (for at most kMsdMaxTiles tiles), or one digit pass per 8 bits.  The
@@ -131,6 +139,8 @@ inline int pick_sort_path(uint32_t tiles, uint32_t last_max_bucket) {
 // (bucket d holds the original keys [d << key_shift, (d + 1) << key_shift))
 // and writes that part of level nlev.  nlev = 0: no fusion.
 constexpr int kMaxFuse = 8;
+static_assert(kSkewFloor == static_cast<uint32_t>(kLocalCap >> kMaxFuse),
+              "the skew record keeps every size that can change a fused depth");
 struct FuseArgs {
   int nlev;
   int key_shift;
@@ -149,8 +159,7 @@ struct SortArgs {
   BatchSrc src;
   int lo_bit;               // lowest key-variable bit sorted
   int passes;               // 8-bit digit passes
-  uint32_t key_limit_bits;  // checked mode: keys must be < 2^key_limit_bits
-  int checked;
+  uint32_t key_limit_bits;  // keys are < 2^key_limit_bits
   SortMeta meta;
   uint32_t* tmp_kv[2];      // radix ping-pong, b elements each
   uint32_t* tmp_val[2];
@@ -159,7 +168,8 @@ struct SortArgs {
   uint32_t* out_fence;      // fences of the output when it is a level, else null
   uint32_t* out_digit;      // top-digit index of the output level (top-digit path), or null
   int path;                 // SortPath; both paths give the same order
-  uint32_t* skew_out;       // optional: receives the largest top-digit bucket
+  uint32_t* skew_out;       // optional: receives the largest top-digit bucket of an
+                            // earlier sort (a hint for the choice of the next sorts)
   FuseArgs fuse;            // top-digit path only
 };
 
@@ -209,7 +219,7 @@ struct LevelDst {
 };
 
 size_t sort_meta_words(uint32_t b);
-SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity);
+SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity, int slot);
 
 // Sorts one batch into (out_kv, out_val): key variables ascending over bits
 // [lo_bit, lo_bit + 8 * passes), equal key variables with the later batch
@@ -218,6 +228,16 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity);
 // were launched (all of them unless an error is returned).
 hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers,
                        int* launched);
+
+// The two halves of the top-digit sort, for batches of at most kMsdMaxTiles
+// tiles: the tile scatter (into meta's slot and tmp_kv[0] / tmp_val[0]) and
+// the per-bucket sort with its fused cascade (from the same).
+hipError_t launch_scatter(const SortArgs& a, hipStream_t stream, const KTimer* t);
+hipError_t launch_buckets(const SortArgs& a, hipStream_t stream, const KTimer* t);
+// Both halves in one launch, for two batches in different slots: the bucket
+// sort of bk and the tile scatter of sc (the pipelined insertion).
+hipError_t launch_sort_step(const SortArgs& bk, const SortArgs& sc, hipStream_t stream,
+                            const KTimer* t);
 // Number of kernels launch_sort issues (and timers it uses) for a.
 int sort_kernel_count(const SortArgs& a);
 

@@ -490,7 +490,6 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(SortArgs a) {
   for (uint32_t i = tid; i < static_cast<uint32_t>(kMaxPasses * kRadix); i += kThreads) s_h[i] = 0u;
   __syncthreads();
 
-  bool bad = false;
   for (uint32_t t = blockIdx.x; t < m.num_sort_tiles; t += gridDim.x) {
     const uint32_t tb = t * kSortTile;
     uint32_t kv[kSortItems], key[kSortItems], val[kSortItems];
@@ -499,7 +498,6 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(SortArgs a) {
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
       if (!valid[i]) continue;
-      if (a.checked) bad |= (key[i] >> a.key_limit_bits) != 0u;
       for (int p = 0; p < a.passes; ++p)
         atomicAdd(&s_h[p * kRadix + ((kv[i] >> (a.lo_bit + kRadixBits * p)) & (kRadix - 1))], 1u);
     }
@@ -508,7 +506,6 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(SortArgs a) {
   uint32_t* mine = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
   for (uint32_t i = tid; i < static_cast<uint32_t>(a.passes * kRadix); i += kThreads)
     if (s_h[i] != 0u) atomicAdd(&mine[i], s_h[i]);
-  if (a.checked && bad) atomicOr(&m.err[0], 1u);
 }
 
 // One stable counting pass of the batch sort on digit `pass`.  Tiles take
@@ -591,39 +588,39 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint32_t* 
   return prev + r;
 }
 
-// Clears the other digit-pass histogram buffer, whatever the grid size: the
-// next sort on this scratch may be a digit-pass sort that uses every pass's
-// counts (the buffer a sort uses starts zeroed whichever path it takes).
-__device__ __forceinline__ void clear_other_hist(const SortMeta& m) {
-  uint32_t* other = m.hist + static_cast<size_t>(m.parity ^ 1) * kMaxPasses * kRadix;
-  const size_t gid = static_cast<size_t>(blockIdx.x) * kThreads + threadIdx.x;
-  for (size_t i = gid; i < static_cast<size_t>(kMaxPasses) * kRadix;
-       i += static_cast<size_t>(gridDim.x) * kThreads)
-    other[i] = 0u;
-}
-
-// Stable ranks of a wave's items among equal digits, item i of every lane
-// after item i - 1 (tile order is item-major within the wave).  For each
-// item, every lane ORs its lane bit into mask[d] of the wave's own table,
-// reads the mask back (the lanes of the item with digit d) and clears it;
-// the three LDS operations of all items are issued back to back (one wave's
-// LDS operations are applied in issue order, so each item sees exactly its
-// own lanes).  Invalid items use the spare entry kTopBuckets.  Then the
-// lowest lane of each digit group adds the group's size to wcnt[d] with an
-// LDS fetch-and-add, items in order, and its old count is broadcast to the
-// group.  The tables are this wave's own, so no work-group barrier is
-// needed; mask entries are zero before and after.
+// Stable ranks of a wave's items among equal top digits, item i of every
+// lane after item i - 1 (tile order is item-major within the wave).  The
+// 10-bit digit is split into two 5-bit halves with a table of lane masks
+// each: for every item, each lane ORs its lane bit into the entry of its
+// high half in one table and of its low half in the other, reads both
+// entries back and clears them, and the AND of the two masks is the set of
+// lanes whose item has the same digit.  The six LDS operations of all items
+// are issued back to back (one wave's LDS operations are applied in issue
+// order, so each item sees exactly its own lanes).  Invalid items use the
+// spare entry kHalf of both tables.  Then the lowest lane of each digit
+// group adds the group's size to wcnt[d] with an LDS fetch-and-add, items in
+// order, and its old count is broadcast to the group.  The tables are this
+// wave's own, so no work-group barrier is needed; their entries are zero
+// before and after.
+constexpr uint32_t kHalfBits = kTopBits / 2;
+constexpr uint32_t kHalf = 1u << kHalfBits;
+static_assert(2 * kHalfBits == kTopBits, "the top digit splits into two equal halves");
 template <int kN>
 __device__ __forceinline__ void wave_rank_items(const uint32_t (&d)[kN], const bool (&valid)[kN],
-                                                uint64_t* mask, uint32_t* wcnt, uint32_t (&off)[kN]) {
+                                                uint64_t* mhi, uint64_t* mlo, uint32_t* wcnt,
+                                                uint32_t (&off)[kN]) {
   const uint32_t lane = lane_id();
+  const uint64_t bit = 1ull << lane;
   uint64_t grp[kN];
 #pragma unroll
   for (int i = 0; i < kN; ++i) {
-    uint64_t* e = &mask[valid[i] ? d[i] : kTopBuckets];
-    __hip_atomic_fetch_or(e, 1ull << lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    grp[i] = *e;
-    *e = 0ull;
+    uint64_t* eh = &mhi[valid[i] ? (d[i] >> kHalfBits) : kHalf];
+    uint64_t* el = &mlo[valid[i] ? (d[i] & (kHalf - 1)) : kHalf];
+    __hip_atomic_fetch_or(eh, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_or(el, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    grp[i] = *eh & *el;
+    *eh = 0ull;
+    *el = 0ull;
   }
   uint32_t r[kN], lead[kN], size[kN];
 #pragma unroll
@@ -645,19 +642,21 @@ __device__ __forceinline__ void wave_rank_items(const uint32_t (&d)[kN], const b
 
 // Stable scatter of one tile on the top digit, tile-major: the tile's
 // elements, grouped by digit (stable within a digit), go back to the tile's
-// own range of tmp_kv[0] / tmp_val[0] with coalesced writes.  The tile also
+// own range of tmp_kv[0] / tmp_val[0] with coalesced writes, and the tile
 // records where each digit's group starts (two 16-bit starts per word; a
-// tile holds at most kSortTile elements) and adds its digit counts into the
-// batch totals hist[parity] (zeroed by the previous sort, which used the
-// other buffer).  A bucket's elements are then its digit's group in every
-// tile, in tile order.  Thread t owns the digits [kTopPer t, kTopPer t +
-// kTopPer).
+// tile holds at most kSortTile elements).  A bucket's elements are then its
+// digit's group in every tile, in tile order.  Thread t owns the digits
+// [kTopPer t, kTopPer t + kTopPer).  Tile 0 also hands the largest bucket
+// recorded by the previous sort in this scratch slot to the host-visible
+// hint and restarts the record.
 struct ScatterLds {
-  uint64_t mask[kWaves][kTopBuckets + 1];  // ranking: lanes per digit, zero between items
-  uint32_t kv[kSortTile];
+  uint32_t wcnt[kWaves][kTopBuckets];  // per-wave digit counts, then group offsets
+  uint32_t kv[kSortTile];              // the tile grouped by digit
   uint32_t val[kSortTile];
-  uint32_t wcnt[kWaves][kTopBuckets];
-  uint32_t local[kTopBuckets];
+  union {
+    uint64_t mask[kWaves][2][kHalf + 1];  // ranking tables, zero between items
+    uint32_t local[kTopBuckets];          // each digit's group start in the tile
+  } u;
   uint32_t tmp[2 * kWaves];
 };
 
@@ -671,18 +670,17 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
   uint32_t kv[kSortItems], val[kSortItems], off[kSortItems], dg[kSortItems], key[kSortItems];
   bool valid[kSortItems];
   tile_items<kSortItems>(a.src, tbase, wave, lane, kv, val, key, valid);
+  if (tile == 0 && tid == 0) {
+    if (a.skew_out != nullptr) *a.skew_out = *m.skew;
+    *m.skew = 0u;
+  }
   // Rank the tile: each wave clears and fills its own tables.
   for (uint32_t i = lane; i < kTopBuckets; i += 64) S.wcnt[wave][i] = 0u;
-  for (uint32_t i = lane; i <= kTopBuckets; i += 64) S.mask[wave][i] = 0ull;
-  bool bad = false;
+  for (uint32_t i = lane; i < 2 * (kHalf + 1); i += 64) (&S.u.mask[wave][0][0])[i] = 0ull;
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    dg[i] = (kv[i] >> top_shift) & (kTopBuckets - 1);
-    if (a.checked && valid[i]) bad |= (key[i] >> a.key_limit_bits) != 0u;
-  }
-  if (a.checked && bad) atomicOr(&m.err[0], 1u);
-  wave_rank_items(dg, valid, S.mask[wave], S.wcnt[wave], off);
-  __syncthreads();
+  for (int i = 0; i < kSortItems; ++i) dg[i] = (kv[i] >> top_shift) & (kTopBuckets - 1);
+  wave_rank_items(dg, valid, S.u.mask[wave][0], S.u.mask[wave][1], S.wcnt[wave], off);
+  __syncthreads();  // every wave is done with its tables: S.u.local may be written
   uint32_t cnt[kTopPer], tsum = 0;
 #pragma unroll
   for (int q = 0; q < kTopPer; ++q) {
@@ -703,7 +701,7 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
 #pragma unroll
   for (int q = 0; q < kTopPer; ++q) {
     start[q] = lrun;
-    S.local[d0 + q] = lrun;
+    S.u.local[d0 + q] = lrun;
     lrun += cnt[q];
   }
   __syncthreads();
@@ -711,33 +709,27 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
   for (int i = 0; i < kSortItems; ++i) {
     if (valid[i]) {
       const uint32_t dd = dg[i];
-      const uint32_t pos = S.local[dd] + S.wcnt[wave][dd] + off[i];
+      const uint32_t pos = S.u.local[dd] + S.wcnt[wave][dd] + off[i];
       S.kv[pos] = kv[i];
       S.val[pos] = val[i];
     }
   }
   __syncthreads();
-  // Global writes last, so that no barrier waits for them: the group starts,
-  // the totals and the grouped tile.
+  // Global writes last, so that no barrier waits for them: the group starts
+  // and the grouped tile.
   uint32_t* row = m.tile_cnt + static_cast<size_t>(tile) * (kTopBuckets / 2);
   row[2 * tid] = start[0] | (start[1] << 16);
   row[2 * tid + 1] = start[2] | (start[3] << 16);
-  uint32_t* tot = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
-  static_assert(kTopBuckets <= kMaxPasses * kRadix, "totals fit one histogram buffer");
-#pragma unroll
-  for (int q = 0; q < kTopPer; ++q)
-    if (cnt[q] != 0u) atomicAdd(&tot[d0 + q], cnt[q]);
   const uint32_t tile_n = (b - tbase) < static_cast<uint32_t>(kSortTile) ? (b - tbase) : kSortTile;
   for (uint32_t x = tid; x < tile_n; x += kThreads) {
     a.tmp_kv[0][tbase + x] = S.kv[x];
     a.tmp_val[0][tbase + x] = S.val[x];
   }
-  __syncthreads();  // the caller may reuse S
+  (void)key;
 }
 
 __global__ __launch_bounds__(kThreads) void k_msd_scatter(SortArgs a, int top_shift) {
   __shared__ ScatterLds S;
-  clear_other_hist(a.meta);
   tile_scatter(a, top_shift, blockIdx.x, S);
 }
 
@@ -986,16 +978,13 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   const int R = f.nlev + 1;  // runs: the batch, then levels 0..j-1
   // Bucket d is digit d's group in every tile of the tile-major scatter, in
   // tile order; its sorted output starts at s, the number of batch elements
-  // with a smaller digit.  Every load of this prologue is issued
-  // unconditionally (clamped index), so the batch totals, each tile's group
-  // bounds and the levels' digit ranges are in flight together.
+  // with a smaller digit, which is the sum over the tiles of the start of
+  // digit d's group.  Every load of this prologue is issued unconditionally
+  // (clamped index), so each tile's group bounds and the levels' digit
+  // ranges are in flight together.
   auto next_of = [](uint32_t q) { return q + 1 < kTopBuckets ? q + 1 : q; };
   const uint32_t ntiles = m.num_sort_tiles;
   static_assert(kMsdMaxTiles <= kThreads, "one tile per thread");
-  const uint32_t* tot = m.hist + static_cast<size_t>(m.parity) * kMaxPasses * kRadix;
-  uint32_t gt[kTopPer];
-#pragma unroll
-  for (int q = 0; q < kTopPer; ++q) gt[q] = *(tot + tid * kTopPer + q);
   const uint32_t* row = m.tile_cnt + static_cast<size_t>(tid < ntiles ? tid : 0) * (kTopBuckets / 2);
   const uint32_t seg_w0 = row[d >> 1];
   const uint32_t seg_w1 = row[next_of(d) >> 1];
@@ -1023,10 +1012,12 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   const uint32_t g_en = d + 1 < kTopBuckets ? (((d + 1) & 1) ? seg_w1 >> 16 : seg_w1 & 0xFFFFu)
                                             : tile_n;
   const uint32_t g_c = (tid < ntiles && g_en > g_st) ? g_en - g_st : 0u;
-  // One pass of two scans: the digit totals (bucket starts) and the group
-  // sizes (each group's first position in the bucket).
-  uint32_t tsum = gt[0] + gt[1] + gt[2] + gt[3], csum = g_c;
-  block_excl_scan2(tsum, csum, L.tmp);
+  // One pass of two scans: the group starts (their total is the bucket's
+  // output start) and the group sizes (each group's first position in the
+  // bucket; their total is the bucket's size).
+  const uint32_t g_s0 = tid < ntiles ? g_st : 0u;
+  uint32_t ssum = g_s0, csum = g_c;
+  block_excl_scan2(ssum, csum, L.tmp);
   uint32_t* segb = &L.wcnt[0][0] + (kRankSortMax + 8);  // group sources in the batch
   uint32_t* segp = segb + kMsdMaxTiles;                  // group starts in the bucket
   static_assert(kRankSortMax + 8 + 2 * kMsdMaxTiles <= kWaves * kRadix,
@@ -1035,27 +1026,22 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
     segb[tid] = tid * kSortTile + g_st;
     segp[tid] = csum;
   }
-  if ((d >> 2) == tid) {
-    uint32_t pre = tsum;
-#pragma unroll
-    for (int q = 0; q < kTopPer; ++q) {
-      if (static_cast<uint32_t>(q) == (d & 3)) {
-        L.tmp[2 * kWaves] = pre;
-        L.tmp[2 * kWaves + 1] = gt[q];
-      }
-      pre += gt[q];
-    }
+  if (tid == kThreads - 1) {
+    L.tmp[2 * kWaves] = ssum + g_s0;
+    L.tmp[2 * kWaves + 1] = csum + g_c;
   }
   if (tid == 0) {  // run 0 of the load table: the scattered batch
     L.run_k[0] = a.tmp_kv[0];
     L.run_v[0] = a.tmp_val[0];
     L.run_delta[0] = 0;
   }
-  if (d == 0 && a.skew_out != nullptr)
-    record_max(max(max(gt[0], gt[1]), max(gt[2], gt[3])), a.skew_out, L.tmp);
   __syncthreads();
   const uint32_t s = L.tmp[2 * kWaves];
   const uint32_t n = L.tmp[2 * kWaves + 1];
+  // The sort's largest bucket, for the choice of the next sorts' path and
+  // fused depth (only sizes that can change those choices are recorded).
+  if (tid == 0 && n > kSkewFloor && n > *reinterpret_cast<volatile uint32_t*>(m.skew))
+    atomicMax(m.skew, n);
   if (!fused && a.out_digit != nullptr && tid == 0) a.out_digit[d] = s;
   if (n == 0 && !fused) return;
 
@@ -1307,6 +1293,26 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
 __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit, int passes) {
   __shared__ LocalLds L;
   bucket_sort(a, lo_bit, passes, blockIdx.x, L);
+}
+
+// One step of the pipelined top-digit sort: the first work-groups scatter
+// the tiles of the new batch (sc) into one scratch slot while the others
+// sort the buckets of the previous batch (bk) out of the other slot, with
+// its fused cascade.  The two halves share no memory except what each reads
+// from earlier kernels, so they need no synchronisation.
+union StepLds {
+  ScatterLds S;
+  LocalLds L;
+};
+static_assert(sizeof(ScatterLds) <= sizeof(LocalLds),
+              "the scatter half must not raise the step's LDS above the bucket sort's");
+
+__global__ __launch_bounds__(kThreads) void k_sort_step(SortArgs bk, int lo_bit, int passes,
+                                                        SortArgs sc, int top_shift) {
+  __shared__ StepLds U;
+  const uint32_t nt = sc.meta.num_sort_tiles;
+  if (blockIdx.x < nt) tile_scatter(sc, top_shift, blockIdx.x, U.S);
+  else bucket_sort(bk, lo_bit, passes, blockIdx.x - nt, U.L);
 }
 
 // ------------------------------------------------------------ merge
@@ -1975,17 +1981,21 @@ hipError_t launch(Kernel k, unsigned grid, unsigned block, hipStream_t s, const 
 size_t sort_meta_words(uint32_t b) {
   const size_t ns = grid_for(b, kSortTile);
   return static_cast<size_t>(2) * kMaxPasses * kRadix + static_cast<size_t>(kMaxPasses) * ns * kRadix +
-         kMaxPasses + 4 + ns * kTopBuckets + kTopBuckets + 4;
+         kMaxPasses + 4 + kSortSlots * (ns * (kTopBuckets / 2) + 4);
 }
 
-SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity) {
+SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity, int slot) {
   SortMeta m;
-  m.num_sort_tiles = grid_for(b, kSortTile);
+  const size_t ns = grid_for(b, kSortTile);
+  m.num_sort_tiles = static_cast<uint32_t>(ns);
   m.hist = base;
   m.status = m.hist + static_cast<size_t>(2) * kMaxPasses * kRadix;
-  m.tile_ctr = m.status + static_cast<size_t>(kMaxPasses) * m.num_sort_tiles * kRadix;
+  m.tile_ctr = m.status + static_cast<size_t>(kMaxPasses) * ns * kRadix;
   m.err = m.tile_ctr + kMaxPasses;
-  m.tile_cnt = m.err + 4;  // 16-byte aligned (vector loads of packed counts)
+  // Per slot: the group starts (16-byte aligned), then the skew record.
+  uint32_t* slot_base = m.err + 4 + static_cast<size_t>(slot) * (ns * (kTopBuckets / 2) + 4);
+  m.tile_cnt = slot_base;
+  m.skew = slot_base + ns * (kTopBuckets / 2);
   m.parity = parity;
   return m;
 }
@@ -1995,19 +2005,36 @@ int sort_kernel_count(const SortArgs& a) {
   return 1 + a.passes;
 }
 
+// The number of 8-bit passes that sort a top-digit bucket: the key-variable
+// bits below the top digit.
+static int bucket_passes(const SortArgs& a) {
+  return (sort_top_shift(a) - a.lo_bit + kRadixBits - 1) / kRadixBits;
+}
+
+hipError_t launch_scatter(const SortArgs& a, hipStream_t stream, const KTimer* t) {
+  return launch(k_msd_scatter, a.meta.num_sort_tiles, kThreads, stream, t, a, sort_top_shift(a));
+}
+
+hipError_t launch_buckets(const SortArgs& a, hipStream_t stream, const KTimer* t) {
+  return launch(k_local_sort, kTopBuckets, kThreads, stream, t, a, a.lo_bit, bucket_passes(a));
+}
+
+hipError_t launch_sort_step(const SortArgs& bk, const SortArgs& sc, hipStream_t stream,
+                            const KTimer* t) {
+  return launch(k_sort_step, sc.meta.num_sort_tiles + kTopBuckets, kThreads, stream, t, bk,
+                bk.lo_bit, bucket_passes(bk), sc, sort_top_shift(sc));
+}
+
 hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers,
                        int* launched) {
   const uint32_t tiles = a.meta.num_sort_tiles;
   *launched = 0;
   if (a.path == kSortMsd && tiles <= static_cast<uint32_t>(kMsdMaxTiles)) {
     // Top digit: the highest 8 bits a key variable of this handle can have.
-    const int top = sort_top_shift(a);
-    const int local_passes = (top - a.lo_bit + kRadixBits - 1) / kRadixBits;
-    hipError_t e = launch(k_msd_scatter, tiles, kThreads, stream, timers ? &timers[0] : nullptr, a, top);
+    hipError_t e = launch_scatter(a, stream, timers ? &timers[0] : nullptr);
     if (e != hipSuccess) return e;
     *launched = 1;
-    e = launch(k_local_sort, kTopBuckets, kThreads, stream, timers ? &timers[1] : nullptr, a,
-               a.lo_bit, local_passes);
+    e = launch_buckets(a, stream, timers ? &timers[1] : nullptr);
     if (e == hipSuccess) *launched = 2;
     return e;
   }

@@ -43,12 +43,13 @@ class Stats(ctypes.Structure):
 
 KERNEL_NAMES = ("k_sort_hist", "k_sort_pass", "k_merge", "k_lookup", "k_count", "k_scan",
                 "k_range_emit", "k_order", "k_clean", "(unused)", "k_msd_scatter",
-                "k_local_sort", "(unused)")
+                "k_local_sort", "k_sort_step")
 # rocprofv3 kernel names behind each profiler kind that covers several kernels.
 KERNEL_TRACE_NAMES = {"k_order": ("k_successor", "k_predecessor"),
                       "k_clean": ("k_clean_count", "k_clean_scatter", "k_clean_pad"),
                       "k_merge": ("k_merge<4>", "k_merge<8>", "k_merge<16>")}
 _NK = len(KERNEL_NAMES)
+PROF_SIZES = 40  # LSM_PROF_SIZES
 
 
 class Profile(ctypes.Structure):
@@ -57,7 +58,10 @@ class Profile(ctypes.Structure):
                 ("elems", ctypes.c_uint64 * _NK), ("kernel_ms", ctypes.c_double * _NK),
                 ("kernel_bytes", ctypes.c_double * _NK), ("update_ms", ctypes.c_double),
                 ("update_p50_ms", ctypes.c_double), ("update_p99_ms", ctypes.c_double),
-                ("update_max_ms", ctypes.c_double), ("query_ms", ctypes.c_double * 3)]
+                ("update_max_ms", ctypes.c_double), ("query_ms", ctypes.c_double * 3),
+                ("merge_launches_by_size", ctypes.c_uint64 * PROF_SIZES),
+                ("merge_ms_by_size", ctypes.c_double * PROF_SIZES),
+                ("merge_bytes_by_size", ctypes.c_double * PROF_SIZES)]
 
 
 _lib = None
@@ -100,6 +104,7 @@ _SIGNATURES = {
     "lsm_autotune": (ctypes.c_int, [_vp, _u32, _u32]),
     "lsm_get_tuning": (ctypes.c_int, [_vp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float)]),
     "lsm_set_tuning": (ctypes.c_int, [_vp, _u32, _u32]),
+    "lsm_struct_sizes": (None, [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
 }
 
 
@@ -120,6 +125,12 @@ def load_library(path: str = LIB_PATH):
             f = getattr(lib, name)
             f.restype = res
             f.argtypes = args
+        ss, ps = ctypes.c_size_t(), ctypes.c_size_t()
+        lib.lsm_struct_sizes(ctypes.byref(ss), ctypes.byref(ps))
+        if (ss.value, ps.value) != (ctypes.sizeof(Stats), ctypes.sizeof(Profile)):
+            raise RuntimeError("lsm_stats_t / lsm_profile_t layout differs from the binding: "
+                               "%s vs %s" % ((ss.value, ps.value),
+                                             (ctypes.sizeof(Stats), ctypes.sizeof(Profile))))
         _lib = lib
     return _lib
 

@@ -57,3 +57,10 @@ def test_null_handle_calls(lib):
     assert lib.lsm_set_stream(None, None) == L.LSM_EINVAL
     st = L.Stats()
     assert lib.lsm_get_stats(None, ctypes.byref(st)) == L.LSM_EINVAL
+
+
+def test_struct_layouts_match_the_binding(lib):
+    ss, ps = ctypes.c_size_t(), ctypes.c_size_t()
+    lib.lsm_struct_sizes(ctypes.byref(ss), ctypes.byref(ps))
+    assert ss.value == ctypes.sizeof(L.Stats)
+    assert ps.value == ctypes.sizeof(L.Profile)

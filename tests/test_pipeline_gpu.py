@@ -1,0 +1,113 @@
+"""GPU parity of the pipelined insertion: a batch sorted by the top-digit
+sort has its tiles scattered by its own update call and its buckets sorted
+(with the fused cascade) by the next call's launch or when anything reads
+the levels.  Streams of many batches with no read in between run the
+combined kernel on every call; the levels then equal the cascade oracle's
+byte for byte and the answers the map oracle's.  Covers partial batches,
+deletions, mixed batches, b across tile edges, fused depths, sort-path
+switches in the middle of a stream (the digit-pass sort completes the
+pending batch first), lsm_clear with a pending batch, and the profile of
+the pipeline.  Integer results, tolerance 0."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1707_05354_amd import workload as W
+from paper_1707_05354_amd.lsm import KERNEL_NAMES, LSM
+from _gpu import Trio, dev, dev_u8, host, note
+
+pytestmark = pytest.mark.gpu
+
+K = {n: i for i, n in enumerate(KERNEL_NAMES)}
+
+
+def feed(t, ops, rng=None, mixed_every=0):
+    for i, (kind, k, v) in enumerate(ops):
+        if mixed_every and i % mixed_every == mixed_every - 1:
+            vv = v if v is not None else k
+            t.mixed(k, vv, (rng.random(k.size) < 0.4).astype(np.uint8))
+        elif kind == "insert":
+            t.insert(k, v)
+        else:
+            t.delete(k)
+
+
+@pytest.mark.parametrize("b,R,domain", [(1, 70, 9), (64, 67, 3000), (2047, 33, 5000),
+                                        (4099, 40, 1 << 14), (10000, 35, 1 << 31),
+                                        (1 << 16, 35, 1 << 31)])
+def test_unread_stream_equals_oracle(b, R, domain):
+    note("pipelined stream b=%d R=%d" % (b, R))
+    ops, q, lo, hi = W.random_small(900 + b, b, R, domain, p_delete=0.3, nq=500)
+    t = Trio(b)
+    feed(t, ops, np.random.default_rng(b), mixed_every=7)
+    t.check_levels()
+    t.check_queries(q, lo, hi)
+    st = t.g.stats()
+    assert st.sorts_top_digit == R and st.sorts_digit_passes == 0
+    t.g.close()
+
+
+def test_path_switches_and_fusion_changes_mid_stream():
+    """Forced sort-path and fusion changes between batches: a digit-pass
+    batch completes the pending top-digit one first."""
+    b, R = 3000, 40
+    note("pipeline path switches b=%d" % b)
+    ops, q, lo, hi = W.random_small(77, b, R, 1 << 20, p_delete=0.25, nq=400)
+    t = Trio(b)
+    modes = [LSM.SORT_AUTO, LSM.SORT_DIGIT_PASSES, LSM.SORT_TOP_DIGIT]
+    for i, (kind, k, v) in enumerate(ops):
+        t.g.set_sort_path(modes[(i // 3) % 3])
+        t.g.set_fusion([-1, 0, 2, 5][(i // 5) % 4])
+        if kind == "insert":
+            t.insert(k, v)
+        else:
+            t.delete(k)
+        if i % 11 == 10:
+            t.check_queries(q, lo, hi)
+    t.check_levels()
+    t.check_queries(q, lo, hi)
+    st = t.g.stats()
+    assert st.sorts_top_digit + st.sorts_digit_passes == R
+    assert st.sorts_top_digit > 0 and st.sorts_digit_passes > 0
+    t.g.close()
+
+
+def test_clear_drops_the_pending_batch():
+    b = 512
+    note("pipeline clear b=%d" % b)
+    rng = np.random.default_rng(3)
+    t = Trio(b)
+    for _ in range(5):
+        k = rng.integers(0, 10**6, b).astype(np.uint32)
+        t.g.insert(dev(k), dev(k))  # pending at the end; never read
+    t.g.clear()
+    assert t.g.num_batches == 0
+    ops, q, lo, hi = W.random_small(5, b, 9, 4000, nq=300)
+    feed(t, ops)
+    t.check_levels()
+    t.check_queries(q, lo, hi)
+    t.g.close()
+
+
+def test_pipeline_profile_and_sync():
+    """R batches: one scatter, R - 1 steps, and lsm_sync completes the last
+    batch (one bucket sort); the levels are then complete."""
+    b, R = 4096, 21
+    note("pipeline profile b=%d" % b)
+    rng = np.random.default_rng(8)
+    t = Trio(b)
+    t.g.set_sort_path(LSM.SORT_TOP_DIGIT)
+    t.g.profile(True)
+    t.g.profile_read(reset=True)
+    for _ in range(R):
+        t.insert(rng.integers(0, 1 << 31, b, dtype=np.uint64).astype(np.uint32),
+                 rng.integers(0, 2**32, b, dtype=np.uint64).astype(np.uint32))
+    t.g.sync()
+    p = t.g.profile_read(reset=True)
+    assert int(p.launches[K["k_msd_scatter"]]) == 1
+    assert int(p.launches[K["k_sort_step"]]) == R - 1
+    assert int(p.launches[K["k_local_sort"]]) == 1
+    assert p.update_calls == R
+    t.g.profile(False)
+    t.check_levels()
+    t.g.close()

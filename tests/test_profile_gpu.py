@@ -66,7 +66,10 @@ def test_profile_counts_follow_the_path(mode, fusion):
     expect = {"k_merge": sum(max(0, ffz(r) - depth) for r in range(R)), "k_lookup": 1, "k_order": 2,
               "k_range_emit": 1, "k_scan": 1, "k_count": 2}
     if mode == LSM.SORT_TOP_DIGIT:
-        expect.update({"k_msd_scatter": R, "k_local_sort": R})  # the two-kernel top-digit sort
+        # Pipelined: the first batch's scatter alone, then one step per batch
+        # (its scatter with the previous batch's buckets), and the last
+        # batch's buckets when the first query needs the levels.
+        expect.update({"k_msd_scatter": 1, "k_sort_step": R - 1, "k_local_sort": 1})
     else:
         expect.update({"k_sort_hist": R, "k_sort_pass": R * passes})
     for name, n in expect.items():
