@@ -561,8 +561,17 @@ hipError_t launch_pending(lsm_t h, const SortArgs* next, Timed* first, Timed* la
 // calls this first.
 lsm_status_t drain(lsm_t h) {
   if (!h->pend.on) return LSM_OK;
+  const int slot = h->pend.slot;
   Timed first, last;
   if (launch_pending(h, nullptr, &first, &last) != hipSuccess) return LSM_EHIP;
+  // Hand the just-sorted batch's largest bucket to the host-visible hint
+  // (within a pipelined stream a later scatter hands it over, one batch
+  // late), so that a caller that synchronises sees the latest sort's skew.
+  // A failed copy only leaves the hint older; the insertion itself is done.
+  const SortMeta m = sort_meta_carve(h->meta, h->b, h->hist_parity, slot);
+  if (hipMemcpyAsync(h->skew_host, m.skew, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream) !=
+      hipSuccess)
+    (void)hipGetLastError();
   return LSM_OK;
 }
 
