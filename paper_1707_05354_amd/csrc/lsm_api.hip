@@ -74,6 +74,10 @@ struct lsm_s {
   uint32_t* mrg_kv[2] = {};  // cascade ping-pong
   uint32_t* mrg_val[2] = {};
   uint64_t mrg_cap = 0;
+  // Top-digit indexes of the cascade's intermediate runs: the two merge
+  // buffers and the sorted batch (buf_kv).
+  uint32_t* mrg_digit[2] = {};
+  uint32_t* buf_digit = nullptr;
 
   uint32_t* q_counts = nullptr;  // range pass 1 output
   uint64_t* q_status = nullptr;  // range scan look-back words
@@ -262,6 +266,8 @@ void release_all(lsm_t h) {
   }
   dev_free(h, h->buf_kv, bb);
   dev_free(h, h->buf_val, bb);
+  for (int i = 0; i < 2; ++i) dev_free(h, h->mrg_digit[i], kTopBuckets * sizeof(uint32_t));
+  dev_free(h, h->buf_digit, kTopBuckets * sizeof(uint32_t));
   dev_free(h, h->meta, sort_meta_words(h->b) * sizeof(uint32_t));
   if (h->q_cap) {
     dev_free(h, h->q_counts, h->q_cap * sizeof(uint32_t));
@@ -364,6 +370,7 @@ void setup_fusion(lsm_t h, SortArgs& sa, int j) {
     sa.out_digit = h->lvl_digit[0];
     return;
   }
+  sa.out_digit = h->buf_digit;  // the sorted batch, when no level is fused
   int nf = j < h->fuse_max ? j : h->fuse_max;
   if (nf > kMaxFuse) nf = kMaxFuse;
   // Keep the fused runs of a bucket within LDS: the previous sort's largest
@@ -374,6 +381,7 @@ void setup_fusion(lsm_t h, SortArgs& sa, int j) {
   for (int l = 0; l < nf; ++l)
     if (h->digit_shift[l] != shift) nf = l;
   if (nf < 1) return;
+  sa.out_digit = nullptr;
   FuseArgs& f = sa.fuse;
   f.nlev = nf;
   f.key_shift = shift;
@@ -393,15 +401,21 @@ void setup_fusion(lsm_t h, SortArgs& sa, int j) {
     f.out_kv = h->mrg_kv[(nf + 1) & 1];
     f.out_val = h->mrg_val[(nf + 1) & 1];
     f.out_fence = nullptr;
-    f.out_digit = nullptr;
+    f.out_digit = h->mrg_digit[(nf + 1) & 1];
   }
 }
 
 // Records whether the level an insert wrote carries a top-digit index.
-void note_digit_index(lsm_t h, const SortArgs& sa, int j) {
-  const bool indexed = (j == 0) ? sa.out_digit != nullptr
-                                : (sa.fuse.nlev == j && sa.fuse.out_digit != nullptr);
+void note_digit_index(lsm_t h, const SortArgs& sa, int j, bool indexed) {
   h->digit_shift[j] = indexed ? sort_top_shift(sa) - 1 : -1;
+}
+
+// Merges partition their output by top-digit ranges (no split search) when
+// the keys are not skewed: the latest sort's largest bucket is within a few
+// times the mean bucket.  Either way the result is the same.
+bool merge_by_digit(lsm_t h) {
+  const uint64_t big = *reinterpret_cast<volatile uint32_t*>(h->skew_host);
+  return big <= 4ull * ((h->b + kTopBuckets - 1) / kTopBuckets) + 32;
 }
 
 // Sort parameters of a batch: single-type batches sort the key variable
@@ -484,29 +498,39 @@ double bucket_bytes(lsm_t h, const SortArgs& sa) {
 // level i); the last merge writes straight into level j.  Enqueued on s,
 // after the sort and after the levels the sort fused (whose output is then
 // the first input).
+// *indexed receives whether level j ends up with a top-digit index: written
+// by the sort itself (j = 0, or every level fused), or by the last merge when
+// both of its runs carried one (a run's index is the sort's, or a merge's of
+// two indexed runs; level i's counts when built for the sort's key shift).
 hipError_t enqueue_cascade(lsm_t h, const SortArgs& sa, int j, hipStream_t s, Timed* last,
-                           uint64_t* merged_out) {
+                           bool* indexed) {
   const int i0 = sa.fuse.nlev;
   const uint32_t* cur_kv = i0 > 0 ? sa.fuse.out_kv : sa.out_kv;
   const uint32_t* cur_val = i0 > 0 ? sa.fuse.out_val : sa.out_val;
-  uint64_t merged = 0;
-  for (int l = 0; l < i0; ++l) merged += 2ull * level_len(h, l);
+  const uint32_t* cur_dig = i0 > 0 ? sa.fuse.out_digit : sa.out_digit;
+  const int shift = sort_top_shift(sa) - 1;
+  const bool by_digit = merge_by_digit(h);
+  if (indexed != nullptr) *indexed = (j == 0) ? sa.out_digit != nullptr : (i0 == j && cur_dig);
   for (int i = i0; i < j; ++i) {
     uint32_t* o_kv = (i == j - 1) ? h->lvl_kv[j] : h->mrg_kv[i & 1];
     uint32_t* o_val = (i == j - 1) ? h->lvl_val[j] : h->mrg_val[i & 1];
     const uint32_t len = static_cast<uint32_t>(level_len(h, i));
+    const bool both = cur_dig != nullptr && h->digit_shift[i] == shift;
+    MergeIndex mi{cur_dig, both ? h->lvl_digit[i] : nullptr,
+                  both ? ((i == j - 1) ? h->lvl_digit[j] : h->mrg_digit[i & 1]) : nullptr,
+                  both && by_digit ? 1 : 0};
     Timed mt;
     const KTimer* t = (last != nullptr) ? timer(h, mt, kKMerge, 2ull * len, 16.0 * 2.0 * len) : nullptr;
     const hipError_t e = launch_merge(cur_kv, cur_val, len, h->lvl_kv[i], h->lvl_val[i], len,
                                       o_kv, o_val, (i == j - 1) ? h->lvl_fence[j] : nullptr,
-                                      h->merge_variant[i], s, t);
+                                      h->merge_variant[i], s, t, &mi);
     if (e != hipSuccess) return e;
     if (t != nullptr) *last = mt;
-    merged += 2ull * len;
     cur_kv = o_kv;
     cur_val = o_val;
+    cur_dig = mi.out_dig;
+    if (indexed != nullptr && i == j - 1) *indexed = cur_dig != nullptr;
   }
-  if (merged_out) *merged_out = merged;
   return hipSuccess;
 }
 
@@ -550,9 +574,10 @@ hipError_t launch_pending(lsm_t h, const SortArgs* next, Timed* first, Timed* la
     if (first) *first = ts;
     if (last) *last = ts;
   }
-  e = enqueue_cascade(h, bk, j, h->stream, t != nullptr ? last : nullptr, nullptr);
+  bool indexed = false;
+  e = enqueue_cascade(h, bk, j, h->stream, t != nullptr ? last : nullptr, &indexed);
   if (e != hipSuccess) return e;
-  note_digit_index(h, bk, j);
+  note_digit_index(h, bk, j, indexed);
   h->pend.on = false;
   return hipSuccess;
 }
@@ -656,10 +681,11 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
   if (sa.path == kSortLsd && launched > 0) h->hist_parity ^= 1;
   if (se != hipSuccess) return LSM_EHIP;
   Timed last = st[nk - 1];
-  if (enqueue_cascade(h, sa, j, h->stream, timed ? &last : nullptr, nullptr) != hipSuccess)
+  bool indexed = false;
+  if (enqueue_cascade(h, sa, j, h->stream, timed ? &last : nullptr, &indexed) != hipSuccess)
     return LSM_EHIP;
   if (timed) call_span(h, kSpanUpdate, st[0], last, h->b);
-  note_digit_index(h, sa, j);
+  note_digit_index(h, sa, j, indexed);
   h->sorts_by_path[path] += 1;
   commit_insert(h, j);
   return LSM_OK;
@@ -751,6 +777,11 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
     if ((s = dev_alloc(h, &p, bb)) == LSM_OK) h->scat_kv[i] = static_cast<uint32_t*>(p);
     if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->scat_val[i] = static_cast<uint32_t*>(p);
   }
+  for (int i = 0; i < 2 && s == LSM_OK; ++i)
+    if ((s = dev_alloc(h, &p, kTopBuckets * sizeof(uint32_t))) == LSM_OK)
+      h->mrg_digit[i] = static_cast<uint32_t*>(p);
+  if (s == LSM_OK && (s = dev_alloc(h, &p, kTopBuckets * sizeof(uint32_t))) == LSM_OK)
+    h->buf_digit = static_cast<uint32_t*>(p);
   for (int i = 0; i < kMaxLevels; ++i) h->merge_variant[i] = kDefaultMergeVariant;
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->stage_kv = static_cast<uint32_t*>(p);
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->stage_val = static_cast<uint32_t*>(p);

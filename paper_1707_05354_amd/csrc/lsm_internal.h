@@ -241,12 +241,24 @@ hipError_t launch_sort_step(const SortArgs& bk, const SortArgs& sc, hipStream_t 
 // Number of kernels launch_sort issues (and timers it uses) for a.
 int sort_kernel_count(const SortArgs& a);
 
+// Top-digit indexes of a merge's two runs (both needed) and its output:
+// with both, the output's index is written (when out_dig is set) and, when
+// by_digit is set, the work-groups partition the output by digit ranges
+// instead of searching for merge-path splits.
+struct MergeIndex {
+  const uint32_t* a_dig;
+  const uint32_t* b_dig;
+  uint32_t* out_dig;
+  int by_digit;
+};
+
 // Stable merge of a newer run (first on equal original keys) with an older
-// run into out (na + nb elements), with merge variant `variant`.
+// run into out (na + nb elements), with merge variant `variant`; idx is
+// optional.
 hipError_t launch_merge(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na,
                         const uint32_t* b_kv, const uint32_t* b_val, uint32_t nb,
                         uint32_t* out_kv, uint32_t* out_val, uint32_t* out_fence, int variant,
-                        hipStream_t stream, const KTimer* t);
+                        hipStream_t stream, const KTimer* t, const MergeIndex* idx = nullptr);
 
 // Coalescer: encodes n operations as key variables (status 0 for a
 // deletion, value 0) into staging[at .. at + n).  Element i deletes when

@@ -1353,11 +1353,6 @@ __device__ uint32_t wave_merge_path(const uint32_t* a, uint32_t na, const uint32
 }
 
 
-// Each work-group merges a contiguous run of `tiles_per_wg` output tiles of
-// kMergeTile = 256 * kMergeItems elements.  Only the first tile's split is searched in global
-// memory (64-ary wave search); every later split is found inside LDS
-// windows holding the next kMergeTile elements of each input, which are the
-// elements the tile is about to consume anyway.
 // Merge-path split inside the work-group's windows, held in circular LDS
 // buffers: window a is positions [a0, a0 + wa) of run a at slots
 // (a0 + i) & mask, window b likewise.  Returns how many of the first dt
@@ -1375,21 +1370,43 @@ __device__ __forceinline__ uint32_t ring_merge_path(const uint32_t* sa, uint32_t
 }
 
 // Merge of run a (newer) with run b (older) on the original key.  Each
-// work-group produces tiles_per_wg consecutive output tiles.  It finds the
-// splits of its first tile and of the end of its range with two wave
-// searches in global memory (waves 0 and 1, side by side), then keeps a
-// window of each run in LDS ring buffers: a tile's outputs consume la
-// elements of a and n - la of b, and the next tile loads exactly those
-// counts; windows never extend past the work-group's end split, so every
-// input element is read from HBM once.  A window's new elements are all
-// loaded before any is stored.  Each thread merges kMergeItems consecutive
-// outputs and stores them with 16-byte stores.
+// work-group produces one contiguous range of the output, found one of two
+// ways:
+//   * digit mode (both runs carry a top-digit index): work-group w takes the
+//     top digits [w per_wg, (w + 1) per_wg); each index gives the range of its
+//     run holding those digits, and the output range starts at the sum of the
+//     two starts (equal keys share a digit, so no tie crosses a range
+//     boundary).  No search at all.  The output's own index is the sum of the
+//     two indexes, digit by digit.
+//   * search mode: work-group w takes output tiles [w per_wg, (w + 1) per_wg)
+//     and finds the splits at the start and the end of its range with two
+//     wave searches in global memory (waves 0 and 1, side by side).
+// The range is then produced tile by tile, the tiles anchored at 16-byte
+// aligned output positions (the first tile of a range may start inside its
+// tile).  Both runs' windows live in LDS ring buffers: a tile's outputs
+// consume la elements of a and n - la of b, and the next tile loads exactly
+// those counts; windows never extend past the range's end, so every input
+// element is read from HBM once.  A window's new elements are all loaded
+// before any is stored.  Each thread merges kMergeItems consecutive outputs
+// and stores them with 16-byte stores.
+struct MergeArgs {
+  const uint32_t* a_kv;
+  const uint32_t* a_val;
+  const uint32_t* b_kv;
+  const uint32_t* b_val;
+  uint32_t na, nb;
+  uint32_t* out_kv;
+  uint32_t* out_val;
+  uint32_t* out_fence;     // the output level's fence tree, or null
+  const uint32_t* a_dig;   // top-digit indexes of both runs, or null
+  const uint32_t* b_dig;
+  uint32_t* out_dig;       // receives the output's index (both runs indexed), or null
+  int digit_mode;          // partition by digit ranges (needs both indexes)
+  uint32_t per_wg;         // digits (digit mode) or output tiles per work-group
+};
+
 template <int kMergeItems>
-__global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const uint32_t* a_val,
-                                                    uint32_t na, const uint32_t* b_kv,
-                                                    const uint32_t* b_val, uint32_t nb,
-                                                    uint32_t* out_kv, uint32_t* out_val,
-                                                    uint32_t* out_fence, uint32_t tiles_per_wg) {
+__global__ __launch_bounds__(kThreads) void k_merge(MergeArgs m) {
   constexpr uint32_t kMergeTile = kThreads * kMergeItems;
   constexpr uint32_t kMask = kMergeTile - 1;
   static_assert((kMergeTile & kMask) == 0, "merge tile must be a power of two");
@@ -1397,25 +1414,44 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
   __shared__ uint32_t sa_k[kMergeTile], sa_v[kMergeTile], sb_k[kMergeTile], sb_v[kMergeTile];
   __shared__ uint32_t s_split, s_split_end;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t na = m.na, nb = m.nb;
   const uint64_t total = static_cast<uint64_t>(na) + nb;
-  const uint64_t tiles = (total + kMergeTile - 1) / kMergeTile;
-  uint64_t t = static_cast<uint64_t>(blockIdx.x) * tiles_per_wg;
-  const uint64_t t_end = (t + tiles_per_wg < tiles) ? t + tiles_per_wg : tiles;
-  if (t >= t_end) return;
-  if (wave == 0) {
-    const uint32_t sp = wave_merge_path(a_kv, na, b_kv, nb, t * kMergeTile);
-    if (lane == 0) s_split = sp;
-  } else if (wave == 1) {
-    const uint64_t de = t_end * kMergeTile;
-    const uint32_t sp = de >= total ? na : wave_merge_path(a_kv, na, b_kv, nb, de);
-    if (lane == 0) s_split_end = sp;
+  uint32_t a0, b0, a_lim, b_lim;  // the work-group consumes a[a0, a_lim), b[b0, b_lim)
+  if (m.digit_mode) {
+    const uint32_t q0 = blockIdx.x * m.per_wg;
+    if (q0 >= kTopBuckets) return;
+    const uint32_t q1 = min(q0 + m.per_wg, kTopBuckets);
+    // Index entries are positions in their run; clamped so that a damaged
+    // index can only give wrong output, never an access out of bounds.
+    a0 = min(m.a_dig[q0], na);
+    b0 = min(m.b_dig[q0], nb);
+    a_lim = q1 < kTopBuckets ? min(max(m.a_dig[q1], a0), na) : na;
+    b_lim = q1 < kTopBuckets ? min(max(m.b_dig[q1], b0), nb) : nb;
+    if (m.out_dig != nullptr)
+      for (uint32_t q = q0 + tid; q < q1; q += kThreads) m.out_dig[q] = m.a_dig[q] + m.b_dig[q];
+  } else {
+    if (m.out_dig != nullptr)
+      for (uint32_t q = blockIdx.x * kThreads + tid; q < kTopBuckets; q += gridDim.x * kThreads)
+        m.out_dig[q] = m.a_dig[q] + m.b_dig[q];
+    const uint64_t tiles = (total + kMergeTile - 1) / kMergeTile;
+    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * m.per_wg;
+    const uint64_t t_end = (t + m.per_wg < tiles) ? t + m.per_wg : tiles;
+    if (t >= t_end) return;
+    if (wave == 0) {
+      const uint32_t sp = wave_merge_path(m.a_kv, na, m.b_kv, nb, t * kMergeTile);
+      if (lane == 0) s_split = sp;
+    } else if (wave == 1) {
+      const uint64_t de = t_end * kMergeTile;
+      const uint32_t sp = de >= total ? na : wave_merge_path(m.a_kv, na, m.b_kv, nb, de);
+      if (lane == 0) s_split_end = sp;
+    }
+    __syncthreads();
+    a0 = s_split;
+    b0 = static_cast<uint32_t>(t * kMergeTile - a0);
+    a_lim = s_split_end;
+    b_lim = static_cast<uint32_t>((t_end * kMergeTile < total ? t_end * kMergeTile : total) - a_lim);
   }
-  __syncthreads();
-  uint32_t a0 = s_split;
-  uint32_t b0 = static_cast<uint32_t>(t * kMergeTile - a0);
-  const uint32_t a_lim = s_split_end;  // the work-group consumes a[a0, a_lim), b[b0, b_lim)
-  const uint32_t b_lim = static_cast<uint32_t>(
-      (t_end * kMergeTile < total ? t_end * kMergeTile : total) - a_lim);
+  const uint64_t o_end = static_cast<uint64_t>(a_lim) + b_lim;
   uint32_t a_end = a0, b_end = b0;  // loaded into the rings up to here
   // New window elements [from, to) of one run into its ring: at most
   // kMergeTile, so kMergeItems per thread; loads at clamped positions first.
@@ -1439,17 +1475,25 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
       }
     }
   };
-  for (; t < t_end; ++t) {
-    const uint64_t d = t * kMergeTile;
-    const uint32_t n = static_cast<uint32_t>((total - d) < kMergeTile ? (total - d) : kMergeTile);
+  // Tiles anchored at 16-byte aligned output positions g0; the next output
+  // is always at a0 + b0.
+  for (uint64_t g0 = (static_cast<uint64_t>(a0) + b0) & ~uint64_t(3); g0 < o_end; g0 += kMergeTile) {
+    const uint64_t p0 = static_cast<uint64_t>(a0) + b0;  // first output of this tile's part
+    const uint64_t tile_end = (g0 + kMergeTile < o_end) ? g0 + kMergeTile : o_end;
+    const uint32_t n = static_cast<uint32_t>(tile_end - p0);
     const uint32_t wa = (a_lim - a0) < n ? (a_lim - a0) : n;
     const uint32_t wb = (b_lim - b0) < n ? (b_lim - b0) : n;
-    fill(a_kv, a_val, a_end, a0 + wa, sa_k, sa_v);
-    fill(b_kv, b_val, b_end, b0 + wb, sb_k, sb_v);
+    fill(m.a_kv, m.a_val, a_end, a0 + wa, sa_k, sa_v);
+    fill(m.b_kv, m.b_val, b_end, b0 + wb, sb_k, sb_v);
     a_end = (a0 + wa > a_end) ? a0 + wa : a_end;
     b_end = (b0 + wb > b_end) ? b0 + wb : b_end;
     __syncthreads();
-    const uint32_t dt = (tid * kMergeItems < n) ? tid * kMergeItems : n;
+    // This thread's outputs: positions p .. p + kMergeItems - 1, of which
+    // those before p0 (first tile of a range only) belong to another range.
+    const uint64_t p = g0 + static_cast<uint64_t>(tid) * kMergeItems;
+    const uint32_t skip =
+        p < p0 ? ((p0 - p) < kMergeItems ? static_cast<uint32_t>(p0 - p) : kMergeItems) : 0u;
+    const uint32_t dt = p < p0 ? 0u : ((p - p0) < n ? static_cast<uint32_t>(p - p0) : n);
     uint32_t ia = ring_merge_path(sa_k, a0, wa, sb_k, b0, wb, dt, kMask);
     uint32_t ib = dt - ia;
     uint32_t rk[kMergeItems], rv[kMergeItems];
@@ -1457,7 +1501,7 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
     for (int k = 0; k < kMergeItems; ++k) {
       rk[k] = 0u;
       rv[k] = 0u;
-      if (dt + k < n) {
+      if (static_cast<uint32_t>(k) >= skip && p + k < tile_end) {
         const uint32_t ka = ia < wa ? sa_k[(a0 + ia) & kMask] : 0u;
         const uint32_t kb = ib < wb ? sb_k[(b0 + ib) & kMask] : 0u;
         const bool take_a = ia < wa && (ib >= wb || (ka >> 1) <= (kb >> 1));
@@ -1468,25 +1512,25 @@ __global__ __launch_bounds__(kThreads) void k_merge(const uint32_t* a_kv, const 
       }
     }
     if (tid == kThreads - 1) s_split = ring_merge_path(sa_k, a0, wa, sb_k, b0, wb, n, kMask);
-    const uint64_t o = d + dt;
-    if (dt + kMergeItems <= n) {
+    if (skip == 0 && p + kMergeItems <= tile_end) {
 #pragma unroll
       for (int k = 0; k < kMergeItems; k += 4) {
-        *reinterpret_cast<uint4*>(out_kv + o + k) = make_uint4(rk[k], rk[k + 1], rk[k + 2], rk[k + 3]);
-        *reinterpret_cast<uint4*>(out_val + o + k) = make_uint4(rv[k], rv[k + 1], rv[k + 2], rv[k + 3]);
+        *reinterpret_cast<uint4*>(m.out_kv + p + k) = make_uint4(rk[k], rk[k + 1], rk[k + 2], rk[k + 3]);
+        *reinterpret_cast<uint4*>(m.out_val + p + k) = make_uint4(rv[k], rv[k + 1], rv[k + 2], rv[k + 3]);
       }
     } else {
 #pragma unroll
       for (int k = 0; k < kMergeItems; ++k) {
-        if (dt + k < n) {
-          out_kv[o + k] = rk[k];
-          out_val[o + k] = rv[k];
+        if (static_cast<uint32_t>(k) >= skip && p + k < tile_end) {
+          m.out_kv[p + k] = rk[k];
+          m.out_val[p + k] = rv[k];
         }
       }
     }
 #pragma unroll
     for (int k = 0; k < kMergeItems; ++k)
-      if (dt + k < n) put_fence(out_fence, total, o + k, rk[k]);
+      if (static_cast<uint32_t>(k) >= skip && p + k < tile_end)
+        put_fence(m.out_fence, total, p + k, rk[k]);
     __syncthreads();
     const uint32_t la = s_split;
     a0 += la;
@@ -2051,36 +2095,50 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* time
 }
 
 template <int kItems>
-hipError_t launch_merge_items(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na,
-                              const uint32_t* b_kv, const uint32_t* b_val, uint32_t nb,
-                              uint32_t* out_kv, uint32_t* out_val, uint32_t* out_fence,
-                              uint32_t max_blocks, hipStream_t stream, const KTimer* t) {
-  const uint64_t total = static_cast<uint64_t>(na) + nb;
+hipError_t launch_merge_items(MergeArgs m, uint32_t max_blocks, hipStream_t stream,
+                              const KTimer* t) {
+  const uint64_t total = static_cast<uint64_t>(m.na) + m.nb;
   const uint64_t tile = static_cast<uint64_t>(kThreads) * kItems;
   const uint64_t tiles = (total + tile - 1) / tile;
-  const uint32_t per = static_cast<uint32_t>((tiles + max_blocks - 1) / max_blocks);
-  return launch(k_merge<kItems>, grid_for(tiles, per), kThreads, stream, t, a_kv, a_val, na, b_kv,
-                b_val, nb, out_kv, out_val, out_fence, per);
+  if (m.digit_mode) {
+    // Work-groups over the digits: at most one per digit, and no more than
+    // output tiles (a small merge takes a few work-groups of many digits).
+    const uint64_t groups = tiles < kTopBuckets ? (tiles > 0 ? tiles : 1) : kTopBuckets;
+    m.per_wg = static_cast<uint32_t>((kTopBuckets + groups - 1) / groups);
+    return launch(k_merge<kItems>, grid_for(kTopBuckets, m.per_wg), kThreads, stream, t, m);
+  }
+  m.per_wg = static_cast<uint32_t>((tiles + max_blocks - 1) / max_blocks);
+  return launch(k_merge<kItems>, grid_for(tiles, m.per_wg), kThreads, stream, t, m);
 }
 
 hipError_t launch_merge(const uint32_t* a_kv, const uint32_t* a_val, uint32_t na,
                         const uint32_t* b_kv, const uint32_t* b_val, uint32_t nb,
                         uint32_t* out_kv, uint32_t* out_val, uint32_t* out_fence, int variant,
-                        hipStream_t stream, const KTimer* t) {
+                        hipStream_t stream, const KTimer* t, const MergeIndex* idx) {
   const uint64_t total = static_cast<uint64_t>(na) + nb;
   if (total == 0) return hipSuccess;
   if (variant < 0 || variant >= kMergeVariants) variant = kDefaultMergeVariant;
+  MergeArgs m{};
+  m.a_kv = a_kv;
+  m.a_val = a_val;
+  m.b_kv = b_kv;
+  m.b_val = b_val;
+  m.na = na;
+  m.nb = nb;
+  m.out_kv = out_kv;
+  m.out_val = out_val;
+  m.out_fence = out_fence;
+  if (idx != nullptr && idx->a_dig != nullptr && idx->b_dig != nullptr) {
+    m.a_dig = idx->a_dig;
+    m.b_dig = idx->b_dig;
+    m.out_dig = idx->out_dig;
+    m.digit_mode = idx->by_digit;
+  }
   const uint32_t blocks = static_cast<uint32_t>(kMergeBlocksOf[variant / 3]);
   switch (kMergeItemsOf[variant % 3]) {
-    case 4:
-      return launch_merge_items<4>(a_kv, a_val, na, b_kv, b_val, nb, out_kv, out_val, out_fence, blocks,
-                                   stream, t);
-    case 16:
-      return launch_merge_items<16>(a_kv, a_val, na, b_kv, b_val, nb, out_kv, out_val, out_fence, blocks,
-                                    stream, t);
-    default:
-      return launch_merge_items<8>(a_kv, a_val, na, b_kv, b_val, nb, out_kv, out_val, out_fence, blocks,
-                                   stream, t);
+    case 4: return launch_merge_items<4>(m, blocks, stream, t);
+    case 16: return launch_merge_items<16>(m, blocks, stream, t);
+    default: return launch_merge_items<8>(m, blocks, stream, t);
   }
 }
 
