@@ -349,6 +349,14 @@ LSM_API const char* lsm_strerror(lsm_status_t s);
 /* Number of resident batches r (sec. III-B); 0 for a NULL handle. */
 LSM_API uint64_t lsm_num_batches(lsm_t h);
 
+/*
+ * Allocation-failure injection, for tests of the strong guarantee: the next
+ * n device allocations of the handle succeed and every later one fails as if
+ * the device were out of memory (the call then returns LSM_ENOMEM and leaves
+ * the dictionary as it was).  A negative n turns the injection off.
+ */
+LSM_API lsm_status_t lsm_fail_alloc_after(lsm_t h, int64_t n);
+
 /* The batch size b; 0 for a NULL handle. */
 LSM_API uint32_t lsm_batch_size(lsm_t h);
 

@@ -22,6 +22,7 @@ using namespace lsm;
 
 static_assert(LSM_PROF_KERNELS == kNumKernelKinds, "profile kernel kinds out of step");
 
+
 // Kinds of whole-call spans in the profiler, above every kernel kind.
 constexpr int kSpanUpdate = 100;
 constexpr int kSpanLookup = 101;  // then count, range
@@ -105,6 +106,9 @@ struct lsm_s {
 
   uint64_t merged_last = 0, merged_total = 0, sorted_total = 0;
   uint64_t device_bytes = 0;
+  // Allocation-failure injection (tests): allocations left before every
+  // further one fails; negative = never fail.
+  int64_t fail_after = -1;
 
   // Profiling: events recorded on the stream between kernels, resolved on
   // lsm_profile_read.  A span is a pair of indices into `marks`.
@@ -137,6 +141,8 @@ struct DeviceGuard {
 
 lsm_status_t dev_alloc(lsm_t h, void** p, size_t bytes) {
   *p = nullptr;
+  if (h->fail_after == 0) return LSM_ENOMEM;
+  if (h->fail_after > 0) --h->fail_after;
   if (bytes == 0) bytes = 4;
   if (hipMalloc(p, bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -917,11 +923,13 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
   if (n > 0xFFFFFFFFull) return LSM_ECAPACITY;
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
-  lsm_status_t s = settle(h);
+  // Staged elements become one batch before the new ones; every allocation
+  // (theirs included) is made before anything changes.
+  lsm_status_t s = h->stage_fill > 0 ? prepare_insert(h, __builtin_ctzll(~h->r)) : LSM_OK;
   if (s != LSM_OK) return s;
   const uint64_t b = h->b;
   const uint64_t k = (n + b - 1) / b;
-  const uint64_t r0 = h->r, r1 = r0 + k;
+  const uint64_t r0 = h->r + (h->stage_fill > 0 ? 1 : 0), r1 = r0 + k;
   if ((r1 >> kMaxLevels) != 0) return LSM_ECAPACITY;
 
   struct Plan {
@@ -990,6 +998,11 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
   if (s != LSM_OK) {
     release();
     return s;
+  }
+  s = settle(h);  // allocates nothing now
+  if (s != LSM_OK || h->r != r0) {
+    release();
+    return s != LSM_OK ? s : LSM_EHIP;
   }
   auto u32 = [](void* p) { return static_cast<uint32_t*>(p); };
   hipError_t e = hipMemsetAsync(meta, 0, meta_bytes, h->stream);
@@ -1070,17 +1083,24 @@ lsm_status_t lsm_cleanup(lsm_t h, uint64_t* h_valid) {
   if (h == nullptr) return LSM_EINVAL;
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
-  lsm_status_t s = settle(h);
-  if (s != LSM_OK) return s;
   if (h_valid != nullptr) *h_valid = 0;
-  if (h->r == 0) return LSM_OK;
-  const uint64_t total = h->r * static_cast<uint64_t>(h->b);
+  // Everything is allocated before anything changes: the staged elements'
+  // level, the scratch, and every level the rebuilt dictionary can occupy
+  // (r' <= r, so levels up to r's highest; they all existed already unless a
+  // bulk insert or cleanup skipped some).
+  lsm_status_t s = h->stage_fill > 0 ? prepare_insert(h, __builtin_ctzll(~h->r)) : LSM_OK;
+  if (s != LSM_OK) return s;
+  const uint64_t r_all = h->r + (h->stage_fill > 0 ? 1 : 0);
+  if (r_all == 0) return drain(h);
+  const uint64_t total = r_all * static_cast<uint64_t>(h->b);
   if (total > 0xFFFFFFFFull) return LSM_ECAPACITY;
+  for (int i = 0; i < kMaxLevels && (r_all >> i) != 0 && s == LSM_OK; ++i) s = ensure_level(h, i);
+  if (s != LSM_OK) return s;
   const uint32_t n = static_cast<uint32_t>(total);
   int occ[kMaxLevels];
   int m = 0;
   for (int i = 0; i < kMaxLevels; ++i)
-    if ((h->r >> i) & 1u) occ[m++] = i;
+    if ((r_all >> i) & 1u) occ[m++] = i;
 
   // Scratch: one or two merge buffers (kv + val), the tiles' offsets.
   const size_t bytes = total * sizeof(uint32_t);
@@ -1102,6 +1122,8 @@ lsm_status_t lsm_cleanup(lsm_t h, uint64_t* h_valid) {
   }
   if (s == LSM_OK) s = dev_alloc(h, &toff, (tiles + 1ull) * sizeof(uint64_t));
   if (s == LSM_OK) s = ensure_query_scratch(h, tiles);
+  if (s == LSM_OK) s = settle(h);  // allocates nothing now
+  if (s == LSM_OK && h->r != r_all) s = LSM_EHIP;
   if (s != LSM_OK) {
     release();
     return s;
@@ -1147,13 +1169,7 @@ lsm_status_t lsm_cleanup(lsm_t h, uint64_t* h_valid) {
     return LSM_EHIP;
   }
   const uint64_t v = *reinterpret_cast<volatile uint64_t*>(h->h_pinned);
-  const uint64_t r2 = (v + h->b - 1) / h->b;
-  for (int i = 0; i < kMaxLevels && s == LSM_OK; ++i)
-    if ((r2 >> i) & 1u) s = ensure_level(h, i);
-  if (s != LSM_OK) {
-    release();
-    return s;
-  }
+  const uint64_t r2 = (v + h->b - 1) / h->b;  // <= r_all: its levels exist
   LevelDst d{};
   for (int i = 0; i < kMaxLevels; ++i) {
     if (((r2 >> i) & 1u) == 0) continue;
@@ -1194,9 +1210,8 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
     return hipMemsetAsync(d_offsets, 0, sizeof(uint64_t), h->stream) == hipSuccess ? LSM_OK
                                                                                   : LSM_EHIP;
   }
-  lsm_status_t s = settle(h);
-  if (s != LSM_OK) return s;
-  s = ensure_query_scratch(h, nq);
+  lsm_status_t s = ensure_query_scratch(h, nq);
+  if (s == LSM_OK) s = settle(h);
   if (s != LSM_OK) return s;
   const LevelSet lv = occupied_levels(h);
   Timed t1, t2, t3;
@@ -1240,6 +1255,13 @@ static lsm_status_t submit(lsm_t h, const uint32_t* d_keys, const uint32_t* d_va
     const lsm_status_t s = check_keys(h, d_keys, n, &bad);
     if (s != LSM_OK) return s;
     if (bad) return LSM_EKEY;
+  }
+  // Every LSM batch this call fills is allocated for before anything is
+  // staged, so that a failure leaves the staged elements as they were.
+  const uint64_t full = (static_cast<uint64_t>(h->stage_fill) + n) / h->b;
+  for (uint64_t k = 0; k < full; ++k) {
+    const lsm_status_t s = prepare_insert(h, __builtin_ctzll(~(h->r + k)));
+    if (s != LSM_OK) return s;
   }
   uint32_t done = 0;
   while (done < n) {
@@ -1285,9 +1307,8 @@ lsm_status_t lsm_range_async(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi
   if (nq == 0)
     return hipMemsetAsync(d_offsets, 0, sizeof(uint64_t), h->stream) == hipSuccess ? LSM_OK
                                                                                   : LSM_EHIP;
-  lsm_status_t s = settle(h);
-  if (s != LSM_OK) return s;
-  s = ensure_query_scratch(h, nq);
+  lsm_status_t s = ensure_query_scratch(h, nq);
+  if (s == LSM_OK) s = settle(h);
   if (s != LSM_OK) return s;
   const LevelSet lv = occupied_levels(h);
   Timed t1, t2, t3;
@@ -1503,6 +1524,12 @@ const char* lsm_strerror(lsm_status_t s) {
 }
 
 uint64_t lsm_num_batches(lsm_t h) { return h ? h->r : 0; }
+
+lsm_status_t lsm_fail_alloc_after(lsm_t h, int64_t n) {
+  if (h == nullptr) return LSM_EINVAL;
+  h->fail_after = n < 0 ? -1 : n;
+  return LSM_OK;
+}
 uint32_t lsm_batch_size(lsm_t h) { return h ? h->b : 0; }
 
 lsm_status_t lsm_level_view(lsm_t h, uint32_t i, const uint32_t** d_kv, const uint32_t** d_vals,

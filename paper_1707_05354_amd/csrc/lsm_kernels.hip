@@ -1629,10 +1629,8 @@ __device__ __forceinline__ uint32_t skip_run(const uint32_t* kv, uint32_t c, uin
 // levels in key order.  For each distinct key the element met first is the
 // newest instance (smaller levels are newer, and inside a level a key's run
 // starts with its newest element); it counts when it is a regular element.
-template <bool kEmit, bool kOneLevel>
-__device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, uint32_t k2,
-                                               uint32_t* out_keys, uint32_t* out_vals,
-                                               uint64_t limit) {
+template <bool kOneLevel>
+__device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, uint32_t k2) {
   if (k1 > k2) return 0u;
   const int L = lv.count;
   if (kOneLevel) {
@@ -1646,11 +1644,10 @@ __device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, 
     uint32_t count = 0, prev = kNoKey;
     while (p < e) {
       const uint32_t m = (e - p) < 16u ? (e - p) : 16u;
-      uint32_t x[16], v[16];
+      uint32_t x[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         x[i] = static_cast<uint32_t>(i) < m ? kv[p + i] : 0u;
-        v[i] = (kEmit && static_cast<uint32_t>(i) < m) ? lv.val[0][p + i] : 0u;
       }
       bool any_start = false;
 #pragma unroll
@@ -1658,13 +1655,7 @@ __device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, 
         if (static_cast<uint32_t>(i) < m) {
           const uint32_t key = x[i] >> 1;
           const bool start = key != prev;
-          if (start && (x[i] & 1u)) {
-            if (kEmit && count < limit) {
-              out_keys[count] = key;
-              out_vals[count] = v[i];
-            }
-            ++count;
-          }
+          if (start && (x[i] & 1u)) ++count;
           any_start |= start;
           prev = key;
         }
@@ -1691,13 +1682,7 @@ __device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, 
     }
     if (mi < 0) break;
     const uint32_t x = lv.kv[mi][cur[mi]];
-    if (x & 1u) {
-      if (kEmit && count < limit) {
-        out_keys[count] = mk;
-        out_vals[count] = lv.val[mi][cur[mi]];
-      }
-      ++count;
-    }
+    if (x & 1u) ++count;
     for (int l = mi; l < L; ++l) {
       if (ck[l] == mk) {
         cur[l] = skip_run(lv.kv[l], cur[l], end[l], mk);
@@ -1720,8 +1705,124 @@ __global__ __launch_bounds__(kQueryThreads) void k_count(LevelSet lv, const uint
       scan_status[w] = 0ull;
   }
   if (gi >= nq) return;
-  counts[gi] = range_walk<false, kOneLevel>(lv, lo[gi], hi[gi], nullptr, nullptr, 0);
+  counts[gi] = range_walk<kOneLevel>(lv, lo[gi], hi[gi]);
 }
+
+// Resumable form of range_walk for the emission pass: the walk of one query
+// keeps its cursors between calls, and each call emits the pairs whose
+// output positions fall in [pos, lim), writing pair position x at
+// sk[x - c0] / sv[x - c0].  Returns the next position.  The pairs and
+// their order are range_walk's.
+struct WalkOne {
+  uint32_t p, e, prev;  // next candidate, end of the candidates, key before p
+};
+struct WalkMany {
+  uint32_t cur[kMaxLevels], end[kMaxLevels], ck[kMaxLevels];
+};
+
+__device__ __forceinline__ void walk_init(const LevelSet& lv, uint32_t k1, uint32_t k2, WalkOne& w) {
+  w.p = w.e = 0;
+  w.prev = kNoKey;
+  if (k1 <= k2) fenced_range(lv.kv[0], lv.fence[0], lv.len[0], k1, k2, w.p, w.e);
+}
+
+__device__ __forceinline__ void walk_init(const LevelSet& lv, uint32_t k1, uint32_t k2, WalkMany& w) {
+  for (int l = 0; l < lv.count; ++l) {
+    w.cur[l] = w.end[l] = 0;
+    if (k1 <= k2) fenced_range(lv.kv[l], lv.fence[l], lv.len[l], k1, k2, w.cur[l], w.end[l]);
+    w.ck[l] = w.cur[l] < w.end[l] ? (lv.kv[l][w.cur[l]] >> 1) : kNoKey;
+  }
+}
+
+// One level: the first element of every key run is that key's newest
+// instance; candidates are scanned 16 at a time, long runs skipped by
+// galloping.  A call stops in front of the first pair it may not emit.
+__device__ __forceinline__ uint64_t walk_emit(const LevelSet& lv, WalkOne& w, uint64_t pos,
+                                              uint64_t lim, uint64_t c0, uint32_t* sk,
+                                              uint32_t* sv) {
+  const uint32_t* kv = lv.kv[0];
+  while (w.p < w.e && pos < lim) {
+    const uint32_t m = (w.e - w.p) < 16u ? (w.e - w.p) : 16u;
+    uint32_t x[16], v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      x[i] = static_cast<uint32_t>(i) < m ? kv[w.p + i] : 0u;
+      v[i] = static_cast<uint32_t>(i) < m ? lv.val[0][w.p + i] : 0u;
+    }
+    bool any_start = false;
+    uint32_t stop = m;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (static_cast<uint32_t>(i) < m && stop == m) {
+        const uint32_t key = x[i] >> 1;
+        const bool start = key != w.prev;
+        if (start && (x[i] & 1u)) {
+          if (pos >= lim) {
+            stop = static_cast<uint32_t>(i);  // resume here, w.prev still the key before it
+          } else {
+            sk[pos - c0] = key;
+            sv[pos - c0] = v[i];
+            ++pos;
+          }
+        }
+        if (stop == m) {
+          any_start |= start;
+          w.prev = key;
+        }
+      }
+    }
+    if (stop < m) {
+      w.p += stop;
+      break;
+    }
+    w.p = any_start ? w.p + m : skip_run(kv, w.p + m - 1, w.e, w.prev);
+  }
+  return pos;
+}
+
+// Several levels: the k-way walk over the level runs in key order; the
+// element met first for each key (smallest level first) is its newest
+// instance, emitted when regular.
+__device__ __forceinline__ uint64_t walk_emit(const LevelSet& lv, WalkMany& w, uint64_t pos,
+                                              uint64_t lim, uint64_t c0, uint32_t* sk,
+                                              uint32_t* sv) {
+  const int L = lv.count;
+  for (;;) {
+    uint32_t mk = kNoKey;
+    int mi = -1;
+    for (int l = 0; l < L; ++l) {
+      if (w.ck[l] < mk) {
+        mk = w.ck[l];
+        mi = l;
+      }
+    }
+    if (mi < 0) break;
+    if (lv.kv[mi][w.cur[mi]] & 1u) {
+      if (pos >= lim) break;  // this key is emitted by a later call
+      sk[pos - c0] = mk;
+      sv[pos - c0] = lv.val[mi][w.cur[mi]];
+      ++pos;
+    }
+    for (int l = mi; l < L; ++l) {
+      if (w.ck[l] == mk) {
+        w.cur[l] = skip_run(lv.kv[l], w.cur[l], w.end[l], mk);
+        w.ck[l] = w.cur[l] < w.end[l] ? (lv.kv[l][w.cur[l]] >> 1) : kNoKey;
+      }
+    }
+  }
+  return pos;
+}
+
+// Stage 3 of sec. IV-C / IV-D with coalesced writes.  The pairs of a wave's
+// 64 consecutive queries form one contiguous span of the output, which the
+// wave produces in chunks of kEmitChunk pairs: every query emits the pairs
+// that fall in the chunk into the wave's LDS buffer (its walk resumes where
+// the previous chunk stopped it), then the wave copies the chunk out with
+// consecutive lanes on consecutive addresses.  A query whose pairs would end
+// beyond cap writes nothing (the caller sees offsets[q + 1] > cap); the other
+// checks only guard against offsets corrupted by a timed-out scan.
+constexpr uint32_t kEmitChunk = 512;
+constexpr int kQueryWaves = kQueryThreads / 64;
 
 template <bool kOneLevel>
 __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const uint32_t* lo,
@@ -1729,16 +1830,49 @@ __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const
                                                               const uint64_t* offsets,
                                                               uint32_t* out_keys,
                                                               uint32_t* out_vals, uint64_t cap) {
-  const uint32_t i = blockIdx.x * kQueryThreads + threadIdx.x;
-  if (i >= nq) return;
-  const uint64_t o = offsets[i];
-  // The walk writes exactly offsets[i+1] - offsets[i] pairs (the same walk
-  // produced the count).  A query whose pairs would end beyond cap writes
-  // nothing (the caller sees offsets[i+1] > cap); the other limits only
-  // guard against offsets corrupted by a timed-out scan.
-  const uint64_t e = offsets[i + 1];
-  if (e < o || e > offsets[nq] || e > cap) return;
-  range_walk<true, kOneLevel>(lv, lo[i], hi[i], out_keys + o, out_vals + o, e - o);
+  __shared__ uint32_t sk[kQueryWaves][kEmitChunk], sv[kQueryWaves][kEmitChunk];
+  __shared__ uint32_t s_rounds[kQueryWaves];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t i = blockIdx.x * kQueryThreads + tid;
+  const uint32_t q0 = blockIdx.x * kQueryThreads + wave * 64;
+  const uint32_t qa = q0 < nq ? q0 : nq, qb = q0 + 64 < nq ? q0 + 64 : nq;
+  const uint64_t base = offsets[qa], span_end = offsets[qb], all = offsets[nq];
+  const bool active = i < nq;
+  const uint64_t o = active ? offsets[i] : 0, e = active ? offsets[i + 1] : 0;
+  const bool fits = active && e >= o && o >= base && e <= span_end && e <= all && e <= cap;
+  // The writable part of the span ends where the first query that does not
+  // fit begins (offsets are non-decreasing).
+  uint64_t stop = (active && !fits) ? o : ~0ull;
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    const uint64_t y = __shfl_xor(stop, d, 64);
+    stop = y < stop ? y : stop;
+  }
+  const uint64_t copy_end = stop < span_end ? stop : span_end;
+  const uint32_t rounds =
+      copy_end > base ? static_cast<uint32_t>((copy_end - base + kEmitChunk - 1) / kEmitChunk) : 0u;
+  if (lane == 0) s_rounds[wave] = rounds;
+  typename std::conditional<kOneLevel, WalkOne, WalkMany>::type w;
+  if (fits) walk_init(lv, lo[i], hi[i], w);
+  __syncthreads();
+  uint32_t R = 0;
+#pragma unroll
+  for (int x = 0; x < kQueryWaves; ++x) R = s_rounds[x] > R ? s_rounds[x] : R;
+  uint64_t pos = o;
+  for (uint32_t r = 0; r < R; ++r) {
+    const uint64_t c0 = base + static_cast<uint64_t>(r) * kEmitChunk;
+    const uint64_t c1 = c0 + kEmitChunk;
+    if (fits && pos < e && pos < c1) pos = walk_emit(lv, w, pos, e < c1 ? e : c1, c0, sk[wave], sv[wave]);
+    __syncthreads();
+    for (uint32_t x = lane; x < kEmitChunk; x += 64) {
+      const uint64_t g = c0 + x;
+      if (g < copy_end) {
+        out_keys[g] = sk[wave][x];
+        out_vals[g] = sv[wave][x];
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------ scan

@@ -104,6 +104,7 @@ _SIGNATURES = {
     "lsm_autotune": (ctypes.c_int, [_vp, _u32, _u32]),
     "lsm_get_tuning": (ctypes.c_int, [_vp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float)]),
     "lsm_set_tuning": (ctypes.c_int, [_vp, _u32, _u32]),
+    "lsm_fail_alloc_after": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "lsm_struct_sizes": (None, [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
 }
 
@@ -393,6 +394,10 @@ class LSM:
         n = int(total.value)
         self._last_total = n
         return offsets, keys[:n], vals[:n]
+
+    def fail_alloc_after(self, n: int) -> None:
+        """Tests: the next n allocations succeed, later ones fail (n < 0: off)."""
+        _check(self._lib.lsm_fail_alloc_after(self._h, int(n)), "lsm_fail_alloc_after")
 
     # -- introspection ------------------------------------------------------
     @property
