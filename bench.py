@@ -470,6 +470,11 @@ def main() -> int:
                   else lib.lsm_insert_batch(h, row_k[i], row_v[i], b))
             if rc:
                 raise L.LSMError(rc, "update batch %d" % i)
+        # The last batch's second half (bucket sort and cascade) belongs to
+        # the update phase: enqueue it before the phase's end event.
+        rc = lib.lsm_flush(h)
+        if rc:
+            raise L.LSMError(rc, "lsm_flush")
 
     def ranges():
         rc = lib.lsm_range(h, rlo_d.data_ptr(), rhi_d.data_ptr(), nr, roff.data_ptr(),

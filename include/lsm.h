@@ -161,7 +161,14 @@ LSM_API lsm_status_t lsm_submit(lsm_t h, const uint32_t* d_keys, const uint32_t*
 LSM_API lsm_status_t lsm_submit_mixed(lsm_t h, const uint32_t* d_keys, const uint32_t* d_vals,
                                       const uint8_t* d_is_delete, uint32_t n);
 
-/* lsm_flush -- insert the staged elements as one (padded) batch, if any. */
+/*
+ * lsm_flush -- insert the staged elements as one (padded) batch, if any, and
+ * enqueue whatever remains of every earlier insertion (an update call may
+ * leave the second half of its batch's sort and its cascade to the next
+ * update call's launch; queries, cleanup and lsm_sync complete it too).
+ * Once the stream has passed the call, every submitted or inserted batch is
+ * in the levels.  LSM_ENOMEM, LSM_ECAPACITY, LSM_EHIP.
+ */
 LSM_API lsm_status_t lsm_flush(lsm_t h);
 
 /* Number of elements staged and not yet inserted. */
@@ -202,7 +209,7 @@ LSM_API lsm_status_t lsm_set_fusion(lsm_t h, int max_levels);
  * LSM_SORT_DIGIT_PASSES: one stable counting pass
  * per 8-bit digit with decoupled look-back.  LSM_SORT_AUTO (the default):
  * the top-digit sort unless the previous sort saw a top-digit bucket above
- * 2048 elements (skewed keys, where one work-group would sort a large bucket
+ * 1536 elements (skewed keys, where one work-group would sort a large bucket
  * alone).  Takes effect at the next sort.  LSM_EINVAL for another mode.
  */
 #define LSM_SORT_AUTO 0
@@ -335,6 +342,7 @@ LSM_API lsm_status_t lsm_sync(lsm_t h);
 LSM_API lsm_status_t lsm_range_async(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi,
                                      uint32_t nq, uint64_t* d_offsets, uint32_t* d_keys,
                                      uint32_t* d_vals, uint64_t cap);
+
 
 /* lsm_destroy -- synchronise the stream and free every allocation. */
 LSM_API lsm_status_t lsm_destroy(lsm_t h);

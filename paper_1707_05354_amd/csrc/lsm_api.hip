@@ -1326,7 +1326,7 @@ lsm_status_t lsm_flush(lsm_t h) {
   if (h == nullptr) return LSM_EINVAL;
   DeviceGuard g(h->device);
   if (!g.ok) return LSM_EHIP;
-  return flush_staged(h);
+  return settle(h);
 }
 
 uint32_t lsm_pending(lsm_t h) { return h ? h->stage_fill : 0; }

@@ -29,7 +29,11 @@ constexpr int kMsdMaxTiles = 256;
 constexpr int kTopBits = 10;
 constexpr uint32_t kTopBuckets = 1u << kTopBits;
 constexpr int kTopPer = static_cast<int>(kTopBuckets) / kThreads;  // buckets per thread
-constexpr int kLocalCap = 2048;
+// kLocalCap keeps the bucket kernel's LDS below 32 KiB, so that five of its
+// work-groups fit one CU: the pipelined step (1024 bucket work-groups beside
+// the next batch's tile scatter) then runs in a single round of work-groups.
+constexpr int kLocalCap = 1536;
+static_assert(kLocalCap % 256 == 0, "the bucket load phase takes kLocalCap / 256 items per thread");
 // Buckets of at most this many elements are sorted by ranking (every
 // element counts the elements that precede it) instead of radix passes.
 constexpr uint32_t kRankSortMax = 256;
@@ -119,7 +123,7 @@ struct SortMeta {
 // Bucket sizes that can change which path the next sort takes or how deep
 // it fuses (more than kLocalCap >> kMaxFuse elements); smaller largest
 // buckets are recorded as 0.
-constexpr uint32_t kSkewFloor = 8;
+constexpr uint32_t kSkewFloor = 6;
 
 // The two sort paths: one scatter on the top digit then a per-bucket LDS
 // sort (for at most kMsdMaxTiles tiles), or one digit pass per 8 bits.  The
@@ -323,5 +327,6 @@ hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint3
                              uint32_t nq, const uint64_t* offsets, uint32_t* out_keys,
                              uint32_t* out_vals, uint64_t cap, hipStream_t stream,
                              const KTimer* t);
+
 
 }  // namespace lsm

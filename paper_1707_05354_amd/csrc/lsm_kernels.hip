@@ -630,14 +630,22 @@ __device__ __forceinline__ void wave_rank_items(const uint32_t (&d)[kN], const b
     size[i] = static_cast<uint32_t>(__popcll(grp[i]));
   }
   // Every lane issues the add (others add 0, so the leader's old count is the
-  // count before this item whatever order the lanes are applied in).
+  // count before this item whatever order the lanes are applied in).  The
+  // counts are 16-bit halves of wcnt's words (digit d in half d & 1 of word
+  // d >> 1): a wave adds at most 64 kN <= 65535 per digit, so no carry
+  // crosses into the other half.
+  static_assert(64 * kN <= 0xFFFF, "per-wave digit counts fit 16 bits");
   uint32_t prev[kN];
 #pragma unroll
-  for (int i = 0; i < kN; ++i)
-    prev[i] = atomicAdd(&wcnt[valid[i] ? d[i] : 0u], (valid[i] && r[i] == 0) ? size[i] : 0u);
+  for (int i = 0; i < kN; ++i) {
+    const uint32_t dd = valid[i] ? d[i] : 0u;
+    const uint32_t sh = (dd & 1u) * 16u;
+    prev[i] = atomicAdd(&wcnt[dd >> 1], ((valid[i] && r[i] == 0) ? size[i] : 0u) << sh) >> sh;
+  }
 #pragma unroll
-  for (int i = 0; i < kN; ++i) off[i] = static_cast<uint32_t>(__shfl(static_cast<int>(prev[i]),
-                                                                      static_cast<int>(lead[i]), 64)) + r[i];
+  for (int i = 0; i < kN; ++i)
+    off[i] = (static_cast<uint32_t>(__shfl(static_cast<int>(prev[i]), static_cast<int>(lead[i]), 64)) &
+              0xFFFFu) + r[i];
 }
 
 // Stable scatter of one tile on the top digit, tile-major: the tile's
@@ -650,7 +658,9 @@ __device__ __forceinline__ void wave_rank_items(const uint32_t (&d)[kN], const b
 // recorded by the previous sort in this scratch slot to the host-visible
 // hint and restarts the record.
 struct ScatterLds {
-  uint32_t wcnt[kWaves][kTopBuckets];  // per-wave digit counts, then group offsets
+  // Per-wave digit counts, then each wave's offset inside each digit's
+  // group: 16-bit halves, digit d in half d & 1 of word d >> 1.
+  uint32_t wcnt[kWaves][kTopBuckets / 2];
   uint32_t kv[kSortTile];              // the tile grouped by digit
   uint32_t val[kSortTile];
   union {
@@ -675,26 +685,37 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
     *m.skew = 0u;
   }
   // Rank the tile: each wave clears and fills its own tables.
-  for (uint32_t i = lane; i < kTopBuckets; i += 64) S.wcnt[wave][i] = 0u;
+  for (uint32_t i = lane; i < kTopBuckets / 2; i += 64) S.wcnt[wave][i] = 0u;
   for (uint32_t i = lane; i < 2 * (kHalf + 1); i += 64) (&S.u.mask[wave][0][0])[i] = 0ull;
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) dg[i] = (kv[i] >> top_shift) & (kTopBuckets - 1);
   wave_rank_items(dg, valid, S.u.mask[wave][0], S.u.mask[wave][1], S.wcnt[wave], off);
   __syncthreads();  // every wave is done with its tables: S.u.local may be written
+  // This thread's four digits are the halves of words d0 / 2 and d0 / 2 + 1;
+  // the wave offsets inside a group are below kSortTile, so they fit too.
   uint32_t cnt[kTopPer], tsum = 0;
+  uint32_t wpk[kWaves][2];
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    wpk[w][0] = S.wcnt[w][d0 / 2];
+    wpk[w][1] = S.wcnt[w][d0 / 2 + 1];
+  }
+  uint32_t wo[kWaves][kTopPer];
 #pragma unroll
   for (int q = 0; q < kTopPer; ++q) {
-    uint32_t x[kWaves];
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) x[w] = S.wcnt[w][d0 + q];
     uint32_t run = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) {
-      S.wcnt[w][d0 + q] = run;
-      run += x[w];
+      wo[w][q] = run;
+      run += (wpk[w][q >> 1] >> ((q & 1) * 16)) & 0xFFFFu;
     }
     cnt[q] = run;
     tsum += run;
+  }
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    S.wcnt[w][d0 / 2] = wo[w][0] | (wo[w][1] << 16);
+    S.wcnt[w][d0 / 2 + 1] = wo[w][2] | (wo[w][3] << 16);
   }
   uint32_t lrun = block_excl_scan(tsum, S.tmp);
   uint32_t start[kTopPer];
@@ -709,7 +730,8 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
   for (int i = 0; i < kSortItems; ++i) {
     if (valid[i]) {
       const uint32_t dd = dg[i];
-      const uint32_t pos = S.u.local[dd] + S.wcnt[wave][dd] + off[i];
+      const uint32_t wof = (S.wcnt[wave][dd >> 1] >> ((dd & 1u) * 16u)) & 0xFFFFu;
+      const uint32_t pos = S.u.local[dd] + wof + off[i];
       S.kv[pos] = kv[i];
       S.val[pos] = val[i];
     }
