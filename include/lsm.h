@@ -212,6 +212,19 @@ LSM_API lsm_status_t lsm_set_fusion(lsm_t h, int max_levels);
  * 1536 elements (skewed keys, where one work-group would sort a large bucket
  * alone).  Takes effect at the next sort.  LSM_EINVAL for another mode.
  */
+/*
+ * lsm_set_max_inflight -- launch pacing of the update calls.  An update call
+ * that sorts its batch by the top-digit sort first waits (spinning on a word
+ * of mapped host memory that each such launch writes when it starts, no
+ * runtime call) until at most `launches` of its earlier launches are still
+ * waiting to start on the stream; 0 turns pacing off.  On MI355X the device
+ * ran long queues of these launches markedly slower than short ones, so the
+ * default (4) keeps the host a few launches ahead of the device.  A wait
+ * gives up after 500 ms.  Results never depend on it.  LSM_EINVAL for a
+ * negative value.
+ */
+LSM_API lsm_status_t lsm_set_max_inflight(lsm_t h, int launches);
+
 #define LSM_SORT_AUTO 0
 #define LSM_SORT_TOP_DIGIT 1
 #define LSM_SORT_DIGIT_PASSES 2

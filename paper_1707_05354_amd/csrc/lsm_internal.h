@@ -174,6 +174,8 @@ struct SortArgs {
   int path;                 // SortPath; both paths give the same order
   uint32_t* skew_out;       // optional: receives the largest top-digit bucket of an
                             // earlier sort (a hint for the choice of the next sorts)
+  uint64_t* progress;       // optional (top-digit scatter): receives seq when the
+  uint64_t seq;             // launch starts, for the host's launch pacing
   FuseArgs fuse;            // top-digit path only
 };
 

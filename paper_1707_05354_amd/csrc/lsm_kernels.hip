@@ -656,7 +656,9 @@ __device__ __forceinline__ void wave_rank_items(const uint32_t (&d)[kN], const b
 // digit's group in every tile, in tile order.  Thread t owns the digits
 // [kTopPer t, kTopPer t + kTopPer).  Tile 0 also hands the largest bucket
 // recorded by the previous sort in this scratch slot to the host-visible
-// hint and restarts the record.
+// hint and restarts the record, and first writes the launch's sequence
+// number to the host-visible progress word (the launch has started, so every
+// earlier launch on the stream has finished).
 struct ScatterLds {
   // Per-wave digit counts, then each wave's offset inside each digit's
   // group: 16-bit halves, digit d in half d & 1 of word d >> 1.
@@ -681,6 +683,8 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
   bool valid[kSortItems];
   tile_items<kSortItems>(a.src, tbase, wave, lane, kv, val, key, valid);
   if (tile == 0 && tid == 0) {
+    if (a.progress != nullptr)
+      __hip_atomic_store(a.progress, a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     if (a.skew_out != nullptr) *a.skew_out = *m.skew;
     *m.skew = 0u;
   }

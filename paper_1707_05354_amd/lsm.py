@@ -84,6 +84,7 @@ _SIGNATURES = {
     "lsm_bulk_insert": (ctypes.c_int, [_vp, _vp, _vp, _u64]),
     "lsm_set_sort_path": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lsm_set_fusion": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lsm_set_max_inflight": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lsm_destroy": (ctypes.c_int, [_vp]),
     "lsm_clear": (ctypes.c_int, [_vp]),
     "lsm_sync": (ctypes.c_int, [_vp]),
@@ -300,6 +301,10 @@ class LSM:
     def set_fusion(self, max_levels: int) -> None:
         """Deepest cascade fused into the top-digit sort (0 off, -1 default)."""
         _check(self._lib.lsm_set_fusion(self._h, int(max_levels)), "lsm_set_fusion")
+
+    def set_max_inflight(self, launches: int) -> None:
+        """Update launches the host may queue ahead of the device (0: no pacing)."""
+        _check(self._lib.lsm_set_max_inflight(self._h, int(launches)), "lsm_set_max_inflight")
 
     def set_tuning(self, level: int, variant: int) -> None:
         _check(self._lib.lsm_set_tuning(self._h, int(level), int(variant)), "lsm_set_tuning")
