@@ -356,6 +356,34 @@ LSM_API lsm_status_t lsm_range_async(lsm_t h, const uint32_t* d_lo, const uint32
                                      uint32_t nq, uint64_t* d_offsets, uint32_t* d_keys,
                                      uint32_t* d_vals, uint64_t cap);
 
+/*
+ * lsm_range_async_noalloc -- lsm_range_async for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same outputs, bit for bit,
+ * with the per-query counts and the scan's look-back words kept in a fixed
+ * array inside the library's code object instead of handle scratch.  The
+ * call makes no hipMalloc, hipFree or other allocating call and records no
+ * kernel timing.
+ *   nq : at most LSM_NOALLOC_MAX_QUERIES; larger batches return
+ *        LSM_ECAPACITY with nothing enqueued.
+ * The fixed array (4 MiB) exists once per GPU, for the life of the process,
+ * and is shared by every handle on that GPU: calls on one GPU whose work
+ * overlaps on the device (different streams, not ordered by events) race on
+ * it and give undefined output.  Each call clears what it needs, so calls
+ * ordered one after another (one stream, or joined by events) are exact.
+ * Elements staged by lsm_submit and the pending insertion are completed
+ * first, as for every query; when that insertion would need a level or
+ * merge buffer the handle has not allocated yet, the call returns
+ * LSM_ENOMEM and changes nothing (any query call that may allocate, e.g.
+ * lsm_flush, settles it).  Asynchronous.  LSM_EINVAL, LSM_ECAPACITY,
+ * LSM_ENOMEM, LSM_EHIP (also when the array's address could not be looked
+ * up at lsm_create).
+ */
+#define LSM_NOALLOC_MAX_QUERIES (1u << 20)
+LSM_API lsm_status_t lsm_range_async_noalloc(lsm_t h, const uint32_t* d_lo,
+                                             const uint32_t* d_hi, uint32_t nq,
+                                             uint64_t* d_offsets, uint32_t* d_keys,
+                                             uint32_t* d_vals, uint64_t cap);
 
 /* lsm_destroy -- synchronise the stream and free every allocation. */
 LSM_API lsm_status_t lsm_destroy(lsm_t h);

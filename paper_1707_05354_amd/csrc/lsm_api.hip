@@ -22,6 +22,7 @@
 using namespace lsm;
 
 static_assert(LSM_PROF_KERNELS == kNumKernelKinds, "profile kernel kinds out of step");
+static_assert(LSM_NOALLOC_MAX_QUERIES == kFixedMaxQueries, "fixed scratch limit out of step");
 
 
 // Kinds of whole-call spans in the profiler, above every kernel kind.
@@ -93,6 +94,9 @@ struct lsm_s {
   uint32_t* q_counts = nullptr;  // range pass 1 output
   uint64_t* q_status = nullptr;  // range scan look-back words
   uint64_t q_cap = 0;
+  // The device's fixed range scratch (lsm_range_async_noalloc), or nulls
+  // when its address could not be looked up.
+  FixedScratch fixed = {nullptr, nullptr};
 
   uint64_t* h_pinned = nullptr;  // read-backs (range total, key check)
   // Largest top-digit bucket of the most recent sort, written by the sort
@@ -881,6 +885,12 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
     delete h;
     return s;
   }
+  // The fixed range scratch of this device (looked up once per device); a
+  // failed lookup only disables lsm_range_async_noalloc.
+  if (fixed_scratch(&h->fixed) != hipSuccess) {
+    (void)hipGetLastError();
+    h->fixed = FixedScratch{nullptr, nullptr};
+  }
   *out = h;
   return LSM_OK;
 }
@@ -1377,6 +1387,44 @@ lsm_status_t lsm_range_async(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi
                   timer(h, t2, kKScan, nq, 12.0 * nq)) != hipSuccess ||
       launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, d_keys, d_vals, cap, h->stream,
                         timer(h, t3, kKRangeEmit, nq, 0.0)) != hipSuccess)
+    return LSM_EHIP;
+  return LSM_OK;
+}
+
+// lsm_range_async with the query scratch in the device's fixed array: no
+// allocation of any kind.  The staged elements and the pending insertion
+// are completed first, as for every query, but only when that needs no
+// memory the handle does not already hold; kernel timing stays off for the
+// call (it creates events).
+lsm_status_t lsm_range_async_noalloc(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi,
+                                     uint32_t nq, uint64_t* d_offsets, uint32_t* d_keys,
+                                     uint32_t* d_vals, uint64_t cap) {
+  if (h == nullptr || d_offsets == nullptr) return LSM_EINVAL;
+  if (nq > 0 && (d_lo == nullptr || d_hi == nullptr)) return LSM_EINVAL;
+  if (cap > 0 && (d_keys == nullptr || d_vals == nullptr)) return LSM_EINVAL;
+  if (nq > kFixedMaxQueries) return LSM_ECAPACITY;
+  DeviceGuard g(h->device);
+  if (!g.ok) return LSM_EHIP;
+  if (h->fixed.counts == nullptr) return LSM_EHIP;
+  if (nq == 0) return launch_zero_u64(d_offsets, h->stream) == hipSuccess ? LSM_OK : LSM_EHIP;
+  if (h->stage_fill > 0) {
+    const int j = __builtin_ctzll(~h->r);
+    if (j < kMaxLevels && (h->lvl_kv[j] == nullptr ||
+                           (j >= 2 && h->mrg_cap < level_len(h, j - 1))))
+      return LSM_ENOMEM;
+  }
+  const bool prof = h->prof;
+  h->prof = false;
+  const lsm_status_t s = settle(h);
+  h->prof = prof;
+  if (s != LSM_OK) return s;
+  const LevelSet lv = occupied_levels(h);
+  if (launch_count(lv, d_lo, d_hi, nq, h->fixed.counts, h->fixed.status, scan_status_words(nq),
+                   h->stream, nullptr) != hipSuccess ||
+      launch_scan(h->fixed.counts, nq, d_offsets, h->fixed.status, h->fault, h->stream,
+                  nullptr) != hipSuccess ||
+      launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, d_keys, d_vals, cap, h->stream,
+                        nullptr) != hipSuccess)
     return LSM_EHIP;
   return LSM_OK;
 }

@@ -330,5 +330,20 @@ hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint3
                              uint32_t* out_vals, uint64_t cap, hipStream_t stream,
                              const KTimer* t);
 
+// Writes *p = 0 with a one-thread kernel (no memset node on the stream).
+hipError_t launch_zero_u64(uint64_t* p, hipStream_t stream);
+
+// Query scratch that lives in the code object instead of an allocation: the
+// per-query counts and the scan's look-back words of a range query batch of
+// up to kFixedMaxQueries queries.  Each device holds one copy for the life
+// of the process, shared by every handle on it.
+constexpr uint32_t kFixedMaxQueries = 1u << 20;
+struct FixedScratch {
+  uint32_t* counts;   // kFixedMaxQueries words
+  uint64_t* status;   // scan_status_words(kFixedMaxQueries) words
+};
+// The device address of the current device's copy (looked up once per
+// device; the device must be current).  Returns the lookup's error, if any.
+hipError_t fixed_scratch(FixedScratch* out);
 
 }  // namespace lsm

@@ -35,6 +35,7 @@
 
 #include "lsm_internal.h"
 
+#include <mutex>
 #include <type_traits>
 
 namespace lsm {
@@ -2167,6 +2168,10 @@ __global__ __launch_bounds__(kThreads) void k_clean_pad(LevelDst d, uint64_t v, 
   dst_write(d, dst_level(d, p, 0), p, kPlaceboKv, 0u);
 }
 
+// Writes one zero word: clears a range call's total where a memset node on
+// the stream is not wanted.
+__global__ void k_zero_u64(uint64_t* p) { *p = 0ull; }
+
 inline unsigned grid_for(uint64_t n, uint64_t per) { return static_cast<unsigned>((n + per - 1) / per); }
 
 template <typename Kernel, typename... Args>
@@ -2180,6 +2185,48 @@ hipError_t launch(Kernel k, unsigned grid, unsigned block, hipStream_t s, const 
 }
 
 }  // namespace
+
+// ------------------------------------------------------------ fixed scratch
+// Range scratch held in the code object (the per-query counts, then the
+// scan's look-back words), for callers that cannot allocate.  Every device
+// that loads the library holds its own copy until the process ends.  Host
+// code must never pass `scratch` itself to a kernel: on the host the name
+// stands for a host-side shadow, so kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr uint64_t kFixedStatusWords = 1 + (kFixedMaxQueries + kScanTile - 1) / kScanTile;
+constexpr uint64_t kFixedWords = kFixedMaxQueries / 2 + kFixedStatusWords;
+static __device__ __align__(256) uint64_t scratch[kFixedWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void* g_fixed_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t fixed_scratch(FixedScratch* out) {
+  out->counts = nullptr;
+  out->status = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_fixed_mu);
+  if (g_fixed_addr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    g_fixed_addr[dev] = p;
+  }
+  uint64_t* base = static_cast<uint64_t*>(g_fixed_addr[dev]);
+  out->counts = reinterpret_cast<uint32_t*>(base);
+  out->status = base + kFixedMaxQueries / 2;
+  return hipSuccess;
+}
+
+hipError_t launch_zero_u64(uint64_t* p, hipStream_t stream) {
+  return launch(k_zero_u64, 1, 1, stream, nullptr, p);
+}
 
 // ------------------------------------------------------------ launchers
 size_t sort_meta_words(uint32_t b) {

@@ -101,6 +101,7 @@ _SIGNATURES = {
     "lsm_flush": (ctypes.c_int, [_vp]),
     "lsm_submit_mixed": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32]),
     "lsm_range_async": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _u64]),
+    "lsm_range_async_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _u64]),
     "lsm_pending": (_u32, [_vp]),
     "lsm_autotune": (ctypes.c_int, [_vp, _u32, _u32]),
     "lsm_get_tuning": (ctypes.c_int, [_vp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float)]),
