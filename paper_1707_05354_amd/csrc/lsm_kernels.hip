@@ -1652,15 +1652,44 @@ __device__ __forceinline__ uint32_t skip_run(const uint32_t* kv, uint32_t c, uin
   return hi;
 }
 
+// The bounds [lower_bound(k1), upper_bound(k2)) of the first kW occupied
+// levels, kept in registers: level l's bounds go to slot l through a
+// compare per slot, so no register array is indexed at run time (which
+// would put the walk state in scratch memory).
+template <int kW>
+__device__ __forceinline__ void level_bounds(const LevelSet& lv, uint32_t k1, uint32_t k2,
+                                             uint32_t (&cur)[kW], uint32_t (&end)[kW]) {
+#pragma unroll
+  for (int q = 0; q < kW; ++q) cur[q] = end[q] = 0u;
+  if (k1 > k2) return;
+  for (int l = 0; l < lv.count && l < kW; ++l) {
+    uint32_t lo, hi;
+    fenced_range(lv.kv[l], lv.fence[l], lv.len[l], k1, k2, lo, hi);
+#pragma unroll
+    for (int q = 0; q < kW; ++q) {
+      if (q == l) {
+        cur[q] = lo;
+        end[q] = hi;
+      }
+    }
+  }
+}
+
+// Key of the candidate at cur in a level, or kNoKey past its end.
+__device__ __forceinline__ uint32_t cand_key(const uint32_t* kv, uint32_t cur, uint32_t end) {
+  return cur < end ? (kv[cur] >> 1) : kNoKey;
+}
+
 // Walk the candidate runs [lower_bound(k1), upper_bound(k2)) of all occupied
 // levels in key order.  For each distinct key the element met first is the
 // newest instance (smaller levels are newer, and inside a level a key's run
 // starts with its newest element); it counts when it is a regular element.
-template <bool kOneLevel>
+// kW = 1: one occupied level; otherwise at most kW occupied levels, the walk
+// state in registers (loops unrolled over the kW slots).
+template <int kW>
 __device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, uint32_t k2) {
   if (k1 > k2) return 0u;
-  const int L = lv.count;
-  if (kOneLevel) {
+  if constexpr (kW == 1) {
     // One level: the first element of every key run is that key's newest
     // instance, so the candidates are scanned in order, 16 at a time (their
     // loads independent); a chunk that holds no run start lies inside one
@@ -1691,37 +1720,33 @@ __device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, 
     }
     return count;
   } else {
-  uint32_t cur[kMaxLevels], end[kMaxLevels], ck[kMaxLevels];
-  for (int l = 0; l < L; ++l) {
-    const uint32_t* kv = lv.kv[l];
-    fenced_range(kv, lv.fence[l], lv.len[l], k1, k2, cur[l], end[l]);
-    ck[l] = cur[l] < end[l] ? (kv[cur[l]] >> 1) : kNoKey;
-  }
-  uint32_t count = 0;
-  for (;;) {
-    uint32_t mk = kNoKey;
-    int mi = -1;
-    for (int l = 0; l < L; ++l) {
-      if (ck[l] < mk) {
-        mk = ck[l];
-        mi = l;
+    uint32_t cur[kW], end[kW], ck[kW];
+    level_bounds<kW>(lv, k1, k2, cur, end);
+#pragma unroll
+    for (int l = 0; l < kW; ++l) ck[l] = cand_key(lv.kv[l], cur[l], end[l]);
+    uint32_t count = 0;
+    for (;;) {
+      uint32_t mk = kNoKey;
+#pragma unroll
+      for (int l = 0; l < kW; ++l) mk = ck[l] < mk ? ck[l] : mk;
+      if (mk == kNoKey) break;
+      bool newest = true;
+#pragma unroll
+      for (int l = 0; l < kW; ++l) {
+        if (ck[l] == mk) {
+          const uint32_t* kv = lv.kv[l];
+          if (newest) count += kv[cur[l]] & 1u;
+          newest = false;
+          cur[l] = skip_run(kv, cur[l], end[l], mk);
+          ck[l] = cand_key(kv, cur[l], end[l]);
+        }
       }
     }
-    if (mi < 0) break;
-    const uint32_t x = lv.kv[mi][cur[mi]];
-    if (x & 1u) ++count;
-    for (int l = mi; l < L; ++l) {
-      if (ck[l] == mk) {
-        cur[l] = skip_run(lv.kv[l], cur[l], end[l], mk);
-        ck[l] = cur[l] < end[l] ? (lv.kv[l][cur[l]] >> 1) : kNoKey;
-      }
-    }
-  }
-  return count;
+    return count;
   }
 }
 
-template <bool kOneLevel>
+template <int kW>
 __global__ __launch_bounds__(kQueryThreads) void k_count(LevelSet lv, const uint32_t* lo,
                                                          const uint32_t* hi, uint32_t nq,
                                                          uint32_t* counts, uint64_t* scan_status,
@@ -1732,7 +1757,7 @@ __global__ __launch_bounds__(kQueryThreads) void k_count(LevelSet lv, const uint
       scan_status[w] = 0ull;
   }
   if (gi >= nq) return;
-  counts[gi] = range_walk<kOneLevel>(lv, lo[gi], hi[gi]);
+  counts[gi] = range_walk<kW>(lv, lo[gi], hi[gi]);
 }
 
 // Resumable form of range_walk for the emission pass: the walk of one query
@@ -1743,8 +1768,9 @@ __global__ __launch_bounds__(kQueryThreads) void k_count(LevelSet lv, const uint
 struct WalkOne {
   uint32_t p, e, prev;  // next candidate, end of the candidates, key before p
 };
+template <int kW>
 struct WalkMany {
-  uint32_t cur[kMaxLevels], end[kMaxLevels], ck[kMaxLevels];
+  uint32_t cur[kW], end[kW], ck[kW];
 };
 
 __device__ __forceinline__ void walk_init(const LevelSet& lv, uint32_t k1, uint32_t k2, WalkOne& w) {
@@ -1753,12 +1779,11 @@ __device__ __forceinline__ void walk_init(const LevelSet& lv, uint32_t k1, uint3
   if (k1 <= k2) fenced_range(lv.kv[0], lv.fence[0], lv.len[0], k1, k2, w.p, w.e);
 }
 
-__device__ __forceinline__ void walk_init(const LevelSet& lv, uint32_t k1, uint32_t k2, WalkMany& w) {
-  for (int l = 0; l < lv.count; ++l) {
-    w.cur[l] = w.end[l] = 0;
-    if (k1 <= k2) fenced_range(lv.kv[l], lv.fence[l], lv.len[l], k1, k2, w.cur[l], w.end[l]);
-    w.ck[l] = w.cur[l] < w.end[l] ? (lv.kv[l][w.cur[l]] >> 1) : kNoKey;
-  }
+template <int kW>
+__device__ __forceinline__ void walk_init(const LevelSet& lv, uint32_t k1, uint32_t k2, WalkMany<kW>& w) {
+  level_bounds<kW>(lv, k1, k2, w.cur, w.end);
+#pragma unroll
+  for (int l = 0; l < kW; ++l) w.ck[l] = cand_key(lv.kv[l], w.cur[l], w.end[l]);
 }
 
 // One level: the first element of every key run is that key's newest
@@ -1810,30 +1835,37 @@ __device__ __forceinline__ uint64_t walk_emit(const LevelSet& lv, WalkOne& w, ui
 // Several levels: the k-way walk over the level runs in key order; the
 // element met first for each key (smallest level first) is its newest
 // instance, emitted when regular.
-__device__ __forceinline__ uint64_t walk_emit(const LevelSet& lv, WalkMany& w, uint64_t pos,
+template <int kW>
+__device__ __forceinline__ uint64_t walk_emit(const LevelSet& lv, WalkMany<kW>& w, uint64_t pos,
                                               uint64_t lim, uint64_t c0, uint32_t* sk,
                                               uint32_t* sv) {
-  const int L = lv.count;
   for (;;) {
     uint32_t mk = kNoKey;
-    int mi = -1;
-    for (int l = 0; l < L; ++l) {
-      if (w.ck[l] < mk) {
-        mk = w.ck[l];
-        mi = l;
+#pragma unroll
+    for (int l = 0; l < kW; ++l) mk = w.ck[l] < mk ? w.ck[l] : mk;
+    if (mk == kNoKey) break;
+    // The newest instance: the first level holding the key.
+    uint32_t x = 0, v = 0;
+    bool newest = true;
+#pragma unroll
+    for (int l = 0; l < kW; ++l) {
+      if (newest && w.ck[l] == mk) {
+        x = lv.kv[l][w.cur[l]];
+        v = lv.val[l][w.cur[l]];
+        newest = false;
       }
     }
-    if (mi < 0) break;
-    if (lv.kv[mi][w.cur[mi]] & 1u) {
+    if (x & 1u) {
       if (pos >= lim) break;  // this key is emitted by a later call
       sk[pos - c0] = mk;
-      sv[pos - c0] = lv.val[mi][w.cur[mi]];
+      sv[pos - c0] = v;
       ++pos;
     }
-    for (int l = mi; l < L; ++l) {
+#pragma unroll
+    for (int l = 0; l < kW; ++l) {
       if (w.ck[l] == mk) {
         w.cur[l] = skip_run(lv.kv[l], w.cur[l], w.end[l], mk);
-        w.ck[l] = w.cur[l] < w.end[l] ? (lv.kv[l][w.cur[l]] >> 1) : kNoKey;
+        w.ck[l] = cand_key(lv.kv[l], w.cur[l], w.end[l]);
       }
     }
   }
@@ -1851,7 +1883,7 @@ __device__ __forceinline__ uint64_t walk_emit(const LevelSet& lv, WalkMany& w, u
 constexpr uint32_t kEmitChunk = 512;
 constexpr int kQueryWaves = kQueryThreads / 64;
 
-template <bool kOneLevel>
+template <int kW>
 __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const uint32_t* lo,
                                                               const uint32_t* hi, uint32_t nq,
                                                               const uint64_t* offsets,
@@ -1879,7 +1911,7 @@ __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const
   const uint32_t rounds =
       copy_end > base ? static_cast<uint32_t>((copy_end - base + kEmitChunk - 1) / kEmitChunk) : 0u;
   if (lane == 0) s_rounds[wave] = rounds;
-  typename std::conditional<kOneLevel, WalkOne, WalkMany>::type w;
+  typename std::conditional<kW == 1, WalkOne, WalkMany<kW>>::type w;
   if (fits) walk_init(lv, lo[i], hi[i], w);
   __syncthreads();
   uint32_t R = 0;
@@ -2382,8 +2414,9 @@ hipError_t launch_count(const LevelSet& lv, const uint32_t* lo, const uint32_t* 
                         uint32_t* counts, uint64_t* scan_status, size_t scan_words,
                         hipStream_t stream, const KTimer* t) {
   if (nq == 0) return hipSuccess;
-  return launch(lv.count == 1 ? k_count<true> : k_count<false>, grid_for(nq, kQueryThreads),
-                kQueryThreads, stream, t, lv, lo, hi, nq,
+  auto k = lv.count <= 1 ? k_count<1> : lv.count <= 8 ? k_count<8> : lv.count <= 16 ? k_count<16>
+                                                                           : k_count<kMaxLevels>;
+  return launch(k, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi, nq,
                 counts, scan_status, static_cast<uint64_t>(scan_words));
 }
 
@@ -2441,9 +2474,10 @@ hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint3
                              uint32_t* out_vals, uint64_t cap, hipStream_t stream,
                              const KTimer* t) {
   if (nq == 0) return hipSuccess;
-  return launch(lv.count == 1 ? k_range_emit<true> : k_range_emit<false>,
-                grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi,
-                nq, offsets, out_keys, out_vals, cap);
+  auto k = lv.count <= 1 ? k_range_emit<1> : lv.count <= 8 ? k_range_emit<8>
+            : lv.count <= 16 ? k_range_emit<16> : k_range_emit<kMaxLevels>;
+  return launch(k, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi, nq, offsets,
+                out_keys, out_vals, cap);
 }
 
 }  // namespace lsm
