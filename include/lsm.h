@@ -225,6 +225,19 @@ LSM_API lsm_status_t lsm_set_fusion(lsm_t h, int max_levels);
  */
 LSM_API lsm_status_t lsm_set_max_inflight(lsm_t h, int launches);
 
+/*
+ * lsm_set_pairing -- pair batches in the top-digit sort (on by default; for
+ * b <= 2^18).  An insertion that would fill level 0 (even batch counter) is
+ * held back until the next update call, and the two batches are then sorted
+ * together (the newer first on equal keys) straight into the level the
+ * second one fills: one bucket sort for two batches, and level 0 is never
+ * written.  Mixed batches (lsm_update_batch), whose sort orders a key's
+ * tombstone before its insertion, never pair.  Queries, cleanup, bulk
+ * insertion and lsm_flush complete a batch held back alone.  Results never
+ * depend on it.
+ */
+LSM_API lsm_status_t lsm_set_pairing(lsm_t h, int on);
+
 #define LSM_SORT_AUTO 0
 #define LSM_SORT_TOP_DIGIT 1
 #define LSM_SORT_DIGIT_PASSES 2

@@ -61,26 +61,36 @@ struct lsm_s {
 
   uint32_t* tmp_kv[2] = {};  // radix ping-pong, b elements each
   uint32_t* tmp_val[2] = {};
-  uint32_t* scat_kv[kSortSlots] = {};  // top-digit sort: the tile-grouped batch of each slot
+  // Top-digit sort: the tile-grouped batch of each slot, slots one after
+  // another in one buffer (a pair's bucket sort reads two of them).
+  uint32_t* scat_kv[kSortSlots] = {};
   uint32_t* scat_val[kSortSlots] = {};
-  uint32_t* buf_kv = nullptr;  // the sorted batch when it has to be merged
+  uint32_t* buf_kv = nullptr;  // the sorted batch (or pair) when it has to be merged
   uint32_t* buf_val = nullptr;
+  // 2 when two batches can be sorted as a pair (b of at most 2^18, so that
+  // both batches' tiles fit one group table): buf and tmp[1] then hold 2b.
+  uint32_t pair_cap = 1;
   uint32_t* meta = nullptr;  // sort histograms, look-back words, group starts, error words
   int hist_parity = 0;       // which histogram buffer the next digit-pass sort uses
 
-  // Pipelined insertion: the newest batch sorted by the top-digit sort has
-  // had its tiles scattered (into scratch slot `slot`) but not its buckets
-  // sorted and merged; that second half runs in the same launch as the next
-  // batch's scatter, or on its own when anything needs the levels.  The
-  // batch already counts in r; it fills level j.
+  // Pipelined insertion: batches sorted by the top-digit sort have had their
+  // tiles scattered (each into its scratch slot) but not their buckets
+  // sorted and merged; that second half runs in the same launch as a later
+  // batch's scatter, or on its own when anything needs the levels.  One
+  // pending batch is sorted alone; two are a pair: a batch that would fill
+  // level 0 alone (even counter) and the next one, sorted together (newer
+  // first on equal keys) straight into the level the second one fills.
+  // Pending batches already count in r.
   struct Pending {
-    bool on = false;
     int slot = 0;
-    int j = 0;
+    int j = 0;        // the level the batch's insertion fills
     int lo_bit = 1;
     int passes = 0;
-  } pend;
-  int next_slot = 0;
+    uint64_t r = 0;   // the batch counter before the batch
+  };
+  Pending pend[2];
+  int npend = 0;
+  bool pairing = true;
   uint32_t* fault = nullptr; // sticky device fault word (inside meta)
 
   uint32_t* mrg_kv[2] = {};  // cascade ping-pong
@@ -284,17 +294,15 @@ void release_all(lsm_t h) {
     dev_free(h, h->lvl_digit[i], kTopBuckets * sizeof(uint32_t));
   }
   for (int i = 0; i < 2; ++i) {
-    dev_free(h, h->tmp_kv[i], bb);
-    dev_free(h, h->tmp_val[i], bb);
+    dev_free(h, h->tmp_kv[i], i == 1 ? h->pair_cap * bb : bb);
+    dev_free(h, h->tmp_val[i], i == 1 ? h->pair_cap * bb : bb);
     dev_free(h, h->mrg_kv[i], h->mrg_cap * sizeof(uint32_t));
     dev_free(h, h->mrg_val[i], h->mrg_cap * sizeof(uint32_t));
   }
-  for (int i = 0; i < kSortSlots; ++i) {
-    dev_free(h, h->scat_kv[i], bb);
-    dev_free(h, h->scat_val[i], bb);
-  }
-  dev_free(h, h->buf_kv, bb);
-  dev_free(h, h->buf_val, bb);
+  dev_free(h, h->scat_kv[0], kSortSlots * bb);
+  dev_free(h, h->scat_val[0], kSortSlots * bb);
+  dev_free(h, h->buf_kv, h->pair_cap * bb);
+  dev_free(h, h->buf_val, h->pair_cap * bb);
   for (int i = 0; i < 2; ++i) dev_free(h, h->mrg_digit[i], kTopBuckets * sizeof(uint32_t));
   dev_free(h, h->buf_digit, kTopBuckets * sizeof(uint32_t));
   dev_free(h, h->meta, sort_meta_words(h->b) * sizeof(uint32_t));
@@ -386,52 +394,60 @@ int default_fuse_max(uint32_t b) {
   return J;
 }
 
-// Fuses the first levels of an insert's cascade into the top-digit sort:
-// levels 0..nf-1 with nf = min(j, fuse_max), cut short at the first level
-// without a top-digit index for this key shift.  When nf = j the sort
-// writes level j (and its index); otherwise it writes the merge scratch
-// buffer that the pairwise merge of level nf then reads.
-void setup_fusion(lsm_t h, SortArgs& sa, int j) {
+// Fuses the first levels of an insert's cascade into the top-digit sort.
+// The sorted run stands for level `base` (0 for one batch; 1 for a pair,
+// whose two batches make a run of level 1's size); levels base..J-1 are
+// merged with it in the bucket work-groups, J = min(j, fuse_max) cut short
+// where a bucket would outgrow LDS and at the first level without a
+// top-digit index for this key shift.  When J = j the sort writes level j
+// (and its index); otherwise it writes the merge scratch buffer that the
+// pairwise merge of level J then reads.
+void setup_fusion(lsm_t h, SortArgs& sa, int j, int base) {
   sa.fuse.nlev = 0;
   sa.out_digit = nullptr;
   if (sa.path != kSortMsd || sort_top_shift(sa) < 1) return;
   const int shift = sort_top_shift(sa) - 1;
-  if (j == 0) {
-    sa.out_digit = h->lvl_digit[0];
+  if (j == base) {
+    sa.out_digit = h->lvl_digit[base];
     return;
   }
-  sa.out_digit = h->buf_digit;  // the sorted batch, when no level is fused
-  int nf = j < h->fuse_max ? j : h->fuse_max;
-  if (nf > kMaxFuse) nf = kMaxFuse;
-  // Keep the fused runs of a bucket within LDS: the previous sort's largest
-  // bucket, grown 2^nf times by the levels, must fit (skewed keys otherwise
+  sa.out_digit = h->buf_digit;  // the sorted run, when no level is fused
+  int J = j < h->fuse_max ? j : h->fuse_max;
+  if (J > base + kMaxFuse) J = base + kMaxFuse;
+  // Keep the fused runs of a bucket within LDS: one batch's largest bucket
+  // (the previous sort's), grown 2^J times, must fit (skewed keys otherwise
   // leave one work-group ranking a huge bucket through global memory).
   const uint64_t big = *reinterpret_cast<volatile uint32_t*>(h->skew_host);
-  while (nf > 0 && (big << nf) > static_cast<uint64_t>(kLocalCap)) --nf;
-  for (int l = 0; l < nf; ++l)
-    if (h->digit_shift[l] != shift) nf = l;
+  while (J > base && (big << J) > static_cast<uint64_t>(kLocalCap)) --J;
+  for (int l = base; l < J; ++l) {
+    if (h->digit_shift[l] != shift) {
+      J = l;
+      break;
+    }
+  }
+  const int nf = J - base;
   if (nf < 1) return;
   sa.out_digit = nullptr;
   FuseArgs& f = sa.fuse;
   f.nlev = nf;
   f.key_shift = shift;
-  for (int l = 0; l < nf; ++l) {
-    f.kv[l] = h->lvl_kv[l];
-    f.val[l] = h->lvl_val[l];
-    f.digit[l] = h->lvl_digit[l];
-    f.len[l] = static_cast<uint32_t>(level_len(h, l));
+  for (int q = 0; q < nf; ++q) {
+    f.kv[q] = h->lvl_kv[base + q];
+    f.val[q] = h->lvl_val[base + q];
+    f.digit[q] = h->lvl_digit[base + q];
+    f.len[q] = static_cast<uint32_t>(level_len(h, base + q));
   }
-  f.out_len = level_len(h, nf);
-  if (nf == j) {
+  f.out_len = level_len(h, J);
+  if (J == j) {
     f.out_kv = h->lvl_kv[j];
     f.out_val = h->lvl_val[j];
     f.out_fence = h->lvl_fence[j];
     f.out_digit = h->lvl_digit[j];
   } else {
-    f.out_kv = h->mrg_kv[(nf + 1) & 1];
-    f.out_val = h->mrg_val[(nf + 1) & 1];
+    f.out_kv = h->mrg_kv[(J + 1) & 1];
+    f.out_val = h->mrg_val[(J + 1) & 1];
     f.out_fence = nullptr;
-    f.out_digit = h->mrg_digit[(nf + 1) & 1];
+    f.out_digit = h->mrg_digit[(J + 1) & 1];
   }
 }
 
@@ -471,9 +487,10 @@ SortArgs sort_args(lsm_t h, const BatchSrc& src, int j, int path) {
   sa.out_kv = (j == 0) ? h->lvl_kv[0] : h->buf_kv;
   sa.out_val = (j == 0) ? h->lvl_val[0] : h->buf_val;
   sa.out_fence = (j == 0) ? h->lvl_fence[0] : nullptr;
+  sa.out_n = h->b;
   sa.path = path;
   sa.skew_out = h->skew_dev;
-  setup_fusion(h, sa, j);
+  setup_fusion(h, sa, j, 0);
   return sa;
 }
 
@@ -490,32 +507,46 @@ SortArgs scatter_args(lsm_t h, const BatchSrc& src, int slot) {
   sa.tmp_val[0] = h->scat_val[slot];
   sa.tmp_kv[1] = h->tmp_kv[1];
   sa.tmp_val[1] = h->tmp_val[1];
+  sa.out_n = h->b;
   sa.path = kSortMsd;
   sa.skew_out = h->skew_dev;
   return sa;
 }
 
-// Arguments of the bucket sort (and fused cascade) of the pending batch, for
-// the state of the levels it meets: every earlier batch's insertion has been
-// enqueued.
-SortArgs pending_args(lsm_t h) {
-  const lsm_s::Pending& p = h->pend;
+// Arguments of the bucket sort (and fused cascade) of the pending batches --
+// one batch, or a pair -- for the state of the levels they meet: every
+// earlier batch's insertion has been enqueued.  *j receives the level the
+// insertion fills and *base the level the sorted run stands for.
+SortArgs pending_args(lsm_t h, int* j, int* base) {
+  const bool pair = h->npend == 2;
+  const lsm_s::Pending& p = h->pend[h->npend - 1];  // the newest batch
   SortArgs sa{};
-  sa.src = BatchSrc{nullptr, nullptr, nullptr, h->b, h->b, kInsert};  // read from the slot
+  sa.src = BatchSrc{nullptr, nullptr, nullptr, h->b, h->b, kInsert};  // read from the slots
   sa.lo_bit = p.lo_bit;
   sa.passes = p.passes;
   sa.key_limit_bits = h->key_bits;
   sa.meta = sort_meta_carve(h->meta, h->b, h->hist_parity, p.slot);
-  sa.tmp_kv[0] = h->scat_kv[p.slot];
-  sa.tmp_val[0] = h->scat_val[p.slot];
+  sa.tmp_kv[0] = h->scat_kv[0];  // every slot; the batch starts at src_off
+  sa.tmp_val[0] = h->scat_val[0];
+  sa.src_off = static_cast<uint32_t>(p.slot) * h->b;
+  if (pair) {
+    const lsm_s::Pending& o = h->pend[0];  // the older batch
+    const SortMeta om = sort_meta_carve(h->meta, h->b, h->hist_parity, o.slot);
+    sa.meta.tile_cnt2 = om.tile_cnt;
+    sa.meta.skew2 = om.skew;
+    sa.src_off2 = static_cast<uint32_t>(o.slot) * h->b;
+  }
   sa.tmp_kv[1] = h->tmp_kv[1];
   sa.tmp_val[1] = h->tmp_val[1];
-  sa.out_kv = (p.j == 0) ? h->lvl_kv[0] : h->buf_kv;
-  sa.out_val = (p.j == 0) ? h->lvl_val[0] : h->buf_val;
-  sa.out_fence = (p.j == 0) ? h->lvl_fence[0] : nullptr;
+  *j = p.j;
+  *base = pair ? 1 : 0;
+  sa.out_kv = (p.j == *base) ? h->lvl_kv[p.j] : h->buf_kv;
+  sa.out_val = (p.j == *base) ? h->lvl_val[p.j] : h->buf_val;
+  sa.out_fence = (p.j == *base) ? h->lvl_fence[p.j] : nullptr;
+  sa.out_n = pair ? 2 * h->b : h->b;
   sa.path = kSortMsd;
   sa.skew_out = h->skew_dev;
-  setup_fusion(h, sa, p.j);
+  setup_fusion(h, sa, p.j, *base);
   return sa;
 }
 
@@ -523,8 +554,9 @@ SortArgs pending_args(lsm_t h) {
 // and value read and written, and with a fused cascade every element of the
 // levels it takes over read and of the level it writes written.
 double bucket_bytes(lsm_t h, const SortArgs& sa) {
-  return sa.fuse.nlev > 0 ? 16.0 * static_cast<double>(level_len(h, sa.fuse.nlev))
-                          : 16.0 * static_cast<double>(h->b);
+  (void)h;
+  return sa.fuse.nlev > 0 ? 16.0 * static_cast<double>(sa.fuse.out_len)
+                          : 16.0 * static_cast<double>(sa.out_n);
 }
 
 // The cascade of Fig. 2(a): while level i is full, buffer <- merge(buffer,
@@ -535,15 +567,16 @@ double bucket_bytes(lsm_t h, const SortArgs& sa) {
 // by the sort itself (j = 0, or every level fused), or by the last merge when
 // both of its runs carried one (a run's index is the sort's, or a merge's of
 // two indexed runs; level i's counts when built for the sort's key shift).
-hipError_t enqueue_cascade(lsm_t h, const SortArgs& sa, int j, hipStream_t s, Timed* last,
-                           bool* indexed) {
-  const int i0 = sa.fuse.nlev;
-  const uint32_t* cur_kv = i0 > 0 ? sa.fuse.out_kv : sa.out_kv;
-  const uint32_t* cur_val = i0 > 0 ? sa.fuse.out_val : sa.out_val;
-  const uint32_t* cur_dig = i0 > 0 ? sa.fuse.out_digit : sa.out_digit;
+hipError_t enqueue_cascade(lsm_t h, const SortArgs& sa, int j, int base, hipStream_t s,
+                           Timed* last, bool* indexed) {
+  const int i0 = base + sa.fuse.nlev;
+  const bool fused = sa.fuse.nlev > 0;
+  const uint32_t* cur_kv = fused ? sa.fuse.out_kv : sa.out_kv;
+  const uint32_t* cur_val = fused ? sa.fuse.out_val : sa.out_val;
+  const uint32_t* cur_dig = fused ? sa.fuse.out_digit : sa.out_digit;
   const int shift = sort_top_shift(sa) - 1;
   const bool by_digit = merge_by_digit(h);
-  if (indexed != nullptr) *indexed = (j == 0) ? sa.out_digit != nullptr : (i0 == j && cur_dig);
+  if (indexed != nullptr) *indexed = (j == base) ? sa.out_digit != nullptr : (i0 == j && cur_dig);
   for (int i = i0; i < j; ++i) {
     uint32_t* o_kv = (i == j - 1) ? h->lvl_kv[j] : h->mrg_kv[i & 1];
     uint32_t* o_val = (i == j - 1) ? h->lvl_val[j] : h->mrg_val[i & 1];
@@ -588,13 +621,14 @@ void commit_insert(lsm_t h, int j) {
   h->sorted_total += h->b;
 }
 
-// Enqueues the second half of the pending batch's insertion (its bucket sort
-// with the fused cascade, then the remaining merges), in one launch with the
-// tile scatter `next` when given.  On failure the batch stays pending (its
-// slot is untouched, so it can be redone) and the state is unchanged.
+// Enqueues the second half of the pending insertion (the bucket sort of
+// the pending batch or pair with its fused cascade, then the remaining
+// merges), in one launch with the tile scatter `next` when given.  On
+// failure the batches stay pending (their slots are untouched, so the work
+// can be redone) and the state is unchanged.
 hipError_t launch_pending(lsm_t h, const SortArgs* next, Timed* first, Timed* last) {
-  const SortArgs bk = pending_args(h);
-  const int j = h->pend.j;
+  int j = 0, base = 0;
+  const SortArgs bk = pending_args(h, &j, &base);
   Timed ts;
   const KTimer* t =
       next != nullptr
@@ -608,10 +642,10 @@ hipError_t launch_pending(lsm_t h, const SortArgs* next, Timed* first, Timed* la
     if (last) *last = ts;
   }
   bool indexed = false;
-  e = enqueue_cascade(h, bk, j, h->stream, t != nullptr ? last : nullptr, &indexed);
+  e = enqueue_cascade(h, bk, j, base, h->stream, t != nullptr ? last : nullptr, &indexed);
   if (e != hipSuccess) return e;
   note_digit_index(h, bk, j, indexed);
-  h->pend.on = false;
+  h->npend = 0;
   return hipSuccess;
 }
 
@@ -640,8 +674,8 @@ void pace(lsm_t h) {
 // Completes the pending insertion, if any: everything that reads the levels
 // calls this first.
 lsm_status_t drain(lsm_t h) {
-  if (!h->pend.on) return LSM_OK;
-  const int slot = h->pend.slot;
+  if (h->npend == 0) return LSM_OK;
+  const int slot = h->pend[h->npend - 1].slot;  // its record holds the sort's skew
   Timed first, last;
   if (launch_pending(h, nullptr, &first, &last) != hipSuccess) return LSM_EHIP;
   // Hand the just-sorted batch's largest bucket to the host-visible hint
@@ -691,12 +725,28 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
   const int path = sort_path(h, sort_meta_carve(h->meta, h->b, 0, 0).num_sort_tiles);
 
   if (path == kSortMsd) {
-    const int slot = h->pend.on ? (h->pend.slot ^ 1) : h->next_slot;
+    // This batch's slot: one that no pending batch holds.
+    int slot = 0;
+    while ((h->npend > 0 && h->pend[0].slot == slot) || (h->npend > 1 && h->pend[1].slot == slot))
+      ++slot;
     pace(h);
     const SortArgs sc = scatter_args(h, src, slot);
+    // A batch pending alone that filled level 0 (even counter) and this one,
+    // the next batch, are sorted as a pair at the next launch; otherwise the
+    // pending batches' buckets run beside this batch's scatter.  Only
+    // batches whose sort leaves the status bit out pair up: a stable sort of
+    // both on the original key, the newer batch first, is then what merging
+    // the two sorted batches gives.  (A mixed batch sorts its tombstone of a
+    // key before its insertion, which a pair's sort would apply across the
+    // two batches.)
+    const uint64_t r0 = h->r;
+    const bool pair_up = h->pairing && h->pair_cap == 2 && h->npend == 1 &&
+                         (h->pend[0].r & 1u) == 0 && r0 == h->pend[0].r + 1 &&
+                         h->pend[0].lo_bit == 1 && sc.lo_bit == 1 &&
+                         h->pend[0].passes == sc.passes;
     Timed first, last;
     hipError_t e;
-    if (h->pend.on) {
+    if (h->npend > 0 && !pair_up) {
       e = launch_pending(h, &sc, &first, &last);
     } else {
       const KTimer* t = timer(h, first, kKMsdScatter, h->b, 16.0 * h->b);
@@ -706,12 +756,9 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
     if (e != hipSuccess) return LSM_EHIP;
     h->launch_seq += 1;
     if (h->prof) call_span(h, kSpanUpdate, first, last, h->b);
-    h->pend.on = true;
-    h->pend.slot = slot;
-    h->pend.j = j;
-    h->pend.lo_bit = sc.lo_bit;
-    h->pend.passes = sc.passes;
-    h->next_slot = slot ^ 1;
+    const lsm_s::Pending np{slot, j, sc.lo_bit, sc.passes, r0};
+    h->pend[h->npend] = np;  // launch_pending emptied the list; a pair appends
+    h->npend += 1;
     h->sorts_by_path[kSortMsd] += 1;
     commit_insert(h, j);
     return LSM_OK;
@@ -739,7 +786,7 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
   if (se != hipSuccess) return LSM_EHIP;
   Timed last = st[nk - 1];
   bool indexed = false;
-  if (enqueue_cascade(h, sa, j, h->stream, timed ? &last : nullptr, &indexed) != hipSuccess)
+  if (enqueue_cascade(h, sa, j, 0, h->stream, timed ? &last : nullptr, &indexed) != hipSuccess)
     return LSM_EHIP;
   if (timed) call_span(h, kSpanUpdate, st[0], last, h->b);
   note_digit_index(h, sa, j, indexed);
@@ -824,16 +871,18 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
     return LSM_EHIP;
   }
   const size_t bb = static_cast<size_t>(b) * sizeof(uint32_t);
+  h->pair_cap = 2u * ((b + kSortTile - 1) / kSortTile) <= static_cast<uint32_t>(kThreads) ? 2u : 1u;
   void* p = nullptr;
   lsm_status_t s = LSM_OK;
   for (int i = 0; i < 2 && s == LSM_OK; ++i) {
-    if ((s = dev_alloc(h, &p, bb)) == LSM_OK) h->tmp_kv[i] = static_cast<uint32_t*>(p);
-    if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->tmp_val[i] = static_cast<uint32_t*>(p);
+    const size_t sz = i == 1 ? h->pair_cap * bb : bb;
+    if ((s = dev_alloc(h, &p, sz)) == LSM_OK) h->tmp_kv[i] = static_cast<uint32_t*>(p);
+    if (s == LSM_OK && (s = dev_alloc(h, &p, sz)) == LSM_OK) h->tmp_val[i] = static_cast<uint32_t*>(p);
   }
-  for (int i = 0; i < kSortSlots && s == LSM_OK; ++i) {
-    if ((s = dev_alloc(h, &p, bb)) == LSM_OK) h->scat_kv[i] = static_cast<uint32_t*>(p);
-    if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->scat_val[i] = static_cast<uint32_t*>(p);
-  }
+  if (s == LSM_OK && (s = dev_alloc(h, &p, kSortSlots * bb)) == LSM_OK)
+    for (int i = 0; i < kSortSlots; ++i) h->scat_kv[i] = static_cast<uint32_t*>(p) + static_cast<size_t>(i) * b;
+  if (s == LSM_OK && (s = dev_alloc(h, &p, kSortSlots * bb)) == LSM_OK)
+    for (int i = 0; i < kSortSlots; ++i) h->scat_val[i] = static_cast<uint32_t*>(p) + static_cast<size_t>(i) * b;
   for (int i = 0; i < 2 && s == LSM_OK; ++i)
     if ((s = dev_alloc(h, &p, kTopBuckets * sizeof(uint32_t))) == LSM_OK)
       h->mrg_digit[i] = static_cast<uint32_t*>(p);
@@ -842,8 +891,8 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
   for (int i = 0; i < kMaxLevels; ++i) h->merge_variant[i] = kDefaultMergeVariant;
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->stage_kv = static_cast<uint32_t*>(p);
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->stage_val = static_cast<uint32_t*>(p);
-  if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->buf_kv = static_cast<uint32_t*>(p);
-  if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->buf_val = static_cast<uint32_t*>(p);
+  if (s == LSM_OK && (s = dev_alloc(h, &p, h->pair_cap * bb)) == LSM_OK) h->buf_kv = static_cast<uint32_t*>(p);
+  if (s == LSM_OK && (s = dev_alloc(h, &p, h->pair_cap * bb)) == LSM_OK) h->buf_val = static_cast<uint32_t*>(p);
   if (s == LSM_OK && (s = dev_alloc(h, &p, sort_meta_words(b) * sizeof(uint32_t))) == LSM_OK) {
     h->meta = static_cast<uint32_t*>(p);
     h->fault = sort_meta_carve(h->meta, b, 0, 0).err + 1;
@@ -1095,6 +1144,7 @@ lsm_status_t lsm_bulk_insert(lsm_t h, const uint32_t* d_keys, const uint32_t* d_
     sa.out_kv = p.n_old == 0 ? h->lvl_kv[i] : u32(mg[0][0]);
     sa.out_val = p.n_old == 0 ? h->lvl_val[i] : u32(mg[0][1]);
     sa.out_fence = p.n_old == 0 ? h->lvl_fence[i] : nullptr;
+    sa.out_n = static_cast<uint32_t>(len);
     sa.path = sort_path(h, sa.meta.num_sort_tiles);
     sa.skew_out = h->skew_dev;
     Timed ts[1 + kMaxPasses];
@@ -1535,7 +1585,7 @@ lsm_status_t lsm_sync(lsm_t h) {
 
 lsm_status_t lsm_clear(lsm_t h) {
   if (h == nullptr) return LSM_EINVAL;
-  h->pend.on = false;  // its half-done insertion is simply dropped
+  h->npend = 0;  // the half-done insertions are simply dropped
   h->r = 0;
   h->stage_fill = 0;
   h->merged_last = 0;
@@ -1685,6 +1735,12 @@ lsm_status_t lsm_level_copy(lsm_t h, uint32_t i, uint32_t* d_kv_out, uint32_t* d
 lsm_status_t lsm_set_fusion(lsm_t h, int max_levels) {
   if (h == nullptr || max_levels > kMaxFuse) return LSM_EINVAL;
   h->fuse_max = max_levels < 0 ? default_fuse_max(h->b) : max_levels;
+  return LSM_OK;
+}
+
+lsm_status_t lsm_set_pairing(lsm_t h, int on) {
+  if (h == nullptr) return LSM_EINVAL;
+  h->pairing = on != 0;
   return LSM_OK;
 }
 

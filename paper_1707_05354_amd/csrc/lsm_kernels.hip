@@ -835,7 +835,7 @@ __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, 
     const uint32_t k = a.tmp_kv[0][at];
     bk[first][x] = k;
     bv[first][x] = a.tmp_val[0][at];
-    if (passes == 0) put_fence(a.out_fence, a.src.b, s + x, k);
+    if (passes == 0) put_fence(a.out_fence, a.out_n, s + x, k);
   }
   if (passes == 0) return;
   __threadfence_block();
@@ -892,7 +892,7 @@ __device__ void local_sort_streaming(const SortArgs& a, int lo_bit, int passes, 
           if (o < n) {
             ok[o] = kv[i];
             ov[o] = vv[i];
-            if (p == passes - 1) put_fence(a.out_fence, a.src.b, s + o, kv[i]);
+            if (p == passes - 1) put_fence(a.out_fence, a.out_n, s + o, kv[i]);
           }
         }
       }
@@ -1010,9 +1010,16 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   // (clamped index), so each tile's group bounds and the levels' digit
   // ranges are in flight together.
   auto next_of = [](uint32_t q) { return q + 1 < kTopBuckets ? q + 1 : q; };
+  // A pair (two consecutive batches sorted together, the newer first on
+  // equal keys) has the newer batch's tiles, then the older batch's: nta
+  // group-table entries, one per thread.
   const uint32_t ntiles = m.num_sort_tiles;
+  const bool pair = m.tile_cnt2 != nullptr;
+  const uint32_t nta = pair ? 2 * ntiles : ntiles;
   static_assert(kMsdMaxTiles <= kThreads, "one tile per thread");
-  const uint32_t* row = m.tile_cnt + static_cast<size_t>(tid < ntiles ? tid : 0) * (kTopBuckets / 2);
+  const bool older = pair && tid >= ntiles && tid < nta;
+  const uint32_t tt = older ? tid - ntiles : (tid < ntiles ? tid : 0u);  // tile in its batch
+  const uint32_t* row = (older ? m.tile_cnt2 : m.tile_cnt) + static_cast<size_t>(tt) * (kTopBuckets / 2);
   const uint32_t seg_w0 = row[d >> 1];
   const uint32_t seg_w1 = row[next_of(d) >> 1];
   // The digit's range in each fused level, from the level's top-digit index:
@@ -1035,22 +1042,22 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   // the tile (the last digit's ends at the tile's size).
   const uint32_t g_st = (d & 1) ? seg_w0 >> 16 : seg_w0 & 0xFFFFu;
   const uint32_t tile_n =
-      tid < ntiles ? min(a.src.b - tid * kSortTile, static_cast<uint32_t>(kSortTile)) : 0u;
+      tid < nta ? min(a.src.b - tt * kSortTile, static_cast<uint32_t>(kSortTile)) : 0u;
   const uint32_t g_en = d + 1 < kTopBuckets ? (((d + 1) & 1) ? seg_w1 >> 16 : seg_w1 & 0xFFFFu)
                                             : tile_n;
-  const uint32_t g_c = (tid < ntiles && g_en > g_st) ? g_en - g_st : 0u;
+  const uint32_t g_c = (tid < nta && g_en > g_st) ? g_en - g_st : 0u;
   // One pass of two scans: the group starts (their total is the bucket's
   // output start) and the group sizes (each group's first position in the
   // bucket; their total is the bucket's size).
-  const uint32_t g_s0 = tid < ntiles ? g_st : 0u;
+  const uint32_t g_s0 = tid < nta ? g_st : 0u;
   uint32_t ssum = g_s0, csum = g_c;
   block_excl_scan2(ssum, csum, L.tmp);
   uint32_t* segb = &L.wcnt[0][0] + (kRankSortMax + 8);  // group sources in the batch
   uint32_t* segp = segb + kMsdMaxTiles;                  // group starts in the bucket
   static_assert(kRankSortMax + 8 + 2 * kMsdMaxTiles <= kWaves * kRadix,
                 "group tables fit beside the rank-sort keys");
-  if (tid < ntiles) {
-    segb[tid] = tid * kSortTile + g_st;
+  if (tid < nta) {
+    segb[tid] = (older ? a.src_off2 : a.src_off) + tt * kSortTile + g_st;
     segp[tid] = csum;
   }
   if (tid == kThreads - 1) {
@@ -1067,8 +1074,13 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   const uint32_t n = L.tmp[2 * kWaves + 1];
   // The sort's largest bucket, for the choice of the next sorts' path and
   // fused depth (only sizes that can change those choices are recorded).
-  if (tid == 0 && n > kSkewFloor && n > *reinterpret_cast<volatile uint32_t*>(m.skew))
-    atomicMax(m.skew, n);
+  // A pair's bucket holds two batches' elements: half of it is recorded, in
+  // both batches' slots (the next scatter into either slot hands it over).
+  const uint32_t n_rec = pair ? (n + 1) / 2 : n;
+  if (tid == 0 && n_rec > kSkewFloor) {
+    if (n_rec > *reinterpret_cast<volatile uint32_t*>(m.skew)) atomicMax(m.skew, n_rec);
+    if (pair && n_rec > *reinterpret_cast<volatile uint32_t*>(m.skew2)) atomicMax(m.skew2, n_rec);
+  }
   if (!fused && a.out_digit != nullptr && tid == 0) a.out_digit[d] = s;
   if (n == 0 && !fused) return;
 
@@ -1171,15 +1183,15 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
     const uint32_t xbmax = n > 0 ? n - 1 : 0u;
     auto search = [&](auto cnt_c) {
       constexpr int kS = decltype(cnt_c)::value;
-      for (uint32_t step = 1u << (31 - __builtin_clz(ntiles)); step > 0; step >>= 1) {
+      for (uint32_t step = 1u << (31 - __builtin_clz(nta)); step > 0; step >>= 1) {
 #pragma unroll
         for (int i = 0; i < kS; ++i) {
           const uint32_t x = tid + i * kThreads;
           const uint32_t xb = x < xbmax ? x : xbmax;
           const uint32_t probe = bidx[i] + step;
-          const uint32_t pc = probe < ntiles ? probe : ntiles - 1;
+          const uint32_t pc = probe < nta ? probe : nta - 1;
           const uint32_t v = segp[pc];
-          bidx[i] = ((probe < ntiles) & (v <= xb)) ? probe : bidx[i];
+          bidx[i] = ((probe < nta) & (v <= xb)) ? probe : bidx[i];
         }
       }
     };
@@ -1246,7 +1258,7 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
     }
   } else {
     sorted_lds = false;
-    local_sort_streaming(a, lo_bit, passes, s, n, L, segb, segp, ntiles);
+    local_sort_streaming(a, lo_bit, passes, s, n, L, segb, segp, nta);
   }
 
   if (!fused) {
@@ -1255,7 +1267,7 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
         const uint32_t k = L.k[buf][x];
         out_k[x] = k;
         out_v[x] = L.v[buf][x];
-        put_fence(a.out_fence, a.src.b, s + x, k);
+        put_fence(a.out_fence, a.out_n, s + x, k);
       }
     }
     return;
@@ -2278,6 +2290,8 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity, int slot) {
   // Per slot: the group starts (16-byte aligned), then the skew record.
   uint32_t* slot_base = m.err + 4 + static_cast<size_t>(slot) * (ns * (kTopBuckets / 2) + 4);
   m.tile_cnt = slot_base;
+  m.tile_cnt2 = nullptr;
+  m.skew2 = nullptr;
   m.skew = slot_base + ns * (kTopBuckets / 2);
   m.parity = parity;
   return m;

@@ -29,6 +29,37 @@ def host(t: torch.Tensor) -> np.ndarray:
     return a
 
 
+def ffz(r: int) -> int:
+    """Index of the lowest zero bit of r: the level batch r fills."""
+    j = 0
+    while (r >> j) & 1:
+        j += 1
+    return j
+
+
+def pipeline_schedule(R: int, pairing: bool = True):
+    """Launches of R top-digit insert batches with no read in between, then
+    one read: a batch pending alone with an even counter waits for the next
+    batch (a pair) when pairing is on; otherwise the pending batches' bucket
+    sort runs in the next batch's scatter launch (a step), and the read
+    completes what is pending (a lone bucket sort).  Returns (scatters
+    alone, steps, lone bucket sorts, the counters of the batches that end a
+    pair)."""
+    scat = step = 0
+    pend, paired = [], []
+    for r in range(R):
+        pair_up = pairing and len(pend) == 1 and pend[0] % 2 == 0 and r == pend[0] + 1
+        if pend and not pair_up:
+            step += 1
+            pend = []
+        else:
+            scat += 1
+        if pair_up:
+            paired.append(r)
+        pend.append(r)
+    return scat, step, 1 if pend else 0, paired
+
+
 def note(msg: str) -> None:
     """Name the case before a GPU step (visible even if the step dies)."""
     sys.stdout.write("[case] %s\n" % msg)

@@ -6,15 +6,17 @@ combined kernel on every call; the levels then equal the cascade oracle's
 byte for byte and the answers the map oracle's.  Covers partial batches,
 deletions, mixed batches, b across tile edges, fused depths, sort-path
 switches in the middle of a stream (the digit-pass sort completes the
-pending batch first), lsm_clear with a pending batch, and the profile of
-the pipeline.  Integer results, tolerance 0."""
+pending batch first), lsm_clear with a pending batch, the profile of the
+pipeline, and pairs (a batch that would fill level 0 waits for the next
+one; both are sorted together into the level the second fills).  Integer
+results, tolerance 0."""
 import numpy as np
 import pytest
 import torch
 
 from paper_1707_05354_amd import workload as W
 from paper_1707_05354_amd.lsm import KERNEL_NAMES, LSM
-from _gpu import Trio, dev, dev_u8, host, note
+from _gpu import Trio, dev, dev_u8, host, note, pipeline_schedule
 
 pytestmark = pytest.mark.gpu
 
@@ -94,14 +96,20 @@ def test_clear_drops_the_pending_batch():
     t.g.close()
 
 
-def test_pipeline_profile_and_sync():
-    """R batches: one scatter, R - 1 steps, and lsm_sync completes the last
-    batch (one bucket sort); the levels are then complete."""
-    b, R = 4096, 21
-    note("pipeline profile b=%d" % b)
+@pytest.mark.parametrize("pairing,R", [(False, 21), (True, 21), (True, 20)])
+def test_pipeline_profile_and_sync(pairing, R):
+    """R batches with no read between them.  Without pairing: one scatter,
+    R - 1 steps, and lsm_sync completes the last batch (one bucket sort).
+    With pairing, each even batch waits for the next: the odd batches'
+    scatters run alone, the even batches' in a step with the pair before
+    them, and lsm_sync sorts what is pending (a lone even batch, or a pair
+    when R is even).  The levels are then complete."""
+    b = 4096
+    note("pipeline profile b=%d R=%d pairing=%d" % (b, R, pairing))
     rng = np.random.default_rng(8)
     t = Trio(b)
     t.g.set_sort_path(LSM.SORT_TOP_DIGIT)
+    t.g.set_pairing(pairing)
     t.g.profile(True)
     t.g.profile_read(reset=True)
     for _ in range(R):
@@ -109,10 +117,91 @@ def test_pipeline_profile_and_sync():
                  rng.integers(0, 2**32, b, dtype=np.uint64).astype(np.uint32))
     t.g.sync()
     p = t.g.profile_read(reset=True)
-    assert int(p.launches[K["k_msd_scatter"]]) == 1
-    assert int(p.launches[K["k_sort_step"]]) == R - 1
-    assert int(p.launches[K["k_local_sort"]]) == 1
+    scat, step, lone, _ = pipeline_schedule(R, pairing)
+    if not pairing:
+        assert (scat, step, lone) == (1, R - 1, 1)
+    else:
+        assert (scat, step, lone) == (1 + R // 2, R - 1 - R // 2, 1)
+    assert int(p.launches[K["k_msd_scatter"]]) == scat
+    assert int(p.launches[K["k_sort_step"]]) == step
+    assert int(p.launches[K["k_local_sort"]]) == lone
     assert p.update_calls == R
     t.g.profile(False)
     t.check_levels()
+    t.g.close()
+
+
+@pytest.mark.parametrize("b,domain", [(1, 1 << 31), (2048, 1 << 31), (2049, 1 << 31),
+                                      (30000, 1 << 31), (256, 779), (700, 1500), (3000, 9000),
+                                      (1 << 18, 1 << 31), ((1 << 18) + 1, 1 << 31)])
+def test_pairing_gives_the_same_levels(b, domain):
+    """The same stream (partial, deleting and mixed batches) with pairing on
+    and off: the levels equal the cascade oracle's and each other byte for
+    byte.  The paired dictionary is read at random points (a read completes
+    a batch that waits alone, so the next batch starts no pair).  Small key
+    domains put every key into one top-digit bucket, so a pair's bucket is
+    ranked by the LDS radix passes (2b <= 1536) or in global memory, and
+    keys repeat across the two batches of a pair and within mixed batches.
+    b = 2^18 is the largest batch that pairs (both batches' tiles in one
+    group table); b = 2^18 + 1 never pairs."""
+    R = 12 if b >= 1 << 18 else 37
+    note("pairing on/off b=%d domain=%d R=%d" % (b, domain, R))
+    ops, q, lo, hi = W.random_small(4400 + b % 97, b, R, domain, p_delete=0.3, nq=300)
+    rng = np.random.default_rng(b)
+    reads = set(rng.choice(R, size=R // 5, replace=False).tolist())
+    tr = [Trio(b), Trio(b)]
+    tr[0].g.set_pairing(True)
+    tr[1].g.set_pairing(False)
+    for t in tr:
+        t.g.set_sort_path(LSM.SORT_TOP_DIGIT)
+    for i, (kind, k, v) in enumerate(ops):
+        dl = (rng.random(k.size) < 0.5).astype(np.uint8)
+        for t in tr:
+            if kind == "insert":
+                t.insert(k, v)
+            elif i % 4 == 3:
+                t.mixed(k, k, dl)
+            else:
+                t.delete(k)
+        if i in reads:
+            tr[0].check_queries(q[:50], lo[:20], hi[:20])
+    for t in tr:
+        t.check_levels()
+    for i in tr[0].c.occupied():
+        a, c = tr[0].g.level(i), tr[1].g.level(i)
+        assert all(np.array_equal(host(x), host(y)) for x, y in zip(a, c)), i
+    tr[0].check_queries(q, lo, hi)
+    st = tr[0].g.stats()
+    assert st.sorts_top_digit == R
+    for t in tr:
+        t.g.close()
+
+
+def test_mixed_batches_never_pair():
+    """Mixed batches sort a key's tombstone before its insertion; across the
+    two batches of a pair that would put an older tombstone before a newer
+    insertion, so they are never paired: a stream of mixed batches over a
+    small key domain (keys repeating within and across batches) runs one
+    scatter and then steps only, and its levels equal the cascade oracle's."""
+    b, R = 256, 24
+    note("mixed batches never pair b=%d" % b)
+    rng = np.random.default_rng(11)
+    t = Trio(b)
+    t.g.set_sort_path(LSM.SORT_TOP_DIGIT)
+    t.g.profile(True)
+    t.g.profile_read(reset=True)
+    for _ in range(R):
+        k = rng.integers(0, 600, b).astype(np.uint32)
+        t.mixed(k, rng.integers(0, 2**32, b, dtype=np.uint64).astype(np.uint32),
+                (rng.random(b) < 0.5).astype(np.uint8))
+    t.g.sync()
+    p = t.g.profile_read(reset=True)
+    t.g.profile(False)
+    scat, step, lone, _ = pipeline_schedule(R, pairing=False)
+    assert int(p.launches[K["k_msd_scatter"]]) == scat
+    assert int(p.launches[K["k_sort_step"]]) == step
+    assert int(p.launches[K["k_local_sort"]]) == lone
+    t.check_levels()
+    q = np.arange(602, dtype=np.uint32)
+    t.check_queries(q, q[:300:3], q[:300:3] + 40)
     t.g.close()

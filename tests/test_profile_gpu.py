@@ -7,18 +7,11 @@ import pytest
 import torch
 
 from paper_1707_05354_amd.lsm import KERNEL_NAMES, LSM
-from _gpu import Trio, dev, host, note
+from _gpu import Trio, dev, ffz, host, note, pipeline_schedule
 
 pytestmark = pytest.mark.gpu
 
 K = {n: i for i, n in enumerate(KERNEL_NAMES)}
-
-
-def ffz(r):
-    j = 0
-    while (r >> j) & 1:
-        j += 1
-    return j
 
 
 def default_fusion(b):
@@ -28,19 +21,21 @@ def default_fusion(b):
     return j
 
 
-@pytest.mark.parametrize("mode,fusion", [
-    (LSM.SORT_TOP_DIGIT, -1), (LSM.SORT_TOP_DIGIT, 0), (LSM.SORT_TOP_DIGIT, 2),
-    (LSM.SORT_DIGIT_PASSES, -1),
+@pytest.mark.parametrize("mode,fusion,pairing", [
+    (LSM.SORT_TOP_DIGIT, -1, True), (LSM.SORT_TOP_DIGIT, 0, True), (LSM.SORT_TOP_DIGIT, 2, True),
+    (LSM.SORT_TOP_DIGIT, 0, False), (LSM.SORT_TOP_DIGIT, 2, False), (LSM.SORT_DIGIT_PASSES, -1, True),
 ])
-def test_profile_counts_follow_the_path(mode, fusion):
+def test_profile_counts_follow_the_path(mode, fusion, pairing):
     """Merge launches: one per level the cascade passes beyond the levels
-    fused into the top-digit sort (none fused on the digit-pass path)."""
+    fused into the top-digit sort (none fused on the digit-pass path; a
+    pair's sort takes level 0's merge, fused or not)."""
     b, R = 4096, 13
     rng = np.random.default_rng(5)
-    note("profile counts mode=%d fusion=%d" % (mode, fusion))
+    note("profile counts mode=%d fusion=%d pairing=%d" % (mode, fusion, pairing))
     t = Trio(b)
     t.g.set_sort_path(mode)
     t.g.set_fusion(fusion)
+    t.g.set_pairing(pairing)
     depth = 0 if mode == LSM.SORT_DIGIT_PASSES else (default_fusion(b) if fusion < 0 else fusion)
     t.g.profile(True)
     t.g.profile_read(reset=True)
@@ -63,13 +58,18 @@ def test_profile_counts_follow_the_path(mode, fusion):
     p = t.g.profile_read(reset=True)
     t.g.profile(False)
     passes = 4  # 31-bit keys, status bit not sorted
-    expect = {"k_merge": sum(max(0, ffz(r) - depth) for r in range(R)), "k_lookup": 1, "k_order": 2,
+    scat, step, lone, paired = pipeline_schedule(R, pairing)
+    if mode != LSM.SORT_TOP_DIGIT:
+        paired = []
+    merges = sum(max(0, ffz(r) - (max(depth, 1) if r in paired else depth)) for r in range(R))
+    expect = {"k_merge": merges, "k_lookup": 1, "k_order": 2,
               "k_range_emit": 1, "k_scan": 1, "k_count": 2}
     if mode == LSM.SORT_TOP_DIGIT:
-        # Pipelined: the first batch's scatter alone, then one step per batch
-        # (its scatter with the previous batch's buckets), and the last
-        # batch's buckets when the first query needs the levels.
-        expect.update({"k_msd_scatter": 1, "k_sort_step": R - 1, "k_local_sort": 1})
+        # Pipelined: scatters alone (the first batch's, and with pairing
+        # each batch that completes a pair), steps (a batch's scatter with
+        # the buckets of the batch or pair before it), and the buckets of
+        # what is pending when the first query needs the levels.
+        expect.update({"k_msd_scatter": scat, "k_sort_step": step, "k_local_sort": lone})
     else:
         expect.update({"k_sort_hist": R, "k_sort_pass": R * passes})
     for name, n in expect.items():
