@@ -103,6 +103,7 @@ struct lsm_s {
 
   uint32_t* q_counts = nullptr;  // range pass 1 output
   uint64_t* q_status = nullptr;  // range scan look-back words
+  uint32_t* q_bounds = nullptr;  // range pass 1: candidate bounds (one level), 2 words a query
   uint64_t q_cap = 0;
   // The device's fixed range scratch (lsm_range_async_noalloc), or nulls
   // when its address could not be looked up.
@@ -266,19 +267,26 @@ lsm_status_t ensure_query_scratch(lsm_t h, uint32_t nq) {
   if (h->q_cap >= nq) return LSM_OK;
   uint64_t cap = h->q_cap ? h->q_cap : 4096;
   while (cap < nq) cap *= 2;
-  void *c = nullptr, *s = nullptr;
+  void *c = nullptr, *s = nullptr, *bd = nullptr;
   if (dev_alloc(h, &c, cap * sizeof(uint32_t)) != LSM_OK) return LSM_ENOMEM;
   const size_t sw = scan_status_words(static_cast<uint32_t>(cap < 0xFFFFFFFFull ? cap : 0xFFFFFFFFull));
   if (dev_alloc(h, &s, sw * sizeof(uint64_t)) != LSM_OK) {
     dev_free(h, c, cap * sizeof(uint32_t));
     return LSM_ENOMEM;
   }
+  if (dev_alloc(h, &bd, 2 * cap * sizeof(uint32_t)) != LSM_OK) {
+    dev_free(h, c, cap * sizeof(uint32_t));
+    dev_free(h, s, sw * sizeof(uint64_t));
+    return LSM_ENOMEM;
+  }
   if (h->q_cap) {
     dev_free(h, h->q_counts, h->q_cap * sizeof(uint32_t));
     dev_free(h, h->q_status, scan_status_words(static_cast<uint32_t>(h->q_cap)) * sizeof(uint64_t));
+    dev_free(h, h->q_bounds, 2 * h->q_cap * sizeof(uint32_t));
   }
   h->q_counts = static_cast<uint32_t*>(c);
   h->q_status = static_cast<uint64_t*>(s);
+  h->q_bounds = static_cast<uint32_t*>(bd);
   h->q_cap = cap;
   return LSM_OK;
 }
@@ -309,6 +317,7 @@ void release_all(lsm_t h) {
   if (h->q_cap) {
     dev_free(h, h->q_counts, h->q_cap * sizeof(uint32_t));
     dev_free(h, h->q_status, scan_status_words(static_cast<uint32_t>(h->q_cap)) * sizeof(uint64_t));
+    dev_free(h, h->q_bounds, 2 * h->q_cap * sizeof(uint32_t));
   }
   if (h->h_pinned) (void)hipHostFree(h->h_pinned);
   if (h->skew_host) (void)hipHostFree(h->skew_host);
@@ -992,7 +1001,7 @@ lsm_status_t lsm_count(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   const LevelSet lv = occupied_levels(h);
   Timed tc;
   const KTimer* t = timer(h, tc, kKCount, nq, 0.0);
-  if (launch_count(lv, d_lo, d_hi, nq, d_counts, nullptr, 0, h->stream, t) != hipSuccess)
+  if (launch_count(lv, d_lo, d_hi, nq, d_counts, nullptr, 0, nullptr, h->stream, t) != hipSuccess)
     return LSM_EHIP;
   if (t != nullptr) call_span(h, kSpanCount, tc, tc, nq);
   return LSM_OK;
@@ -1336,7 +1345,7 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   Timed t1, t2, t3;
   // Stage 1: per-query live counts (also clears the scan's look-back words).
   if (launch_count(lv, d_lo, d_hi, nq, h->q_counts, h->q_status, scan_status_words(nq),
-                   h->stream, timer(h, t1, kKCount, nq, 0.0)) != hipSuccess)
+                   h->q_bounds, h->stream, timer(h, t1, kKCount, nq, 0.0)) != hipSuccess)
     return LSM_EHIP;
   // Stage 2: exclusive scan into the caller's offsets.
   if (launch_scan(h->q_counts, nq, d_offsets, h->q_status, h->fault, h->stream,
@@ -1351,8 +1360,8 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
   if (total > cap) return LSM_ECAPACITY;
   // Stage 3: each query writes its live pairs in key order at its offset.
   if (total > 0) {
-    if (launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, d_keys, d_vals, cap, h->stream,
-                          timer(h, t3, kKRangeEmit, nq, 0.0)) != hipSuccess)
+    if (launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, h->q_bounds, d_keys, d_vals, cap,
+                          h->stream, timer(h, t3, kKRangeEmit, nq, 0.0)) != hipSuccess)
       return LSM_EHIP;
     call_span(h, kSpanRange, t1, t3, nq);
   } else {
@@ -1432,11 +1441,11 @@ lsm_status_t lsm_range_async(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi
   const LevelSet lv = occupied_levels(h);
   Timed t1, t2, t3;
   if (launch_count(lv, d_lo, d_hi, nq, h->q_counts, h->q_status, scan_status_words(nq),
-                   h->stream, timer(h, t1, kKCount, nq, 0.0)) != hipSuccess ||
+                   h->q_bounds, h->stream, timer(h, t1, kKCount, nq, 0.0)) != hipSuccess ||
       launch_scan(h->q_counts, nq, d_offsets, h->q_status, h->fault, h->stream,
                   timer(h, t2, kKScan, nq, 12.0 * nq)) != hipSuccess ||
-      launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, d_keys, d_vals, cap, h->stream,
-                        timer(h, t3, kKRangeEmit, nq, 0.0)) != hipSuccess)
+      launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, h->q_bounds, d_keys, d_vals, cap,
+                        h->stream, timer(h, t3, kKRangeEmit, nq, 0.0)) != hipSuccess)
     return LSM_EHIP;
   return LSM_OK;
 }
@@ -1470,10 +1479,10 @@ lsm_status_t lsm_range_async_noalloc(lsm_t h, const uint32_t* d_lo, const uint32
   if (s != LSM_OK) return s;
   const LevelSet lv = occupied_levels(h);
   if (launch_count(lv, d_lo, d_hi, nq, h->fixed.counts, h->fixed.status, scan_status_words(nq),
-                   h->stream, nullptr) != hipSuccess ||
+                   nullptr, h->stream, nullptr) != hipSuccess ||
       launch_scan(h->fixed.counts, nq, d_offsets, h->fixed.status, h->fault, h->stream,
                   nullptr) != hipSuccess ||
-      launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, d_keys, d_vals, cap, h->stream,
+      launch_range_emit(lv, d_lo, d_hi, nq, d_offsets, nullptr, d_keys, d_vals, cap, h->stream,
                         nullptr) != hipSuccess)
     return LSM_EHIP;
   return LSM_OK;

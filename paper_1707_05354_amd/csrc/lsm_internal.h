@@ -297,10 +297,12 @@ hipError_t launch_lookup(const LevelSet& lv, const uint32_t* q, uint32_t nq, uin
 
 // Count pass: per query number of live keys in [lo, hi].  When scan_status
 // is non-null the kernel also clears the scan's look-back words
-// (scan_words of them, tile counter included) for the following scan.
+// (scan_words of them, tile counter included) for the following scan.  With
+// one occupied level and bounds non-null (2 nq words), each query's
+// candidate bounds in the level are stored there for the emission pass.
 hipError_t launch_count(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi, uint32_t nq,
                         uint32_t* counts, uint64_t* scan_status, size_t scan_words,
-                        hipStream_t stream, const KTimer* t);
+                        uint32_t* bounds, hipStream_t stream, const KTimer* t);
 
 // Exclusive scan of nq uint32 counts into nq + 1 uint64 offsets.
 size_t scan_status_words(uint32_t nq);
@@ -308,8 +310,6 @@ hipError_t launch_scan(const uint32_t* counts, uint32_t nq, uint64_t* offsets,
                        uint64_t* scan_status, uint32_t* fault, hipStream_t stream,
                        const KTimer* t);
 
-// Range emission pass: writes each query's live pairs at offsets[q], for
-// the queries whose pairs end at or before cap.
 // Order queries: per query the live pair with the smallest key > q
 // (successor) or the largest key < q (predecessor); found = 0 leaves key and
 // value 0.
@@ -335,10 +335,13 @@ hipError_t launch_clean_scatter(const uint32_t* kv, const uint32_t* val, uint32_
 hipError_t launch_clean_pad(const LevelDst& d, uint64_t v, uint64_t total, hipStream_t stream,
                             const KTimer* t);
 
+// Range emission pass: writes each query's live pairs at offsets[q], for
+// the queries whose pairs end at or before cap.  bounds: the count pass's
+// candidate bounds (one occupied level), or null to search them again.
 hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi,
-                             uint32_t nq, const uint64_t* offsets, uint32_t* out_keys,
-                             uint32_t* out_vals, uint64_t cap, hipStream_t stream,
-                             const KTimer* t);
+                             uint32_t nq, const uint64_t* offsets, const uint32_t* bounds,
+                             uint32_t* out_keys, uint32_t* out_vals, uint64_t cap,
+                             hipStream_t stream, const KTimer* t);
 
 // Writes *p = 0 with a one-thread kernel (no memset node on the stream).
 hipError_t launch_zero_u64(uint64_t* p, hipStream_t stream);

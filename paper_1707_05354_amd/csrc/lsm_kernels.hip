@@ -23,7 +23,8 @@
 //   k_count / k_range_emit : per-query bounds in every occupied level and a
 //       merge of the per-level candidate runs in level order, keeping the
 //       first element of each key run when it is a regular element
-//       (sec. III-E, IV-C, IV-D).
+//       (sec. III-E, IV-C, IV-D).  k_range_emit_one : the emission with one
+//       occupied level, a wave copying one query's candidates at a time.
 //   k_scan : single-pass exclusive scan with decoupled look-back for the
 //       range output offsets (stage 2 of sec. IV-C).
 //   k_successor / k_predecessor : the order queries of the sec. I-B
@@ -1692,6 +1693,37 @@ __device__ __forceinline__ uint32_t cand_key(const uint32_t* kv, uint32_t cur, u
   return cur < end ? (kv[cur] >> 1) : kNoKey;
 }
 
+// One level: the live keys among the candidates [p, e) of a level, p a
+// lower bound (so the candidate at p starts a key run).  The first element
+// of every key run is that key's newest instance, so the candidates are
+// scanned in order, 16 at a time (their loads independent); a chunk that
+// holds no run start lies inside one long run, which is skipped by
+// galloping.
+__device__ __forceinline__ uint32_t count_run_starts(const uint32_t* kv, uint32_t p, uint32_t e) {
+  uint32_t count = 0, prev = kNoKey;
+  while (p < e) {
+    const uint32_t m = (e - p) < 16u ? (e - p) : 16u;
+    uint32_t x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      x[i] = static_cast<uint32_t>(i) < m ? kv[p + i] : 0u;
+    }
+    bool any_start = false;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (static_cast<uint32_t>(i) < m) {
+        const uint32_t key = x[i] >> 1;
+        const bool start = key != prev;
+        if (start && (x[i] & 1u)) ++count;
+        any_start |= start;
+        prev = key;
+      }
+    }
+    p = any_start ? p + m : skip_run(kv, p + m - 1, e, prev);
+  }
+  return count;
+}
+
 // Walk the candidate runs [lower_bound(k1), upper_bound(k2)) of all occupied
 // levels in key order.  For each distinct key the element met first is the
 // newest instance (smaller levels are newer, and inside a level a key's run
@@ -1702,35 +1734,9 @@ template <int kW>
 __device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, uint32_t k2) {
   if (k1 > k2) return 0u;
   if constexpr (kW == 1) {
-    // One level: the first element of every key run is that key's newest
-    // instance, so the candidates are scanned in order, 16 at a time (their
-    // loads independent); a chunk that holds no run start lies inside one
-    // long run, which is skipped by galloping.
-    const uint32_t* kv = lv.kv[0];
     uint32_t p, e;
-    fenced_range(kv, lv.fence[0], lv.len[0], k1, k2, p, e);
-    uint32_t count = 0, prev = kNoKey;
-    while (p < e) {
-      const uint32_t m = (e - p) < 16u ? (e - p) : 16u;
-      uint32_t x[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        x[i] = static_cast<uint32_t>(i) < m ? kv[p + i] : 0u;
-      }
-      bool any_start = false;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        if (static_cast<uint32_t>(i) < m) {
-          const uint32_t key = x[i] >> 1;
-          const bool start = key != prev;
-          if (start && (x[i] & 1u)) ++count;
-          any_start |= start;
-          prev = key;
-        }
-      }
-      p = any_start ? p + m : skip_run(kv, p + m - 1, e, prev);
-    }
-    return count;
+    fenced_range(lv.kv[0], lv.fence[0], lv.len[0], k1, k2, p, e);
+    return count_run_starts(lv.kv[0], p, e);
   } else {
     uint32_t cur[kW], end[kW], ck[kW];
     level_bounds<kW>(lv, k1, k2, cur, end);
@@ -1758,90 +1764,46 @@ __device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, 
   }
 }
 
+// Count pass.  With one level and bounds non-null, each query's candidate
+// bounds [lower_bound(lo), upper_bound(hi)) are also stored (two words per
+// query) for the emission pass.
 template <int kW>
 __global__ __launch_bounds__(kQueryThreads) void k_count(LevelSet lv, const uint32_t* lo,
                                                          const uint32_t* hi, uint32_t nq,
                                                          uint32_t* counts, uint64_t* scan_status,
-                                                         uint64_t scan_words) {
+                                                         uint64_t scan_words, uint32_t* bounds) {
   const uint64_t gi = static_cast<uint64_t>(blockIdx.x) * kQueryThreads + threadIdx.x;
   if (scan_status != nullptr) {
     for (uint64_t w = gi; w < scan_words; w += static_cast<uint64_t>(gridDim.x) * kQueryThreads)
       scan_status[w] = 0ull;
   }
   if (gi >= nq) return;
-  counts[gi] = range_walk<kW>(lv, lo[gi], hi[gi]);
+  if constexpr (kW == 1) {
+    const uint32_t k1 = lo[gi], k2 = hi[gi];
+    uint32_t p = 0, e = 0;
+    if (k1 <= k2) fenced_range(lv.kv[0], lv.fence[0], lv.len[0], k1, k2, p, e);
+    if (bounds != nullptr) reinterpret_cast<uint2*>(bounds)[gi] = make_uint2(p, e);
+    counts[gi] = count_run_starts(lv.kv[0], p, e);
+  } else {
+    counts[gi] = range_walk<kW>(lv, lo[gi], hi[gi]);
+  }
 }
 
-// Resumable form of range_walk for the emission pass: the walk of one query
-// keeps its cursors between calls, and each call emits the pairs whose
-// output positions fall in [pos, lim), writing pair position x at
-// sk[x - c0] / sv[x - c0].  Returns the next position.  The pairs and
-// their order are range_walk's.
-struct WalkOne {
-  uint32_t p, e, prev;  // next candidate, end of the candidates, key before p
-};
+// Resumable form of the several-level range_walk for the emission pass:
+// the walk of one query keeps its cursors between calls, and each call
+// emits the pairs whose output positions fall in [pos, lim), writing pair
+// position x at sk[x - c0] / sv[x - c0].  Returns the next position.  The
+// pairs and their order are range_walk's.
 template <int kW>
 struct WalkMany {
   uint32_t cur[kW], end[kW], ck[kW];
 };
-
-__device__ __forceinline__ void walk_init(const LevelSet& lv, uint32_t k1, uint32_t k2, WalkOne& w) {
-  w.p = w.e = 0;
-  w.prev = kNoKey;
-  if (k1 <= k2) fenced_range(lv.kv[0], lv.fence[0], lv.len[0], k1, k2, w.p, w.e);
-}
 
 template <int kW>
 __device__ __forceinline__ void walk_init(const LevelSet& lv, uint32_t k1, uint32_t k2, WalkMany<kW>& w) {
   level_bounds<kW>(lv, k1, k2, w.cur, w.end);
 #pragma unroll
   for (int l = 0; l < kW; ++l) w.ck[l] = cand_key(lv.kv[l], w.cur[l], w.end[l]);
-}
-
-// One level: the first element of every key run is that key's newest
-// instance; candidates are scanned 16 at a time, long runs skipped by
-// galloping.  A call stops in front of the first pair it may not emit.
-__device__ __forceinline__ uint64_t walk_emit(const LevelSet& lv, WalkOne& w, uint64_t pos,
-                                              uint64_t lim, uint64_t c0, uint32_t* sk,
-                                              uint32_t* sv) {
-  const uint32_t* kv = lv.kv[0];
-  while (w.p < w.e && pos < lim) {
-    const uint32_t m = (w.e - w.p) < 16u ? (w.e - w.p) : 16u;
-    uint32_t x[16], v[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      x[i] = static_cast<uint32_t>(i) < m ? kv[w.p + i] : 0u;
-      v[i] = static_cast<uint32_t>(i) < m ? lv.val[0][w.p + i] : 0u;
-    }
-    bool any_start = false;
-    uint32_t stop = m;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      if (static_cast<uint32_t>(i) < m && stop == m) {
-        const uint32_t key = x[i] >> 1;
-        const bool start = key != w.prev;
-        if (start && (x[i] & 1u)) {
-          if (pos >= lim) {
-            stop = static_cast<uint32_t>(i);  // resume here, w.prev still the key before it
-          } else {
-            sk[pos - c0] = key;
-            sv[pos - c0] = v[i];
-            ++pos;
-          }
-        }
-        if (stop == m) {
-          any_start |= start;
-          w.prev = key;
-        }
-      }
-    }
-    if (stop < m) {
-      w.p += stop;
-      break;
-    }
-    w.p = any_start ? w.p + m : skip_run(kv, w.p + m - 1, w.e, w.prev);
-  }
-  return pos;
 }
 
 // Several levels: the k-way walk over the level runs in key order; the
@@ -1884,9 +1846,9 @@ __device__ __forceinline__ uint64_t walk_emit(const LevelSet& lv, WalkMany<kW>& 
   return pos;
 }
 
-// Stage 3 of sec. IV-C / IV-D with coalesced writes.  The pairs of a wave's
-// 64 consecutive queries form one contiguous span of the output, which the
-// wave produces in chunks of kEmitChunk pairs: every query emits the pairs
+// Stage 3 of sec. IV-C / IV-D over several levels, with coalesced writes.
+// The pairs of a wave's 64 consecutive queries form one contiguous span of
+// the output, which the wave produces in chunks of kEmitChunk pairs: every query emits the pairs
 // that fall in the chunk into the wave's LDS buffer (its walk resumes where
 // the previous chunk stopped it), then the wave copies the chunk out with
 // consecutive lanes on consecutive addresses.  A query whose pairs would end
@@ -1923,7 +1885,8 @@ __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const
   const uint32_t rounds =
       copy_end > base ? static_cast<uint32_t>((copy_end - base + kEmitChunk - 1) / kEmitChunk) : 0u;
   if (lane == 0) s_rounds[wave] = rounds;
-  typename std::conditional<kW == 1, WalkOne, WalkMany<kW>>::type w;
+  static_assert(kW > 1, "one level: k_range_emit_one");
+  WalkMany<kW> w;
   if (fits) walk_init(lv, lo[i], hi[i], w);
   __syncthreads();
   uint32_t R = 0;
@@ -1943,6 +1906,104 @@ __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const
       }
     }
     __syncthreads();
+  }
+}
+
+// Stage 3 of sec. IV-C / IV-D with one occupied level, a wave working on
+// one query at a time: the 64 lanes read 64 consecutive candidates with one
+// load, mark the regular run starts (a key that differs from the candidate
+// before it; the first candidate, at a lower bound, always starts a run) and
+// store them at the query's offset, ranked by a ballot, so every store
+// instruction writes one contiguous piece of the output.  A chunk with no
+// run start lies inside one long run, which is skipped by galloping.  The
+// query is done once its pairs are written.
+__device__ __forceinline__ void emit_run_starts(const uint32_t* kv, const uint32_t* vv, uint32_t c,
+                                                uint32_t e, uint64_t w, uint64_t z, uint32_t x,
+                                                uint32_t v, uint32_t lane, uint32_t* ok,
+                                                uint32_t* ov) {
+  uint32_t prev = kNoKey;
+  for (;;) {
+    const bool in = c + lane < e;
+    const uint32_t key = x >> 1;
+    uint32_t pk = __shfl_up(key, 1, 64);
+    if (lane == 0) pk = prev;
+    const bool start = in && key != pk;
+    const bool keep = start && (x & 1u);
+    const uint64_t km = ballot(keep);
+    const uint64_t at = w + count_below(km);
+    if (keep && at < z) {
+      ok[at] = key;
+      ov[at] = v;
+    }
+    w += static_cast<uint64_t>(__popcll(km));
+    const uint32_t n = (e - c) < 64u ? (e - c) : 64u;
+    prev = __shfl(key, static_cast<int>(n - 1), 64);
+    const bool any_start = ballot(start) != 0;
+    c += n;
+    if (c >= e || w >= z) break;
+    if (!any_start) {
+      c = skip_run(kv, c - 1, e, prev);
+      if (c >= e) break;
+    }
+    const bool in2 = c + lane < e;
+    x = in2 ? kv[c + lane] : 0u;
+    v = in2 ? vv[c + lane] : 0u;
+  }
+}
+
+// The wave's 64 queries are taken kU at a time, their first chunks loaded
+// together.  Each query's candidate bounds come from the count pass
+// (bounds non-null) or are searched here, one query per lane.  A query
+// whose pairs would end beyond cap writes nothing (the caller sees
+// offsets[q + 1] > cap); writes stay inside [offsets[q], offsets[q + 1])
+// even for offsets corrupted by a timed-out scan.
+template <int kU>
+__global__ __launch_bounds__(kQueryThreads) void k_range_emit_one(
+    LevelSet lv, const uint32_t* lo, const uint32_t* hi, uint32_t nq, const uint64_t* offsets,
+    const uint32_t* bounds, uint32_t* out_keys, uint32_t* out_vals, uint64_t cap) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t i = blockIdx.x * kQueryThreads + threadIdx.x;
+  const uint32_t* kv = lv.kv[0];
+  const uint32_t* vv = lv.val[0];
+  const uint32_t len = lv.len[0];
+  uint32_t p = 0, e = 0;
+  uint64_t o = 0, z = 0;
+  if (i < nq) {
+    const uint64_t a = offsets[i], b = offsets[i + 1];
+    if (b > a && b <= offsets[nq] && b <= cap) {
+      o = a;
+      z = b;
+      if (bounds != nullptr) {
+        const uint2 pe = reinterpret_cast<const uint2*>(bounds)[i];
+        p = pe.x;
+        e = pe.y;
+      } else if (lo[i] <= hi[i]) {
+        fenced_range(kv, lv.fence[0], len, lo[i], hi[i], p, e);
+      }
+      e = e < len ? e : len;
+      p = p < e ? p : e;
+    }
+  }
+  // Every lane stays to the end: the loop below is uniform over the wave.
+  for (uint32_t q0 = 0; q0 < 64; q0 += kU) {
+    uint32_t qp[kU], qe[kU], x[kU], v[kU];
+    uint64_t qo[kU], qz[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int src = static_cast<int>(q0) + u;
+      qp[u] = __shfl(p, src, 64);
+      qe[u] = __shfl(e, src, 64);
+      qo[u] = __shfl(o, src, 64);
+      qz[u] = __shfl(z, src, 64);
+      const uint32_t at = qp[u] + lane;
+      const bool in = at < qe[u];
+      x[u] = in ? kv[at] : 0u;
+      v[u] = in ? vv[at] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (qp[u] < qe[u])
+        emit_run_starts(kv, vv, qp[u], qe[u], qo[u], qz[u], x[u], v[u], lane, out_keys, out_vals);
   }
 }
 
@@ -2426,12 +2487,12 @@ hipError_t launch_lookup(const LevelSet& lv, const uint32_t* q, uint32_t nq, uin
 
 hipError_t launch_count(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi, uint32_t nq,
                         uint32_t* counts, uint64_t* scan_status, size_t scan_words,
-                        hipStream_t stream, const KTimer* t) {
+                        uint32_t* bounds, hipStream_t stream, const KTimer* t) {
   if (nq == 0) return hipSuccess;
   auto k = lv.count <= 1 ? k_count<1> : lv.count <= 8 ? k_count<8> : lv.count <= 16 ? k_count<16>
                                                                            : k_count<kMaxLevels>;
   return launch(k, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi, nq,
-                counts, scan_status, static_cast<uint64_t>(scan_words));
+                counts, scan_status, static_cast<uint64_t>(scan_words), bounds);
 }
 
 size_t scan_status_words(uint32_t nq) { return 1 + grid_for(nq, kScanTile); }
@@ -2484,12 +2545,15 @@ hipError_t launch_clean_pad(const LevelDst& d, uint64_t v, uint64_t total, hipSt
 }
 
 hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi,
-                             uint32_t nq, const uint64_t* offsets, uint32_t* out_keys,
-                             uint32_t* out_vals, uint64_t cap, hipStream_t stream,
-                             const KTimer* t) {
+                             uint32_t nq, const uint64_t* offsets, const uint32_t* bounds,
+                             uint32_t* out_keys, uint32_t* out_vals, uint64_t cap,
+                             hipStream_t stream, const KTimer* t) {
   if (nq == 0) return hipSuccess;
-  auto k = lv.count <= 1 ? k_range_emit<1> : lv.count <= 8 ? k_range_emit<8>
-            : lv.count <= 16 ? k_range_emit<16> : k_range_emit<kMaxLevels>;
+  if (lv.count <= 1)
+    return launch(k_range_emit_one<4>, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv,
+                  lo, hi, nq, offsets, bounds, out_keys, out_vals, cap);
+  auto k = lv.count <= 8 ? k_range_emit<8> : lv.count <= 16 ? k_range_emit<16>
+                                                            : k_range_emit<kMaxLevels>;
   return launch(k, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi, nq, offsets,
                 out_keys, out_vals, cap);
 }

@@ -237,6 +237,58 @@ def test_range_two_phase_capacity():
     assert np.array_equal(host(k), want_k) and np.array_equal(host(v), want_v)
 
 
+def test_one_level_ranges_over_long_runs():
+    """Ranges over one occupied level (emitted one query at a time per wave,
+    64 candidates a chunk): key runs far longer than a chunk (batches of one
+    key, the padding of partial batches), a tombstone run under newer
+    insertions of the same key, ranges starting and ending inside runs, the
+    whole key space, and a capacity that cuts the output."""
+    b = 3000
+    note("one-level ranges over long runs b=%d" % b)
+    rng = np.random.default_rng(21)
+    t = Trio(b)
+
+    def vals(n):
+        return rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+
+    t.insert(np.full(b, 500, np.uint32), vals(b))
+    t.insert(rng.integers(0, 2000, 37).astype(np.uint32), vals(37))  # 2963 padding copies
+    t.delete(np.full(b, 700, np.uint32))
+    t.insert(np.full(b, 700, np.uint32), vals(b))
+    t.mixed(rng.integers(0, 2000, b).astype(np.uint32), vals(b),
+            (rng.random(b) < 0.5).astype(np.uint8))
+    t.insert(rng.integers(0, 2000, b).astype(np.uint32), vals(b))
+    t.delete(rng.integers(0, 2000, 500).astype(np.uint32))
+    t.insert(np.full(b, 500, np.uint32), vals(b))
+    t.check_levels()
+    assert t.g.occupied() == [3]
+    lo = np.r_[np.array([500, 499, 0, 700, 699, 701, 0, 2000], np.uint32),
+               rng.integers(0, 2100, 3000).astype(np.uint32)]
+    hi = np.r_[np.array([500, 501, 2**31 - 1, 700, 700, 2**32 - 1, 499, 1999], np.uint32),
+               (lo[8:] + rng.integers(0, 300, 3000)).astype(np.uint32)]
+    q = np.arange(0, 2100, dtype=np.uint32)
+    t.check_queries(q, lo, hi)
+    # A capacity inside the output: lsm_range writes nothing and reports the
+    # total; lsm_range_async writes the queries that fit, in full.
+    want_off, want_k, want_v = t.m.range(lo, hi)
+    cap = int(want_off[-1]) // 2
+    off = torch.empty(lo.size + 1, dtype=torch.int64, device="cuda")
+    k = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+    v = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+    with pytest.raises(LSMError) as ei:
+        t.g.range_raw(dev(lo), dev(hi), off, k, v, cap)
+    assert ei.value.status == LSM_ECAPACITY
+    torch.cuda.synchronize()
+    assert np.array_equal(host(off), want_off) and np.all(host(k) == np.uint32(0xFFFFFFFF))
+    t.g.range_async(dev(lo), dev(hi), off, k, v, cap)
+    torch.cuda.synchronize()
+    end = int(want_off[np.searchsorted(want_off[1:], cap, side="right")])
+    assert np.array_equal(host(off), want_off)
+    assert np.array_equal(host(k)[:end], want_k[:end]) and np.array_equal(host(v)[:end], want_v[:end])
+    assert np.all(host(k)[end:] == np.uint32(0xFFFFFFFF))
+    t.g.close()
+
+
 def test_merges_with_several_tiles_per_workgroup():
     """b = 2^20 + 5: merges of 2^21 + 10 and 2^22 + 20 outputs need more
     tiles than work-groups, so each work-group walks a run of tiles (ragged
