@@ -221,16 +221,35 @@ __device__ __forceinline__ uint32_t fenced_bound(const uint32_t* kv, const uint3
   return r;
 }
 
-// [lower_bound(k1), upper_bound(k2)) of a level, the two descents of its
-// fence tree in lockstep: at every tree level both lines are loaded before
-// either is examined, so the two chains of loads overlap.  A descent that
-// has reached position 0 stays there (its line loads are then harmless
-// reads of the first line).
-__device__ __forceinline__ void fenced_range(const uint32_t* kv, const uint32_t* tree, uint32_t n,
-                                             uint32_t k1, uint32_t k2, uint32_t& lo,
-                                             uint32_t& hi) {
-  lo = hi = 0;
-  if (n == 0) return;
+// Sum over the eight lanes of an octet (lanes 8o .. 8o + 7), in every lane
+// of it: DPP swaps with lane ^ 1 and lane ^ 2, then the half-row mirror
+// (lane i with lane 7 - i inside each group of eight).  Every lane of the
+// octet must be active.
+__device__ __forceinline__ uint32_t octet_sum(uint32_t x) {
+  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0xB1, 0xf, 0xf, true));
+  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x4E, 0xf, 0xf, true));
+  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x141, 0xf, 0xf, true));
+  return x;
+}
+
+// fenced_bound for a whole wave at once, the eight lanes of an octet
+// searching the octet's eight queries together: at every tree level lane s
+// of the octet reads bytes 16 s .. 16 s + 15 of each of the eight queries'
+// 128-byte lines, so a load instruction of the wave reads eight whole lines
+// instead of 64 scattered 16-byte pieces of 64 lines (the per-lane search
+// keeps the texture addresser busy nearly all the time).  Entry counts are
+// summed over the octet.  Each lane passes its own key and receives its own
+// bound; every lane of the wave must call it (lanes without a query pass
+// any key and ignore the result).
+template <bool kUpper>
+__device__ __forceinline__ uint32_t octet_bound(const uint32_t* kv, const uint32_t* tree,
+                                                uint32_t n, uint32_t k) {
+  const uint32_t lane = lane_id(), sub = lane & 7u, ob = lane & ~7u;
+  uint32_t kq[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) kq[j] = __shfl(k, static_cast<int>(ob) + j, 64);
+  if (n == 0) return 0u;
+  auto qual = [](uint32_t x, uint32_t key) { return kUpper ? x <= key : x < key; };
   uint64_t off = 0, c = (static_cast<uint64_t>(n) + 31) / 32;
   int t = 1;
   while (c > 32) {
@@ -238,32 +257,74 @@ __device__ __forceinline__ void fenced_range(const uint32_t* kv, const uint32_t*
     c = (c + 31) / 32;
     ++t;
   }
-  uint32_t g1 = line_count(tree + off, 0, static_cast<uint32_t>(c), k1, false, false);
-  uint32_t g2 = line_count(tree + off, 0, static_cast<uint32_t>(c), k2, true, false);
+  uint32_t g[8];
+  {
+    // The root line, the same for every query.
+    const uint4 w = *reinterpret_cast<const uint4*>(tree + off + 4u * sub);
+    const uint32_t e4[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cnt += (4u * sub + r < c && qual(e4[r], kq[j])) ? 1u : 0u;
+      g[j] = octet_sum(cnt);
+    }
+  }
   for (--t; t >= 1; --t) {
     const uint64_t ct = (static_cast<uint64_t>(n) + (1ull << (5 * t)) - 1) >> (5 * t);
     off -= fence_pad(ct);
-    const uint32_t b1 = g1 > 0 ? (g1 - 1) * 32u : 0u, b2 = g2 > 0 ? (g2 - 1) * 32u : 0u;
-    const uint32_t e1 = (b1 + 32u < ct) ? b1 + 32u : static_cast<uint32_t>(ct);
-    const uint32_t e2 = (b2 + 32u < ct) ? b2 + 32u : static_cast<uint32_t>(ct);
-    const uint32_t c1 = line_count(tree + off + b1, 1, e1 - b1, k1, false, false);
-    const uint32_t c2 = line_count(tree + off + b2, 1, e2 - b2, k2, true, false);
-    g1 = g1 > 0 ? b1 + c1 + 1u : 0u;
-    g2 = g2 > 0 ? b2 + c2 + 1u : 0u;
-  }
-  auto finish = [&](uint32_t g, uint32_t k, bool upper) -> uint32_t {
-    if (g == 0) return 0u;
-    const uint32_t base = (g - 1) * 32u;
-    if (base + 32u <= n) return base + line_count(kv + base, 1, 32, k, upper, true) + 1u;
-    uint32_t r = base + 1u;
-    for (uint32_t i = base + 1u; i < n; ++i) {
-      const uint32_t x = kv[i] >> 1;
-      r += (upper ? x <= k : x < k) ? 1u : 0u;
+    uint4 w[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t base = g[j] > 0 ? (g[j] - 1) * 32u : 0u;
+      w[j] = *reinterpret_cast<const uint4*>(tree + off + base + 4u * sub);
     }
-    return r;
-  };
-  lo = finish(g1, k1, false);
-  hi = finish(g2, k2, true);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t base = g[j] > 0 ? (g[j] - 1) * 32u : 0u;
+      const uint32_t lim = (base + 32u < ct) ? 32u : static_cast<uint32_t>(ct - base);
+      const uint32_t e4[4] = {w[j].x, w[j].y, w[j].z, w[j].w};
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t i = 4u * sub + r;
+        cnt += (i >= 1u && i < lim && qual(e4[r], kq[j])) ? 1u : 0u;
+      }
+      const uint32_t sum = octet_sum(cnt);
+      g[j] = g[j] > 0 ? base + sum + 1u : 0u;
+    }
+  }
+  // The level's own line (the last one may be partial: read what exists).
+  uint4 w[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint32_t i0 = (g[j] > 0 ? (g[j] - 1) * 32u : 0u) + 4u * sub;
+    if (i0 + 4u <= n) {
+      w[j] = *reinterpret_cast<const uint4*>(kv + i0);
+    } else {
+      w[j].x = i0 < n ? kv[i0] : 0u;
+      w[j].y = i0 + 1u < n ? kv[i0 + 1u] : 0u;
+      w[j].z = i0 + 2u < n ? kv[i0 + 2u] : 0u;
+      w[j].w = 0u;
+    }
+  }
+  uint32_t res = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint32_t base = g[j] > 0 ? (g[j] - 1) * 32u : 0u;
+    const uint32_t lim = (base + 32u <= n) ? 32u : n - base;
+    const uint32_t e4[4] = {w[j].x, w[j].y, w[j].z, w[j].w};
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t i = 4u * sub + r;
+      cnt += (i >= 1u && i < lim && qual(e4[r] >> 1, kq[j])) ? 1u : 0u;
+    }
+    const uint32_t sum = octet_sum(cnt);
+    const uint32_t b = g[j] > 0 ? base + sum + 1u : 0u;
+    res = (sub == static_cast<uint32_t>(j)) ? b : res;
+  }
+  return res;
 }
 
 // Records output position o of a level of n elements in the level's fence
@@ -1617,28 +1678,33 @@ __global__ __launch_bounds__(kThreads) void k_fill_runs(uint32_t* a_kv, uint32_t
 __global__ __launch_bounds__(kQueryThreads) void k_lookup(LevelSet lv, const uint32_t* q,
                                                           uint32_t nq, uint32_t* out_val,
                                                           uint8_t* out_found) {
+  // Every lane stays until the wave is done: the searches are wave-wide.
   const uint32_t i = blockIdx.x * kQueryThreads + threadIdx.x;
-  if (i >= nq) return;
-  const uint32_t k = q[i];
+  const bool active = i < nq;
+  const uint32_t k = active ? q[i] : 0u;
   uint32_t v = 0u;
   uint8_t f = 0;
+  bool done = !active;
   for (int l = 0; l < lv.count; ++l) {
+    if (ballot(!done) == 0) break;
     const uint32_t* kv = lv.kv[l];
     const uint32_t n = lv.len[l];
-    const uint32_t p = fenced_bound(kv, lv.fence[l], n, k, false);
-    if (p < n) {
+    const uint32_t p = octet_bound<false>(kv, lv.fence[l], n, k);
+    if (!done && p < n) {
       const uint32_t x = kv[p];
       if ((x >> 1) == k) {
         if (x & 1u) {
           v = lv.val[l][p];
           f = 1;
         }
-        break;  // the newest instance decides, tombstone or not
+        done = true;  // the newest instance decides, tombstone or not
       }
     }
   }
-  out_val[i] = v;
-  out_found[i] = f;
+  if (active) {
+    out_val[i] = v;
+    out_found[i] = f;
+  }
 }
 
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;  // above every original key (< 2^31)
@@ -1665,103 +1731,113 @@ __device__ __forceinline__ uint32_t skip_run(const uint32_t* kv, uint32_t c, uin
   return hi;
 }
 
-// The bounds [lower_bound(k1), upper_bound(k2)) of the first kW occupied
-// levels, kept in registers: level l's bounds go to slot l through a
-// compare per slot, so no register array is indexed at run time (which
-// would put the walk state in scratch memory).
+// The candidates of a query [k1, k2] in the first kW occupied levels run
+// from lower_bound(k1) (one fence-tree descent per level) up to the first
+// key above k2, which the walks find by reading on (they read every
+// candidate anyway), so no second descent is made.  The cursors are kept in
+// registers: level l's goes to slot l through a compare per slot, so no
+// register array is indexed at run time (which would put the walk state in
+// scratch memory).  A slot past the occupied levels stays at 0 of a level of
+// length 0 (lv.len is zero there).
+// The descents are wave-wide (octet_bound): every lane of the wave calls
+// this; for k1 > k2 the walks then find no candidate (every key from the
+// lower bound on is above k2).
 template <int kW>
-__device__ __forceinline__ void level_bounds(const LevelSet& lv, uint32_t k1, uint32_t k2,
-                                             uint32_t (&cur)[kW], uint32_t (&end)[kW]) {
+__device__ __forceinline__ void level_bounds(const LevelSet& lv, uint32_t k1,
+                                             uint32_t (&cur)[kW]) {
 #pragma unroll
-  for (int q = 0; q < kW; ++q) cur[q] = end[q] = 0u;
-  if (k1 > k2) return;
+  for (int q = 0; q < kW; ++q) cur[q] = 0u;
   for (int l = 0; l < lv.count && l < kW; ++l) {
-    uint32_t lo, hi;
-    fenced_range(lv.kv[l], lv.fence[l], lv.len[l], k1, k2, lo, hi);
+    const uint32_t lo = octet_bound<false>(lv.kv[l], lv.fence[l], lv.len[l], k1);
 #pragma unroll
     for (int q = 0; q < kW; ++q) {
-      if (q == l) {
-        cur[q] = lo;
-        end[q] = hi;
-      }
+      if (q == l) cur[q] = lo;
     }
   }
 }
 
-// Key of the candidate at cur in a level, or kNoKey past its end.
-__device__ __forceinline__ uint32_t cand_key(const uint32_t* kv, uint32_t cur, uint32_t end) {
-  return cur < end ? (kv[cur] >> 1) : kNoKey;
+// Key of the candidate at cur in a level, or kNoKey past the level's end or
+// past k2.
+__device__ __forceinline__ uint32_t cand_key(const uint32_t* kv, uint32_t cur, uint32_t end,
+                                             uint32_t k2) {
+  if (cur >= end) return kNoKey;
+  const uint32_t key = kv[cur] >> 1;
+  return key <= k2 ? key : kNoKey;
 }
 
-// One level: the live keys among the candidates [p, e) of a level, p a
-// lower bound (so the candidate at p starts a key run).  The first element
-// of every key run is that key's newest instance, so the candidates are
+// One level: the live keys among the candidates of [k1, k2], from p =
+// lower_bound(k1) (so the candidate at p starts a key run) to the first key
+// above k2 or n, whichever comes first, which goes to *e.  The first element of
+// every key run is that key's newest instance, so the candidates are
 // scanned in order, 16 at a time (their loads independent); a chunk that
 // holds no run start lies inside one long run, which is skipped by
 // galloping.
-__device__ __forceinline__ uint32_t count_run_starts(const uint32_t* kv, uint32_t p, uint32_t e) {
+__device__ __forceinline__ uint32_t count_run_starts(const uint32_t* kv, uint32_t p, uint32_t n,
+                                                     uint32_t k2, uint32_t* e) {
   uint32_t count = 0, prev = kNoKey;
-  while (p < e) {
-    const uint32_t m = (e - p) < 16u ? (e - p) : 16u;
+  while (p < n) {
+    const uint32_t m = (n - p) < 16u ? (n - p) : 16u;
     uint32_t x[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       x[i] = static_cast<uint32_t>(i) < m ? kv[p + i] : 0u;
     }
     bool any_start = false;
+    uint32_t stop = m;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      if (static_cast<uint32_t>(i) < m) {
+      if (static_cast<uint32_t>(i) < stop) {
         const uint32_t key = x[i] >> 1;
-        const bool start = key != prev;
-        if (start && (x[i] & 1u)) ++count;
-        any_start |= start;
-        prev = key;
-      }
-    }
-    p = any_start ? p + m : skip_run(kv, p + m - 1, e, prev);
-  }
-  return count;
-}
-
-// Walk the candidate runs [lower_bound(k1), upper_bound(k2)) of all occupied
-// levels in key order.  For each distinct key the element met first is the
-// newest instance (smaller levels are newer, and inside a level a key's run
-// starts with its newest element); it counts when it is a regular element.
-// kW = 1: one occupied level; otherwise at most kW occupied levels, the walk
-// state in registers (loops unrolled over the kW slots).
-template <int kW>
-__device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, uint32_t k2) {
-  if (k1 > k2) return 0u;
-  if constexpr (kW == 1) {
-    uint32_t p, e;
-    fenced_range(lv.kv[0], lv.fence[0], lv.len[0], k1, k2, p, e);
-    return count_run_starts(lv.kv[0], p, e);
-  } else {
-    uint32_t cur[kW], end[kW], ck[kW];
-    level_bounds<kW>(lv, k1, k2, cur, end);
-#pragma unroll
-    for (int l = 0; l < kW; ++l) ck[l] = cand_key(lv.kv[l], cur[l], end[l]);
-    uint32_t count = 0;
-    for (;;) {
-      uint32_t mk = kNoKey;
-#pragma unroll
-      for (int l = 0; l < kW; ++l) mk = ck[l] < mk ? ck[l] : mk;
-      if (mk == kNoKey) break;
-      bool newest = true;
-#pragma unroll
-      for (int l = 0; l < kW; ++l) {
-        if (ck[l] == mk) {
-          const uint32_t* kv = lv.kv[l];
-          if (newest) count += kv[cur[l]] & 1u;
-          newest = false;
-          cur[l] = skip_run(kv, cur[l], end[l], mk);
-          ck[l] = cand_key(kv, cur[l], end[l]);
+        if (key > k2) {
+          stop = static_cast<uint32_t>(i);
+        } else {
+          const bool start = key != prev;
+          if (start && (x[i] & 1u)) ++count;
+          any_start |= start;
+          prev = key;
         }
       }
     }
-    return count;
+    if (stop < m) {
+      p += stop;
+      break;
+    }
+    p = any_start ? p + m : skip_run(kv, p + m - 1, n, prev);
   }
+  *e = p < n ? p : n;
+  return count;
+}
+
+// Walk the candidates of all occupied levels in key order.  For each
+// distinct key the element met first is the newest instance (smaller levels
+// are newer, and inside a level a key's run starts with its newest
+// element); it counts when it is a regular element.  At most kW occupied
+// levels, the walk state in registers (loops unrolled over the kW slots).
+template <int kW>
+__device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, uint32_t k2) {
+  uint32_t cur[kW], ck[kW];
+  level_bounds<kW>(lv, k1, cur);
+#pragma unroll
+  for (int l = 0; l < kW; ++l) ck[l] = cand_key(lv.kv[l], cur[l], lv.len[l], k2);
+  uint32_t count = 0;
+  for (;;) {
+    uint32_t mk = kNoKey;
+#pragma unroll
+    for (int l = 0; l < kW; ++l) mk = ck[l] < mk ? ck[l] : mk;
+    if (mk == kNoKey) break;
+    bool newest = true;
+#pragma unroll
+    for (int l = 0; l < kW; ++l) {
+      if (ck[l] == mk) {
+        const uint32_t* kv = lv.kv[l];
+        if (newest) count += kv[cur[l]] & 1u;
+        newest = false;
+        cur[l] = skip_run(kv, cur[l], lv.len[l], mk);
+        ck[l] = cand_key(kv, cur[l], lv.len[l], k2);
+      }
+    }
+  }
+  return count;
 }
 
 // Count pass.  With one level and bounds non-null, each query's candidate
@@ -1777,15 +1853,23 @@ __global__ __launch_bounds__(kQueryThreads) void k_count(LevelSet lv, const uint
     for (uint64_t w = gi; w < scan_words; w += static_cast<uint64_t>(gridDim.x) * kQueryThreads)
       scan_status[w] = 0ull;
   }
-  if (gi >= nq) return;
+  // Every lane takes part in the wave-wide descents; lanes without a query
+  // search the empty range [1, 0].
+  const bool active = gi < nq;
+  const uint32_t k1 = active ? lo[gi] : 1u, k2 = active ? hi[gi] : 0u;
   if constexpr (kW == 1) {
-    const uint32_t k1 = lo[gi], k2 = hi[gi];
-    uint32_t p = 0, e = 0;
-    if (k1 <= k2) fenced_range(lv.kv[0], lv.fence[0], lv.len[0], k1, k2, p, e);
+    // Both bounds by descents, so the scan reads only the candidates.
+    uint32_t p = octet_bound<false>(lv.kv[0], lv.fence[0], lv.len[0], k1);
+    uint32_t e = octet_bound<true>(lv.kv[0], lv.fence[0], lv.len[0], k2);
+    if (!active) return;
+    uint32_t c = 0;
+    if (k1 <= k2) c = count_run_starts(lv.kv[0], p, e, k2, &e);
+    else p = e = 0;
     if (bounds != nullptr) reinterpret_cast<uint2*>(bounds)[gi] = make_uint2(p, e);
-    counts[gi] = count_run_starts(lv.kv[0], p, e);
+    counts[gi] = c;
   } else {
-    counts[gi] = range_walk<kW>(lv, lo[gi], hi[gi]);
+    const uint32_t c = range_walk<kW>(lv, k1, k2);
+    if (active) counts[gi] = c;
   }
 }
 
@@ -1796,14 +1880,16 @@ __global__ __launch_bounds__(kQueryThreads) void k_count(LevelSet lv, const uint
 // pairs and their order are range_walk's.
 template <int kW>
 struct WalkMany {
-  uint32_t cur[kW], end[kW], ck[kW];
+  uint32_t cur[kW], ck[kW];
+  uint32_t k2;
 };
 
 template <int kW>
 __device__ __forceinline__ void walk_init(const LevelSet& lv, uint32_t k1, uint32_t k2, WalkMany<kW>& w) {
-  level_bounds<kW>(lv, k1, k2, w.cur, w.end);
+  w.k2 = k2;
+  level_bounds<kW>(lv, k1, w.cur);
 #pragma unroll
-  for (int l = 0; l < kW; ++l) w.ck[l] = cand_key(lv.kv[l], w.cur[l], w.end[l]);
+  for (int l = 0; l < kW; ++l) w.ck[l] = cand_key(lv.kv[l], w.cur[l], lv.len[l], k2);
 }
 
 // Several levels: the k-way walk over the level runs in key order; the
@@ -1838,8 +1924,8 @@ __device__ __forceinline__ uint64_t walk_emit(const LevelSet& lv, WalkMany<kW>& 
 #pragma unroll
     for (int l = 0; l < kW; ++l) {
       if (w.ck[l] == mk) {
-        w.cur[l] = skip_run(lv.kv[l], w.cur[l], w.end[l], mk);
-        w.ck[l] = cand_key(lv.kv[l], w.cur[l], w.end[l]);
+        w.cur[l] = skip_run(lv.kv[l], w.cur[l], lv.len[l], mk);
+        w.ck[l] = cand_key(lv.kv[l], w.cur[l], lv.len[l], w.k2);
       }
     }
   }
@@ -1887,7 +1973,7 @@ __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const
   if (lane == 0) s_rounds[wave] = rounds;
   static_assert(kW > 1, "one level: k_range_emit_one");
   WalkMany<kW> w;
-  if (fits) walk_init(lv, lo[i], hi[i], w);
+  walk_init(lv, fits ? lo[i] : 1u, fits ? hi[i] : 0u, w);  // wave-wide descents
   __syncthreads();
   uint32_t R = 0;
 #pragma unroll
@@ -1968,22 +2054,31 @@ __global__ __launch_bounds__(kQueryThreads) void k_range_emit_one(
   const uint32_t len = lv.len[0];
   uint32_t p = 0, e = 0;
   uint64_t o = 0, z = 0;
+  bool emit = false;
   if (i < nq) {
     const uint64_t a = offsets[i], b = offsets[i + 1];
     if (b > a && b <= offsets[nq] && b <= cap) {
       o = a;
       z = b;
-      if (bounds != nullptr) {
-        const uint2 pe = reinterpret_cast<const uint2*>(bounds)[i];
-        p = pe.x;
-        e = pe.y;
-      } else if (lo[i] <= hi[i]) {
-        fenced_range(kv, lv.fence[0], len, lo[i], hi[i], p, e);
-      }
-      e = e < len ? e : len;
-      p = p < e ? p : e;
+      emit = true;
     }
   }
+  if (bounds != nullptr) {
+    if (emit) {
+      const uint2 pe = reinterpret_cast<const uint2*>(bounds)[i];
+      p = pe.x;
+      e = pe.y;
+    }
+  } else {
+    // Wave-wide descents: every lane searches (an empty range if it emits
+    // nothing).
+    const uint32_t k1 = emit ? lo[i] : 1u, k2 = emit ? hi[i] : 0u;
+    p = octet_bound<false>(kv, lv.fence[0], len, k1);
+    e = octet_bound<true>(kv, lv.fence[0], len, k2);
+    if (!emit || k1 > k2) p = e = 0;
+  }
+  e = e < len ? e : len;
+  p = p < e ? p : e;
   // Every lane stays to the end: the loop below is uniform over the wave.
   for (uint32_t q0 = 0; q0 < 64; q0 += kU) {
     uint32_t qp[kU], qe[kU], x[kU], v[kU];
@@ -2097,17 +2192,19 @@ __global__ __launch_bounds__(kQueryThreads) void k_successor(LevelSet lv, const 
                                                              uint32_t* out_val,
                                                              uint8_t* out_found) {
   const uint32_t i = blockIdx.x * kQueryThreads + threadIdx.x;
-  if (i >= nq) return;
-  const uint32_t k = q[i];
+  const bool active = i < nq;
+  const uint32_t k = active ? q[i] : 0u;
   uint32_t rk = 0u, rv = 0u;
   uint8_t f = 0;
+  // The first descents are wave-wide: every lane makes them.
+  uint32_t cur[kMaxLevels], ck[kMaxLevels];
+  const int L = lv.count;
+  for (int l = 0; l < L; ++l) {
+    cur[l] = octet_bound<true>(lv.kv[l], lv.fence[l], lv.len[l], k);
+    ck[l] = cur[l] < lv.len[l] ? (lv.kv[l][cur[l]] >> 1) : kNoKey;
+  }
+  if (!active) return;
   if (k < kMaxKey) {
-    uint32_t cur[kMaxLevels], ck[kMaxLevels];
-    const int L = lv.count;
-    for (int l = 0; l < L; ++l) {
-      cur[l] = fenced_bound(lv.kv[l], lv.fence[l], lv.len[l], k, true);
-      ck[l] = cur[l] < lv.len[l] ? (lv.kv[l][cur[l]] >> 1) : kNoKey;
-    }
     for (;;) {
       uint32_t mk = kNoKey;
       int mi = -1;
@@ -2146,17 +2243,19 @@ __global__ __launch_bounds__(kQueryThreads) void k_predecessor(LevelSet lv, cons
                                                                uint32_t* out_val,
                                                                uint8_t* out_found) {
   const uint32_t i = blockIdx.x * kQueryThreads + threadIdx.x;
-  if (i >= nq) return;
-  const uint32_t k = q[i];
+  const bool active = i < nq;
+  const uint32_t k = active ? q[i] : 0u;
   uint32_t rk = 0u, rv = 0u;
   uint8_t f = 0;
+  // The first descents are wave-wide: every lane makes them.
+  uint32_t e[kMaxLevels], ck[kMaxLevels];  // ck = key just below e, or kNoKey
+  const int L = lv.count;
+  for (int l = 0; l < L; ++l) {
+    e[l] = octet_bound<false>(lv.kv[l], lv.fence[l], lv.len[l], k);
+    ck[l] = e[l] > 0u ? (lv.kv[l][e[l] - 1u] >> 1) : kNoKey;
+  }
+  if (!active) return;
   if (k > 0u) {
-    uint32_t e[kMaxLevels], ck[kMaxLevels];  // ck = key just below e, or kNoKey
-    const int L = lv.count;
-    for (int l = 0; l < L; ++l) {
-      e[l] = fenced_bound(lv.kv[l], lv.fence[l], lv.len[l], k, false);
-      ck[l] = e[l] > 0u ? (lv.kv[l][e[l] - 1u] >> 1) : kNoKey;
-    }
     for (;;) {
       uint32_t mk = 0u;
       int mi = -1;
