@@ -2038,12 +2038,14 @@ __device__ __forceinline__ void emit_run_starts(const uint32_t* kv, const uint32
 }
 
 // The wave's 64 queries are taken kU at a time, their first chunks loaded
-// together.  Each query's candidate bounds come from the count pass
-// (bounds non-null) or are searched here, one query per lane.  A query
+// together.  Each query's candidate bounds come from the count pass, or,
+// with kSearch, are searched here (wave-wide descents; a separate
+// instantiation, so that the usual form keeps its smaller register
+// footprint).  A query
 // whose pairs would end beyond cap writes nothing (the caller sees
 // offsets[q + 1] > cap); writes stay inside [offsets[q], offsets[q + 1])
 // even for offsets corrupted by a timed-out scan.
-template <int kU>
+template <int kU, bool kSearch>
 __global__ __launch_bounds__(kQueryThreads) void k_range_emit_one(
     LevelSet lv, const uint32_t* lo, const uint32_t* hi, uint32_t nq, const uint64_t* offsets,
     const uint32_t* bounds, uint32_t* out_keys, uint32_t* out_vals, uint64_t cap) {
@@ -2063,7 +2065,7 @@ __global__ __launch_bounds__(kQueryThreads) void k_range_emit_one(
       emit = true;
     }
   }
-  if (bounds != nullptr) {
+  if constexpr (!kSearch) {
     if (emit) {
       const uint2 pe = reinterpret_cast<const uint2*>(bounds)[i];
       p = pe.x;
@@ -2649,8 +2651,9 @@ hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint3
                              hipStream_t stream, const KTimer* t) {
   if (nq == 0) return hipSuccess;
   if (lv.count <= 1)
-    return launch(k_range_emit_one<4>, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv,
-                  lo, hi, nq, offsets, bounds, out_keys, out_vals, cap);
+    return launch(bounds != nullptr ? k_range_emit_one<4, false> : k_range_emit_one<4, true>,
+                  grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi, nq, offsets,
+                  bounds, out_keys, out_vals, cap);
   auto k = lv.count <= 8 ? k_range_emit<8> : lv.count <= 16 ? k_range_emit<16>
                                                             : k_range_emit<kMaxLevels>;
   return launch(k, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi, nq, offsets,
