@@ -226,17 +226,21 @@ LSM_API lsm_status_t lsm_set_fusion(lsm_t h, int max_levels);
 LSM_API lsm_status_t lsm_set_max_inflight(lsm_t h, int launches);
 
 /*
- * lsm_set_pairing -- pair batches in the top-digit sort (on by default; for
- * b <= 2^18).  An insertion that would fill level 0 (even batch counter) is
- * held back until the next update call, and the two batches are then sorted
- * together (the newer first on equal keys) straight into the level the
- * second one fills: one bucket sort for two batches, and level 0 is never
- * written.  Mixed batches (lsm_update_batch), whose sort orders a key's
- * tombstone before its insertion, never pair.  Queries, cleanup, bulk
- * insertion and lsm_flush complete a batch held back alone.  Results never
- * depend on it.
+ * lsm_set_grouping -- sort consecutive batches together in the top-digit
+ * sort: at most max_batches (rounded down to 1, 2 or 4; also capped by b:
+ * 4 for b <= 2^17, 2 for b <= 2^18, 1 above; the default is 2 where b
+ * allows it).  A
+ * batch whose counter r is a multiple of the group size G is held back
+ * until the next G - 1 batches have come, and the G batches are then
+ * sorted together (the newer first on equal keys) straight into the level
+ * the last one fills: one bucket sort for G batches, and the levels below
+ * log2 G are never written.  Mixed batches (lsm_update_batch), whose sort
+ * orders a key's tombstone before its insertion, never join a group.
+ * Queries, cleanup, bulk insertion and lsm_flush complete an incomplete
+ * group (as aligned groups of 2 and 1).  max_batches = 1 turns grouping
+ * off.  Results never depend on it.  LSM_EINVAL for max_batches < 0.
  */
-LSM_API lsm_status_t lsm_set_pairing(lsm_t h, int on);
+LSM_API lsm_status_t lsm_set_grouping(lsm_t h, int max_batches);
 
 #define LSM_SORT_AUTO 0
 #define LSM_SORT_TOP_DIGIT 1

@@ -62,25 +62,28 @@ struct lsm_s {
   uint32_t* tmp_kv[2] = {};  // radix ping-pong, b elements each
   uint32_t* tmp_val[2] = {};
   // Top-digit sort: the tile-grouped batch of each slot, slots one after
-  // another in one buffer (a pair's bucket sort reads two of them).
+  // another in one buffer (a group's bucket sort reads several of them).
   uint32_t* scat_kv[kSortSlots] = {};
   uint32_t* scat_val[kSortSlots] = {};
-  uint32_t* buf_kv = nullptr;  // the sorted batch (or pair) when it has to be merged
+  uint32_t* buf_kv = nullptr;  // the sorted batch (or group) when it has to be merged
   uint32_t* buf_val = nullptr;
-  // 2 when two batches can be sorted as a pair (b of at most 2^18, so that
-  // both batches' tiles fit one group table): buf and tmp[1] then hold 2b.
-  uint32_t pair_cap = 1;
+  // The most batches that can be sorted as one group (1, 2 or 4: every
+  // batch's tiles must fit one group table, so 4 for b <= 2^17 and 2 for
+  // b <= 2^18): buf and tmp[1] hold grp_cap * b.
+  uint32_t grp_cap = 1;
   uint32_t* meta = nullptr;  // sort histograms, look-back words, group starts, error words
   int hist_parity = 0;       // which histogram buffer the next digit-pass sort uses
 
   // Pipelined insertion: batches sorted by the top-digit sort have had their
   // tiles scattered (each into its scratch slot) but not their buckets
   // sorted and merged; that second half runs in the same launch as a later
-  // batch's scatter, or on its own when anything needs the levels.  One
-  // pending batch is sorted alone; two are a pair: a batch that would fill
-  // level 0 alone (even counter) and the next one, sorted together (newer
-  // first on equal keys) straight into the level the second one fills.
-  // Pending batches already count in r.
+  // batch's scatter, or on its own when anything needs the levels.  Pending
+  // batches form groups: a batch whose counter is a multiple of group_max
+  // waits for the next group_max - 1 batches, and the group is sorted
+  // together (newer first on equal keys) straight into the level its last
+  // batch fills; any other batch pending alone is sorted alone.  An
+  // incomplete group is sorted as aligned groups of 2 and 1.  Pending
+  // batches already count in r.
   struct Pending {
     int slot = 0;
     int j = 0;        // the level the batch's insertion fills
@@ -88,9 +91,9 @@ struct lsm_s {
     int passes = 0;
     uint64_t r = 0;   // the batch counter before the batch
   };
-  Pending pend[2];
+  Pending pend[kMaxGroup];
   int npend = 0;
-  bool pairing = true;
+  int group_max = 1;  // 1 (no grouping), 2 or 4; at most grp_cap
   uint32_t* fault = nullptr; // sticky device fault word (inside meta)
 
   uint32_t* mrg_kv[2] = {};  // cascade ping-pong
@@ -302,15 +305,15 @@ void release_all(lsm_t h) {
     dev_free(h, h->lvl_digit[i], kTopBuckets * sizeof(uint32_t));
   }
   for (int i = 0; i < 2; ++i) {
-    dev_free(h, h->tmp_kv[i], i == 1 ? h->pair_cap * bb : bb);
-    dev_free(h, h->tmp_val[i], i == 1 ? h->pair_cap * bb : bb);
+    dev_free(h, h->tmp_kv[i], i == 1 ? h->grp_cap * bb : bb);
+    dev_free(h, h->tmp_val[i], i == 1 ? h->grp_cap * bb : bb);
     dev_free(h, h->mrg_kv[i], h->mrg_cap * sizeof(uint32_t));
     dev_free(h, h->mrg_val[i], h->mrg_cap * sizeof(uint32_t));
   }
   dev_free(h, h->scat_kv[0], kSortSlots * bb);
   dev_free(h, h->scat_val[0], kSortSlots * bb);
-  dev_free(h, h->buf_kv, h->pair_cap * bb);
-  dev_free(h, h->buf_val, h->pair_cap * bb);
+  dev_free(h, h->buf_kv, h->grp_cap * bb);
+  dev_free(h, h->buf_val, h->grp_cap * bb);
   for (int i = 0; i < 2; ++i) dev_free(h, h->mrg_digit[i], kTopBuckets * sizeof(uint32_t));
   dev_free(h, h->buf_digit, kTopBuckets * sizeof(uint32_t));
   dev_free(h, h->meta, sort_meta_words(h->b) * sizeof(uint32_t));
@@ -404,8 +407,8 @@ int default_fuse_max(uint32_t b) {
 }
 
 // Fuses the first levels of an insert's cascade into the top-digit sort.
-// The sorted run stands for level `base` (0 for one batch; 1 for a pair,
-// whose two batches make a run of level 1's size); levels base..J-1 are
+// The sorted run stands for level `base` (0 for one batch; log2 G for a
+// group of G batches, a run of that level's size); levels base..J-1 are
 // merged with it in the bucket work-groups, J = min(j, fuse_max) cut short
 // where a bucket would outgrow LDS and at the first level without a
 // top-digit index for this key shift.  When J = j the sort writes level j
@@ -522,37 +525,38 @@ SortArgs scatter_args(lsm_t h, const BatchSrc& src, int slot) {
   return sa;
 }
 
-// Arguments of the bucket sort (and fused cascade) of the pending batches --
-// one batch, or a pair -- for the state of the levels they meet: every
+// Arguments of the bucket sort (and fused cascade) of the first G pending
+// batches, a group (G = 1, 2 or 4 consecutive batches, the first one's
+// counter a multiple of G), for the state of the levels they meet: every
 // earlier batch's insertion has been enqueued.  *j receives the level the
-// insertion fills and *base the level the sorted run stands for.
-SortArgs pending_args(lsm_t h, int* j, int* base) {
-  const bool pair = h->npend == 2;
-  const lsm_s::Pending& p = h->pend[h->npend - 1];  // the newest batch
+// group's insertion fills (its newest batch's) and *base the level the
+// sorted run stands for (log2 G: the group has that level's size).
+SortArgs pending_args(lsm_t h, int G, int* j, int* base) {
+  const lsm_s::Pending& p = h->pend[G - 1];  // the newest batch of the group
   SortArgs sa{};
   sa.src = BatchSrc{nullptr, nullptr, nullptr, h->b, h->b, kInsert};  // read from the slots
   sa.lo_bit = p.lo_bit;
   sa.passes = p.passes;
   sa.key_limit_bits = h->key_bits;
   sa.meta = sort_meta_carve(h->meta, h->b, h->hist_parity, p.slot);
-  sa.tmp_kv[0] = h->scat_kv[0];  // every slot; the batch starts at src_off
+  sa.tmp_kv[0] = h->scat_kv[0];  // every slot; batch q starts at grp_off[q]
   sa.tmp_val[0] = h->scat_val[0];
-  sa.src_off = static_cast<uint32_t>(p.slot) * h->b;
-  if (pair) {
-    const lsm_s::Pending& o = h->pend[0];  // the older batch
-    const SortMeta om = sort_meta_carve(h->meta, h->b, h->hist_parity, o.slot);
-    sa.meta.tile_cnt2 = om.tile_cnt;
-    sa.meta.skew2 = om.skew;
-    sa.src_off2 = static_cast<uint32_t>(o.slot) * h->b;
+  sa.group = static_cast<uint32_t>(G);
+  for (int q = 0; q < G; ++q) {
+    const lsm_s::Pending& x = h->pend[G - 1 - q];  // newest first
+    const SortMeta xm = sort_meta_carve(h->meta, h->b, h->hist_parity, x.slot);
+    sa.grp_cnt[q] = xm.tile_cnt;
+    sa.grp_skew[q] = xm.skew;
+    sa.grp_off[q] = static_cast<uint32_t>(x.slot) * h->b;
   }
   sa.tmp_kv[1] = h->tmp_kv[1];
   sa.tmp_val[1] = h->tmp_val[1];
   *j = p.j;
-  *base = pair ? 1 : 0;
+  *base = G == 4 ? 2 : G == 2 ? 1 : 0;
   sa.out_kv = (p.j == *base) ? h->lvl_kv[p.j] : h->buf_kv;
   sa.out_val = (p.j == *base) ? h->lvl_val[p.j] : h->buf_val;
   sa.out_fence = (p.j == *base) ? h->lvl_fence[p.j] : nullptr;
-  sa.out_n = pair ? 2 * h->b : h->b;
+  sa.out_n = static_cast<uint32_t>(G) * h->b;
   sa.path = kSortMsd;
   sa.skew_out = h->skew_dev;
   setup_fusion(h, sa, p.j, *base);
@@ -630,31 +634,41 @@ void commit_insert(lsm_t h, int j) {
   h->sorted_total += h->b;
 }
 
-// Enqueues the second half of the pending insertion (the bucket sort of
-// the pending batch or pair with its fused cascade, then the remaining
-// merges), in one launch with the tile scatter `next` when given.  On
-// failure the batches stay pending (their slots are untouched, so the work
-// can be redone) and the state is unchanged.
+// Enqueues the second half of the pending insertions: for each group, the
+// bucket sort with its fused cascade, then the remaining merges.  A complete
+// group (or a batch pending alone) is one group; an incomplete one is taken
+// as aligned groups of 2 and 1, largest first.  The last group's sort runs
+// in one launch with the tile scatter `next` when given.  On failure the
+// batches not yet enqueued stay pending (their slots are untouched, so the
+// work can be redone) and the state holds what was enqueued.
 hipError_t launch_pending(lsm_t h, const SortArgs* next, Timed* first, Timed* last) {
-  int j = 0, base = 0;
-  const SortArgs bk = pending_args(h, &j, &base);
-  Timed ts;
-  const KTimer* t =
-      next != nullptr
-          ? timer(h, ts, kKSortStep, h->b, bucket_bytes(h, bk) + 16.0 * static_cast<double>(h->b))
-          : timer(h, ts, kKLocalSort, h->b, bucket_bytes(h, bk));
-  hipError_t e = next != nullptr ? launch_sort_step(bk, *next, h->stream, t)
+  bool have_first = false;
+  while (h->npend > 0) {
+    int G = 1;
+    while (2 * G <= h->npend) G *= 2;
+    const SortArgs* nx = G == h->npend ? next : nullptr;
+    int j = 0, base = 0;
+    const SortArgs bk = pending_args(h, G, &j, &base);
+    Timed ts;
+    const double bytes = bucket_bytes(h, bk);
+    const KTimer* t = nx != nullptr
+                          ? timer(h, ts, kKSortStep, h->b, bytes + 16.0 * static_cast<double>(h->b))
+                          : timer(h, ts, kKLocalSort, h->b, bytes);
+    hipError_t e = nx != nullptr ? launch_sort_step(bk, *nx, h->stream, t)
                                  : launch_buckets(bk, h->stream, t);
-  if (e != hipSuccess) return e;
-  if (t != nullptr) {
-    if (first) *first = ts;
-    if (last) *last = ts;
+    if (e != hipSuccess) return e;
+    if (t != nullptr) {
+      if (first && !have_first) *first = ts;
+      have_first = true;
+      if (last) *last = ts;
+    }
+    bool indexed = false;
+    e = enqueue_cascade(h, bk, j, base, h->stream, t != nullptr ? last : nullptr, &indexed);
+    if (e != hipSuccess) return e;
+    note_digit_index(h, bk, j, indexed);
+    for (int q = G; q < h->npend; ++q) h->pend[q - G] = h->pend[q];
+    h->npend -= G;
   }
-  bool indexed = false;
-  e = enqueue_cascade(h, bk, j, base, h->stream, t != nullptr ? last : nullptr, &indexed);
-  if (e != hipSuccess) return e;
-  note_digit_index(h, bk, j, indexed);
-  h->npend = 0;
   return hipSuccess;
 }
 
@@ -736,26 +750,30 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
   if (path == kSortMsd) {
     // This batch's slot: one that no pending batch holds.
     int slot = 0;
-    while ((h->npend > 0 && h->pend[0].slot == slot) || (h->npend > 1 && h->pend[1].slot == slot))
-      ++slot;
+    for (bool taken = true; taken; ) {
+      taken = false;
+      for (int q = 0; q < h->npend; ++q) taken |= h->pend[q].slot == slot;
+      if (taken) ++slot;
+    }
     pace(h);
     const SortArgs sc = scatter_args(h, src, slot);
-    // A batch pending alone that filled level 0 (even counter) and this one,
-    // the next batch, are sorted as a pair at the next launch; otherwise the
-    // pending batches' buckets run beside this batch's scatter.  Only
-    // batches whose sort leaves the status bit out pair up: a stable sort of
-    // both on the original key, the newer batch first, is then what merging
-    // the two sorted batches gives.  (A mixed batch sorts its tombstone of a
-    // key before its insertion, which a pair's sort would apply across the
-    // two batches.)
+    // This batch joins the pending group when the group started at a
+    // counter that is a multiple of group_max, is not complete, and this
+    // batch is the next one; otherwise the pending batches' buckets run
+    // beside this batch's scatter.  Only batches whose sort leaves the
+    // status bit out are grouped: a stable sort of the group on the original
+    // key, the newer batches first, is then what merging the batches one by
+    // one gives.  (A mixed batch sorts its tombstone of a key before its
+    // insertion, which a group's sort would apply across batches.)
     const uint64_t r0 = h->r;
-    const bool pair_up = h->pairing && h->pair_cap == 2 && h->npend == 1 &&
-                         (h->pend[0].r & 1u) == 0 && r0 == h->pend[0].r + 1 &&
-                         h->pend[0].lo_bit == 1 && sc.lo_bit == 1 &&
-                         h->pend[0].passes == sc.passes;
+    const int gm = h->group_max;
+    const bool join = gm > 1 && h->npend > 0 && h->npend < gm &&
+                      h->pend[0].r % static_cast<uint64_t>(gm) == 0 &&
+                      r0 == h->pend[h->npend - 1].r + 1 && h->pend[0].lo_bit == 1 &&
+                      sc.lo_bit == 1 && h->pend[0].passes == sc.passes;
     Timed first, last;
     hipError_t e;
-    if (h->npend > 0 && !pair_up) {
+    if (h->npend > 0 && !join) {
       e = launch_pending(h, &sc, &first, &last);
     } else {
       const KTimer* t = timer(h, first, kKMsdScatter, h->b, 16.0 * h->b);
@@ -766,7 +784,7 @@ lsm_status_t update_batch(lsm_t h, const uint32_t* keys, const uint32_t* vals,
     h->launch_seq += 1;
     if (h->prof) call_span(h, kSpanUpdate, first, last, h->b);
     const lsm_s::Pending np{slot, j, sc.lo_bit, sc.passes, r0};
-    h->pend[h->npend] = np;  // launch_pending emptied the list; a pair appends
+    h->pend[h->npend] = np;  // launch_pending emptied the list; a group appends
     h->npend += 1;
     h->sorts_by_path[kSortMsd] += 1;
     commit_insert(h, j);
@@ -880,11 +898,19 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
     return LSM_EHIP;
   }
   const size_t bb = static_cast<size_t>(b) * sizeof(uint32_t);
-  h->pair_cap = 2u * ((b + kSortTile - 1) / kSortTile) <= static_cast<uint32_t>(kThreads) ? 2u : 1u;
+  {
+    const uint32_t tiles = (b + kSortTile - 1) / kSortTile;
+    h->grp_cap = 4u * tiles <= static_cast<uint32_t>(kMsdMaxTiles)   ? 4u
+                 : 2u * tiles <= static_cast<uint32_t>(kMsdMaxTiles) ? 2u
+                                                                      : 1u;
+    // Pairs by default: groups of four measured no faster at b = 2^16 (their
+    // buckets outgrow the rank sort and take three LDS radix passes).
+    h->group_max = h->grp_cap < 2u ? 1 : 2;
+  }
   void* p = nullptr;
   lsm_status_t s = LSM_OK;
   for (int i = 0; i < 2 && s == LSM_OK; ++i) {
-    const size_t sz = i == 1 ? h->pair_cap * bb : bb;
+    const size_t sz = i == 1 ? h->grp_cap * bb : bb;
     if ((s = dev_alloc(h, &p, sz)) == LSM_OK) h->tmp_kv[i] = static_cast<uint32_t*>(p);
     if (s == LSM_OK && (s = dev_alloc(h, &p, sz)) == LSM_OK) h->tmp_val[i] = static_cast<uint32_t*>(p);
   }
@@ -900,8 +926,8 @@ lsm_status_t lsm_create(lsm_t* out, uint32_t b, uint32_t flags, void* stream) {
   for (int i = 0; i < kMaxLevels; ++i) h->merge_variant[i] = kDefaultMergeVariant;
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->stage_kv = static_cast<uint32_t*>(p);
   if (s == LSM_OK && (s = dev_alloc(h, &p, bb)) == LSM_OK) h->stage_val = static_cast<uint32_t*>(p);
-  if (s == LSM_OK && (s = dev_alloc(h, &p, h->pair_cap * bb)) == LSM_OK) h->buf_kv = static_cast<uint32_t*>(p);
-  if (s == LSM_OK && (s = dev_alloc(h, &p, h->pair_cap * bb)) == LSM_OK) h->buf_val = static_cast<uint32_t*>(p);
+  if (s == LSM_OK && (s = dev_alloc(h, &p, h->grp_cap * bb)) == LSM_OK) h->buf_kv = static_cast<uint32_t*>(p);
+  if (s == LSM_OK && (s = dev_alloc(h, &p, h->grp_cap * bb)) == LSM_OK) h->buf_val = static_cast<uint32_t*>(p);
   if (s == LSM_OK && (s = dev_alloc(h, &p, sort_meta_words(b) * sizeof(uint32_t))) == LSM_OK) {
     h->meta = static_cast<uint32_t*>(p);
     h->fault = sort_meta_carve(h->meta, b, 0, 0).err + 1;
@@ -1747,9 +1773,11 @@ lsm_status_t lsm_set_fusion(lsm_t h, int max_levels) {
   return LSM_OK;
 }
 
-lsm_status_t lsm_set_pairing(lsm_t h, int on) {
-  if (h == nullptr) return LSM_EINVAL;
-  h->pairing = on != 0;
+lsm_status_t lsm_set_grouping(lsm_t h, int max_batches) {
+  if (h == nullptr || max_batches < 0) return LSM_EINVAL;
+  int g = max_batches >= 4 ? 4 : max_batches >= 2 ? 2 : 1;
+  while (g > static_cast<int>(h->grp_cap)) g /= 2;
+  h->group_max = g;
   return LSM_OK;
 }
 

@@ -104,11 +104,12 @@ struct BatchSrc {
 // Sort scratch layout (uint32 words) for a batch of b elements.  The global
 // digit histogram of the digit-pass sort is double-buffered: a sort
 // accumulates into hist[parity] and clears hist[parity ^ 1] for the next one
-// (both start zeroed).  The top-digit sort has three slots, so that one batch
-// can be scattered while the buckets of one or two earlier batches (a pair)
-// are sorted: each slot holds a scattered batch, the tiles' digit-group
-// starts and the slot's largest-bucket record.
-constexpr int kSortSlots = 3;
+// (both start zeroed).  The top-digit sort has kMaxGroup + 1 slots, so that
+// one batch can be scattered while the buckets of up to kMaxGroup earlier
+// batches (a group sorted together) are sorted: each slot holds a scattered
+// batch, the tiles' digit-group starts and the slot's largest-bucket record.
+constexpr int kMaxGroup = 4;
+constexpr int kSortSlots = kMaxGroup + 1;
 struct SortMeta {
   uint32_t* hist;         // [2][kMaxPasses][256]
   uint32_t* status;       // [kMaxPasses][num_sort_tiles][256] look-back words
@@ -117,10 +118,7 @@ struct SortMeta {
                           // [1] sticky device fault (a bounded wait expired)
   uint32_t* tile_cnt;     // this slot's [num_sort_tiles][kTopBuckets / 2] digit-group
                           // starts (top-digit sort; two 16-bit starts per word)
-  uint32_t* tile_cnt2;    // bucket sort of a pair: the older batch's group starts
-                          // (its own slot), else null
   uint32_t* skew;         // this slot's largest top-digit bucket (top-digit sort)
-  uint32_t* skew2;        // bucket sort of a pair: the older batch's slot record, else null
   uint32_t num_sort_tiles;
   int parity;
 };
@@ -177,10 +175,14 @@ struct SortArgs {
   uint32_t* out_digit;      // top-digit index of the output level (top-digit path), or null
   uint32_t out_n;           // elements of the sorted output (b; 2b for a pair)
   // Bucket half of the top-digit sort: tmp_kv[0] / tmp_val[0] hold every
-  // slot's scattered batch; the batch (the newer one of a pair) starts at
-  // element src_off, the older one of a pair at src_off2.
-  uint32_t src_off;
-  uint32_t src_off2;
+  // slot's scattered batch.  `group` batches (1, 2 or 4) are sorted
+  // together, the newer first on equal keys; batch q of the group (q = 0 the
+  // newest) has its digit-group starts at grp_cnt[q], its largest-bucket
+  // record at grp_skew[q] and its scattered elements from element grp_off[q].
+  uint32_t group;
+  const uint32_t* grp_cnt[kMaxGroup];
+  uint32_t* grp_skew[kMaxGroup];
+  uint32_t grp_off[kMaxGroup];
   int path;                 // SortPath; both paths give the same order
   uint32_t* skew_out;       // optional: receives the largest top-digit bucket of an
                             // earlier sort (a hint for the choice of the next sorts)

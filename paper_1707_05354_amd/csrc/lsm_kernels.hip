@@ -1072,16 +1072,23 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   // (clamped index), so each tile's group bounds and the levels' digit
   // ranges are in flight together.
   auto next_of = [](uint32_t q) { return q + 1 < kTopBuckets ? q + 1 : q; };
-  // A pair (two consecutive batches sorted together, the newer first on
-  // equal keys) has the newer batch's tiles, then the older batch's: nta
-  // group-table entries, one per thread.
+  // A group (consecutive batches sorted together, the newer first on equal
+  // keys) has the newest batch's tiles, then the next older batch's, and so
+  // on: nta group-table entries, one per thread.
   const uint32_t ntiles = m.num_sort_tiles;
-  const bool pair = m.tile_cnt2 != nullptr;
-  const uint32_t nta = pair ? 2 * ntiles : ntiles;
+  const uint32_t G = a.group;
+  const uint32_t nta = G * ntiles;
   static_assert(kMsdMaxTiles <= kThreads, "one tile per thread");
-  const bool older = pair && tid >= ntiles && tid < nta;
-  const uint32_t tt = older ? tid - ntiles : (tid < ntiles ? tid : 0u);  // tile in its batch
-  const uint32_t* row = (older ? m.tile_cnt2 : m.tile_cnt) + static_cast<size_t>(tt) * (kTopBuckets / 2);
+  static_assert(kMaxGroup == 4, "the batch of a tile is chosen among four");
+  const uint32_t bq = tid >= nta ? 0u
+                    : (tid >= ntiles ? 1u : 0u) + (tid >= 2 * ntiles ? 1u : 0u) +
+                          (tid >= 3 * ntiles ? 1u : 0u);  // the tile's batch in the group
+  const uint32_t tt = tid < nta ? tid - bq * ntiles : 0u;  // tile in its batch
+  const uint32_t* cnt_q = bq == 0 ? a.grp_cnt[0] : bq == 1 ? a.grp_cnt[1]
+                        : bq == 2 ? a.grp_cnt[2] : a.grp_cnt[3];
+  const uint32_t off_q = bq == 0 ? a.grp_off[0] : bq == 1 ? a.grp_off[1]
+                       : bq == 2 ? a.grp_off[2] : a.grp_off[3];
+  const uint32_t* row = cnt_q + static_cast<size_t>(tt) * (kTopBuckets / 2);
   const uint32_t seg_w0 = row[d >> 1];
   const uint32_t seg_w1 = row[next_of(d) >> 1];
   // The digit's range in each fused level, from the level's top-digit index:
@@ -1119,7 +1126,7 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   static_assert(kRankSortMax + 8 + 2 * kMsdMaxTiles <= kWaves * kRadix,
                 "group tables fit beside the rank-sort keys");
   if (tid < nta) {
-    segb[tid] = (older ? a.src_off2 : a.src_off) + tt * kSortTile + g_st;
+    segb[tid] = off_q + tt * kSortTile + g_st;
     segp[tid] = csum;
   }
   if (tid == kThreads - 1) {
@@ -1136,12 +1143,14 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   const uint32_t n = L.tmp[2 * kWaves + 1];
   // The sort's largest bucket, for the choice of the next sorts' path and
   // fused depth (only sizes that can change those choices are recorded).
-  // A pair's bucket holds two batches' elements: half of it is recorded, in
-  // both batches' slots (the next scatter into either slot hands it over).
-  const uint32_t n_rec = pair ? (n + 1) / 2 : n;
-  if (tid == 0 && n_rec > kSkewFloor) {
-    if (n_rec > *reinterpret_cast<volatile uint32_t*>(m.skew)) atomicMax(m.skew, n_rec);
-    if (pair && n_rec > *reinterpret_cast<volatile uint32_t*>(m.skew2)) atomicMax(m.skew2, n_rec);
+  // A group's bucket holds G batches' elements: its share per batch is
+  // recorded, in every batch's slot (the next scatter into any of them hands
+  // it over).
+  const uint32_t n_rec = (n + G - 1) / G;
+  if (tid < G && n_rec > kSkewFloor) {
+    uint32_t* rec = tid == 0 ? a.grp_skew[0] : tid == 1 ? a.grp_skew[1]
+                  : tid == 2 ? a.grp_skew[2] : a.grp_skew[3];
+    if (n_rec > *reinterpret_cast<volatile uint32_t*>(rec)) atomicMax(rec, n_rec);
   }
   if (!fused && a.out_digit != nullptr && tid == 0) a.out_digit[d] = s;
   if (n == 0 && !fused) return;
@@ -2452,8 +2461,6 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity, int slot) {
   // Per slot: the group starts (16-byte aligned), then the skew record.
   uint32_t* slot_base = m.err + 4 + static_cast<size_t>(slot) * (ns * (kTopBuckets / 2) + 4);
   m.tile_cnt = slot_base;
-  m.tile_cnt2 = nullptr;
-  m.skew2 = nullptr;
   m.skew = slot_base + ns * (kTopBuckets / 2);
   m.parity = parity;
   return m;
@@ -2474,14 +2481,27 @@ hipError_t launch_scatter(const SortArgs& a, hipStream_t stream, const KTimer* t
   return launch(k_msd_scatter, a.meta.num_sort_tiles, kThreads, stream, t, a, sort_top_shift(a));
 }
 
+// Arguments without a group (group == 0) sort the one batch of their slot,
+// scattered from element 0 of tmp_kv[0].
+SortArgs grouped(SortArgs a) {
+  if (a.group == 0) {
+    a.group = 1;
+    a.grp_cnt[0] = a.meta.tile_cnt;
+    a.grp_skew[0] = a.meta.skew;
+    a.grp_off[0] = 0;
+  }
+  return a;
+}
+
 hipError_t launch_buckets(const SortArgs& a, hipStream_t stream, const KTimer* t) {
-  return launch(k_local_sort, kTopBuckets, kThreads, stream, t, a, a.lo_bit, bucket_passes(a));
+  return launch(k_local_sort, kTopBuckets, kThreads, stream, t, grouped(a), a.lo_bit,
+                bucket_passes(a));
 }
 
 hipError_t launch_sort_step(const SortArgs& bk, const SortArgs& sc, hipStream_t stream,
                             const KTimer* t) {
-  return launch(k_sort_step, sc.meta.num_sort_tiles + kTopBuckets, kThreads, stream, t, bk,
-                bk.lo_bit, bucket_passes(bk), sc, sort_top_shift(sc));
+  return launch(k_sort_step, sc.meta.num_sort_tiles + kTopBuckets, kThreads, stream, t,
+                grouped(bk), bk.lo_bit, bucket_passes(bk), sc, sort_top_shift(sc));
 }
 
 hipError_t launch_sort(const SortArgs& a, hipStream_t stream, const KTimer* timers,

@@ -85,7 +85,7 @@ _SIGNATURES = {
     "lsm_set_sort_path": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lsm_set_fusion": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lsm_set_max_inflight": (ctypes.c_int, [_vp, ctypes.c_int]),
-    "lsm_set_pairing": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lsm_set_grouping": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lsm_destroy": (ctypes.c_int, [_vp]),
     "lsm_clear": (ctypes.c_int, [_vp]),
     "lsm_sync": (ctypes.c_int, [_vp]),
@@ -308,9 +308,9 @@ class LSM:
         """Update launches the host may queue ahead of the device (0: no pacing)."""
         _check(self._lib.lsm_set_max_inflight(self._h, int(launches)), "lsm_set_max_inflight")
 
-    def set_pairing(self, on: bool) -> None:
-        """Sort two consecutive batches together (a level-0 batch and the next)."""
-        _check(self._lib.lsm_set_pairing(self._h, 1 if on else 0), "lsm_set_pairing")
+    def set_grouping(self, max_batches: int) -> None:
+        """Sort up to max_batches (1, 2 or 4) consecutive batches together."""
+        _check(self._lib.lsm_set_grouping(self._h, int(max_batches)), "lsm_set_grouping")
 
     def set_tuning(self, level: int, variant: int) -> None:
         _check(self._lib.lsm_set_tuning(self._h, int(level), int(variant)), "lsm_set_tuning")

@@ -37,27 +37,50 @@ def ffz(r: int) -> int:
     return j
 
 
-def pipeline_schedule(R: int, pairing: bool = True):
+def _split(m: int):
+    """An incomplete group of m batches as aligned groups, largest first."""
+    out = []
+    while m:
+        g = 1
+        while 2 * g <= m:
+            g *= 2
+        out.append(g)
+        m -= g
+    return out
+
+
+def pipeline_schedule(R: int, group: int = 4):
     """Launches of R top-digit insert batches with no read in between, then
-    one read: a batch pending alone with an even counter waits for the next
-    batch (a pair) when pairing is on; otherwise the pending batches' bucket
-    sort runs in the next batch's scatter launch (a step), and the read
-    completes what is pending (a lone bucket sort).  Returns (scatters
-    alone, steps, lone bucket sorts, the counters of the batches that end a
-    pair)."""
-    scat = step = 0
-    pend, paired = [], []
+    one read.  A batch whose counter is a multiple of `group` waits for the
+    next group - 1 batches (their scatters run alone); any other batch is
+    pending alone; a batch that does not join the pending batches has its
+    scatter in one launch with their bucket sort (a step), an incomplete
+    group being sorted as aligned groups of 2 and 1 (lone bucket sorts
+    before the step's).  The read sorts what is pending.  Returns (scatters
+    alone, steps, lone bucket sorts, [(newest counter, size) of every bucket
+    sort])."""
+    scat = step = lone = 0
+    pend, sorts = [], []
     for r in range(R):
-        pair_up = pairing and len(pend) == 1 and pend[0] % 2 == 0 and r == pend[0] + 1
-        if pend and not pair_up:
-            step += 1
-            pend = []
+        join = (group > 1 and 0 < len(pend) < group and pend[0] % group == 0
+                and r == pend[-1] + 1)
+        if pend and not join:
+            sizes = _split(len(pend))
+            for i, g in enumerate(sizes):
+                sorts.append((pend[g - 1], g))
+                pend = pend[g:]
+                if i == len(sizes) - 1:
+                    step += 1
+                else:
+                    lone += 1
         else:
             scat += 1
-        if pair_up:
-            paired.append(r)
         pend.append(r)
-    return scat, step, 1 if pend else 0, paired
+    for g in _split(len(pend)):
+        sorts.append((pend[g - 1], g))
+        pend = pend[g:]
+        lone += 1
+    return scat, step, lone, sorts
 
 
 def note(msg: str) -> None:

@@ -96,20 +96,21 @@ def test_clear_drops_the_pending_batch():
     t.g.close()
 
 
-@pytest.mark.parametrize("pairing,R", [(False, 21), (True, 21), (True, 20)])
-def test_pipeline_profile_and_sync(pairing, R):
-    """R batches with no read between them.  Without pairing: one scatter,
-    R - 1 steps, and lsm_sync completes the last batch (one bucket sort).
-    With pairing, each even batch waits for the next: the odd batches'
-    scatters run alone, the even batches' in a step with the pair before
-    them, and lsm_sync sorts what is pending (a lone even batch, or a pair
-    when R is even).  The levels are then complete."""
+@pytest.mark.parametrize("group,R", [(1, 21), (2, 21), (2, 20), (4, 21), (4, 22), (4, 23)])
+def test_pipeline_profile_and_sync(group, R):
+    """R batches with no read between them, then lsm_sync.  Without
+    grouping: one scatter, R - 1 steps, and lsm_sync completes the last batch
+    (one bucket sort).  With groups of G, a batch whose counter is a multiple
+    of G waits for the next G - 1 (their scatters run alone), the group's
+    bucket sort runs beside the next group's first scatter, and lsm_sync
+    sorts what is pending (an incomplete group as groups of 2 and 1).  The
+    levels are then complete."""
     b = 4096
-    note("pipeline profile b=%d R=%d pairing=%d" % (b, R, pairing))
+    note("pipeline profile b=%d R=%d group=%d" % (b, R, group))
     rng = np.random.default_rng(8)
     t = Trio(b)
     t.g.set_sort_path(LSM.SORT_TOP_DIGIT)
-    t.g.set_pairing(pairing)
+    t.g.set_grouping(group)
     t.g.profile(True)
     t.g.profile_read(reset=True)
     for _ in range(R):
@@ -117,11 +118,14 @@ def test_pipeline_profile_and_sync(pairing, R):
                  rng.integers(0, 2**32, b, dtype=np.uint64).astype(np.uint32))
     t.g.sync()
     p = t.g.profile_read(reset=True)
-    scat, step, lone, _ = pipeline_schedule(R, pairing)
-    if not pairing:
+    scat, step, lone, sorts = pipeline_schedule(R, group)
+    # Closed forms of the schedule (the helper is checked against them).
+    if group == 1:
         assert (scat, step, lone) == (1, R - 1, 1)
     else:
-        assert (scat, step, lone) == (1 + R // 2, R - 1 - R // 2, 1)
+        full = (R - 1) // group  # complete groups followed by a later batch
+        assert (scat, step, lone) == (R - full, full, bin(R - full * group).count("1"))
+    assert sum(g for _, g in sorts) == R
     assert int(p.launches[K["k_msd_scatter"]]) == scat
     assert int(p.launches[K["k_sort_step"]]) == step
     assert int(p.launches[K["k_local_sort"]]) == lone
@@ -131,27 +135,30 @@ def test_pipeline_profile_and_sync(pairing, R):
     t.g.close()
 
 
-@pytest.mark.parametrize("b,domain", [(1, 1 << 31), (2048, 1 << 31), (2049, 1 << 31),
-                                      (30000, 1 << 31), (256, 779), (700, 1500), (3000, 9000),
-                                      (1 << 18, 1 << 31), ((1 << 18) + 1, 1 << 31)])
-def test_pairing_gives_the_same_levels(b, domain):
-    """The same stream (partial, deleting and mixed batches) with pairing on
-    and off: the levels equal the cascade oracle's and each other byte for
-    byte.  The paired dictionary is read at random points (a read completes
-    a batch that waits alone, so the next batch starts no pair).  Small key
-    domains put every key into one top-digit bucket, so a pair's bucket is
-    ranked by the LDS radix passes (2b <= 1536) or in global memory, and
-    keys repeat across the two batches of a pair and within mixed batches.
-    b = 2^18 is the largest batch that pairs (both batches' tiles in one
-    group table); b = 2^18 + 1 never pairs."""
-    R = 12 if b >= 1 << 18 else 37
-    note("pairing on/off b=%d domain=%d R=%d" % (b, domain, R))
-    ops, q, lo, hi = W.random_small(4400 + b % 97, b, R, domain, p_delete=0.3, nq=300)
+@pytest.mark.parametrize("b,domain,group", [
+    (1, 1 << 31, 4), (2048, 1 << 31, 4), (2049, 1 << 31, 4), (30000, 1 << 31, 4),
+    (256, 779, 4), (700, 1500, 2), (3000, 9000, 4), (1 << 17, 1 << 31, 4),
+    ((1 << 17) + 1, 1 << 31, 4), ((1 << 18) + 1, 1 << 31, 4)])
+def test_grouping_gives_the_same_levels(b, domain, group):
+    """The same stream (partial, deleting and mixed batches) with grouping
+    on and off: the levels equal the cascade oracle's and each other byte
+    for byte.  The grouped dictionary is read at random points (a read
+    completes an incomplete group, so groups of 1, 2 and 4 all occur).
+    Small key domains put every key into one top-digit bucket, so a group's
+    bucket is ranked by the LDS radix passes (<= 1536 elements) or in global
+    memory, and keys repeat across the batches of a group and within mixed
+    batches.  b = 2^17 is the largest batch for groups of four (all tiles in
+    one group table), 2^17 + 1 takes pairs, 2^18 + 1 no groups."""
+    R = 13 if b >= 1 << 17 else 37
+    note("grouping on/off b=%d domain=%d group=%d R=%d" % (b, domain, group, R))
+    ops, q, lo, _ = W.random_small(4400 + b % 97, b, R, domain, p_delete=0.3, nq=300)
+    # Ranges of about 40 keys at the largest sizes (the map oracle lists every pair).
+    hi = np.minimum(lo.astype(np.int64) + max(40 * domain // (b * R), 8), 2**32 - 1).astype(np.uint32)
     rng = np.random.default_rng(b)
     reads = set(rng.choice(R, size=R // 5, replace=False).tolist())
     tr = [Trio(b), Trio(b)]
-    tr[0].g.set_pairing(True)
-    tr[1].g.set_pairing(False)
+    tr[0].g.set_grouping(group)
+    tr[1].g.set_grouping(1)
     for t in tr:
         t.g.set_sort_path(LSM.SORT_TOP_DIGIT)
     for i, (kind, k, v) in enumerate(ops):
@@ -177,14 +184,14 @@ def test_pairing_gives_the_same_levels(b, domain):
         t.g.close()
 
 
-def test_mixed_batches_never_pair():
+def test_mixed_batches_never_group():
     """Mixed batches sort a key's tombstone before its insertion; across the
-    two batches of a pair that would put an older tombstone before a newer
-    insertion, so they are never paired: a stream of mixed batches over a
+    batches of a group that would put an older tombstone before a newer
+    insertion, so they never join a group: a stream of mixed batches over a
     small key domain (keys repeating within and across batches) runs one
     scatter and then steps only, and its levels equal the cascade oracle's."""
     b, R = 256, 24
-    note("mixed batches never pair b=%d" % b)
+    note("mixed batches never group b=%d" % b)
     rng = np.random.default_rng(11)
     t = Trio(b)
     t.g.set_sort_path(LSM.SORT_TOP_DIGIT)
@@ -197,7 +204,7 @@ def test_mixed_batches_never_pair():
     t.g.sync()
     p = t.g.profile_read(reset=True)
     t.g.profile(False)
-    scat, step, lone, _ = pipeline_schedule(R, pairing=False)
+    scat, step, lone, _ = pipeline_schedule(R, group=1)
     assert int(p.launches[K["k_msd_scatter"]]) == scat
     assert int(p.launches[K["k_sort_step"]]) == step
     assert int(p.launches[K["k_local_sort"]]) == lone

@@ -21,21 +21,23 @@ def default_fusion(b):
     return j
 
 
-@pytest.mark.parametrize("mode,fusion,pairing", [
-    (LSM.SORT_TOP_DIGIT, -1, True), (LSM.SORT_TOP_DIGIT, 0, True), (LSM.SORT_TOP_DIGIT, 2, True),
-    (LSM.SORT_TOP_DIGIT, 0, False), (LSM.SORT_TOP_DIGIT, 2, False), (LSM.SORT_DIGIT_PASSES, -1, True),
+@pytest.mark.parametrize("mode,fusion,group", [
+    (LSM.SORT_TOP_DIGIT, -1, 4), (LSM.SORT_TOP_DIGIT, 0, 4), (LSM.SORT_TOP_DIGIT, 2, 4),
+    (LSM.SORT_TOP_DIGIT, 1, 4), (LSM.SORT_TOP_DIGIT, 0, 2), (LSM.SORT_TOP_DIGIT, 0, 1),
+    (LSM.SORT_TOP_DIGIT, 2, 1), (LSM.SORT_DIGIT_PASSES, -1, 4),
 ])
-def test_profile_counts_follow_the_path(mode, fusion, pairing):
+def test_profile_counts_follow_the_path(mode, fusion, group):
     """Merge launches: one per level the cascade passes beyond the levels
-    fused into the top-digit sort (none fused on the digit-pass path; a
-    pair's sort takes level 0's merge, fused or not)."""
+    fused into the top-digit sort (none fused on the digit-pass path; the
+    sort of a group of G batches takes the merges of the levels below
+    log2 G, fused or not)."""
     b, R = 4096, 13
     rng = np.random.default_rng(5)
-    note("profile counts mode=%d fusion=%d pairing=%d" % (mode, fusion, pairing))
+    note("profile counts mode=%d fusion=%d group=%d" % (mode, fusion, group))
     t = Trio(b)
     t.g.set_sort_path(mode)
     t.g.set_fusion(fusion)
-    t.g.set_pairing(pairing)
+    t.g.set_grouping(group)
     depth = 0 if mode == LSM.SORT_DIGIT_PASSES else (default_fusion(b) if fusion < 0 else fusion)
     t.g.profile(True)
     t.g.profile_read(reset=True)
@@ -58,17 +60,17 @@ def test_profile_counts_follow_the_path(mode, fusion, pairing):
     p = t.g.profile_read(reset=True)
     t.g.profile(False)
     passes = 4  # 31-bit keys, status bit not sorted
-    scat, step, lone, paired = pipeline_schedule(R, pairing)
+    scat, step, lone, sorts = pipeline_schedule(R, group)
     if mode != LSM.SORT_TOP_DIGIT:
-        paired = []
-    merges = sum(max(0, ffz(r) - (max(depth, 1) if r in paired else depth)) for r in range(R))
+        sorts = [(r, 1) for r in range(R)]
+    merges = sum(max(0, ffz(r) - max(depth, g.bit_length() - 1)) for r, g in sorts)
     expect = {"k_merge": merges, "k_lookup": 1, "k_order": 2,
               "k_range_emit": 1, "k_scan": 1, "k_count": 2}
     if mode == LSM.SORT_TOP_DIGIT:
-        # Pipelined: scatters alone (the first batch's, and with pairing
-        # each batch that completes a pair), steps (a batch's scatter with
-        # the buckets of the batch or pair before it), and the buckets of
-        # what is pending when the first query needs the levels.
+        # Pipelined: scatters alone (the first batch's, and each batch that
+        # joins a group), steps (a batch's scatter with the buckets of the
+        # batch or group before it), and the buckets of what is pending when
+        # the first query needs the levels.
         expect.update({"k_msd_scatter": scat, "k_sort_step": step, "k_local_sort": lone})
     else:
         expect.update({"k_sort_hist": R, "k_sort_pass": R * passes})
