@@ -546,7 +546,7 @@ SortArgs pending_args(lsm_t h, int G, int* j, int* base) {
     const lsm_s::Pending& x = h->pend[G - 1 - q];  // newest first
     const SortMeta xm = sort_meta_carve(h->meta, h->b, h->hist_parity, x.slot);
     sa.grp_cnt[q] = xm.tile_cnt;
-    sa.grp_skew[q] = xm.skew;
+    sa.grp_n[q] = xm.bucket_n;
     sa.grp_off[q] = static_cast<uint32_t>(x.slot) * h->b;
   }
   sa.tmp_kv[1] = h->tmp_kv[1];
@@ -698,17 +698,15 @@ void pace(lsm_t h) {
 // calls this first.
 lsm_status_t drain(lsm_t h) {
   if (h->npend == 0) return LSM_OK;
-  const int slot = h->pend[h->npend - 1].slot;  // its record holds the sort's skew
+  const int slot = h->pend[h->npend - 1].slot;  // its record holds the last sort's buckets
   Timed first, last;
   if (launch_pending(h, nullptr, &first, &last) != hipSuccess) return LSM_EHIP;
   // Hand the just-sorted batch's largest bucket to the host-visible hint
   // (within a pipelined stream a later scatter hands it over, one batch
   // late), so that a caller that synchronises sees the latest sort's skew.
-  // A failed copy only leaves the hint older; the insertion itself is done.
+  // A failed launch only leaves the hint older; the insertion itself is done.
   const SortMeta m = sort_meta_carve(h->meta, h->b, h->hist_parity, slot);
-  if (hipMemcpyAsync(h->skew_host, m.skew, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream) !=
-      hipSuccess)
-    (void)hipGetLastError();
+  if (launch_rec_max(m.bucket_n, h->skew_dev, h->stream) != hipSuccess) (void)hipGetLastError();
   return LSM_OK;
 }
 

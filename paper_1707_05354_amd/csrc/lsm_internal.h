@@ -118,15 +118,12 @@ struct SortMeta {
                           // [1] sticky device fault (a bounded wait expired)
   uint32_t* tile_cnt;     // this slot's [num_sort_tiles][kTopBuckets / 2] digit-group
                           // starts (top-digit sort; two 16-bit starts per word)
-  uint32_t* skew;         // this slot's largest top-digit bucket (top-digit sort)
+  uint32_t* bucket_n;     // this slot's [kTopBuckets] record: each top-digit bucket's size
+                          // (its share per batch for a group) in the slot's last bucket
+                          // sort (top-digit sort)
   uint32_t num_sort_tiles;
   int parity;
 };
-// Bucket sizes that can change which path the next sort takes or how deep
-// it fuses (more than kLocalCap >> kMaxFuse elements); smaller largest
-// buckets are recorded as 0.
-constexpr uint32_t kSkewFloor = 6;
-
 // The two sort paths: one scatter on the top digit then a per-bucket LDS
 // sort (for at most kMsdMaxTiles tiles), or one digit pass per 8 bits.  The
 // first is faster unless a top-digit bucket outgrows kLocalCap (skewed keys),
@@ -145,8 +142,6 @@ inline int pick_sort_path(uint32_t tiles, uint32_t last_max_bucket) {
 // (bucket d holds the original keys [d << key_shift, (d + 1) << key_shift))
 // and writes that part of level nlev.  nlev = 0: no fusion.
 constexpr int kMaxFuse = 8;
-static_assert(kSkewFloor == static_cast<uint32_t>(kLocalCap >> kMaxFuse),
-              "the skew record keeps every size that can change a fused depth");
 struct FuseArgs {
   int nlev;
   int key_shift;
@@ -177,11 +172,11 @@ struct SortArgs {
   // Bucket half of the top-digit sort: tmp_kv[0] / tmp_val[0] hold every
   // slot's scattered batch.  `group` batches (1, 2 or 4) are sorted
   // together, the newer first on equal keys; batch q of the group (q = 0 the
-  // newest) has its digit-group starts at grp_cnt[q], its largest-bucket
-  // record at grp_skew[q] and its scattered elements from element grp_off[q].
+  // newest) has its digit-group starts at grp_cnt[q], its bucket-size record
+  // at grp_n[q] and its scattered elements from element grp_off[q].
   uint32_t group;
   const uint32_t* grp_cnt[kMaxGroup];
-  uint32_t* grp_skew[kMaxGroup];
+  uint32_t* grp_n[kMaxGroup];
   uint32_t grp_off[kMaxGroup];
   int path;                 // SortPath; both paths give the same order
   uint32_t* skew_out;       // optional: receives the largest top-digit bucket of an
@@ -344,6 +339,10 @@ hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint3
                              uint32_t nq, const uint64_t* offsets, const uint32_t* bounds,
                              uint32_t* out_keys, uint32_t* out_vals, uint64_t cap,
                              hipStream_t stream, const KTimer* t);
+
+// The largest entry of a slot's bucket-size record (kTopBuckets words) into
+// *out, with one work-group.
+hipError_t launch_rec_max(const uint32_t* rec, uint32_t* out, hipStream_t stream);
 
 // Writes *p = 0 with a one-thread kernel (no memset node on the stream).
 hipError_t launch_zero_u64(uint64_t* p, hipStream_t stream);

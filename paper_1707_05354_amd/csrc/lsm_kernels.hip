@@ -733,6 +733,7 @@ struct ScatterLds {
     uint32_t local[kTopBuckets];          // each digit's group start in the tile
   } u;
   uint32_t tmp[2 * kWaves];
+  uint32_t rmax[kWaves];
 };
 
 __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, ScatterLds& S) {
@@ -745,12 +746,15 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
   uint32_t kv[kSortItems], val[kSortItems], off[kSortItems], dg[kSortItems], key[kSortItems];
   bool valid[kSortItems];
   tile_items<kSortItems>(a.src, tbase, wave, lane, kv, val, key, valid);
-  if (tile == 0 && tid == 0) {
-    if (a.progress != nullptr)
-      __hip_atomic_store(a.progress, a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    if (a.skew_out != nullptr) *a.skew_out = *m.skew;
-    *m.skew = 0u;
-  }
+  if (tile == 0 && tid == 0 && a.progress != nullptr)
+    __hip_atomic_store(a.progress, a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  // Tile 0 hands over the largest bucket of the slot's previous bucket sort
+  // (a hint for the choice of the next sorts): its loads go out now, the
+  // maximum is taken after the tile's ranking.
+  static_assert(kTopBuckets == 4 * kThreads, "four bucket records per thread");
+  const bool hand = tile == 0 && a.skew_out != nullptr;
+  uint4 rec4 = make_uint4(0u, 0u, 0u, 0u);
+  if (hand) rec4 = reinterpret_cast<const uint4*>(m.bucket_n)[tid];
   // Rank the tile: each wave clears and fills its own tables.
   for (uint32_t i = lane; i < kTopBuckets / 2; i += 64) S.wcnt[wave][i] = 0u;
   for (uint32_t i = lane; i < 2 * (kHalf + 1); i += 64) (&S.u.mask[wave][0][0])[i] = 0ull;
@@ -804,6 +808,19 @@ __device__ void tile_scatter(const SortArgs& a, int top_shift, uint32_t tile, Sc
     }
   }
   __syncthreads();
+  if (hand) {
+    uint32_t x = max(max(rec4.x, rec4.y), max(rec4.z, rec4.w));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = max(x, static_cast<uint32_t>(__shfl_xor(x, o, 64)));
+    if (lane == 0) S.rmax[wave] = x;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t mx = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) mx = max(mx, S.rmax[w]);
+      *a.skew_out = mx;
+    }
+  }
   // Global writes last, so that no barrier waits for them: the group starts
   // and the grouped tile.
   uint32_t* row = m.tile_cnt + static_cast<size_t>(tile) * (kTopBuckets / 2);
@@ -1143,14 +1160,14 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   const uint32_t n = L.tmp[2 * kWaves + 1];
   // The sort's largest bucket, for the choice of the next sorts' path and
   // fused depth (only sizes that can change those choices are recorded).
-  // A group's bucket holds G batches' elements: its share per batch is
-  // recorded, in every batch's slot (the next scatter into any of them hands
-  // it over).
-  const uint32_t n_rec = (n + G - 1) / G;
-  if (tid < G && n_rec > kSkewFloor) {
-    uint32_t* rec = tid == 0 ? a.grp_skew[0] : tid == 1 ? a.grp_skew[1]
-                  : tid == 2 ? a.grp_skew[2] : a.grp_skew[3];
-    if (n_rec > *reinterpret_cast<volatile uint32_t*>(rec)) atomicMax(rec, n_rec);
+  // Bucket d's size (for a group, its share per batch) goes to the record of
+  // every batch's slot with a plain store: every bucket sort writes all of
+  // a record, so no atomics and no clearing are needed; the next scatter
+  // into any of the slots takes the largest entry.
+  if (tid < G) {
+    uint32_t* rec = tid == 0 ? a.grp_n[0] : tid == 1 ? a.grp_n[1]
+                  : tid == 2 ? a.grp_n[2] : a.grp_n[3];
+    rec[d] = (n + G - 1) / G;
   }
   if (!fused && a.out_digit != nullptr && tid == 0) a.out_digit[d] = s;
   if (n == 0 && !fused) return;
@@ -2447,7 +2464,7 @@ hipError_t launch_zero_u64(uint64_t* p, hipStream_t stream) {
 size_t sort_meta_words(uint32_t b) {
   const size_t ns = grid_for(b, kSortTile);
   return static_cast<size_t>(2) * kMaxPasses * kRadix + static_cast<size_t>(kMaxPasses) * ns * kRadix +
-         kMaxPasses + 4 + kSortSlots * (ns * (kTopBuckets / 2) + 4);
+         kMaxPasses + 4 + kSortSlots * (ns * (kTopBuckets / 2) + kTopBuckets);
 }
 
 SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity, int slot) {
@@ -2458,10 +2475,12 @@ SortMeta sort_meta_carve(uint32_t* base, uint32_t b, int parity, int slot) {
   m.status = m.hist + static_cast<size_t>(2) * kMaxPasses * kRadix;
   m.tile_ctr = m.status + static_cast<size_t>(kMaxPasses) * ns * kRadix;
   m.err = m.tile_ctr + kMaxPasses;
-  // Per slot: the group starts (16-byte aligned), then the skew record.
-  uint32_t* slot_base = m.err + 4 + static_cast<size_t>(slot) * (ns * (kTopBuckets / 2) + 4);
+  // Per slot: the group starts, then the bucket-size record (both 16-byte
+  // aligned).
+  uint32_t* slot_base =
+      m.err + 4 + static_cast<size_t>(slot) * (ns * (kTopBuckets / 2) + kTopBuckets);
   m.tile_cnt = slot_base;
-  m.skew = slot_base + ns * (kTopBuckets / 2);
+  m.bucket_n = slot_base + ns * (kTopBuckets / 2);
   m.parity = parity;
   return m;
 }
@@ -2481,13 +2500,35 @@ hipError_t launch_scatter(const SortArgs& a, hipStream_t stream, const KTimer* t
   return launch(k_msd_scatter, a.meta.num_sort_tiles, kThreads, stream, t, a, sort_top_shift(a));
 }
 
+// The largest entry of a slot's bucket-size record into *out (one work-group).
+__global__ __launch_bounds__(kThreads) void k_rec_max(const uint32_t* rec, uint32_t* out) {
+  __shared__ uint32_t s_max[kWaves];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint4 r = reinterpret_cast<const uint4*>(rec)[tid];
+  uint32_t x = max(max(r.x, r.y), max(r.z, r.w));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = max(x, static_cast<uint32_t>(__shfl_xor(x, o, 64)));
+  if (lane == 0) s_max[wave] = x;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t mx = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) mx = max(mx, s_max[w]);
+    *out = mx;
+  }
+}
+
+hipError_t launch_rec_max(const uint32_t* rec, uint32_t* out, hipStream_t stream) {
+  return launch(k_rec_max, 1, kThreads, stream, nullptr, rec, out);
+}
+
 // Arguments without a group (group == 0) sort the one batch of their slot,
 // scattered from element 0 of tmp_kv[0].
 SortArgs grouped(SortArgs a) {
   if (a.group == 0) {
     a.group = 1;
     a.grp_cnt[0] = a.meta.tile_cnt;
-    a.grp_skew[0] = a.meta.skew;
+    a.grp_n[0] = a.meta.bucket_n;
     a.grp_off[0] = 0;
   }
   return a;
