@@ -1417,9 +1417,17 @@ __device__ void bucket_sort(const SortArgs& a, int lo_bit, int passes, uint32_t 
   }
 }
 
+// Bucket work-group w (counted from the first bucket work-group) takes top
+// digit (w % 8) * 128 + w / 8: work-groups go to the 8 XCDs in turn, so the
+// work-groups with one w % 8 share an XCD, take 128 consecutive digits and
+// read each tile's groups (adjacent in the tile) through that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_digit(uint32_t w) {
+  return (w & 7u) * (kTopBuckets / 8) + (w >> 3);
+}
+
 __global__ __launch_bounds__(kThreads) void k_local_sort(SortArgs a, int lo_bit, int passes) {
   __shared__ LocalLds L;
-  bucket_sort(a, lo_bit, passes, blockIdx.x, L);
+  bucket_sort(a, lo_bit, passes, xcd_digit(blockIdx.x), L);
 }
 
 // One step of the pipelined top-digit sort: the first work-groups scatter
@@ -1439,7 +1447,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_step(SortArgs bk, int lo_bit,
   __shared__ StepLds U;
   const uint32_t nt = sc.meta.num_sort_tiles;
   if (blockIdx.x < nt) tile_scatter(sc, top_shift, blockIdx.x, U.S);
-  else bucket_sort(bk, lo_bit, passes, blockIdx.x - nt, U.L);
+  else bucket_sort(bk, lo_bit, passes, xcd_digit(blockIdx.x - nt), U.L);
 }
 
 // ------------------------------------------------------------ merge
