@@ -111,6 +111,9 @@ def zipf_sweep(torch, L, W, reps: int = 2):
                       else lib.lsm_insert_batch(h, rows_k[i], rows_v[i], b))
                 if rc:
                     raise L.LSMError(rc, "sweep update")
+            rc = lib.lsm_flush(h)  # the last pending insertion belongs to the update phase
+            if rc:
+                raise L.LSMError(rc, "sweep flush")
             e[1].record()
             g.lookup(qd, out=(lv, lf))
             e[2].record()
