@@ -15,7 +15,7 @@ import pytest
 import torch
 
 from paper_1707_05354_amd import workload as W
-from paper_1707_05354_amd.lsm import KERNEL_NAMES, LSM
+from paper_1707_05354_amd.lsm import KERNEL_NAMES, LSM, LSMError, LSM_EINVAL
 from _gpu import Trio, dev, dev_u8, host, note, pipeline_schedule
 
 pytestmark = pytest.mark.gpu
@@ -212,3 +212,31 @@ def test_mixed_batches_never_group():
     q = np.arange(602, dtype=np.uint32)
     t.check_queries(q, q[:300:3], q[:300:3] + 40)
     t.g.close()
+
+
+@pytest.mark.parametrize("b,asked,effective", [(4096, 0, 1), (4096, 3, 2), (4096, 100, 4),
+                                               (1 << 18, 4, 2), ((1 << 18) + 1, 2, 1)])
+def test_grouping_argument_is_rounded_and_capped(b, asked, effective):
+    """lsm_set_grouping rounds down to 1, 2 or 4 and caps by b (four when
+    4 tiles of every batch fit one group table, two for b <= 2^18): the
+    launch schedule of 9 unread batches is that of the effective size."""
+    note("grouping argument b=%d asked=%d" % (b, asked))
+    R = 9
+    rng = np.random.default_rng(b + asked)
+    g = LSM(b)
+    g.set_sort_path(LSM.SORT_TOP_DIGIT)
+    g.set_grouping(asked)
+    g.profile(True)
+    g.profile_read(reset=True)
+    for _ in range(R):
+        k = rng.integers(0, 1 << 31, b, dtype=np.uint64).astype(np.uint32)
+        g.insert(dev(k), dev(k))
+    g.sync()
+    p = g.profile_read(reset=True)
+    scat, step, lone, _ = pipeline_schedule(R, effective)
+    assert (int(p.launches[K["k_msd_scatter"]]), int(p.launches[K["k_sort_step"]]),
+            int(p.launches[K["k_local_sort"]])) == (scat, step, lone)
+    with pytest.raises(LSMError) as ei:
+        g.set_grouping(-1)
+    assert ei.value.status == LSM_EINVAL
+    g.close()
