@@ -1018,7 +1018,7 @@ __device__ void lds_merge_pair(const uint32_t* sk, const uint32_t* sv, uint32_t 
 // The keys are distinct, so the rank of element x, the number of smaller
 // keys, orders by field and then by position (a stable sort, the same order
 // as the radix passes over those bits).  The keys are read four at a time
-// (16-byte LDS reads, two in flight); the entries past n are above every
+// (16-byte LDS reads, eight in flight); the entries past n are above every
 // element's key.  Waves without elements skip the count.
 __device__ void rank_sort(LocalLds& L, const uint32_t* fld, uint32_t n) {
   static_assert(kRankSortMax <= 256u && kRankSortMax <= static_cast<uint32_t>(kThreads),
@@ -1029,12 +1029,22 @@ __device__ void rank_sort(LocalLds& L, const uint32_t* fld, uint32_t n) {
     const uint32_t cx = tid < n ? fld[tid] : 0u;
     uint32_t rank = 0;
     const uint4* f4 = reinterpret_cast<const uint4*>(fld);
-    for (uint32_t y = 0; y < n8; y += 8) {
+    auto below = [cx](const uint4& p) {
+      return (p.x < cx ? 1u : 0u) + (p.y < cx ? 1u : 0u) + (p.z < cx ? 1u : 0u) +
+             (p.w < cx ? 1u : 0u);
+    };
+    uint32_t y = 0;
+    for (; y + 32u <= n8; y += 32u) {  // eight 16-byte reads in flight
+      uint4 p[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p[u] = f4[y / 4 + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) rank += below(p[u]);
+    }
+    for (; y < n8; y += 8u) {
       const uint4 p = f4[y / 4];
       const uint4 q = f4[y / 4 + 1];
-      rank += (p.x < cx ? 1u : 0u) + (p.y < cx ? 1u : 0u) + (p.z < cx ? 1u : 0u) +
-              (p.w < cx ? 1u : 0u) + (q.x < cx ? 1u : 0u) + (q.y < cx ? 1u : 0u) +
-              (q.z < cx ? 1u : 0u) + (q.w < cx ? 1u : 0u);
+      rank += below(p) + below(q);
     }
     if (tid < n) {
       L.k[1][rank] = L.k[0][tid];
