@@ -106,7 +106,8 @@ struct lsm_s {
 
   uint32_t* q_counts = nullptr;  // range pass 1 output
   uint64_t* q_status = nullptr;  // range scan look-back words
-  uint32_t* q_bounds = nullptr;  // range pass 1: candidate bounds (one level), 2 words a query
+  uint32_t* q_bounds = nullptr;  // range pass 1: per-query positions in the levels
+  uint64_t q_bwords = 0;         // words of q_bounds
   uint64_t q_cap = 0;
   // The device's fixed range scratch (lsm_range_async_noalloc), or nulls
   // when its address could not be looked up.
@@ -270,27 +271,39 @@ lsm_status_t ensure_query_scratch(lsm_t h, uint32_t nq) {
   if (h->q_cap >= nq) return LSM_OK;
   uint64_t cap = h->q_cap ? h->q_cap : 4096;
   while (cap < nq) cap *= 2;
-  void *c = nullptr, *s = nullptr, *bd = nullptr;
+  void *c = nullptr, *s = nullptr;
   if (dev_alloc(h, &c, cap * sizeof(uint32_t)) != LSM_OK) return LSM_ENOMEM;
   const size_t sw = scan_status_words(static_cast<uint32_t>(cap < 0xFFFFFFFFull ? cap : 0xFFFFFFFFull));
   if (dev_alloc(h, &s, sw * sizeof(uint64_t)) != LSM_OK) {
     dev_free(h, c, cap * sizeof(uint32_t));
     return LSM_ENOMEM;
   }
-  if (dev_alloc(h, &bd, 2 * cap * sizeof(uint32_t)) != LSM_OK) {
-    dev_free(h, c, cap * sizeof(uint32_t));
-    dev_free(h, s, sw * sizeof(uint64_t));
-    return LSM_ENOMEM;
-  }
   if (h->q_cap) {
     dev_free(h, h->q_counts, h->q_cap * sizeof(uint32_t));
     dev_free(h, h->q_status, scan_status_words(static_cast<uint32_t>(h->q_cap)) * sizeof(uint64_t));
-    dev_free(h, h->q_bounds, 2 * h->q_cap * sizeof(uint32_t));
   }
   h->q_counts = static_cast<uint32_t*>(c);
   h->q_status = static_cast<uint64_t*>(s);
-  h->q_bounds = static_cast<uint32_t*>(bd);
   h->q_cap = cap;
+  return LSM_OK;
+}
+
+// The range scratch for nq queries' positions in the levels the query will
+// see (those of r after the staged elements are inserted): two words a query
+// with one occupied level, one per level with several.  Grown on demand,
+// before anything changes.
+lsm_status_t ensure_bounds(lsm_t h, uint32_t nq) {
+  const uint64_t r_after = h->r + (h->stage_fill > 0 ? 1 : 0);
+  const int levels = __builtin_popcountll(r_after);
+  const uint64_t words = static_cast<uint64_t>(nq) * (levels > 2 ? levels : 2);
+  if (h->q_bwords >= words) return LSM_OK;
+  uint64_t cap = h->q_bwords ? h->q_bwords : 8192;
+  while (cap < words) cap *= 2;
+  void* p = nullptr;
+  if (dev_alloc(h, &p, cap * sizeof(uint32_t)) != LSM_OK) return LSM_ENOMEM;
+  dev_free(h, h->q_bounds, h->q_bwords * sizeof(uint32_t));
+  h->q_bounds = static_cast<uint32_t*>(p);
+  h->q_bwords = cap;
   return LSM_OK;
 }
 
@@ -320,8 +333,8 @@ void release_all(lsm_t h) {
   if (h->q_cap) {
     dev_free(h, h->q_counts, h->q_cap * sizeof(uint32_t));
     dev_free(h, h->q_status, scan_status_words(static_cast<uint32_t>(h->q_cap)) * sizeof(uint64_t));
-    dev_free(h, h->q_bounds, 2 * h->q_cap * sizeof(uint32_t));
   }
+  dev_free(h, h->q_bounds, h->q_bwords * sizeof(uint32_t));
   if (h->h_pinned) (void)hipHostFree(h->h_pinned);
   if (h->skew_host) (void)hipHostFree(h->skew_host);
   if (h->progress_host) (void)hipHostFree(h->progress_host);
@@ -1363,6 +1376,7 @@ lsm_status_t lsm_range(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi, uint
                                                                                   : LSM_EHIP;
   }
   lsm_status_t s = ensure_query_scratch(h, nq);
+  if (s == LSM_OK) s = ensure_bounds(h, nq);
   if (s == LSM_OK) s = settle(h);
   if (s != LSM_OK) return s;
   const LevelSet lv = occupied_levels(h);
@@ -1460,6 +1474,7 @@ lsm_status_t lsm_range_async(lsm_t h, const uint32_t* d_lo, const uint32_t* d_hi
     return hipMemsetAsync(d_offsets, 0, sizeof(uint64_t), h->stream) == hipSuccess ? LSM_OK
                                                                                   : LSM_EHIP;
   lsm_status_t s = ensure_query_scratch(h, nq);
+  if (s == LSM_OK) s = ensure_bounds(h, nq);
   if (s == LSM_OK) s = settle(h);
   if (s != LSM_OK) return s;
   const LevelSet lv = occupied_levels(h);

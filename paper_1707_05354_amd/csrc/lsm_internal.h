@@ -295,8 +295,10 @@ hipError_t launch_lookup(const LevelSet& lv, const uint32_t* q, uint32_t nq, uin
 // Count pass: per query number of live keys in [lo, hi].  When scan_status
 // is non-null the kernel also clears the scan's look-back words
 // (scan_words of them, tile counter included) for the following scan.  With
-// one occupied level and bounds non-null (2 nq words), each query's
-// candidate bounds in the level are stored there for the emission pass.
+// bounds non-null, each query's position in the levels is stored there for
+// the emission pass: with one occupied level its candidate bounds (2 nq
+// words, two per query), with several its lower bound in every level
+// (lv.count * nq words, level-major).
 hipError_t launch_count(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi, uint32_t nq,
                         uint32_t* counts, uint64_t* scan_status, size_t scan_words,
                         uint32_t* bounds, hipStream_t stream, const KTimer* t);
@@ -333,8 +335,8 @@ hipError_t launch_clean_pad(const LevelDst& d, uint64_t v, uint64_t total, hipSt
                             const KTimer* t);
 
 // Range emission pass: writes each query's live pairs at offsets[q], for
-// the queries whose pairs end at or before cap.  bounds: the count pass's
-// candidate bounds (one occupied level), or null to search them again.
+// the queries whose pairs end at or before cap.  bounds: what the count pass
+// stored, or null to search again.
 hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint32_t* hi,
                              uint32_t nq, const uint64_t* offsets, const uint32_t* bounds,
                              uint32_t* out_keys, uint32_t* out_vals, uint64_t cap,

@@ -1858,9 +1858,9 @@ __device__ __forceinline__ uint32_t count_run_starts(const uint32_t* kv, uint32_
 // element); it counts when it is a regular element.  At most kW occupied
 // levels, the walk state in registers (loops unrolled over the kW slots).
 template <int kW>
-__device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t k1, uint32_t k2) {
-  uint32_t cur[kW], ck[kW];
-  level_bounds<kW>(lv, k1, cur);
+__device__ __forceinline__ uint32_t range_walk(const LevelSet& lv, uint32_t (&cur)[kW],
+                                               uint32_t k2) {
+  uint32_t ck[kW];
 #pragma unroll
   for (int l = 0; l < kW; ++l) ck[l] = cand_key(lv.kv[l], cur[l], lv.len[l], k2);
   uint32_t count = 0;
@@ -1898,7 +1898,9 @@ __global__ __launch_bounds__(kQueryThreads) void k_count(LevelSet lv, const uint
       scan_status[w] = 0ull;
   }
   // Every lane takes part in the wave-wide descents; lanes without a query
-  // search the empty range [1, 0].
+  // search the empty range [1, 0].  Several levels: with bounds non-null,
+  // each query's per-level cursors (lower bounds) are stored level-major
+  // (word l * nq + query) for the emission pass.
   const bool active = gi < nq;
   const uint32_t k1 = active ? lo[gi] : 1u, k2 = active ? hi[gi] : 0u;
   if constexpr (kW == 1) {
@@ -1912,7 +1914,14 @@ __global__ __launch_bounds__(kQueryThreads) void k_count(LevelSet lv, const uint
     if (bounds != nullptr) reinterpret_cast<uint2*>(bounds)[gi] = make_uint2(p, e);
     counts[gi] = c;
   } else {
-    const uint32_t c = range_walk<kW>(lv, k1, k2);
+    uint32_t cur[kW];
+    level_bounds<kW>(lv, k1, cur);
+    if (bounds != nullptr && active) {
+#pragma unroll
+      for (int q = 0; q < kW; ++q)
+        if (q < lv.count) bounds[static_cast<size_t>(q) * nq + gi] = cur[q];
+    }
+    const uint32_t c = range_walk<kW>(lv, cur, k2);
     if (active) counts[gi] = c;
   }
 }
@@ -1928,10 +1937,21 @@ struct WalkMany {
   uint32_t k2;
 };
 
+// The cursors come from the count pass (cursors non-null: word l * nq + i
+// for query i, read only when `use`) or from wave-wide descents (every lane
+// of the wave calls it then).
 template <int kW>
-__device__ __forceinline__ void walk_init(const LevelSet& lv, uint32_t k1, uint32_t k2, WalkMany<kW>& w) {
+__device__ __forceinline__ void walk_init(const LevelSet& lv, uint32_t k1, uint32_t k2,
+                                          const uint32_t* cursors, uint32_t nq, uint32_t i,
+                                          bool use, WalkMany<kW>& w) {
   w.k2 = k2;
-  level_bounds<kW>(lv, k1, w.cur);
+  if (cursors != nullptr) {
+#pragma unroll
+    for (int q = 0; q < kW; ++q)
+      w.cur[q] = (use && q < lv.count) ? cursors[static_cast<size_t>(q) * nq + i] : 0u;
+  } else {
+    level_bounds<kW>(lv, k1, w.cur);
+  }
 #pragma unroll
   for (int l = 0; l < kW; ++l) w.ck[l] = cand_key(lv.kv[l], w.cur[l], lv.len[l], k2);
 }
@@ -1991,6 +2011,7 @@ template <int kW>
 __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const uint32_t* lo,
                                                               const uint32_t* hi, uint32_t nq,
                                                               const uint64_t* offsets,
+                                                              const uint32_t* cursors,
                                                               uint32_t* out_keys,
                                                               uint32_t* out_vals, uint64_t cap) {
   __shared__ uint32_t sk[kQueryWaves][kEmitChunk], sv[kQueryWaves][kEmitChunk];
@@ -2017,7 +2038,9 @@ __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const
   if (lane == 0) s_rounds[wave] = rounds;
   static_assert(kW > 1, "one level: k_range_emit_one");
   WalkMany<kW> w;
-  walk_init(lv, fits ? lo[i] : 1u, fits ? hi[i] : 0u, w);  // wave-wide descents
+  // Stored cursors (only the queries that emit read theirs), or wave-wide
+  // descents by every lane.
+  walk_init(lv, fits ? lo[i] : 1u, fits ? hi[i] : 0u, cursors, nq, i, fits, w);
   __syncthreads();
   uint32_t R = 0;
 #pragma unroll
@@ -2736,7 +2759,7 @@ hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint3
   auto k = lv.count <= 8 ? k_range_emit<8> : lv.count <= 16 ? k_range_emit<16>
                                                             : k_range_emit<kMaxLevels>;
   return launch(k, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi, nq, offsets,
-                out_keys, out_vals, cap);
+                bounds, out_keys, out_vals, cap);
 }
 
 }  // namespace lsm
