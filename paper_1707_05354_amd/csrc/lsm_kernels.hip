@@ -1940,12 +1940,12 @@ struct WalkMany {
 // The cursors come from the count pass (cursors non-null: word l * nq + i
 // for query i, read only when `use`) or from wave-wide descents (every lane
 // of the wave calls it then).
-template <int kW>
+template <int kW, bool kSearch>
 __device__ __forceinline__ void walk_init(const LevelSet& lv, uint32_t k1, uint32_t k2,
                                           const uint32_t* cursors, uint32_t nq, uint32_t i,
                                           bool use, WalkMany<kW>& w) {
   w.k2 = k2;
-  if (cursors != nullptr) {
+  if constexpr (!kSearch) {
 #pragma unroll
     for (int q = 0; q < kW; ++q)
       w.cur[q] = (use && q < lv.count) ? cursors[static_cast<size_t>(q) * nq + i] : 0u;
@@ -2007,7 +2007,7 @@ __device__ __forceinline__ uint64_t walk_emit(const LevelSet& lv, WalkMany<kW>& 
 constexpr uint32_t kEmitChunk = 512;
 constexpr int kQueryWaves = kQueryThreads / 64;
 
-template <int kW>
+template <int kW, bool kSearch>
 __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const uint32_t* lo,
                                                               const uint32_t* hi, uint32_t nq,
                                                               const uint64_t* offsets,
@@ -2040,7 +2040,7 @@ __global__ __launch_bounds__(kQueryThreads) void k_range_emit(LevelSet lv, const
   WalkMany<kW> w;
   // Stored cursors (only the queries that emit read theirs), or wave-wide
   // descents by every lane.
-  walk_init(lv, fits ? lo[i] : 1u, fits ? hi[i] : 0u, cursors, nq, i, fits, w);
+  walk_init<kW, kSearch>(lv, fits ? lo[i] : 1u, fits ? hi[i] : 0u, cursors, nq, i, fits, w);
   __syncthreads();
   uint32_t R = 0;
 #pragma unroll
@@ -2756,8 +2756,14 @@ hipError_t launch_range_emit(const LevelSet& lv, const uint32_t* lo, const uint3
     return launch(bounds != nullptr ? k_range_emit_one<4, false> : k_range_emit_one<4, true>,
                   grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi, nq, offsets,
                   bounds, out_keys, out_vals, cap);
-  auto k = lv.count <= 8 ? k_range_emit<8> : lv.count <= 16 ? k_range_emit<16>
-                                                            : k_range_emit<kMaxLevels>;
+  // Emission from stored cursors and emission that searches (no scratch)
+  // are separate instantiations, so that the first keeps a smaller register
+  // footprint.
+  auto k = bounds != nullptr
+               ? (lv.count <= 8 ? k_range_emit<8, false> : lv.count <= 16 ? k_range_emit<16, false>
+                                                                          : k_range_emit<kMaxLevels, false>)
+               : (lv.count <= 8 ? k_range_emit<8, true> : lv.count <= 16 ? k_range_emit<16, true>
+                                                                         : k_range_emit<kMaxLevels, true>);
   return launch(k, grid_for(nq, kQueryThreads), kQueryThreads, stream, t, lv, lo, hi, nq, offsets,
                 bounds, out_keys, out_vals, cap);
 }
