@@ -4,11 +4,22 @@
     python -m paper_1707_05354_amd.profsum counters <fetch.csv> <write.csv> \\
         <copy_fetch.csv> <copy_write.csv> <copy_bytes> <out.md>
 
+    python -m paper_1707_05354_amd.profsum readsizes <sizes.csv> <copy_sizes.csv> \
+        <copy_bytes> <traffic.md> <out.md>
+
 `counters` scales FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by what the same
 counters read for a plain device copy of copy_bytes bytes, and writes a
 Markdown summary whose `traffic-json:` line bench.py reads back.  The line
 records the SHA-256 of the kernel source the counters were taken with; when
 the source has changed since, bench.py reports traffic as null.
+
+`readsizes` checks that scale per kernel.  FETCH_SIZE weighs the L2's read
+requests to memory by their size, and one scale taken from a streaming copy
+is exact only for kernels whose requests have the copy's size mix.  The
+gfx950 L2 also counts its 32-, 64- and 128-byte read requests separately
+(TCC_EA0_RDREQ_32B/64B/128B); their byte sum is the read traffic with no
+scale at all, and the summary sets it beside the scaled FETCH_SIZE of the
+traffic summary for every kernel.
 """
 from __future__ import annotations
 
@@ -90,6 +101,68 @@ def counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, o
     return doc
 
 
+SIZE_COUNTERS = (("TCC_EA0_RDREQ_32B_sum", 32), ("TCC_EA0_RDREQ_64B_sum", 64),
+                 ("TCC_EA0_RDREQ_128B_sum", 128))
+
+
+def request_sizes(path: str):
+    """kernel -> (dispatches, mean 32/64/128-byte read requests per dispatch)."""
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    names = {}
+    for r in csv.DictReader(open(path)):
+        d = r["Dispatch_Id"]
+        names[d] = short_name(r["Kernel_Name"])
+        per[d][r["Counter_Name"]] += float(r["Counter_Value"])
+    agg = collections.defaultdict(lambda: [0, [0.0, 0.0, 0.0]])
+    for d, c in per.items():
+        a = agg[names[d]]
+        a[0] += 1
+        for i, (name, _) in enumerate(SIZE_COUNTERS):
+            a[1][i] += c.get(name, 0.0)
+    return {k: (n, [v / n for v in t]) for k, (n, t) in agg.items()}
+
+
+def request_bytes(reqs) -> float:
+    return sum(n * size for n, (_, size) in zip(reqs, SIZE_COUNTERS))
+
+
+def readsizes(sizes_csv, copy_csv, copy_bytes, traffic_md, out_md, command):
+    sz = request_sizes(sizes_csv)
+    cp = request_sizes(copy_csv)
+    copy_rows = [(k, v) for k, v in cp.items() if "copy" in k.lower()]
+    copy_read = max(request_bytes(v[1]) for _, v in copy_rows)
+    traffic = load_traffic(traffic_md)
+    scaled = traffic["kernels"] if traffic else {}
+    rows = {}
+    for k, (n, reqs) in sorted(sz.items()):
+        b = request_bytes(reqs)
+        f = scaled.get(k, {}).get("fetch_bytes_per_launch")
+        rows[k] = {"dispatches": n, "req32": reqs[0], "req64": reqs[1], "req128": reqs[2],
+                   "read_bytes_per_launch": b, "scaled_fetch_bytes_per_launch": f,
+                   "scaled_over_sized": (f / b) if (f and b > 0) else None}
+    doc = {"kernel_source_sha256": kernel_source_sha256(), "copy_bytes": copy_bytes,
+           "copy_read_bytes_from_sizes": copy_read, "kernels": rows}
+    lines = ["# Read traffic per kernel from the L2's request sizes (rocprofv3, gfx950)", "",
+             "Bytes read from memory per launch = 32 x TCC_EA0_RDREQ_32B_sum + 64 x "
+             "TCC_EA0_RDREQ_64B_sum + 128 x TCC_EA0_RDREQ_128B_sum, with no calibration "
+             "factor, beside the copy-scaled FETCH_SIZE figure of the traffic summary of the "
+             "same kernel source (ratio 1 when the scale is right for that kernel).", "",
+             "Commands (from the repository root):", "", "```"] + command + ["```", "",
+             "Plain device copy: %d bytes read; the request sizes give %.0f bytes (%.4f)."
+             % (copy_bytes, copy_read, copy_read / copy_bytes), "",
+             "| kernel | dispatches | 32 B req | 64 B req | 128 B req | read bytes / launch "
+             "| scaled FETCH_SIZE / launch | scaled / sized |", "|---|---|---|---|---|---|---|---|"]
+    for k, v in rows.items():
+        lines.append("| %s | %d | %.0f | %.0f | %.0f | %.0f | %s | %s |" % (
+            k, v["dispatches"], v["req32"], v["req64"], v["req128"], v["read_bytes_per_launch"],
+            "%.0f" % v["scaled_fetch_bytes_per_launch"] if v["scaled_fetch_bytes_per_launch"] else "-",
+            "%.3f" % v["scaled_over_sized"] if v["scaled_over_sized"] else "-"))
+    lines += ["", "readsizes-json: " + json.dumps(doc, sort_keys=True), ""]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines))
+    return doc
+
+
 def load_traffic(md_path: str):
     """The traffic table of a summary, or None when missing or stale."""
     if not os.path.exists(md_path):
@@ -111,6 +184,10 @@ def main(argv):
     elif argv[0] == "counters":
         cmd = os.environ.get("PROFSUM_COMMANDS", "").split(";;")
         doc = counters(argv[1], argv[2], argv[3], argv[4], int(argv[5]), argv[6], [c for c in cmd if c])
+        print(json.dumps(doc, indent=1))
+    elif argv[0] == "readsizes":
+        cmd = os.environ.get("PROFSUM_COMMANDS", "").split(";;")
+        doc = readsizes(argv[1], argv[2], int(argv[3]), argv[4], argv[5], [c for c in cmd if c])
         print(json.dumps(doc, indent=1))
     else:
         raise SystemExit(__doc__)
