@@ -136,9 +136,19 @@ lsm_status_t random_op(lsm_t h, uint32_t b, uint32_t domain, int op) {
       Buf<uint64_t> off(nq + 1);
       fill_keys(lo, nq, domain);
       fill_keys(hi, nq, domain);
-      lsm_status_t s = below(2) ? lsm_range_async(h, lo.p, hi.p, nq, off.p, ok.p, ov.p, 4 * nq)
-                                : lsm_range_async_noalloc(h, lo.p, hi.p, nq, off.p, ok.p, ov.p,
-                                                          4 * nq);
+      lsm_status_t s;
+      if (below(2)) {
+        s = lsm_range_async(h, lo.p, hi.p, nq, off.p, ok.p, ov.p, 4 * nq);
+      } else {
+        const uint32_t staged = lsm_pending(h);
+        s = lsm_range_async_noalloc(h, lo.p, hi.p, nq, off.p, ok.p, ov.p, 4 * nq);
+        if (s == LSM_ENOMEM && staged > 0 && lsm_pending(h) == staged) {
+          // Documented refusal: inserting the staged elements first would
+          // need memory.  The caller flushes (which may allocate) and retries.
+          s = lsm_flush(h);
+          if (s == LSM_OK) s = lsm_range_async_noalloc(h, lo.p, hi.p, nq, off.p, ok.p, ov.p, 4 * nq);
+        }
+      }
       if (s == LSM_OK) s = lsm_sync(h);
       return s;
     }
@@ -204,6 +214,9 @@ void run(uint32_t b, uint32_t flags, uint32_t domain, int steps) {
     CHECK(lsm_fail_alloc_after(h, -1) == LSM_OK);
     standin_fail_launch_after(-1);
     if (st != LSM_OK) {
+      if (!(st == LSM_ENOMEM || st == LSM_EHIP) || inject > 1)
+        std::fprintf(stderr, "b %u step %d op %d: status %d without an injected failure (%d)\n",
+                     b, s, op, static_cast<int>(st), inject);
       CHECK(st == LSM_ENOMEM || st == LSM_EHIP);
       g_enomem += st == LSM_ENOMEM;
       g_ehip += st == LSM_EHIP;
@@ -268,7 +281,9 @@ void run(uint32_t b, uint32_t flags, uint32_t domain, int steps) {
 
 }  // namespace
 
-int main() {
+int main(int argc, char** argv) {
+  // An optional argument replaces the seed (for longer runs by hand).
+  if (argc > 1) g_state = std::strtoull(argv[1], nullptr, 0);
   lsm_t h = nullptr;
   CHECK(lsm_create(&h, 0, 0, nullptr) == LSM_EINVAL && h == nullptr);
   CHECK(lsm_create(&h, (1u << 28) + 1, 0, nullptr) == LSM_EINVAL);
