@@ -19,6 +19,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "lsm.h"
@@ -282,8 +283,18 @@ void run(uint32_t b, uint32_t flags, uint32_t domain, int steps) {
 }  // namespace
 
 int main(int argc, char** argv) {
-  // An optional argument replaces the seed (for longer runs by hand).
+  // Optional arguments, for longer runs by hand: a seed, then "large" for
+  // the benchmark's batch size (1500 operations at b = 2^16, reaching level
+  // 10) and b = 2^18 instead of the small sizes.
   if (argc > 1) g_state = std::strtoull(argv[1], nullptr, 0);
+  if (argc > 2 && std::strcmp(argv[2], "large") == 0) {
+    run(65536, 0, 1u << 31, 1500);
+    run(1u << 18, LSM_CHECKED, 1u << 31, 300);
+    if (g_fail) return 1;
+    std::printf("host sanitize check: ok (%ld calls failed with LSM_ENOMEM, %ld with LSM_EHIP)\n",
+                g_enomem, g_ehip);
+    return 0;
+  }
   lsm_t h = nullptr;
   CHECK(lsm_create(&h, 0, 0, nullptr) == LSM_EINVAL && h == nullptr);
   CHECK(lsm_create(&h, (1u << 28) + 1, 0, nullptr) == LSM_EINVAL);
