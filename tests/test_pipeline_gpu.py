@@ -240,3 +240,24 @@ def test_grouping_argument_is_rounded_and_capped(b, asked, effective):
         g.set_grouping(-1)
     assert ei.value.status == LSM_EINVAL
     g.close()
+
+
+@pytest.mark.parametrize("depth", [0, 1, 16])
+def test_pacing_depth_changes_nothing(depth):
+    """Launch pacing only delays the host: free-running (0), one launch
+    ahead (1) or sixteen ahead, the same unread stream of full, partial,
+    deleting and mixed batches gives the cascade oracle's levels byte for
+    byte and the map oracle's answers.  A negative depth is refused."""
+    b, R = 5000, 37
+    note("pacing depth %d" % depth)
+    ops, q, lo, hi = W.random_small(7100 + depth, b, R, 1 << 31, p_delete=0.3, nq=200)
+    t = Trio(b)
+    t.g.set_sort_path(LSM.SORT_TOP_DIGIT)
+    t.g.set_max_inflight(depth)
+    feed(t, ops, np.random.default_rng(depth), mixed_every=5)
+    t.check_levels()
+    t.check_queries(q, lo, hi)
+    with pytest.raises(LSMError) as ei:
+        t.g.set_max_inflight(-1)
+    assert ei.value.status == LSM_EINVAL
+    t.g.close()
