@@ -12,7 +12,9 @@ real layout.  ``driver.cpp`` then calls every C entry point on seeded random
 operation streams with allocation and launch failures injected; a sanitizer
 report or a failed status check fails the test.  A second case plants a
 one-element-short scratch allocation in a copy of the host code and checks
-that the run reports it.
+that the run reports it.  A third case checks the sort-scratch carving
+itself: regions inside the allocation, disjoint, per-slot ones 16-byte
+aligned.
 """
 import os
 import re
@@ -98,3 +100,22 @@ def test_planted_short_scratch_is_reported(tmp_path):
     run = build_and_run(tmp_path, str(bad))
     assert run.returncode != 0
     assert "AddressSanitizer" in run.stderr, run.stderr[-3000:]
+
+
+def test_sort_scratch_layout(tmp_path):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    gen = tmp_path / "gen"
+    gen.mkdir()
+    (gen / "layout_gen.inc").write_text(extract_layout(open(KERNELS).read()))
+    exe = str(tmp_path / "layout_check")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-I", HERE, "-I", str(gen), "-I", CSRC,
+           os.path.join(HERE, "layout_check.cpp"), "-o", exe]
+    build = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    if build.returncode != 0 and "sanitize" in build.stderr and "cannot find" in build.stderr:
+        pytest.skip("sanitizer runtime not installed: " + build.stderr.strip()[:200])
+    assert build.returncode == 0, build.stderr[-4000:]
+    run = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert run.returncode == 0, (run.stdout + run.stderr)[-4000:]
+    assert "sort scratch layout: ok" in run.stdout
