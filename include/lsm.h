@@ -31,7 +31,8 @@
  *   - Every call returns a status.  On any error the dictionary is left
  *     exactly as it was before the call (strong guarantee).
  *   - A handle is not thread-safe; calls on different handles are
- *     independent.
+ *     independent, except lsm_range_async_noalloc, whose calls share one
+ *     scratch array per GPU (see there).
  */
 #ifndef LSM_H_
 #define LSM_H_

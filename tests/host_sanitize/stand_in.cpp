@@ -30,10 +30,12 @@ struct ihipEvent_t {
 };
 
 namespace {
-int g_device = 0;
-long g_fail_launch_after = -1;  // < 0: never; 0: the next launch fails
-long g_fail_alloc_after = -1;   // the same for device and pinned allocations
-long g_launches = 0;
+// Per thread, like the runtime's current device; the injection counters are
+// per thread too, so that threads driving their own handles stay apart.
+thread_local int g_device = 0;
+thread_local long g_fail_launch_after = -1;  // < 0: never; 0: the next launch fails
+thread_local long g_fail_alloc_after = -1;   // the same for device and pinned allocations
+thread_local long g_launches = 0;
 
 bool alloc_fails() {
   if (g_fail_alloc_after == 0) return true;  // sticky until reset
@@ -493,13 +495,11 @@ hipError_t launch_zero_u64(uint64_t* p, hipStream_t) {
 
 hipError_t fixed_scratch(FixedScratch* out) {
   // The code object's fixed array: kFixedMaxQueries counts, then the scan's
-  // look-back words for that many queries (one allocation, as one array).
-  static uint64_t* base = nullptr;
-  if (base == nullptr) {
-    const size_t words = kFixedMaxQueries / 2 + scan_status_words(kFixedMaxQueries);
-    base = static_cast<uint64_t*>(std::calloc(words, sizeof(uint64_t)));
-    if (base == nullptr) return hipErrorOutOfMemory;
-  }
+  // look-back words for that many queries (one allocation, as one array,
+  // made once for the process).
+  static uint64_t* const base = static_cast<uint64_t*>(
+      std::calloc(kFixedMaxQueries / 2 + scan_status_words(kFixedMaxQueries), sizeof(uint64_t)));
+  if (base == nullptr) return hipErrorOutOfMemory;
   out->counts = reinterpret_cast<uint32_t*>(base);
   out->status = base + kFixedMaxQueries / 2;
   return hipSuccess;

@@ -14,7 +14,9 @@ report or a failed status check fails the test.  A second case plants a
 one-element-short scratch allocation in a copy of the host code and checks
 that the run reports it.  A third case checks the sort-scratch carving
 itself: regions inside the allocation, disjoint, per-slot ones 16-byte
-aligned.
+aligned.  A fourth builds the same host code with ThreadSanitizer and drives
+handles from four threads at once (calls on different handles are
+independent).
 """
 import os
 import re
@@ -58,15 +60,15 @@ def extract_layout(src: str) -> str:
     return "\n".join(out) + "\n"
 
 
-def build_and_run(tmp_path, api_src):
+def build_and_run(tmp_path, api_src, sanitize="address,undefined", args=()):
     if shutil.which("g++") is None:
         pytest.skip("g++ not available")
     gen = tmp_path / "gen"
     gen.mkdir()
     (gen / "layout_gen.inc").write_text(extract_layout(open(KERNELS).read()))
     exe = str(tmp_path / "host_sanitize")
-    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
-           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-pthread",
+           "-fsanitize=" + sanitize, "-fno-sanitize-recover=all",
            "-I", HERE, "-I", str(gen), "-I", CSRC, "-I", os.path.join(ROOT, "include"),
            "-x", "c++", api_src, "-x", "none",
            os.path.join(HERE, "stand_in.cpp"), os.path.join(HERE, "driver.cpp"), "-o", exe]
@@ -77,7 +79,9 @@ def build_and_run(tmp_path, api_src):
     env = dict(os.environ)
     env["ASAN_OPTIONS"] = "detect_leaks=1:halt_on_error=1"
     env["UBSAN_OPTIONS"] = "print_stacktrace=1:halt_on_error=1"
-    return subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
+    env["TSAN_OPTIONS"] = "halt_on_error=1"
+    return subprocess.run([exe] + list(args), capture_output=True, text=True, timeout=600,
+                          env=env)
 
 
 def test_host_code_is_clean_under_sanitizers(tmp_path):
@@ -119,3 +123,11 @@ def test_sort_scratch_layout(tmp_path):
     run = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     assert run.returncode == 0, (run.stdout + run.stderr)[-4000:]
     assert "sort scratch layout: ok" in run.stdout
+
+
+def test_handles_on_threads_under_thread_sanitizer(tmp_path):
+    run = build_and_run(tmp_path, os.path.join(CSRC, "lsm_api.hip"), sanitize="thread",
+                        args=("1", "threads"))
+    assert run.returncode == 0, (run.stdout + run.stderr)[-6000:]
+    assert "ThreadSanitizer" not in run.stderr, run.stderr[-4000:]
+    assert "host sanitize check, threads: ok" in run.stdout
