@@ -370,3 +370,36 @@ def test_forced_sort_paths(mode):
                 t.delete(k)
         t.check_levels()
         t.check_queries(q, lo, hi)
+
+
+@pytest.mark.parametrize("key_bits,b", [(1, 3000), (4, 3000), (9, 2049), (9, 40000)])
+def test_few_key_bits(key_bits, b):
+    """Keys below 2^key_bits with key_bits under the top digit's 10 bits:
+    the top digit then holds every key bit, so a bucket is sorted with no
+    digit pass (equal key variables keep their batch order), mixed batches
+    put the status bit into the top digit, and most of the 1024 buckets stay
+    empty while the others hold many copies of one key.  Partial, deleting
+    and mixed batches through the pipelined insertion (pairs, fusion) and
+    the automatic path choice; levels byte for byte against the cascade
+    oracle, answers against the map oracle."""
+    note("few key bits: key_bits=%d b=%d" % (key_bits, b))
+    R = 23 if b > 10000 else 37
+    ops, _, _, _ = W.random_small(3300 + key_bits, b, R, 1 << key_bits, p_delete=0.3, nq=10)
+    t = Trio(b, key_bits=key_bits, checked=True)
+    rng = np.random.default_rng(key_bits)
+    for i, (kind, k, v) in enumerate(ops):
+        if i % 5 == 4:
+            vv = v if v is not None else k
+            t.mixed(k, vv, (rng.random(k.size) < 0.5).astype(np.uint8))
+        elif kind == "insert":
+            t.insert(k, v)
+        else:
+            t.delete(k)
+    t.check_levels()
+    top = (1 << key_bits) - 1
+    q = np.arange(top + 3, dtype=np.uint32)
+    lo = np.arange(top + 1, dtype=np.uint32)
+    hi = np.minimum(lo + 1 + top // 3, top + 1).astype(np.uint32)
+    t.check_queries(q, lo, hi)
+    t.check_order(q)
+    t.g.close()
